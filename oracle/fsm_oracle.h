@@ -1,0 +1,118 @@
+/*
+ * fsm_oracle.h -- interface of the FP64 CPU oracle for the forward solution method (FSM)
+ * of milled surface topography.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and fsm_oracle.c are a plain, slow, obviously
+ * correct restatement of the method, used to check the GPU library.  They share no code,
+ * header, table or constant with the library under paper_2603_28160_amd/.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load the oracle; the
+ * product path never does.
+ *
+ * Units: lengths in mm, angles in rad.  Every function returns 0 on success and a negative
+ * value on invalid parameters.
+ */
+#ifndef FSM_ORACLE_H
+#define FSM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_MAX_TEETH 8
+
+/* Tool description (Sec. 2.1; helix, pitch, eccentric runout and tilt extend Eq. (2)-(5)). */
+typedef struct or_tool {
+    int kind;            /* 0: round edge (circular insert / corner radius, Eq. (1)); 1: ball end */
+    int n_teeth;         /* z_n */
+    int n_edge;          /* N, discretised points per edge (Eq. (6)) */
+    int uniform_pitch;   /* nonzero: tooth K sits at 2*pi*K/z_n; zero: at theta[K] */
+    double D;            /* cutting diameter through the edges' lowest points (Eq. (2)); ball: 2*R_b */
+    double R_edge;       /* edge profile radius R of Eq. (1) (round edge only) */
+    double helix;        /* helix angle beta */
+    double rake_f;       /* radial rake gamma_f (Eq. (2)) */
+    double rake_p;       /* axial rake gamma_p (Eq. (2)) */
+    double theta[OR_MAX_TEETH];
+    double ecc;          /* eccentric spindle runout e */
+    double ecc_phase;    /* its phase lambda */
+    double eps_r[OR_MAX_TEETH]; /* per-insert radial offset (Eq. (2): (K-1)*eps_r) */
+    double eps_a[OR_MAX_TEETH]; /* per-insert axial offset  (Eq. (2): (K-1)*eps_a) */
+    double tilt_lead;    /* rotation about the workpiece Y axis */
+    double tilt_side;    /* rotation about the workpiece X axis */
+} or_tool;
+
+/* Cutting parameters and tool path. */
+typedef struct or_cut {
+    double f_z;          /* feed per tooth */
+    double a_p;          /* axial depth of cut */
+    double a_e;          /* stepover between parallel passes (<=0: single pass) */
+    double phi0;         /* initial phase angle phi of Eq. (3) */
+    int S;               /* time steps per spindle revolution */
+    int n_passes;        /* 0: enough passes to cover the grid */
+    long long n_steps;   /* steps per pass, 0: enough whole revolutions to cover the grid */
+    double x_start;      /* tool-centre x at step 0 (NaN: auto) */
+    double y_first;      /* tool-centre y of pass 0 (NaN: auto) */
+} or_cut;
+
+/* Workpiece grid (Sec. 2.2): node (i, j) sits at (x0 + i*dd, y0 + j*dd). */
+typedef struct or_grid {
+    double x0, y0, dd;
+    long long nx, ny;
+} or_grid;
+
+typedef struct or_plan_out {
+    double r_reach;      /* bound on the horizontal distance of any edge point from the tool axis */
+    double x_start;
+    double y_first;
+    long long n_passes;
+    long long n_steps;
+    long long n_evals;   /* passes * steps * teeth * edge points */
+} or_plan_out;
+
+typedef struct or_counts {
+    long long n_evals;   /* edge-point evaluations */
+    long long n_binned;  /* evaluations whose point fell inside the grid */
+} or_counts;
+
+typedef struct or_rough {
+    double Sa, Sq, Sp, Sv, Sz, Ssk, Sku, Ra_feed, Ra_pick, mean;
+    long long n_hit, n_feed, n_pick;
+} or_rough;
+
+/* Edge discretisation (Eq. (1), (6) and the chord-length rule of Sec. 2.2) followed by the
+ * cutting-edge -> tool transformation (Eq. (2)), helix lag and eccentric runout.
+ * pC: [N][3] edge points in the cutting-edge frame; pT: [z_n][N][3] tool-frame points.
+ * Either pointer may be NULL. */
+int or_edge_points(const or_tool *t, const or_cut *c, double *pC, double *pT);
+
+/* Travel extent, pass count and step count (auto values where the cut leaves them open). */
+int or_plan(const or_tool *t, const or_cut *c, const or_grid *g, or_plan_out *out);
+
+/* Workpiece-frame position of one evaluation (pass q, step s, tooth K, edge point p), Eq. (5). */
+int or_point(const or_tool *t, const or_cut *c, const or_grid *g,
+             long long q, long long s, int K, int p, double out[3]);
+
+/* Per-cell minimum Z-map (Sec. 2.3, Eq. (7)) restricted to the cell window
+ * [i0,i1) x [j0,j1); Zw is (j1-j0)*(i1-i0) doubles, row-major, filled with +inf for cells no
+ * point reached.  win (nullable) receives the flat evaluation index of each cell's winner. */
+int or_simulate_window(const or_tool *t, const or_cut *c, const or_grid *g,
+                       long long i0, long long i1, long long j0, long long j1,
+                       double *Zw, long long *win, or_counts *cnt);
+
+/* Cells whose single-precision result may legitimately differ from the double one: a cell is
+ * marked when an evaluation lying within `delta` of a cell boundary could land in it (or leave
+ * it) with a height at most `tol` above the cell's double-precision value Z (full grid). */
+int or_ambiguous_cells(const or_tool *t, const or_cut *c, const or_grid *g,
+                       const double *Z, double delta, double tol, unsigned char *mask);
+
+/* Areal and profile roughness of a Z-map (+inf = empty cell). */
+int or_roughness(const double *Z, long long nx, long long ny, or_rough *out);
+
+/* Trajectory-point count of the paper's fixed-time-step mode: z_n * ceil(T / dt) with
+ * T = L / v_f, v_f = f_z z_n n / 60, n = 1000 v_c / (pi D)  (Sec. 4.3). */
+long long or_paper_trajectory_points(double v_c, double f_z, int z_n, double D,
+                                     double L, double dt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

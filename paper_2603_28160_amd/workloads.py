@@ -1,0 +1,186 @@
+"""Seeded synthetic workloads for the milling-topography simulator.
+
+This module only describes inputs: tool, cut and grid parameter records, and the seeded
+random draws that produce them.  It holds none of the method's arithmetic, so both the GPU
+library binding and the CPU oracle can take their inputs from it.
+
+Shapes follow the paper's face-milling workloads (Sec. 4.2, 4.3: a D = 10 mm class tool,
+2-4 teeth, feed per tooth 0.02-0.6 mm, micrometre-scale runout) and extend them with the
+ball-end, helix, tilt, variable-pitch and raster-pass tools of the benchmark configurations.
+Lengths are in mm and angles in rad.  Random numbers come from numpy's PCG64 generator seeded
+with 28160 + configuration number (plus the simulation index inside a batch).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+ROUND = 0   # round cutting edge: circular insert / corner-radius profile (Eq. (1))
+BALL = 1    # ball end
+
+SEED_BASE = 28160
+
+
+@dataclass
+class Tool:
+    kind: int
+    n_teeth: int
+    n_edge: int
+    D: float
+    R_edge: float = 0.0
+    helix: float = 0.0
+    rake_radial: float = 0.0
+    rake_axial: float = 0.0
+    theta: Optional[Tuple[float, ...]] = None   # tooth angles; None = uniform pitch
+    runout_ecc: float = 0.0
+    runout_phase: float = 0.0
+    eps_r: Tuple[float, ...] = ()                # per-insert radial offsets
+    eps_a: Tuple[float, ...] = ()                # per-insert axial offsets
+    tilt_lead: float = 0.0
+    tilt_side: float = 0.0
+
+
+@dataclass
+class Cut:
+    f_z: float
+    a_p: float
+    a_e: float = 0.0
+    phi0: float = 0.0
+    steps_per_rev: int = 360
+    n_passes: int = 0          # 0: auto
+    n_steps: int = 0           # steps per pass, 0: auto
+    x_start: float = math.nan  # NaN: auto
+    y_first: float = math.nan  # NaN: auto
+
+
+@dataclass
+class Grid:
+    x0: float
+    y0: float
+    dd: float
+    nx: int
+    ny: int
+
+
+@dataclass
+class Sim:
+    tool: Tool
+    cut: Cut
+    grid: Grid
+    name: str = ""
+
+    def replace(self, **kw) -> "Sim":
+        return dataclasses.replace(self, **kw)
+
+
+def centred_grid(nx: int, ny: int, dd: float, cx: float = 0.0, cy: float = 0.0) -> Grid:
+    """Grid of nx x ny nodes spaced dd whose node block is centred on (cx, cy)."""
+    return Grid(x0=cx - 0.5 * (nx - 1) * dd, y0=cy - 0.5 * (ny - 1) * dd, dd=dd, nx=nx, ny=ny)
+
+
+def _rng(config: int, index: int = 0) -> np.random.Generator:
+    return np.random.default_rng([SEED_BASE + config, index])
+
+
+# --- configuration 1: plain FP64 single pass -----------------------------------------------
+
+def config1() -> Sim:
+    """Round-edge ("flat") mill D = 10 mm, 2 flutes, helix 30 deg, 5 um runout at a seeded
+    phase, f_z = 0.1 mm, 360 steps/rev, 20 edge points, one straight pass, a_p = 0.5 mm;
+    1 x 1 mm Z-map at 5 um (200 x 200)."""
+    r = _rng(1)
+    tool = Tool(kind=ROUND, n_teeth=2, n_edge=20, D=10.0, R_edge=5.0,
+                helix=math.radians(30.0), runout_ecc=0.005,
+                runout_phase=float(r.uniform(0.0, 2.0 * math.pi)))
+    cut = Cut(f_z=0.1, a_p=0.5, steps_per_rev=360, n_passes=1, y_first=0.0)
+    return Sim(tool, cut, centred_grid(200, 200, 0.005), name="config1_flat_d10_200x200_f64")
+
+
+# --- configuration 2: ball-end raster ---------------------------------------------------------
+
+def config2(nx: int = 5000, ny: int = 5000, dd: float = 0.001) -> Sim:
+    """Ball end R = 3 mm, 4 flutes, helix 30 deg, lead tilt 15 deg, runout U(0, 8) um at a
+    seeded phase, f_z = 0.08 mm, stepover 0.3 mm parallel passes, 720 steps/rev, 64 edge
+    points, a_p = 0.5 mm; 5 x 5 mm at 1 um (5000 x 5000)."""
+    r = _rng(2)
+    ecc = float(r.uniform(0.0, 0.008))
+    phase = float(r.uniform(0.0, 2.0 * math.pi))
+    tool = Tool(kind=BALL, n_teeth=4, n_edge=64, D=6.0, helix=math.radians(30.0),
+                runout_ecc=ecc, runout_phase=phase, tilt_lead=math.radians(15.0))
+    cut = Cut(f_z=0.08, a_p=0.5, a_e=0.3, steps_per_rev=720)
+    return Sim(tool, cut, centred_grid(nx, ny, dd), name=f"config2_ball_r3_{nx}x{ny}")
+
+
+# --- configuration 3: batch of uneven simulations ---------------------------------------------
+
+def random_sim(config: int, index: int, side_max: int = 2048, n_edge: int = 64,
+               steps_per_rev: int = 720) -> Sim:
+    """One seeded simulation of the batch/serving mix: tool type round/ball 50/50,
+    D ~ U(4, 16) mm, flutes in {2, 3, 4}, helix ~ U(20, 45) deg, f_z ~ U(0.02, 0.2) mm,
+    stepover ~ U(0.1, 1.0) mm, runout ~ U(0, 10) um at phase ~ U(0, 2 pi), lead tilt
+    ~ U(0, 30) deg, square grid with side ~ U{256..side_max} cells at dd ~ U(1, 5) um."""
+    r = _rng(config, index)
+    kind = BALL if r.uniform() < 0.5 else ROUND
+    D = float(r.uniform(4.0, 16.0))
+    z_n = int(r.integers(2, 5))
+    helix = math.radians(float(r.uniform(20.0, 45.0)))
+    f_z = float(r.uniform(0.02, 0.2))
+    a_e = float(r.uniform(0.1, 1.0))
+    ecc = float(r.uniform(0.0, 0.010))
+    phase = float(r.uniform(0.0, 2.0 * math.pi))
+    tilt = math.radians(float(r.uniform(0.0, 30.0)))
+    side = int(r.integers(256, side_max + 1))
+    dd = float(r.uniform(0.001, 0.005))
+    tool = Tool(kind=kind, n_teeth=z_n, n_edge=n_edge, D=D,
+                R_edge=0.5 * D if kind == ROUND else 0.0, helix=helix,
+                runout_ecc=ecc, runout_phase=phase, tilt_lead=tilt)
+    cut = Cut(f_z=f_z, a_p=0.5, a_e=a_e, steps_per_rev=steps_per_rev)
+    return Sim(tool, cut, centred_grid(side, side, dd), name=f"mix{config}_{index}")
+
+
+def config3(n: int = 256) -> List[Sim]:
+    """Batch of n seeded simulations (grid sides up to 2048)."""
+    return [random_sim(3, i, side_max=2048) for i in range(n)]
+
+
+def config4_requests(n: int, rate: float, seed_offset: int = 0) -> List[Tuple[float, Sim]]:
+    """Serving workload: n requests drawn like configuration 3 with sides up to 4096 and
+    Poisson arrivals at `rate` requests/s.  Returns (arrival time in s, simulation) pairs."""
+    r = _rng(4, 1_000_000 + seed_offset)
+    gaps = r.exponential(1.0 / rate, size=n)
+    t = np.cumsum(gaps) - gaps[0]
+    return [(float(t[i]), random_sim(4, seed_offset * 1_000_003 + i, side_max=4096))
+            for i in range(n)]
+
+
+# --- configuration 5: one large field ---------------------------------------------------------
+
+def config5(nx: int = 40000, ny: int = 40000, dd: float = 0.0005) -> Sim:
+    """Round-edge mill D = 12 mm, 4 flutes at 0/88/180/268 deg (pitch 88/92/88/92),
+    helix 35 deg, runout 6 um at a seeded phase, lead tilt 5 deg, f_z = 0.12 mm, stepover
+    2 mm, 720 steps/rev, 128 edge points, a_p = 0.5 mm; 20 x 20 mm at 0.5 um."""
+    r = _rng(5)
+    tool = Tool(kind=ROUND, n_teeth=4, n_edge=128, D=12.0, R_edge=6.0,
+                helix=math.radians(35.0),
+                theta=tuple(math.radians(a) for a in (0.0, 88.0, 180.0, 268.0)),
+                runout_ecc=0.006, runout_phase=float(r.uniform(0.0, 2.0 * math.pi)),
+                tilt_lead=math.radians(5.0))
+    cut = Cut(f_z=0.12, a_p=0.5, a_e=2.0, steps_per_rev=720)
+    return Sim(tool, cut, centred_grid(nx, ny, dd), name=f"config5_flat_d12_{nx}x{ny}")
+
+
+# --- the paper's own tool (Case 2, Sec. 4.2) ----------------------------------------------------
+
+def paper_case2_tool(eps_r: float = 0.0, eps_a: float = 0.0, n_edge: int = 40) -> Tool:
+    """Face mill D = 10 mm with 2 round inserts of radius 5 mm, radial rake 0.6 deg, axial
+    rake 0 deg (tool table of Sec. 4.2); insert K carries the runout (K-1)*eps (Eq. (2))."""
+    return Tool(kind=ROUND, n_teeth=2, n_edge=n_edge, D=10.0, R_edge=5.0,
+                rake_radial=math.radians(0.6), rake_axial=0.0,
+                eps_r=(0.0, eps_r), eps_a=(0.0, eps_a))
+
+
+CONFIGS = {1: config1, 2: config2, 5: config5}

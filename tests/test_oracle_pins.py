@@ -1,0 +1,490 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than its own formulas: values printed in
+the paper, closed forms of the geometry, rigid-motion invariants, brute force on tiny grids,
+and closed-form roughness of synthetic surfaces.  Test infrastructure only (no GPU).
+"""
+import dataclasses
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_28160_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def simple_round(**kw):
+    base = dict(kind=W.ROUND, n_teeth=2, n_edge=21, D=10.0, R_edge=5.0)
+    base.update(kw)
+    return W.Tool(**base)
+
+
+def sim_of(tool, cut=None, grid=None):
+    cut = cut or W.Cut(f_z=0.1, a_p=0.5, steps_per_rev=360, n_passes=1, n_steps=720,
+                       x_start=0.3, y_first=-0.2)
+    grid = grid or W.centred_grid(20, 20, 0.05)
+    return W.Sim(tool, cut, grid)
+
+
+# --- time discretisation: the paper's trajectory-point table ---------------------------------
+
+def test_paper_trajectory_point_counts():
+    rows = [list(map(float, ln.split())) for ln in open(os.path.join(GOLDEN, "paper_trajectory_points.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 9
+    for no, vc, fz, ap, pts in rows:
+        got = oracle.paper_trajectory_points(vc, fz, 2, 10.0, 10.0, 0.4e-6)
+        assert got == int(pts), (no, got, pts)
+
+
+# --- edge discretisation (Eq. (1), (6), chord rule) ------------------------------------------
+
+def test_edge_chord_case2_tool():
+    # Case-2 tool: R = 5, radial rake 0.6 deg; a_p = 0.5, f_z = 0.6.  Half chord from the depth
+    # of cut sqrt(R^2 - (R - a_p)^2) = sqrt(4.75) beats f_z / (2 cos gamma_f) = 0.300016.
+    t = W.paper_case2_tool(n_edge=41)
+    s = sim_of(t, W.Cut(f_z=0.6, a_p=0.5, steps_per_rev=360, n_passes=1, n_steps=1))
+    pC, _ = oracle.edge_points(s)
+    dl = math.sqrt(4.75)
+    assert pC[0, 0] == pytest.approx(-dl, abs=1e-15)
+    assert pC[-1, 0] == pytest.approx(dl, abs=1e-15)
+    # the chord ends sit exactly at the depth of cut; the middle point is the lowest (0)
+    assert pC[0, 2] == pytest.approx(0.5, abs=1e-14) and pC[-1, 2] == pytest.approx(0.5, abs=1e-14)
+    assert pC[20, 0] == 0.0 and pC[20, 2] == 0.0
+    # symmetric, uniformly spaced, all on the insert circle x^2 + (z - R)^2 = R^2
+    np.testing.assert_allclose(pC[:, 0], -pC[::-1, 0], atol=1e-15)
+    np.testing.assert_allclose(np.diff(pC[:, 0]), 2 * dl / 40, rtol=1e-12)
+    np.testing.assert_allclose(pC[:, 0] ** 2 + (pC[:, 2] - 5.0) ** 2, 25.0, rtol=1e-14)
+    assert np.all(pC[:, 1] == 0.0)
+
+
+def test_edge_chord_feed_limited():
+    # shallow cut: the feed criterion f_z / (2 cos gamma_f) sets the half chord
+    t = W.paper_case2_tool(n_edge=11)
+    s = sim_of(t, W.Cut(f_z=0.6, a_p=0.001, steps_per_rev=360, n_passes=1, n_steps=1))
+    pC, _ = oracle.edge_points(s)
+    assert pC[-1, 0] == pytest.approx(0.6 / (2 * math.cos(math.radians(0.6))), rel=1e-14)
+
+
+def test_edge_ball_profile():
+    t = W.Tool(kind=W.BALL, n_teeth=1, n_edge=33, D=6.0)
+    s = sim_of(t, W.Cut(f_z=0.1, a_p=0.5, steps_per_rev=360, n_passes=1, n_steps=1))
+    pC, _ = oracle.edge_points(s)
+    assert np.all(pC[0] == 0.0)                              # starts at the tip
+    assert pC[-1, 2] == pytest.approx(0.5, abs=1e-14)        # ends at the depth of cut
+    np.testing.assert_allclose(pC[:, 0] ** 2 + (pC[:, 2] - 3.0) ** 2, 9.0, rtol=1e-14)
+    # tilt extends the meridian by the tilt angle
+    t2 = dataclasses.replace(t, tilt_lead=math.radians(15.0))
+    pC2, _ = oracle.edge_points(sim_of(t2, s.cut))
+    k = math.atan2(pC2[-1, 0], 3.0 - pC2[-1, 2])
+    assert k == pytest.approx(math.radians(15.0) + math.acos(1 - 0.5 / 3), rel=1e-13)
+
+
+def test_single_point_edge():
+    t = simple_round(n_edge=1)
+    pC, _ = oracle.edge_points(sim_of(t))
+    assert pC.tolist() == [[0.0, 0.0, 0.0]]
+
+
+# --- transformation chain (Eq. (2)-(5)) -------------------------------------------------------
+
+def test_identity_case_position():
+    # phi = 0, step 0, tooth 0, no rake/runout/helix/tilt: (l, 0, z) -> (x_c + D/2 + l, y_q, z)
+    t = simple_round()
+    s = sim_of(t)
+    pC, _ = oracle.edge_points(s)
+    for p in range(t.n_edge):
+        w = oracle.point(s, 0, 0, 0, p)
+        np.testing.assert_allclose(w, [0.3 + 5.0 + pC[p, 0], -0.2, pC[p, 2]], atol=1e-15)
+
+
+def test_rotation_sense_quarter_turn_and_tooth_phase():
+    # Eq. (3) as printed, alpha = phi + 2 pi (K-1)/z_n - omega t: the tool turns from +X to
+    # +Y (counter-clockwise seen from +Z) and tooth K trails tooth 0 by 2 pi K / z_n.
+    t = simple_round(n_teeth=4, n_edge=1)
+    S = 360
+    s = sim_of(t, W.Cut(f_z=0.0, a_p=0.5, steps_per_rev=S, n_passes=1, n_steps=S,
+                        x_start=0.0, y_first=0.0))
+    np.testing.assert_allclose(oracle.point(s, 0, S // 4, 0, 0), [0, 5, 0], atol=1e-14)
+    np.testing.assert_allclose(oracle.point(s, 0, S // 2, 0, 0), [-5, 0, 0], atol=1e-14)
+    np.testing.assert_allclose(oracle.point(s, 0, 0, 1, 0), [0, -5, 0], atol=1e-14)
+    np.testing.assert_allclose(oracle.point(s, 0, S // 4, 1, 0), [5, 0, 0], atol=1e-14)
+    # initial phase phi advances every tooth backwards by phi
+    s2 = s.replace(cut=dataclasses.replace(s.cut, phi0=math.pi / 2))
+    np.testing.assert_allclose(oracle.point(s2, 0, 0, 0, 0), [0, -5, 0], atol=1e-14)
+
+
+def test_variable_pitch():
+    th = tuple(math.radians(a) for a in (0.0, 88.0, 180.0, 268.0))
+    t = simple_round(n_teeth=4, n_edge=1, theta=th)
+    s = sim_of(t, W.Cut(f_z=0.0, a_p=0.5, steps_per_rev=360, n_passes=1, n_steps=360,
+                        x_start=0.0, y_first=0.0))
+    for K, a in enumerate((0.0, 88.0, 180.0, 268.0)):
+        w = oracle.point(s, 0, 0, K, 0)
+        ang = math.degrees(math.atan2(w[1], w[0])) % 360.0
+        assert ang == pytest.approx((-a) % 360.0, abs=1e-9)
+
+
+def test_feed_and_pass_offsets():
+    t = simple_round(n_teeth=3, n_edge=5)
+    S = 200
+    s = sim_of(t, W.Cut(f_z=0.07, a_p=0.5, a_e=0.25, steps_per_rev=S, n_passes=3,
+                        n_steps=4 * S, x_start=-1.0, y_first=-0.5))
+    for p in (0, 2, 4):
+        a = oracle.point(s, 0, 17, 1, p)
+        b = oracle.point(s, 0, 17 + S, 1, p)       # one revolution later: moved by z_n f_z
+        np.testing.assert_allclose(b - a, [3 * 0.07, 0, 0], atol=1e-14)
+        c = oracle.point(s, 2, 17, 1, p)           # two passes over: moved by 2 a_e
+        np.testing.assert_allclose(c - a, [0, 0.5, 0], atol=1e-14)
+        d = oracle.point(s, 0, 18, 1, p)           # one step: moved by z_n f_z / S plus a turn
+        r_a = math.hypot(a[0] - (-1.0 + 17 * 0.21 / S), a[1] + 0.5)
+        r_d = math.hypot(d[0] - (-1.0 + 18 * 0.21 / S), d[1] + 0.5)
+        assert r_a == pytest.approx(r_d, abs=1e-13)
+
+
+def test_rake_is_rigid_motion():
+    t = simple_round(n_teeth=2, n_edge=9, rake_radial=math.radians(7.0),
+                     rake_axial=math.radians(-4.0), eps_r=(0.0, 0.02), eps_a=(0.0, 0.01))
+    s = sim_of(t)
+    pC, pT = oracle.edge_points(s)
+    for K in range(2):
+        off = np.array([5.0 + t.eps_r[K], 0.0, t.eps_a[K]])
+        d0 = np.linalg.norm(pC[:, None, :] - pC[None, :, :], axis=-1)
+        d1 = np.linalg.norm(pT[K][:, None, :] - pT[K][None, :, :], axis=-1)
+        np.testing.assert_allclose(d1, d0, atol=1e-14)     # distances preserved
+        # lowest edge point (l = 0) sits exactly at the translation of Eq. (2)
+        np.testing.assert_allclose(pT[K][4], off, atol=1e-15)
+    # radial rake turns the edge about Z_C by -gamma_f: points with l > 0 move to -y
+    assert pT[0][-1][1] < 0 and pT[0][0][1] > 0
+
+
+def test_helix_lag_angle():
+    # a point at profile height z lags behind the lowest point by psi = z tan(beta) / (D/2)
+    beta = math.radians(30.0)
+    t = simple_round(n_teeth=1, n_edge=15, helix=beta)
+    s = sim_of(t)
+    pC, pT = oracle.edge_points(s)
+    for p in range(15):
+        r = math.hypot(pT[0, p, 0], pT[0, p, 1])
+        assert r == pytest.approx(5.0 + pC[p, 0], abs=1e-13)
+        ang = math.atan2(pT[0, p, 1], pT[0, p, 0])
+        assert ang == pytest.approx(-pC[p, 2] * math.tan(beta) / 5.0, abs=1e-14)
+
+
+def test_eccentric_runout_translation():
+    # an eccentric axis offset is one vector fixed in the cutter body: at step 0 (spindle and
+    # body frames aligned) every tooth's points move by (e cos lambda, e sin lambda, 0), and a
+    # step s later by that vector turned with the spindle
+    t0 = simple_round(n_teeth=3, n_edge=7, helix=math.radians(25.0))
+    t1 = dataclasses.replace(t0, runout_ecc=0.008, runout_phase=1.234)
+    S = 360
+    cut = W.Cut(f_z=0.1, a_p=0.5, steps_per_rev=S, n_passes=1, n_steps=S, x_start=0.0,
+                y_first=0.0)
+    for st in (0, 45, 200):
+        turn = 2 * math.pi * st / S
+        e = [0.008 * math.cos(1.234 + turn), 0.008 * math.sin(1.234 + turn), 0.0]
+        for K in range(3):
+            for p in (0, 3, 6):
+                d = oracle.point(sim_of(t1, cut), 0, st, K, p) - oracle.point(sim_of(t0, cut), 0, st, K, p)
+                np.testing.assert_allclose(d, e, atol=1e-15)
+    # so opposite teeth of a two-flute cutter sit at different radii: D/2 +- e cos lambda
+    t2 = simple_round(n_teeth=2, n_edge=1, runout_ecc=0.005, runout_phase=0.4)
+    _, pT = oracle.edge_points(sim_of(t2, cut))
+    assert math.hypot(*pT[0, 0, :2]) - math.hypot(*pT[1, 0, :2]) == pytest.approx(
+        2 * 0.005 * math.cos(0.4), rel=1e-5)
+
+
+def test_tilt_rigid_about_pivot_and_lowers_leading_side():
+    tau = math.radians(12.0)
+    t = simple_round(n_teeth=2, n_edge=7, helix=math.radians(30))
+    tt = dataclasses.replace(t, tilt_lead=tau)
+    S = 360
+    cut = W.Cut(f_z=0.1, a_p=0.5, steps_per_rev=S, n_passes=1, n_steps=S, x_start=0.0,
+                y_first=0.0)
+    s0, s1 = sim_of(t, cut), sim_of(tt, cut)
+    for st in (0, 37, 90, 211):
+        for p in (0, 3, 6):
+            a = oracle.point(s0, 0, st, 1, p)
+            b = oracle.point(s1, 0, st, 1, p)
+            xc = st * 0.2 / S
+            assert np.linalg.norm(b - [xc, 0, 0]) == pytest.approx(np.linalg.norm(a - [xc, 0, 0]), abs=1e-13)
+            assert b[1] == pytest.approx(a[1], abs=1e-15)
+    # the lowest point of tooth 0 at step 0 points along +X (the feed direction): lowered
+    w0 = oracle.point(s1, 0, 0, 0, 3)
+    assert w0[2] == pytest.approx(-math.sin(tau) * 5.0, abs=1e-13)
+    # side tilt raises the +Y side for a positive angle
+    ts = dataclasses.replace(t, tilt_side=tau)
+    w = oracle.point(sim_of(ts, cut), 0, S // 4, 0, 3)
+    assert w[2] == pytest.approx(math.sin(tau) * 5.0, abs=1e-12)
+
+
+def test_tilted_ball_lowest_point():
+    # a sphere of radius R tilted by tau about the tool tip has its lowest point R(1 - cos tau)
+    # below the tip, displaced R sin(tau) towards +X
+    R, tau = 3.0, math.radians(15.0)
+    t = W.Tool(kind=W.BALL, n_teeth=1, n_edge=801, D=2 * R, tilt_lead=tau)
+    S = 720
+    s = W.Sim(t, W.Cut(f_z=0.0, a_p=0.5, steps_per_rev=S, n_passes=1, n_steps=S,
+                       x_start=0.0, y_first=0.0), W.centred_grid(81, 81, 0.01, cx=R * math.sin(tau)))
+    Z, _ = oracle.simulate(s)
+    zmin = -R * (1 - math.cos(tau))
+    assert Z.min() >= zmin - 1e-13
+    assert Z.min() == pytest.approx(zmin, abs=2e-6)
+    j, i = np.unravel_index(np.argmin(Z), Z.shape)
+    assert s.grid.x0 + i * 0.01 == pytest.approx(R * math.sin(tau), abs=0.011)
+    assert s.grid.y0 + j * 0.01 == pytest.approx(0.0, abs=0.011)
+
+
+# --- plan: reach and auto travel ---------------------------------------------------------------
+
+def test_reach_bounds_every_point():
+    s = W.config2(nx=60, ny=50, dd=0.05)
+    pl = oracle.plan(s)
+    S = s.cut.steps_per_rev
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        q = int(rng.integers(pl["n_passes"]))
+        st = int(rng.integers(pl["n_steps"]))
+        K = int(rng.integers(4))
+        p = int(rng.integers(64))
+        w = oracle.point(s, q, st, K, p)
+        xc = pl["x_start"] + st * 4 * 0.08 / S
+        yq = pl["y_first"] + q * 0.3
+        assert math.hypot(w[0] - xc, w[1] - yq) <= pl["r_reach"] + 1e-12
+    # the auto path starts and ends a full reach outside the grid on every side
+    g = s.grid
+    assert pl["x_start"] <= g.x0 - g.dd / 2 - pl["r_reach"] + 1e-12
+    x_end = pl["x_start"] + (pl["n_steps"] - 1) * 0.32 / S
+    assert x_end >= g.x0 + (g.nx - 0.5) * g.dd + pl["r_reach"] - 0.32
+    y_last = pl["y_first"] + (pl["n_passes"] - 1) * 0.3
+    assert y_last >= g.y0 + (g.ny - 0.5) * g.dd + pl["r_reach"]
+
+
+def test_eval_count():
+    s = W.config1()
+    pl = oracle.plan(s)
+    assert pl["n_evals"] == pl["n_passes"] * pl["n_steps"] * 2 * 20
+    assert pl["n_steps"] % 360 == 0
+
+
+# --- binning and per-cell minimum: brute force on a tiny grid (Eq. (7)) -------------------------
+
+def _brute_force(s):
+    pl = oracle.plan(s)
+    g = s.grid
+    pts = []
+    for q in range(pl["n_passes"]):
+        for st in range(pl["n_steps"]):
+            for K in range(s.tool.n_teeth):
+                for p in range(s.tool.n_edge):
+                    pts.append(oracle.point(s, q, st, K, p))
+    pts = np.array(pts)
+    Z = np.full((g.ny, g.nx), np.inf)
+    binned = 0
+    for j in range(g.ny):
+        yj = g.y0 + j * g.dd
+        iny = (pts[:, 1] >= yj - g.dd / 2) & (pts[:, 1] < yj + g.dd / 2)
+        for i in range(g.nx):
+            xi = g.x0 + i * g.dd
+            m = iny & (pts[:, 0] >= xi - g.dd / 2) & (pts[:, 0] < xi + g.dd / 2)
+            binned += int(m.sum())
+            if m.any():
+                Z[j, i] = pts[m, 2].min()
+    return Z, binned, pts
+
+
+@pytest.mark.parametrize("kind", [W.ROUND, W.BALL])
+def test_binning_brute_force(kind):
+    if kind == W.ROUND:
+        t = W.Tool(kind=W.ROUND, n_teeth=2, n_edge=5, D=1.0, R_edge=0.4, helix=0.5,
+                   runout_ecc=0.01, runout_phase=0.3, tilt_lead=0.1)
+    else:
+        t = W.Tool(kind=W.BALL, n_teeth=3, n_edge=4, D=0.8, helix=0.6, tilt_lead=0.2,
+                   tilt_side=-0.05, runout_ecc=0.02, runout_phase=2.0)
+    cut = W.Cut(f_z=0.05, a_p=0.2, a_e=0.3, steps_per_rev=16)
+    s = W.Sim(t, cut, W.Grid(x0=-0.31, y0=-0.27, dd=0.07, nx=9, ny=7))
+    Zb, binned, pts = _brute_force(s)
+    Z, cnt = oracle.simulate(s)
+    assert cnt["n_evals"] == len(pts)
+    assert cnt["n_binned"] == binned
+    assert np.array_equal(Z, Zb)
+    # a window of the grid holds exactly the same cells
+    Zw, _ = oracle.simulate(s, window=(2, 7, 1, 5))
+    assert np.array_equal(Zw, Z[1:5, 2:7])
+    # no hit cell lies below the lowest evaluated point, and that point's cell holds it
+    inside = ((pts[:, 0] >= s.grid.x0 - 0.035) & (pts[:, 0] < s.grid.x0 + 8.5 * 0.07) &
+              (pts[:, 1] >= s.grid.y0 - 0.035) & (pts[:, 1] < s.grid.y0 + 6.5 * 0.07))
+    assert Z[np.isfinite(Z)].min() == pts[inside, 2].min()
+
+
+def test_winner_indices_point_at_cell_values():
+    s = W.config1()
+    s = s.replace(grid=W.centred_grid(40, 40, 0.02))
+    Z, cnt, win = oracle.simulate(s, winners=True)
+    pl = oracle.plan(s)
+    hit = np.argwhere(np.isfinite(Z))
+    assert len(hit) > 50
+    for j, i in hit[:: max(1, len(hit) // 40)]:
+        e = int(win[j, i])
+        p = e % 20
+        K = (e // 20) % 2
+        st = (e // 40) % pl["n_steps"]
+        q = e // (40 * pl["n_steps"])
+        w = oracle.point(s, q, st, K, p)
+        assert w[2] == Z[j, i]
+        assert abs(w[0] - (s.grid.x0 + i * 0.02)) <= 0.01 and abs(w[1] - (s.grid.y0 + j * 0.02)) <= 0.01
+
+
+# --- surfaces with closed forms -------------------------------------------------------------------
+
+def test_zero_feed_is_surface_of_revolution():
+    # no feed, no runout/helix/tilt: every hit height is one of the edge-point heights, taken
+    # from a point whose radius matches the cell's distance from the axis
+    t = simple_round(n_teeth=2, n_edge=41, R_edge=2.0, D=4.0)
+    S = 2000
+    s = W.Sim(t, W.Cut(f_z=0.0, a_p=0.3, steps_per_rev=S, n_passes=1, x_start=0.0, y_first=0.0),
+              W.centred_grid(120, 120, 0.025, cx=0.0, cy=0.0))
+    Z, _ = oracle.simulate(s)
+    pC, _ = oracle.edge_points(s)
+    zs = set(pC[:, 2].tolist())
+    hit = np.argwhere(np.isfinite(Z))
+    assert len(hit) > 1000
+    half_diag = 0.025 / math.sqrt(2) * 1.000001
+    radii = 2.0 + pC[:, 0]
+    for j, i in hit:
+        z = Z[j, i]
+        assert z in zs
+        rc = math.hypot(s.grid.x0 + i * 0.025, s.grid.y0 + j * 0.025)
+        cand = pC[:, 2][np.abs(radii - rc) <= half_diag]
+        assert z == cand.min()
+
+
+def test_feed_mark_cusp_height():
+    # front marks of a round edge R spaced f_z apart along the pass centre line cusp at
+    # h = R - sqrt(R^2 - (f_z/2)^2)  (2.500006e-4 mm for R = 5, f_z = 0.1)
+    R, fz = 5.0, 0.1
+    # edge points 0.47 um apart (denser than the 1 um cells); the edge lies exactly on the
+    # pass centre line whenever a tooth passes angle 0, and S = 2000 keeps every other step
+    # more than a cell away from that line
+    t = simple_round(n_teeth=2, n_edge=601, R_edge=R, D=10.0)
+    S = 2000
+    cut = W.Cut(f_z=fz, a_p=0.002, steps_per_rev=S, n_passes=1, n_steps=3 * S,
+                x_start=-5.05, y_first=0.0)
+    g = W.Grid(x0=0.0005, y0=-0.001, dd=0.001, nx=500, ny=3)
+    Z, _ = oracle.simulate(W.Sim(t, cut, g))
+    row = Z[1, 100:400]
+    row = row[np.isfinite(row)]
+    h = R - math.sqrt(R * R - (fz / 2) ** 2)
+    assert row.max() == pytest.approx(h, rel=0.1)
+    assert row.min() == pytest.approx(0.0, abs=2e-7)
+
+
+def test_ball_scallop_height():
+    # parallel passes a_e apart with a ball of radius R leave cusps R - sqrt(R^2 - (a_e/2)^2)
+    R, ae = 3.0, 0.3
+    t = W.Tool(kind=W.BALL, n_teeth=2, n_edge=2000, D=2 * R)
+    cut = W.Cut(f_z=0.0, a_p=0.5, a_e=ae, steps_per_rev=720, n_passes=3, x_start=0.0,
+                y_first=0.0)
+    g = W.Grid(x0=-0.001, y0=0.0, dd=0.001, nx=3, ny=600)
+    Z, _ = oracle.simulate(W.Sim(t, cut, g))
+    col = Z[50:550, 1]
+    col = col[np.isfinite(col)]
+    h = R - math.sqrt(R * R - (ae / 2) ** 2)
+    assert col.max() == pytest.approx(h, rel=0.03)
+    assert col.min() == pytest.approx(0.0, abs=1e-6)
+
+
+def test_runout_periodicity():
+    # with eccentric runout the surface repeats every revolution (z_n f_z = 40 cells here) and
+    # not every tooth period (f_z = 20 cells)
+    s = W.config1()
+    Z, _ = oracle.simulate(s)
+    a, b, c = Z[:, :160], Z[:, 40:], Z[:, 20:180]
+    fa, fb, fc = np.isfinite(a), np.isfinite(b), np.isfinite(c)
+    assert fa.sum() > 1000
+    assert (fa != fb).mean() < 0.002
+    both = fa & fb
+    assert (np.abs(a[both] - b[both]) > 1e-12).mean() < 0.002
+    both2 = fa & fc
+    assert (fa != fc).mean() > 0.01 or (np.abs(a[both2] - c[both2]) > 1e-6).mean() > 0.05
+    # without runout the tooth period is a period too
+    s0 = s.replace(tool=dataclasses.replace(s.tool, runout_ecc=0.0))
+    Z0, _ = oracle.simulate(s0)
+    a0, c0 = Z0[:, :160], Z0[:, 20:180]
+    f0 = np.isfinite(a0) & np.isfinite(c0)
+    assert (np.isfinite(a0) != np.isfinite(c0)).mean() < 0.002
+    assert (np.abs(a0[f0] - c0[f0]) > 1e-12).mean() < 0.002
+
+
+def test_adding_pass_never_raises():
+    s = W.config2(nx=40, ny=30, dd=0.05)
+    pl = oracle.plan(s)
+    s1 = s.replace(cut=dataclasses.replace(s.cut, n_passes=pl["n_passes"] - 3, y_first=pl["y_first"]))
+    Za, _ = oracle.simulate(s1)
+    Zb, _ = oracle.simulate(s)
+    assert np.all(Zb <= Za)
+
+
+# --- roughness (closed forms) -----------------------------------------------------------------------
+
+def test_roughness_sinusoid():
+    A, m = 0.7, 8
+    x = np.arange(64)
+    Z = np.tile(A * np.sin(2 * np.pi * x / m), (4, 1))
+    r = oracle.roughness(Z)
+    assert r["n_hit"] == 256
+    assert r["mean"] == pytest.approx(0.0, abs=1e-15)
+    assert r["Sq"] == pytest.approx(A / math.sqrt(2), rel=1e-14)
+    assert r["Sa"] == pytest.approx(A * (1 + math.sqrt(2)) / 4, rel=1e-14)
+    assert r["Ssk"] == pytest.approx(0.0, abs=1e-13)
+    assert r["Sku"] == pytest.approx(1.5, rel=1e-13)
+    assert r["Sz"] == pytest.approx(2 * A, rel=1e-14)
+    assert r["Sp"] == pytest.approx(A, rel=1e-14) and r["Sv"] == pytest.approx(A, rel=1e-14)
+    assert r["Ra_feed"] == pytest.approx(A * (1 + math.sqrt(2)) / 4, rel=1e-14)
+    assert r["Ra_pick"] == 0.0
+
+
+def test_roughness_two_level_and_ramp():
+    h = 0.013
+    Z = np.where((np.add.outer(np.arange(10), np.arange(12)) % 2) == 0, h, -h)
+    r = oracle.roughness(Z)
+    assert r["Sa"] == pytest.approx(h, rel=1e-14) and r["Sq"] == pytest.approx(h, rel=1e-14)
+    assert r["Ssk"] == pytest.approx(0.0, abs=1e-12) and r["Sku"] == pytest.approx(1.0, rel=1e-13)
+    n = 50
+    Zr = np.tile(np.arange(n, dtype=float), (3, 1))
+    r = oracle.roughness(Zr)
+    assert r["Sq"] ** 2 == pytest.approx((n * n - 1) / 12, rel=1e-13)
+    assert r["Sku"] == pytest.approx(3 * (3 * n * n - 7) / (5 * (n * n - 1)), rel=1e-12)
+    assert r["Ssk"] == pytest.approx(0.0, abs=1e-12)
+    assert r["Sz"] == n - 1
+
+
+def test_roughness_ignores_empty_cells_and_flags_flat():
+    rng = np.random.default_rng(3)
+    Z = rng.normal(size=(20, 30))
+    r0 = oracle.roughness(Z)
+    Z2 = np.full((20, 31), np.inf)
+    Z2[:, :30] = Z
+    r1 = oracle.roughness(Z2)
+    for k in ("Sa", "Sq", "Ssk", "Sku", "Sz", "mean"):
+        assert r1[k] == pytest.approx(r0[k], rel=1e-13)
+    flat = np.full((5, 5), 0.25)
+    flat[0, 0] = np.inf
+    r = oracle.roughness(flat)
+    assert r["Sq"] == 0.0 and math.isnan(r["Ssk"]) and math.isnan(r["Sku"])
+    empty = np.full((3, 3), np.inf)
+    r = oracle.roughness(empty)
+    assert r["n_hit"] == 0 and math.isnan(r["Sa"]) and math.isnan(r["Ra_feed"])
+
+
+def test_roughness_skew_sign():
+    Z = np.zeros((10, 10))
+    Z[3, 4] = 1.0                 # one spike: positive skew, high kurtosis
+    r = oracle.roughness(Z)
+    assert r["Ssk"] > 5 and r["Sku"] > 30
+    r2 = oracle.roughness(-Z)     # one pit: negative skew
+    assert r2["Ssk"] == pytest.approx(-r["Ssk"], rel=1e-13)
