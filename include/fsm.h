@@ -1,0 +1,195 @@
+/*
+ * fsm.h -- C ABI of libfsm, the MI355X (gfx950) library for milled 3D surface topography by
+ * the forward solution method (FSM).
+ *
+ * Problem statement (Sec. 2 and 3 of the paper): tool geometry + cutting parameters +
+ * workpiece grid -> per-cell minimum height map (Z-map) + areal / profile roughness.
+ * The library discretises the cutting edges (Eq. (1), (6)), moves every edge point through the
+ * cutting-edge -> tool -> spindle -> workpiece transformations (Eq. (2)-(5)) at every time
+ * step, bins it into the sampling boundary of a grid node (Eq. (7)), keeps the lowest height
+ * per node (Sec. 2.3), and reduces the Z-map to the ISO 25178-2 amplitude parameters and the
+ * profile Ra along the feed and pick-feed directions (Sec. 4.1, 4.2).
+ *
+ * Conventions
+ *   - Lengths in mm, angles in rad.  Feed runs along +X, parallel passes step along +Y, Z is
+ *     the workpiece normal.  The spindle turns counter-clockwise seen from +Z (the sign of
+ *     omega*t in Eq. (3)); tooth K trails tooth 0 by theta_K.
+ *   - Every call returns FSM_OK (0) or a negative FSM_E* code.  No exception, abort or
+ *     exit crosses the ABI.  Points that fall outside the grid are not errors; they are
+ *     dropped (not clamped) and counted.
+ *   - Parameter structs are plain host memory, borrowed for the duration of the call.
+ *   - Device pointers are caller-owned device memory (for instance a torch tensor's
+ *     data_ptr()); the library never frees them.
+ *   - A context is used by one host thread at a time.  Calls on one context are
+ *     stream-ordered on the stream passed in (a hipStream_t; NULL = the null stream).
+ *
+ * Z-map layout: row-major [ny][nx]; cell (i, j) is the sampling boundary of node
+ * (x0 + i*dd, y0 + j*dd), half-open [x_i - dd/2, x_i + dd/2) x [y_j - dd/2, y_j + dd/2).
+ * Element type double (FSM_F64) or float (FSM_F32).  Cells no point reached hold +inf.
+ */
+#ifndef FSM_H
+#define FSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSM_ABI_VERSION 1
+#define FSM_MAX_TEETH 8
+#define FSM_MAX_EDGE 4096
+
+/* status codes */
+#define FSM_OK 0
+#define FSM_EINVAL (-1)   /* invalid argument or parameter */
+#define FSM_ENOMEM (-2)   /* host or device allocation failed */
+#define FSM_EDEVICE (-3)  /* HIP runtime error (message kept in the context) */
+#define FSM_EAGAIN (-4)   /* batch admission refused: memory budget or slots exhausted */
+#define FSM_ENOTSUP (-5)  /* valid request this build does not support */
+
+/* precision of the Z-map and of the edge-point arithmetic */
+#define FSM_F64 0  /* every operation in double precision; binning bit-exact with the plain
+                      double-precision definition */
+#define FSM_F32 1  /* rotation and tilt of tool-local coordinates in single precision;
+                      tool-centre path, binning and roughness moments in double precision;
+                      Z-map stored as float */
+
+/* tool kinds */
+#define FSM_TOOL_ROUND 0  /* round cutting edge: circular insert / corner-radius profile of
+                             radius R_edge whose lowest point lies at radius D/2 (Eq. (1)) */
+#define FSM_TOOL_BALL 1   /* ball end: sphere of radius D/2 centred on the tool axis */
+
+/* result flags */
+#define FSM_FLAG_SQ_ZERO 1u       /* Sq == 0: Ssk and Sku are NaN */
+#define FSM_FLAG_NO_HIT 2u        /* no cell was reached: every parameter is NaN */
+#define FSM_FLAG_LOW_COVERAGE 4u  /* fewer than 99 % of the cells were reached */
+
+typedef struct fsm_tool {
+    int32_t kind;            /* FSM_TOOL_ROUND or FSM_TOOL_BALL */
+    int32_t n_teeth;         /* z_n, 1..FSM_MAX_TEETH */
+    int32_t n_edge;          /* N, points per cutting edge, 1..FSM_MAX_EDGE (Eq. (6)) */
+    int32_t uniform_pitch;   /* nonzero: tooth K at 2*pi*K/z_n (Eq. (3)); zero: theta[K] */
+    double D;                /* cutting diameter through the edges' lowest points (Eq. (2)) */
+    double R_edge;           /* edge profile radius R (round edge; ignored for a ball) */
+    double helix;            /* helix angle beta: a point at profile height z trails the
+                                lowest point by z*tan(beta)/(D/2) about the tool axis */
+    double rake_radial;      /* gamma_f of Eq. (2) */
+    double rake_axial;       /* gamma_p of Eq. (2) */
+    double theta[FSM_MAX_TEETH];   /* angular position of each tooth (variable pitch) */
+    double runout_ecc;       /* eccentric runout: offset e of the cutter body from the
+                                spindle axis */
+    double runout_phase;     /* its direction lambda in the cutter body */
+    double eps_r[FSM_MAX_TEETH];   /* per-insert radial offset ((K-1)*eps_r of Eq. (2)) */
+    double eps_a[FSM_MAX_TEETH];   /* per-insert axial offset ((K-1)*eps_a of Eq. (2)) */
+    double tilt_lead;        /* tool tilt about the workpiece Y axis; positive lowers the
+                                leading (+X) side */
+    double tilt_side;        /* tool tilt about the workpiece X axis; positive raises +Y */
+} fsm_tool;
+
+typedef struct fsm_cut {
+    double f_z;              /* feed per tooth, >= 0 */
+    double a_p;              /* axial depth of cut, > 0 (sets the engaged edge length) */
+    double a_e;              /* stepover between parallel passes; <= 0: one pass */
+    double phi0;             /* initial phase angle phi of Eq. (3) */
+    int32_t steps_per_rev;   /* S, time steps per spindle revolution, >= 1 */
+    int32_t n_passes;        /* parallel passes; 0: enough to cover the grid */
+    int64_t n_steps;         /* time steps per pass; 0: whole revolutions covering the grid */
+    double x_start;          /* tool-centre x at step 0; NaN: a full reach before the grid */
+    double y_first;          /* tool-centre y of pass 0; NaN: a full reach below the grid
+                                (or the grid centre line for a single pass) */
+} fsm_cut;
+
+typedef struct fsm_grid {
+    double x0, y0;           /* position of node (0, 0) */
+    double dd;               /* sampling interval (Sec. 2.2), > 0 */
+    int64_t nx, ny;          /* nodes along X (feed) and Y (pick feed), >= 1 */
+} fsm_grid;
+
+typedef struct fsm_plan_info {
+    double r_reach;          /* bound on any edge point's horizontal distance from the axis */
+    double x_start;          /* resolved tool-centre start */
+    double y_first;          /* resolved first pass */
+    int64_t n_passes;
+    int64_t n_steps;         /* per pass */
+    int64_t n_evals;         /* passes * steps * teeth * edge points */
+    int64_t n_cells;         /* nx * ny */
+    int64_t zmap_bytes;      /* bytes of the caller's Z-map at this precision */
+    int64_t workspace_bytes; /* device bytes the library needs for this simulation */
+} fsm_plan_info;
+
+typedef struct fsm_rough {
+    double Sa, Sq, Sp, Sv, Sz, Ssk, Sku;   /* areal parameters over the reached cells */
+    double Ra_feed;          /* profile Ra along row ny/2 (feed direction) */
+    double Ra_pick;          /* profile Ra along column nx/2 (pick-feed direction) */
+    double mean;             /* mean height of the reached cells (reference plane) */
+    int64_t n_hit;           /* reached cells */
+    int64_t n_evals;         /* edge-point evaluations */
+    int64_t n_binned;        /* evaluations that fell inside the grid */
+    int64_t n_feed, n_pick;  /* reached cells on the two profiles */
+    uint32_t flags;          /* FSM_FLAG_* */
+    uint32_t reserved;
+} fsm_rough;
+
+/* Per-kernel device times of the last fsm_simulate / fsm_roughness call on a context with
+ * profiling on, measured with HIP events on the caller's stream (milliseconds). */
+typedef struct fsm_timings {
+    float upload_ms;         /* plan tables host -> device */
+    float fill_ms;           /* Z-map initialisation */
+    float scatter_ms;        /* kinematics + binning + per-cell minimum */
+    float rough_ms;          /* roughness passes (or the decode pass) */
+    float total_ms;          /* first event to last event */
+    int32_t valid;           /* 1 once a profiled call has completed */
+} fsm_timings;
+
+typedef struct fsm_ctx fsm_ctx;
+
+/* ABI version (FSM_ABI_VERSION). */
+int fsm_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *fsm_strerror(int code);
+
+/* Host only.  Validates the parameters and resolves the automatic path (Sec. 2.2: travel,
+ * passes and steps), reporting sizes and the memory footprint.  FSM_EINVAL on bad input. */
+int fsm_plan(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, int precision,
+             fsm_plan_info *out);
+
+/* Host only.  The discretised edge of every tooth in the tool frame (Eq. (1), (6), (2) plus
+ * helix lag and eccentric runout): out is caller-owned host memory of n_teeth*n_edge*3
+ * doubles, [tooth][point][x,y,z]. */
+int fsm_edge_points(const fsm_tool *tool, const fsm_cut *cut, double *out);
+
+/* Create a context on HIP device `device`.  The context owns the device workspace (edge,
+ * angle and path tables, reduction partials, counters) and pinned host staging; they grow on
+ * demand and are freed by fsm_ctx_destroy.  FSM_EDEVICE if the device cannot be used. */
+int fsm_ctx_create(fsm_ctx **out, int device);
+void fsm_ctx_destroy(fsm_ctx *ctx);
+
+/* Copy the last error message of the context (NUL-terminated, truncated to n). */
+int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
+
+/* Turn per-kernel event timing on (nonzero) or off for later calls on the context.  Costs
+ * a few event records per call; off by default. */
+int fsm_ctx_set_profiling(fsm_ctx *ctx, int on);
+
+/* Timings of the last profiled call (valid == 0 if there is none). */
+int fsm_last_timings(const fsm_ctx *ctx, fsm_timings *out);
+
+/* One simulation.  zmap_dev: caller-owned device memory of nx*ny doubles (FSM_F64) or floats
+ * (FSM_F32), overwritten with the Z-map.  out: host memory for the roughness, or NULL to
+ * compute the Z-map only.  The work is queued on `stream`; the call returns after it has
+ * finished.  FSM_EINVAL on bad parameters, FSM_EDEVICE on a HIP error. */
+int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid,
+                 int precision, void *zmap_dev, fsm_rough *out, void *stream);
+
+/* Roughness of an existing Z-map in device memory (+inf = empty cell), same estimator as
+ * fsm_simulate.  n_evals and n_binned of the result are zero. */
+int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_dev,
+                  fsm_rough *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSM_H */

@@ -1,0 +1,153 @@
+"""ctypes mirror of include/fsm.h and the loader of libfsm.so.
+
+Argument marshalling only: every step of the simulation runs inside libfsm (host planner and
+HIP kernels).  The library must have been built (python -m paper_2603_28160_amd.build);
+loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfsm.so")
+
+FSM_ABI_VERSION = 1
+MAXT = 8
+MAX_EDGE = 4096
+
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5
+F64, F32 = 0, 1
+TOOL_ROUND, TOOL_BALL = 0, 1
+FLAG_SQ_ZERO, FLAG_NO_HIT, FLAG_LOW_COVERAGE = 1, 2, 4
+
+
+class FsmTool(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_teeth", C.c_int32), ("n_edge", C.c_int32),
+                ("uniform_pitch", C.c_int32), ("D", C.c_double), ("R_edge", C.c_double),
+                ("helix", C.c_double), ("rake_radial", C.c_double), ("rake_axial", C.c_double),
+                ("theta", C.c_double * MAXT), ("runout_ecc", C.c_double),
+                ("runout_phase", C.c_double), ("eps_r", C.c_double * MAXT),
+                ("eps_a", C.c_double * MAXT), ("tilt_lead", C.c_double),
+                ("tilt_side", C.c_double)]
+
+
+class FsmCut(C.Structure):
+    _fields_ = [("f_z", C.c_double), ("a_p", C.c_double), ("a_e", C.c_double),
+                ("phi0", C.c_double), ("steps_per_rev", C.c_int32), ("n_passes", C.c_int32),
+                ("n_steps", C.c_int64), ("x_start", C.c_double), ("y_first", C.c_double)]
+
+
+class FsmGrid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("dd", C.c_double),
+                ("nx", C.c_int64), ("ny", C.c_int64)]
+
+
+class FsmPlanInfo(C.Structure):
+    _fields_ = [("r_reach", C.c_double), ("x_start", C.c_double), ("y_first", C.c_double),
+                ("n_passes", C.c_int64), ("n_steps", C.c_int64), ("n_evals", C.c_int64),
+                ("n_cells", C.c_int64), ("zmap_bytes", C.c_int64),
+                ("workspace_bytes", C.c_int64)]
+
+
+ROUGH_DOUBLES = ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean")
+ROUGH_COUNTS = ("n_hit", "n_evals", "n_binned", "n_feed", "n_pick")
+
+
+class FsmRough(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ROUGH_DOUBLES] + \
+               [(k, C.c_int64) for k in ROUGH_COUNTS] + \
+               [("flags", C.c_uint32), ("reserved", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class FsmTimings(C.Structure):
+    _fields_ = [("upload_ms", C.c_float), ("fill_ms", C.c_float), ("scatter_ms", C.c_float),
+                ("rough_ms", C.c_float), ("total_ms", C.c_float), ("valid", C.c_int32)]
+
+
+# every symbol include/fsm.h declares, with its ctypes signature
+P = C.POINTER
+SIGNATURES = {
+    "fsm_version": ([], C.c_int),
+    "fsm_strerror": ([C.c_int], C.c_char_p),
+    "fsm_plan": ([P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, P(FsmPlanInfo)], C.c_int),
+    "fsm_edge_points": ([P(FsmTool), P(FsmCut), P(C.c_double)], C.c_int),
+    "fsm_ctx_create": ([P(C.c_void_p), C.c_int], C.c_int),
+    "fsm_ctx_destroy": ([C.c_void_p], None),
+    "fsm_last_error": ([C.c_void_p, C.c_char_p, C.c_size_t], C.c_int),
+    "fsm_ctx_set_profiling": ([C.c_void_p, C.c_int], C.c_int),
+    "fsm_last_timings": ([C.c_void_p, P(FsmTimings)], C.c_int),
+    "fsm_simulate": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, C.c_void_p,
+                      P(FsmRough), C.c_void_p], C.c_int),
+    "fsm_roughness": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, P(FsmRough), C.c_void_p],
+                      C.c_int),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class FsmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} [{code}]")
+        self.code = code
+
+
+def load() -> C.CDLL:
+    """Load libfsm.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -m paper_2603_28160_amd.build`")
+            lib = C.CDLL(LIB_PATH)
+            for name, (args, res) in SIGNATURES.items():
+                f = getattr(lib, name)
+                f.argtypes = args
+                f.restype = res
+            if lib.fsm_version() != FSM_ABI_VERSION:
+                raise ImportError("libfsm ABI version mismatch")
+            _lib = lib
+    return _lib
+
+
+def tool_struct(t) -> FsmTool:
+    o = FsmTool()
+    o.kind = int(t.kind)
+    o.n_teeth = int(t.n_teeth)
+    o.n_edge = int(t.n_edge)
+    o.uniform_pitch = 1 if t.theta is None else 0
+    o.D = t.D
+    o.R_edge = t.R_edge
+    o.helix = t.helix
+    o.rake_radial = t.rake_radial
+    o.rake_axial = t.rake_axial
+    if t.theta is not None:
+        if len(t.theta) > MAXT:
+            raise ValueError("too many tooth angles")
+        for k, v in enumerate(t.theta):
+            o.theta[k] = v
+    o.runout_ecc = t.runout_ecc
+    o.runout_phase = t.runout_phase
+    for k, v in enumerate(t.eps_r[:MAXT]):
+        o.eps_r[k] = v
+    for k, v in enumerate(t.eps_a[:MAXT]):
+        o.eps_a[k] = v
+    o.tilt_lead = t.tilt_lead
+    o.tilt_side = t.tilt_side
+    return o
+
+
+def cut_struct(c) -> FsmCut:
+    return FsmCut(f_z=c.f_z, a_p=c.a_p, a_e=c.a_e, phi0=c.phi0,
+                  steps_per_rev=int(c.steps_per_rev), n_passes=int(c.n_passes),
+                  n_steps=int(c.n_steps), x_start=c.x_start, y_first=c.y_first)
+
+
+def grid_struct(g) -> FsmGrid:
+    return FsmGrid(x0=g.x0, y0=g.y0, dd=g.dd, nx=int(g.nx), ny=int(g.ny))

@@ -1,0 +1,153 @@
+"""Python binding of libfsm: the C-ABI calls under the same names, with torch supplying the
+device memory and the stream.
+
+Only argument marshalling happens here; edge discretisation, kinematics, binning, the
+per-cell minimum and the roughness all run inside libfsm.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _abi
+
+PRECISIONS = {"f64": _abi.F64, "f32": _abi.F32, _abi.F64: _abi.F64, _abi.F32: _abi.F32}
+
+
+def _prec(p) -> int:
+    try:
+        return PRECISIONS[p]
+    except KeyError:
+        raise ValueError(f"precision must be 'f64' or 'f32', got {p!r}") from None
+
+
+def _check(rc: int, what: str, ctx=None):
+    if rc != _abi.OK:
+        lib = _abi.load()
+        msg = lib.fsm_strerror(rc).decode()
+        if ctx is not None:
+            buf = C.create_string_buffer(512)
+            lib.fsm_last_error(ctx, buf, 512)
+            if buf.value:
+                msg += ": " + buf.value.decode()
+        raise _abi.FsmError(rc, f"{what}: {msg}")
+
+
+def fsm_version() -> int:
+    return _abi.load().fsm_version()
+
+
+def fsm_plan(sim, precision="f64") -> dict:
+    """Resolved path and sizes of one simulation (host only)."""
+    info = _abi.FsmPlanInfo()
+    rc = _abi.load().fsm_plan(C.byref(_abi.tool_struct(sim.tool)), C.byref(_abi.cut_struct(sim.cut)),
+                              C.byref(_abi.grid_struct(sim.grid)), _prec(precision), C.byref(info))
+    _check(rc, "fsm_plan")
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def fsm_edge_points(sim) -> np.ndarray:
+    """Tool-frame edge points [n_teeth, n_edge, 3] (host only)."""
+    t = sim.tool
+    out = np.zeros((t.n_teeth, t.n_edge, 3))
+    rc = _abi.load().fsm_edge_points(C.byref(_abi.tool_struct(t)), C.byref(_abi.cut_struct(sim.cut)),
+                                     out.ctypes.data_as(C.POINTER(C.c_double)))
+    _check(rc, "fsm_edge_points")
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream, device: int) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """One libfsm context on one HIP device (fsm_ctx_create / fsm_ctx_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        self._lib = _abi.load()
+        h = C.c_void_p()
+        rc = self._lib.fsm_ctx_create(C.byref(h), self.device)
+        _check(rc, "fsm_ctx_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fsm_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def fsm_ctx_set_profiling(self, on: bool = True):
+        _check(self._lib.fsm_ctx_set_profiling(self._h, 1 if on else 0), "fsm_ctx_set_profiling", self._h)
+
+    def fsm_last_timings(self) -> dict:
+        t = _abi.FsmTimings()
+        _check(self._lib.fsm_last_timings(self._h, C.byref(t)), "fsm_last_timings", self._h)
+        return {k: getattr(t, k) for k, _ in t._fields_}
+
+    def new_zmap(self, grid, precision="f64"):
+        torch = _torch()
+        dt = torch.float64 if _prec(precision) == _abi.F64 else torch.float32
+        return torch.empty((int(grid.ny), int(grid.nx)), dtype=dt, device=f"cuda:{self.device}")
+
+    def _check_zmap(self, grid, precision, zmap):
+        torch = _torch()
+        dt = torch.float64 if _prec(precision) == _abi.F64 else torch.float32
+        if (not isinstance(zmap, torch.Tensor) or zmap.dtype != dt or not zmap.is_cuda
+                or zmap.device.index != self.device or not zmap.is_contiguous()
+                or zmap.numel() != int(grid.nx) * int(grid.ny)):
+            raise ValueError("zmap must be a contiguous device tensor of nx*ny elements of the "
+                             "precision's dtype on the context's device")
+
+    def fsm_simulate(self, sim, precision="f64", zmap=None, roughness: bool = True,
+                     stream=None) -> Tuple[object, Optional[dict]]:
+        """Run one simulation; returns (Z-map tensor [ny, nx], roughness dict or None)."""
+        if zmap is None:
+            zmap = self.new_zmap(sim.grid, precision)
+        self._check_zmap(sim.grid, precision, zmap)
+        out = _abi.FsmRough()
+        rc = self._lib.fsm_simulate(
+            self._h, C.byref(_abi.tool_struct(sim.tool)), C.byref(_abi.cut_struct(sim.cut)),
+            C.byref(_abi.grid_struct(sim.grid)), _prec(precision), C.c_void_p(zmap.data_ptr()),
+            C.byref(out) if roughness else None, C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_simulate", self._h)
+        return zmap, (out.as_dict() if roughness else None)
+
+    def fsm_roughness(self, grid, zmap, precision="f64", stream=None) -> dict:
+        """Roughness of an existing device Z-map (+inf = empty cell)."""
+        self._check_zmap(grid, precision, zmap)
+        out = _abi.FsmRough()
+        rc = self._lib.fsm_roughness(self._h, C.byref(_abi.grid_struct(grid)), _prec(precision),
+                                     C.c_void_p(zmap.data_ptr()), C.byref(out),
+                                     C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_roughness", self._h)
+        return out.as_dict()
+
+    # short aliases
+    simulate = fsm_simulate
+    roughness = fsm_roughness

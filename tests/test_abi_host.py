@@ -1,0 +1,147 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol include/fsm.h
+declares, the ctypes mirror matches the C struct layouts, the host planner reproduces the
+oracle's edge points and path bit for bit, and bad arguments come back as status codes."""
+import ctypes as C
+import dataclasses
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_28160_amd import _abi, fsm_edge_points, fsm_plan, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsm_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = _abi.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _abi.SIGNATURES, f"{n} has no ctypes signature"
+    assert lib.fsm_version() == _abi.FSM_ABI_VERSION
+
+
+def test_struct_layouts_match_header(tmp_path):
+    structs = {"fsm_tool": _abi.FsmTool, "fsm_cut": _abi.FsmCut, "fsm_grid": _abi.FsmGrid,
+               "fsm_plan_info": _abi.FsmPlanInfo, "fsm_rough": _abi.FsmRough,
+               "fsm_timings": _abi.FsmTimings}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def all_sims():
+    sims = [W.config1(), W.config2(), W.config5(), W.config2(nx=777, ny=613, dd=0.004)]
+    sims += [W.random_sim(3, i) for i in range(24)]
+    sims += [W.random_sim(4, i, side_max=4096) for i in range(8)]
+    t = W.paper_case2_tool(eps_r=-0.026, eps_a=0.009)
+    sims.append(W.Sim(t, W.Cut(f_z=0.4, a_p=0.4, steps_per_rev=500, a_e=4.0),
+                      W.centred_grid(301, 157, 0.01)))
+    sims.append(W.Sim(dataclasses.replace(W.config2().tool, tilt_side=-0.12, rake_radial=0.1,
+                                          rake_axial=-0.05, theta=(0, 1.5, 3.2, 4.6)),
+                      W.config2().cut, W.centred_grid(50, 60, 0.01)))
+    return sims
+
+
+@pytest.mark.parametrize("idx", range(len(all_sims())))
+def test_host_planner_bitexact_with_oracle(idx):
+    s = all_sims()[idx]
+    a = fsm_edge_points(s)
+    _, b = oracle.edge_points(s)
+    assert np.array_equal(a, b)
+    pa, pb = fsm_plan(s), oracle.plan(s)
+    for k in pb:
+        assert pa[k] == pb[k], (k, pa[k], pb[k])
+    assert pa["n_cells"] == s.grid.nx * s.grid.ny
+    assert pa["zmap_bytes"] == 8 * pa["n_cells"]
+    assert fsm_plan(s, "f32")["zmap_bytes"] == 4 * pa["n_cells"]
+
+
+def _plan_rc(tool=None, cut=None, grid=None, precision=0):
+    base = W.config1()
+    t = _abi.tool_struct(tool or base.tool)
+    c = _abi.cut_struct(cut or base.cut)
+    g = _abi.grid_struct(grid or base.grid)
+    info = _abi.FsmPlanInfo()
+    return _abi.load().fsm_plan(C.byref(t), C.byref(c), C.byref(g), precision, C.byref(info))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tool=dict(n_teeth=0)), dict(tool=dict(n_teeth=9)), dict(tool=dict(n_edge=0)),
+    dict(tool=dict(n_edge=5000)), dict(tool=dict(D=0.0)), dict(tool=dict(D=float("nan"))),
+    dict(tool=dict(R_edge=-1.0)), dict(tool=dict(kind=3)), dict(tool=dict(helix=2.0)),
+    dict(tool=dict(runout_ecc=-0.1)), dict(tool=dict(tilt_lead=float("inf"))),
+    dict(cut=dict(f_z=-0.1)), dict(cut=dict(a_p=0.0)), dict(cut=dict(steps_per_rev=0)),
+    dict(cut=dict(n_passes=-1)), dict(cut=dict(n_steps=-5)), dict(cut=dict(x_start=float("inf"))),
+    dict(grid=dict(dd=0.0)), dict(grid=dict(nx=0)), dict(grid=dict(ny=-3)),
+    dict(grid=dict(nx=3_000_000_000)), dict(precision=7),
+])
+def test_invalid_parameters_rejected(bad):
+    base = W.config1()
+    kw = {}
+    for part in ("tool", "cut", "grid"):
+        if part in bad:
+            kw[part] = dataclasses.replace(getattr(base, part), **bad[part])
+    rc = _plan_rc(**kw, precision=bad.get("precision", 0))
+    assert rc == _abi.EINVAL
+
+
+def test_null_arguments_and_strerror():
+    lib = _abi.load()
+    info = _abi.FsmPlanInfo()
+    assert lib.fsm_plan(None, None, None, 0, C.byref(info)) == _abi.EINVAL
+    assert lib.fsm_edge_points(None, None, None) == _abi.EINVAL
+    assert lib.fsm_simulate(None, None, None, None, 0, None, None, None) == _abi.EINVAL
+    assert lib.fsm_roughness(None, None, 0, None, None, None) == _abi.EINVAL
+    assert lib.fsm_last_error(None, None, 0) == _abi.EINVAL
+    for code in (0, -1, -2, -3, -4, -5, -99):
+        assert lib.fsm_strerror(code)
+    lib.fsm_ctx_destroy(None)
+
+
+def test_ctx_create_without_device_fails_cleanly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = C.c_void_p()
+    assert _abi.load().fsm_ctx_create(C.byref(h), 0) == _abi.EDEVICE
+    assert not h.value
+
+
+def test_auto_path_reaches_past_the_grid():
+    s = W.config2(nx=100, ny=80, dd=0.01)
+    p = fsm_plan(s)
+    g = s.grid
+    x_lo, y_lo = g.x0 - g.dd / 2, g.y0 - g.dd / 2
+    assert p["x_start"] == pytest.approx(x_lo - p["r_reach"])
+    assert p["y_first"] == pytest.approx(y_lo - p["r_reach"])
+    fpr = s.tool.n_teeth * s.cut.f_z
+    assert p["x_start"] + p["n_steps"] / s.cut.steps_per_rev * fpr >= x_lo + g.nx * g.dd + p["r_reach"]
+    assert p["n_steps"] % s.cut.steps_per_rev == 0
+    assert p["n_evals"] == p["n_passes"] * p["n_steps"] * 4 * 64

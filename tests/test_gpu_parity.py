@@ -1,0 +1,211 @@
+"""GPU parity: libfsm (HIP, through the C ABI) against the FP64 CPU oracle.
+
+Double precision: identical hit masks, identical heights (|dZ| <= 1e-9 mm is the stated bar;
+the kernels reproduce the oracle's arithmetic, so the test demands equality), identical
+in-grid counts, roughness within 1e-4 relative.
+Single precision: |dZ| <= 2e-6 mm on every cell the oracle does not flag as ambiguous
+(a point within the single-precision position error of a cell boundary could land in it or
+leave it), hit masks equal outside those cells, roughness within 1e-4 relative.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_28160_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ROUGH_KEYS = ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean")
+F32_TOL = 2e-6       # mm, single-precision Z-map tolerance
+ROUGH_RTOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28160_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, sim, precision):
+    print(f"[gpu] {sim.name or 'sim'} {precision} grid {sim.grid.nx}x{sim.grid.ny}", flush=True)
+    z, r = ctx.fsm_simulate(sim, precision)
+    return z.cpu().numpy().astype(np.float64), r
+
+
+def check_rough(rg, ro, rtol=ROUGH_RTOL, abs_floor=1e-12):
+    assert rg["n_hit"] == ro["n_hit"]
+    assert rg["n_feed"] == ro["n_feed"] and rg["n_pick"] == ro["n_pick"]
+    for k in ROUGH_KEYS:
+        a, b = rg[k], ro[k]
+        if math.isnan(b):
+            assert math.isnan(a), k
+        else:
+            assert abs(a - b) <= rtol * abs(b) + abs_floor, (k, a, b)
+
+
+def check_f64(ctx, sim):
+    zg, rg = run_gpu(ctx, sim, "f64")
+    zo, cnt = oracle.simulate(sim)
+    assert rg["n_evals"] == cnt["n_evals"]
+    assert rg["n_binned"] == cnt["n_binned"]
+    assert np.array_equal(np.isfinite(zg), np.isfinite(zo))
+    assert np.array_equal(zg, zo), float(np.nanmax(np.abs(np.where(np.isfinite(zo), zg - zo, 0))))
+    check_rough(rg, oracle.roughness(zo))
+    return zo
+
+
+def f32_delta(sim):
+    # bound on the single-precision error of a workpiece-frame position: a few ulps of the
+    # largest tool-local coordinate
+    pl = oracle.plan(sim)
+    return 16.0 * 2.0 ** -24 * (pl["r_reach"] + sim.cut.a_p + 1.0)
+
+
+def check_f32(ctx, sim, zo=None, max_ambiguous=0.05):
+    zg, rg = run_gpu(ctx, sim, "f32")
+    if zo is None:
+        zo, _ = oracle.simulate(sim)
+    amb = oracle.ambiguous_cells(sim, zo, f32_delta(sim), F32_TOL)
+    assert amb.mean() <= max_ambiguous, amb.mean()
+    ok = ~amb
+    hit_o, hit_g = np.isfinite(zo), np.isfinite(zg)
+    assert np.array_equal(hit_o[ok], hit_g[ok])
+    both = ok & hit_o
+    err = np.abs(zg[both] - zo[both])
+    assert err.size == 0 or err.max() <= F32_TOL, err.max()
+    ro = oracle.roughness(zo)
+    for k in ("Sa", "Sq", "Ssk", "Sku", "mean"):
+        if math.isnan(ro[k]):
+            continue
+        assert abs(rg[k] - ro[k]) <= ROUGH_RTOL * abs(ro[k]) + 1e-9, (k, rg[k], ro[k])
+    assert abs(rg["n_hit"] - ro["n_hit"]) <= amb.sum()
+    return zg
+
+
+# --- double precision: bit-exact against the oracle ----------------------------------------
+
+def test_config1_f64_exact(ctx):
+    check_f64(ctx, W.config1())
+
+
+def test_config2_reduced_f64_exact(ctx):
+    # same tool and path rules as the 5000 x 5000 case on a ragged 777 x 613 grid
+    check_f64(ctx, W.config2(nx=777, ny=613, dd=0.004))
+
+
+@pytest.mark.parametrize("i", [0, 1, 2, 3, 5, 8])
+def test_mix_sims_f64_exact(ctx, i):
+    s = W.random_sim(3, i, side_max=300)
+    s = s.replace(grid=dataclasses.replace(s.grid, dd=s.grid.dd * 4))
+    check_f64(ctx, s)
+
+
+def test_paper_case2_tool_f64_exact(ctx):
+    # the paper's own face-milling tool with rake and per-insert runout (Sec. 4.2)
+    t = W.paper_case2_tool(eps_r=-0.026, eps_a=0.009, n_edge=30)
+    s = W.Sim(t, W.Cut(f_z=0.4, a_p=0.4, steps_per_rev=500, a_e=4.0),
+              W.centred_grid(301, 157, 0.01), name="paper_case2")
+    check_f64(ctx, s)
+
+
+@pytest.mark.parametrize("case", ["n1", "z1", "s1", "grid1x1", "nofeed", "odd", "sidetilt", "big_n"])
+def test_edge_cases_f64(ctx, case):
+    base = W.config2(nx=90, ny=70, dd=0.02)
+    t, c, g = base.tool, base.cut, base.grid
+    if case == "n1":
+        t = dataclasses.replace(t, n_edge=1)
+    elif case == "z1":
+        t = dataclasses.replace(t, n_teeth=1)
+    elif case == "s1":
+        c = dataclasses.replace(c, steps_per_rev=1)
+    elif case == "grid1x1":
+        g = W.centred_grid(1, 1, 0.05)
+    elif case == "nofeed":
+        c = dataclasses.replace(c, f_z=0.0, a_e=0.0, n_passes=1, x_start=0.0, y_first=0.0)
+    elif case == "odd":
+        g = W.centred_grid(77, 3, 0.013)       # 231 cells: odd, not a multiple of 4
+    elif case == "sidetilt":
+        t = dataclasses.replace(t, tilt_side=math.radians(-7.0), theta=(0.0, 1.5, 3.2, 4.6))
+    elif case == "big_n":
+        t = dataclasses.replace(t, n_edge=300, n_teeth=2)
+    check_f64(ctx, W.Sim(t, c, g, name=case))
+
+
+def test_empty_result(ctx):
+    # the path never reaches the grid: every cell stays +inf and every parameter is NaN
+    s = W.config1()
+    s = s.replace(cut=dataclasses.replace(s.cut, y_first=50.0))
+    zg, rg = run_gpu(ctx, s, "f64")
+    assert np.all(np.isinf(zg)) and rg["n_hit"] == 0 and rg["n_binned"] == 0
+    assert rg["flags"] & 2 and math.isnan(rg["Sa"]) and math.isnan(rg["Ra_feed"])
+
+
+def test_deterministic(ctx):
+    s = W.config2(nx=400, ny=300, dd=0.003)
+    for prec in ("f64", "f32"):
+        z1, r1 = ctx.fsm_simulate(s, prec)
+        a = z1.cpu().numpy().copy()
+        z2, r2 = ctx.fsm_simulate(s, prec)
+        assert np.array_equal(a, z2.cpu().numpy())
+        assert r1 == r2 or all((r1[k] == r2[k]) or (math.isnan(r1[k]) and math.isnan(r2[k])) for k in r1)
+
+
+# --- single precision: tolerance against the oracle --------------------------------------------
+
+def test_config2_reduced_f32(ctx):
+    check_f32(ctx, W.config2(nx=777, ny=613, dd=0.004))
+
+
+@pytest.mark.parametrize("i", [0, 2, 5])
+def test_mix_sims_f32(ctx, i):
+    s = W.random_sim(3, i, side_max=300)
+    s = s.replace(grid=dataclasses.replace(s.grid, dd=s.grid.dd * 4))
+    check_f32(ctx, s)
+
+
+# --- roughness entry point on given surfaces ------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(64, 4), (101, 37), (1, 1), (5, 3)])
+def test_roughness_entry(ctx, prec, shape):
+    import torch
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 31 + ny)
+    Z = rng.normal(0.01, 0.003, size=(ny, nx))
+    Z[rng.uniform(size=Z.shape) < 0.2] = np.inf
+    if prec == "f32":
+        Z = Z.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    zt = torch.tensor(Z, dtype=dt, device="cuda:0")
+    g = W.Grid(0.0, 0.0, 0.001, nx, ny)
+    rg = ctx.fsm_roughness(g, zt, prec)
+    ro = oracle.roughness(Z)
+    check_rough(rg, ro, rtol=1e-10)
+    # the surface is left untouched
+    assert np.array_equal(zt.cpu().numpy().astype(np.float64), Z)
+
+
+def test_roughness_sinusoid_closed_form(ctx):
+    import torch
+    A = 0.3
+    Z = np.tile(A * np.sin(2 * np.pi * np.arange(64) / 8), (4, 1))
+    r = ctx.fsm_roughness(W.Grid(0, 0, 1e-3, 64, 4), torch.tensor(Z, device="cuda:0"), "f64")
+    assert r["Sq"] == pytest.approx(A / math.sqrt(2), rel=1e-12)
+    assert r["Sku"] == pytest.approx(1.5, rel=1e-12)
+    assert r["Sa"] == pytest.approx(A * (1 + math.sqrt(2)) / 4, rel=1e-12)
+
+
+# --- full-size workloads ------------------------------------------------------------------------------
+
+def test_config2_full_f64_exact(ctx):
+    # the 5000 x 5000 ball-end raster exactly as the benchmark runs it
+    zo = check_f64(ctx, W.config2())
+    check_f32(ctx, W.config2(), zo=zo)
