@@ -67,6 +67,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["f64", "f32", "both"], default="both")
+    ap.add_argument("--strategy", choices=["binned", "scatter"], default="binned")
+    ap.add_argument("--compare-strategies", action="store_true",
+                    help="also time the other Z-map strategy (reported, not the value)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reads 1 GiB, writes "
+                         "1 GiB) five times, to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -75,6 +81,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": x.numel() * 8, "launches": 5}), flush=True)
+        return
     from paper_2603_28160_amd import Context, fsm_plan, workloads
 
     sim = workloads.config2()
@@ -83,6 +97,15 @@ def main():
     res = {}
     with Context(0) as ctx:
         precs = ["f64", "f32"] if args.precision == "both" else [args.precision]
+        other = {}
+        if args.compare_strategies:
+            alt = "scatter" if args.strategy == "binned" else "binned"
+            ctx.set_strategy(alt)
+            for prec in precs:
+                o = run_precision(ctx, sim, prec, args.steps, args.warmup)
+                other[prec] = {"ms_per_step": o["ms_per_step"], "zmap_ms": o["scatter_ms"]}
+                print(f"[bench] {alt} {prec}: {o['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        ctx.set_strategy(args.strategy)
         for prec in precs:
             print(f"[bench] {sim.name} {prec}: warmup {args.warmup}, steps {args.steps}",
                   file=sys.stderr, flush=True)
@@ -113,12 +136,13 @@ def main():
                    "dd_mm": sim.grid.dd, "tool": "ball R3 z4 helix30 tilt15",
                    "passes": plan["n_passes"], "steps_per_pass": plan["n_steps"],
                    "edge_points": sim.tool.n_edge, "evals": plan["n_evals"],
-                   "precision": main_prec, "mode": "plain single-simulation launches"},
+                   "precision": main_prec, "mode": "plain single-simulation launches",
+                   "zmap_strategy": args.strategy},
         "sims_per_s": args.steps / m["elapsed_s"],
         "latency_ms": {"p50": pct(m["lat"], 50), "p99": pct(m["lat"], 99)},
         "evals_per_s": plan["n_evals"] * args.steps / m["elapsed_s"],
         "coverage": r["n_hit"] / n_cells,
-        "kernel_ms": {"fill": m["fill_ms"], "scatter": m["scatter_ms"], "roughness": m["rough_ms"]},
+        "kernel_ms": {"fill": m["fill_ms"], "zmap": m["scatter_ms"], "roughness": m["rough_ms"]},
         "roofline": {"bound": "hbm", "kernel": "scatter", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None,
@@ -131,9 +155,11 @@ def main():
         out[prec] = {"value": n_cells * args.steps / o["elapsed_s"], "unit": "cells/s",
                      "ms_per_step": o["ms_per_step"],
                      "latency_ms": {"p50": pct(o["lat"], 50), "p99": pct(o["lat"], 99)},
-                     "kernel_ms": {"fill": o["fill_ms"], "scatter": o["scatter_ms"],
+                     "kernel_ms": {"fill": o["fill_ms"], "zmap": o["scatter_ms"],
                                    "roughness": o["rough_ms"]},
                      "Sa": o["rough"]["Sa"], "Sa_f64": r["Sa"]}
+    if other:
+        out["other_strategy"] = other
     if not args.no_cpu_baseline:
         import oracle
         print("[bench] cpu baseline: FP64 oracle on the full workload, 1 thread",

@@ -137,7 +137,7 @@ typedef struct fsm_rough {
 typedef struct fsm_timings {
     float upload_ms;         /* plan tables host -> device */
     float fill_ms;           /* Z-map initialisation */
-    float scatter_ms;        /* kinematics + binning + per-cell minimum */
+    float scatter_ms;        /* kinematics + binning + per-cell minimum (all slices) */
     float rough_ms;          /* roughness passes (or the decode pass) */
     float total_ms;          /* first event to last event */
     int32_t valid;           /* 1 once a profiled call has completed */
@@ -169,6 +169,20 @@ void fsm_ctx_destroy(fsm_ctx *ctx);
 
 /* Copy the last error message of the context (NUL-terminated, truncated to n). */
 int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
+
+/* context options (fsm_ctx_set_option) */
+#define FSM_OPT_ZMAP_STRATEGY 1   /* how points reach the Z-map:
+                                       FSM_ZMAP_BINNED (default): bucket the points by 64 x 64
+                                       cell tile, then min-reduce each tile in LDS and store it
+                                       once; FSM_ZMAP_SCATTER: one global atomic min per point */
+#define FSM_OPT_BUCKET_BYTES 2    /* device bytes the binned strategy may use for its point
+                                       buckets (default 2 GiB); larger simulations run in
+                                       slices of the evaluation range */
+#define FSM_ZMAP_BINNED 0
+#define FSM_ZMAP_SCATTER 1
+
+/* Set a context option.  FSM_EINVAL for an unknown option or value. */
+int fsm_ctx_set_option(fsm_ctx *ctx, int option, int64_t value);
 
 /* Turn per-kernel event timing on (nonzero) or off for later calls on the context.  Costs
  * a few event records per call; off by default. */

@@ -21,6 +21,8 @@ OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 TOOL_ROUND, TOOL_BALL = 0, 1
 FLAG_SQ_ZERO, FLAG_NO_HIT, FLAG_LOW_COVERAGE = 1, 2, 4
+OPT_ZMAP_STRATEGY, OPT_BUCKET_BYTES = 1, 2
+ZMAP_BINNED, ZMAP_SCATTER = 0, 1
 
 
 class FsmTool(C.Structure):
@@ -79,6 +81,7 @@ SIGNATURES = {
     "fsm_ctx_create": ([P(C.c_void_p), C.c_int], C.c_int),
     "fsm_ctx_destroy": ([C.c_void_p], None),
     "fsm_last_error": ([C.c_void_p, C.c_char_p, C.c_size_t], C.c_int),
+    "fsm_ctx_set_option": ([C.c_void_p, C.c_int, C.c_int64], C.c_int),
     "fsm_ctx_set_profiling": ([C.c_void_p, C.c_int], C.c_int),
     "fsm_last_timings": ([C.c_void_p, P(FsmTimings)], C.c_int),
     "fsm_simulate": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, C.c_void_p,

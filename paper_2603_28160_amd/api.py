@@ -102,6 +102,14 @@ class Context:
     def handle(self):
         return self._h
 
+    def fsm_ctx_set_option(self, option: int, value: int):
+        _check(self._lib.fsm_ctx_set_option(self._h, int(option), int(value)), "fsm_ctx_set_option", self._h)
+
+    def set_strategy(self, name: str):
+        """Z-map strategy: 'binned' (tile buckets + LDS reduction) or 'scatter'."""
+        v = {"binned": _abi.ZMAP_BINNED, "scatter": _abi.ZMAP_SCATTER}[name]
+        self.fsm_ctx_set_option(_abi.OPT_ZMAP_STRATEGY, v)
+
     def fsm_ctx_set_profiling(self, on: bool = True):
         _check(self._lib.fsm_ctx_set_profiling(self._h, 1 if on else 0), "fsm_ctx_set_profiling", self._h)
 

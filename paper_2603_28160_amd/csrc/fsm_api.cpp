@@ -25,6 +25,8 @@ struct fsm_ctx {
     bool profiling = false;
     hipEvent_t ev[5] = {};       // upload, fill, scatter, rough, end
     fsm_timings timings = {};
+    int strategy = fsm::kStrategyBinned;
+    int64_t bucket_bytes = (int64_t)2 << 30;
 };
 
 namespace {
@@ -48,34 +50,54 @@ int hip_err(fsm_ctx *ctx, hipError_t e, const char *where)
     return set_err(ctx, FSM_EDEVICE, m);
 }
 
-// Byte layout of one simulation's workspace image.
+// Byte layout of one simulation's workspace.  The first `upload` bytes are built on the host
+// and copied with one transfer; the rest is device-only scratch.
 struct Layout {
-    size_t sim, base, binned, part1, part2, state, out, pT, pTf, cs, csf, xc, total;
+    size_t sim, base, tbase, binned, pT, pTf, cs, csf, xc, upload;
+    size_t part1, part2, state, out, counts, offsets, cursor, bkey, bidx, total;
+    int64_t n_tiles = 0, cap = 0;
 };
 
-Layout layout_of(const Plan &P)
+int64_t tiles_of(int64_t n) { return (n + fsm::kTile - 1) / fsm::kTile; }
+
+Layout layout_of(const Plan &P, int precision, bool binned, int64_t bucket_bytes)
 {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
     L.sim = take(sizeof(DevSim));
     L.base = take(sizeof(int64_t));
+    L.tbase = take(sizeof(int64_t));
     L.binned = take(sizeof(uint64_t));
-    L.part1 = take(sizeof(fsm::RoughPart1) * fsm::kRoughBlocks);
-    L.part2 = take(sizeof(fsm::RoughPart2) * fsm::kRoughBlocks);
-    L.state = take(sizeof(fsm::RoughState));
-    L.out = take(sizeof(fsm_rough));
     L.pT = take(sizeof(double) * P.pT.size());
     L.pTf = take(sizeof(float) * 4 * (size_t)P.z_n * P.N);
     L.cs = take(sizeof(double) * P.cs.size());
     L.csf = take(sizeof(float) * P.cs.size());
     L.xc = take(sizeof(double) * P.xc.size());
+    L.upload = o;
+    L.part1 = take(sizeof(fsm::RoughPart1) * fsm::kRoughBlocks);
+    L.part2 = take(sizeof(fsm::RoughPart2) * fsm::kRoughBlocks);
+    L.state = take(sizeof(fsm::RoughState));
+    L.out = take(sizeof(fsm_rough));
+    if (binned) {
+        L.n_tiles = tiles_of(P.nx) * tiles_of(P.ny);
+        const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
+        const int64_t per_item = (int64_t)fsm::kBlock * P.N;
+        int64_t cap = bucket_bytes / (key_bytes + 2);
+        if (cap > P.n_evals) cap = P.n_evals;
+        if (cap < per_item) cap = per_item;             // at least one item per slice
+        if (cap > (int64_t)UINT32_MAX) cap = UINT32_MAX; // offsets are 32-bit
+        L.cap = cap;
+        const int64_t nb = (L.n_tiles + 4095) / 4096;
+        L.counts = take(sizeof(uint32_t) * L.n_tiles);
+        L.offsets = take(sizeof(uint32_t) * (L.n_tiles + 1));
+        L.cursor = take(sizeof(uint32_t) * (L.n_tiles + nb));
+        L.bkey = take((size_t)key_bytes * cap);
+        L.bidx = take(sizeof(uint16_t) * cap);
+    }
     L.total = o;
     return L;
 }
-
-// Only the part of the image before the reduction partials must be sent to the device.
-size_t upload_bytes(const Layout &L) { return L.total; }
 
 int ensure(fsm_ctx *ctx, size_t bytes)
 {
@@ -133,6 +155,12 @@ void fill_devsim(const Plan &P, const Layout &L, char *dev, void *zmap, DevSim &
     d.n_chunks = (int32_t)((P.n_steps + d.chunk - 1) / d.chunk);
     d.n_items = P.n_passes * (int64_t)d.n_chunks * P.z_n;
     d.item_base = 0;
+    d.tiles_x = (int32_t)tiles_of(P.nx);
+    d.tiles_y = (int32_t)tiles_of(P.ny);
+    d.n_sblocks = (int32_t)((P.n_steps + fsm::kBlock - 1) / fsm::kBlock);
+    d.n_bitems = P.n_passes * (int64_t)d.n_sblocks * P.z_n;
+    d.bitem_base = 0;
+    d.tile_base = 0;
 }
 
 void fill_image(const Plan &P, const Layout &L, char *host, const DevSim &d)
@@ -140,6 +168,7 @@ void fill_image(const Plan &P, const Layout &L, char *host, const DevSim &d)
     std::memcpy(host + L.sim, &d, sizeof d);
     const int64_t base0 = 0;
     std::memcpy(host + L.base, &base0, sizeof base0);
+    std::memcpy(host + L.tbase, &base0, sizeof base0);
     const uint64_t zero = 0;
     std::memcpy(host + L.binned, &zero, sizeof zero);
     std::memcpy(host + L.pT, P.pT.data(), sizeof(double) * P.pT.size());
@@ -223,7 +252,7 @@ int fsm_plan(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, int
         P.pT.resize((size_t)P.z_n * P.N * 3);
         P.cs.resize((size_t)P.z_n * P.S * 2);
         P.xc.resize((size_t)P.n_steps);
-        out->workspace_bytes = (int64_t)layout_of(P).total;
+        out->workspace_bytes = (int64_t)layout_of(P, precision, true, (int64_t)2 << 30).total;
         return FSM_OK;
     } catch (const std::bad_alloc &) {
         return FSM_ENOMEM;
@@ -266,6 +295,24 @@ int fsm_ctx_create(fsm_ctx **out, int device)
     }
     *out = c;
     return FSM_OK;
+}
+
+int fsm_ctx_set_option(fsm_ctx *ctx, int option, int64_t value)
+{
+    if (!ctx) return FSM_EINVAL;
+    switch (option) {
+    case FSM_OPT_ZMAP_STRATEGY:
+        if (value != FSM_ZMAP_BINNED && value != FSM_ZMAP_SCATTER)
+            return set_err(ctx, FSM_EINVAL, "unknown Z-map strategy");
+        ctx->strategy = (int)value;
+        return FSM_OK;
+    case FSM_OPT_BUCKET_BYTES:
+        if (value < ((int64_t)1 << 20)) return set_err(ctx, FSM_EINVAL, "bucket budget below 1 MiB");
+        ctx->bucket_bytes = value;
+        return FSM_OK;
+    default:
+        return set_err(ctx, FSM_EINVAL, "unknown option");
+    }
 }
 
 int fsm_ctx_set_profiling(fsm_ctx *ctx, int on)
@@ -322,7 +369,8 @@ int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const f
         if (rc != FSM_OK) return set_err(ctx, rc, err);
         hipError_t e = hipSetDevice(ctx->device);
         if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
-        const Layout L = layout_of(P);
+        const bool binned = ctx->strategy == fsm::kStrategyBinned;
+        const Layout L = layout_of(P, precision, binned, ctx->bucket_bytes);
         rc = ensure(ctx, L.total);
         if (rc != FSM_OK) return rc;
         char *dev = static_cast<char *>(ctx->d_ws);
@@ -333,21 +381,42 @@ int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const f
         hipStream_t s = static_cast<hipStream_t>(stream);
         ctx->timings.valid = 0;
         mark(ctx, 0, s);
-        e = hipMemcpyAsync(dev, host, upload_bytes(L), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(dev, host, L.upload, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
         const int64_t n = grid->nx * grid->ny;
-        mark(ctx, 1, s);
-        int he = fsm::launch_fill(zmap_dev, n, precision, stream);
-        if (he) return hip_err(ctx, (hipError_t)he, "fill kernel");
         uint64_t *d_binned = reinterpret_cast<uint64_t *>(dev + L.binned);
+        const DevSim *d_sim = reinterpret_cast<const DevSim *>(dev + L.sim);
+        mark(ctx, 1, s);
+        int he;
+        if (!binned) {
+            he = fsm::launch_fill(zmap_dev, n, precision, stream);
+            if (he) return hip_err(ctx, (hipError_t)he, "fill kernel");
+        }
         mark(ctx, 2, s);
-        he = fsm::launch_scatter(reinterpret_cast<const DevSim *>(dev + L.sim), d, d.n_items, 1,
-                                 reinterpret_cast<const int64_t *>(dev + L.base), precision,
-                                 d_binned, stream);
-        if (he) return hip_err(ctx, (hipError_t)he, "scatter kernel");
+        if (binned) {
+            fsm::BinBuffers bb;
+            bb.counts = reinterpret_cast<uint32_t *>(dev + L.counts);
+            bb.offsets = reinterpret_cast<uint32_t *>(dev + L.offsets);
+            bb.cursor = reinterpret_cast<uint32_t *>(dev + L.cursor);
+            bb.bkey = dev + L.bkey;
+            bb.bidx = reinterpret_cast<uint16_t *>(dev + L.bidx);
+            bb.cap = L.cap;
+            const int64_t per_slice = std::max<int64_t>(1, L.cap / ((int64_t)fsm::kBlock * P.N));
+            for (int64_t b0 = 0; b0 < d.n_bitems; b0 += per_slice) {
+                const int64_t nit = std::min<int64_t>(per_slice, d.n_bitems - b0);
+                he = fsm::launch_binned_slice(d_sim, 1, reinterpret_cast<const int64_t *>(dev + L.base),
+                                              reinterpret_cast<const int64_t *>(dev + L.tbase), L.n_tiles,
+                                              b0, nit, bb, b0 == 0, precision, d_binned, stream);
+                if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
+            }
+        } else {
+            he = fsm::launch_scatter(d_sim, d, d.n_items, 1, reinterpret_cast<const int64_t *>(dev + L.base),
+                                     precision, d_binned, stream);
+            if (he) return hip_err(ctx, (hipError_t)he, "scatter kernel");
+        }
         mark(ctx, 3, s);
         if (out) {
-            he = fsm::launch_rough(zmap_dev, grid->nx, grid->ny, precision, true,
+            he = fsm::launch_rough(zmap_dev, grid->nx, grid->ny, precision, !binned,
                                    reinterpret_cast<fsm::RoughPart1 *>(dev + L.part1),
                                    reinterpret_cast<fsm::RoughPart2 *>(dev + L.part2),
                                    reinterpret_cast<fsm::RoughState *>(dev + L.state),
@@ -356,7 +425,7 @@ int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const f
             if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
             e = hipMemcpyAsync(ctx->h_out, dev + L.out, sizeof(fsm_rough), hipMemcpyDeviceToHost, s);
             if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
-        } else {
+        } else if (!binned) {
             he = fsm::launch_decode(zmap_dev, n, precision, stream);
             if (he) return hip_err(ctx, (hipError_t)he, "decode kernel");
         }
@@ -383,7 +452,7 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
     Plan P;   // empty tables: only the reduction part of the layout is used
-    const Layout L = layout_of(P);
+    const Layout L = layout_of(P, precision, false, 0);
     int rc = ensure(ctx, L.total);
     if (rc != FSM_OK) return rc;
     char *dev = static_cast<char *>(ctx->d_ws);

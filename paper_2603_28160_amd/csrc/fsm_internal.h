@@ -52,6 +52,13 @@ struct DevSim {
     int32_t ppi, spi;        // edge points per step slot, steps in flight per block
     int64_t n_items;         // n_passes * n_chunks * z_n
     int64_t item_base;       // first global work item of this simulation
+    // binned Z-map: the grid is cut into kTile x kTile cell tiles
+    int32_t tiles_x, tiles_y;
+    int32_t n_sblocks;       // step blocks of kBlock steps per (pass, tooth)
+    int32_t pad0;
+    int64_t n_bitems;        // n_passes * n_sblocks * z_n
+    int64_t bitem_base;      // first global binning item of this simulation
+    int64_t tile_base;       // first global tile of this simulation
 };
 
 // Reduction partials and results of the roughness kernels (device memory).
@@ -71,6 +78,23 @@ struct RoughState {
 
 constexpr int kBlock = 256;            // threads per block of every kernel
 constexpr int kRoughBlocks = 1024;     // blocks of the roughness passes (fixed: determinism)
+constexpr int kTileShift = 6;
+constexpr int kTile = 1 << kTileShift; // cells per tile side of the binned Z-map
+constexpr int kScanThreads = 1024;
+
+// Z-map strategies
+constexpr int kStrategyBinned = 0;     // bucket points by tile, reduce each tile in LDS
+constexpr int kStrategyScatter = 1;    // global atomic min per point
+
+// Buffers of the binned Z-map path (device memory).
+struct BinBuffers {
+    uint32_t *counts;        // [n_tiles]
+    uint32_t *offsets;       // [n_tiles + 1]
+    uint32_t *cursor;        // [n_tiles]
+    void *bkey;              // [cap] int64 (FP64) or int32 (FP32) height keys
+    uint16_t *bidx;          // [cap] cell index inside the tile
+    int64_t cap;             // bucket capacity (points)
+};
 
 // Launch wrappers (fsm_kernels.hip).  All return a hipError_t as int.
 int launch_fill(void *zmap, int64_t n, int precision, void *stream);
@@ -80,5 +104,11 @@ int launch_rough(void *zmap, int64_t nx, int64_t ny, int precision, bool decode,
                  RoughPart1 *p1, RoughPart2 *p2, RoughState *st, fsm_rough *d_out,
                  const uint64_t *d_binned, int64_t n_evals, void *stream);
 int launch_decode(void *zmap, int64_t n, int precision, void *stream);
+// One slice of binning items [item_begin, item_begin + n_items) of the binned path:
+// count -> scan -> bucket write -> per-tile LDS reduction into the Z-map.
+int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
+                        const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
+                        int64_t n_items, const BinBuffers &bb, bool first_slice,
+                        int precision, uint64_t *d_binned, void *stream);
 
 }  // namespace fsm

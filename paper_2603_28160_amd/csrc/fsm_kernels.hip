@@ -227,6 +227,322 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
     if (tid == 0 && tot) atomicAdd((unsigned long long *)binned, (unsigned long long)tot);
 }
 
+// ---- binned Z-map ----------------------------------------------------------------------------
+//
+// The scatter form above touches one random cache line of the Z-map per binned point.  The
+// binned form sorts the points by kTile x kTile cell tile first and reduces every tile in LDS:
+//   count : per point, the tile it falls in; lanes are consecutive time steps, so equal tiles
+//           come in runs and one atomic add per run counts them;
+//   scan  : exclusive prefix sum of the counts -> bucket offsets (and write cursors);
+//   write : the same points again, each run claiming its slots with one atomic add and every
+//           lane storing (height key, cell index inside the tile);
+//   reduce: one block per tile: keys in LDS, integer ds_min of every bucket entry, then one
+//           coalesced store of the decoded tile (the Z-map is touched once per slice).
+
+template <int PREC> struct KeyOf;
+template <> struct KeyOf<FSM_F64> { using T = int64_t; static constexpr int64_t inf = kInf64; };
+template <> struct KeyOf<FSM_F32> { using T = int32_t; static constexpr int32_t inf = kInf32; };
+
+constexpr int kUnroll = 4;   // edge points in flight per lane
+
+// Position of one edge point of the current (pass, step, tooth) in the workpiece frame and its
+// bin.  Returns the global tile (or -1 outside the grid), the cell inside the tile and the key.
+template <int PREC>
+struct PointBin {
+    int32_t tile;
+    uint16_t cell;
+    typename KeyOf<PREC>::T key;
+};
+
+template <int PREC>
+__device__ __forceinline__ PointBin<PREC> bin_point(const DevSim &d, double ca, double sa,
+                                                    float caf, float saf, double xcs, double yq,
+                                                    int K, int p)
+{
+    PointBin<PREC> r;
+    r.tile = -1;
+    r.cell = 0;
+    r.key = 0;
+    double xs, ys;
+    typename KeyOf<PREC>::T key;
+    if (PREC == FSM_F64) {
+        const FSM_GLOBAL double *pt = gptr(d.pT + ((size_t)K * d.N + p) * 3);
+        const double xT = pt[0], yT = pt[1], zT = pt[2];
+        // Eq. (3): [[c, s], [-s, c]] applied to the tool-frame point, then the tilt
+        xs = ca * xT + sa * yT;
+        ys = ca * yT - sa * xT;
+        double zs = zT;
+        if (d.tilt_lead) {
+            const double x1 = d.tl_c * xs + d.tl_s * zs;
+            zs = d.tl_c * zs - d.tl_s * xs;
+            xs = x1;
+        }
+        if (d.tilt_side) {
+            const double y1 = d.ts_c * ys - d.ts_s * zs;
+            zs = d.ts_s * ys + d.ts_c * zs;
+            ys = y1;
+        }
+        key = (typename KeyOf<PREC>::T)enc64(__double_as_longlong(zs));
+    } else {
+        const FSM_GLOBAL float *pt = gptr(d.pTf + ((size_t)K * d.N + p) * 4);
+        const float px = pt[0], py = pt[1], pz = pt[2];
+        float xf = fmaf(caf, px, saf * py);
+        float yf = fmaf(caf, py, -(saf * px));
+        float zf = pz;
+        if (d.tilt_lead) {
+            const float c = (float)d.tl_c, s = (float)d.tl_s;
+            const float x1 = fmaf(c, xf, s * zf);
+            zf = fmaf(c, zf, -(s * xf));
+            xf = x1;
+        }
+        if (d.tilt_side) {
+            const float c = (float)d.ts_c, s = (float)d.ts_s;
+            const float y1 = fmaf(c, yf, -(s * zf));
+            zf = fmaf(s, yf, c * zf);
+            yf = y1;
+        }
+        xs = (double)xf;
+        ys = (double)yf;
+        key = (typename KeyOf<PREC>::T)enc32(__float_as_int(zf));
+    }
+    // Eq. (4): tool-centre offset; Eq. (7): half-open sampling boundaries
+    const double fx = ((xcs + xs) - d.x_lo) * d.inv_dd;
+    const double fy = ((yq + ys) - d.y_lo) * d.inv_dd;
+    if (fx >= 0.0 && fx < d.nx_d && fy >= 0.0 && fy < d.ny_d) {
+        const int32_t i = (int32_t)fx, j = (int32_t)fy;
+        r.tile = (int32_t)d.tile_base + (j >> kTileShift) * d.tiles_x + (i >> kTileShift);
+        r.cell = (uint16_t)(((j & (kTile - 1)) << kTileShift) | (i & (kTile - 1)));
+        r.key = key;
+    }
+    return r;
+}
+
+// Runs of equal tiles over the 64 lanes of a wave.  head: first lane of a run; len: run
+// length (valid in head lanes); first: head lane of this lane's run.
+__device__ __forceinline__ void tile_runs(int32_t t, int lane, bool &head, int &len, int &first)
+{
+    int32_t prev = __shfl_up(t, 1, 64);
+    if (lane == 0) prev = -2;
+    head = t >= 0 && t != prev;
+    const uint64_t heads = __ballot(head);
+    const uint64_t ends = heads | __ballot(t < 0);
+    const uint64_t le = (2ull << lane) - 1ull;
+    const uint64_t above = ends & ~le;
+    const int nxt = above ? __ffsll((unsigned long long)above) - 1 : 64;
+    len = nxt - lane;
+    const uint64_t mine = heads & le;
+    first = mine ? 63 - __clzll((long long)mine) : lane;
+}
+
+template <int PREC, bool WRITE>
+__global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ sims, int n_sims,
+                                                     const int64_t *__restrict__ bitem_base,
+                                                     int64_t item_begin, int64_t n_items,
+                                                     uint32_t *__restrict__ counter,
+                                                     void *__restrict__ bkey_v,
+                                                     uint16_t *__restrict__ bidx, int64_t cap)
+{
+    using Key = typename KeyOf<PREC>::T;
+    const int tid = threadIdx.x, lane = tid & 63;
+    FSM_GLOBAL uint32_t *cnt = gptr(counter);
+    FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bkey_v));
+    FSM_GLOBAL uint16_t *bix = gptr(bidx);
+    for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
+        const int64_t round0 = b - blockIdx.x;
+        const int64_t rn = n_items - round0 < (int64_t)gridDim.x ? n_items - round0 : (int64_t)gridDim.x;
+        const int64_t item = item_begin + round0 + xcd_item(b - round0, rn);
+        const int si = n_sims == 1 ? 0 : find_sim(bitem_base, n_sims, item);
+        const DevSim d = sims[si];
+        int64_t local = item - d.bitem_base;
+        const int K = (int)(local % d.z_n);
+        local /= d.z_n;
+        const int sb = (int)(local % d.n_sblocks);
+        const int q = (int)(local / d.n_sblocks);
+        const int s = sb * kBlock + tid;
+        const bool vs = s < d.n_steps;
+        double ca = 0.0, sa = 0.0, xcs = 0.0;
+        float caf = 0.0f, saf = 0.0f;
+        if (vs) {
+            const int m = s % d.S;
+            if (PREC == FSM_F64) {
+                const FSM_GLOBAL double *cs = gptr(d.cs + ((size_t)K * d.S + m) * 2);
+                ca = cs[0];
+                sa = cs[1];
+            } else {
+                const FSM_GLOBAL float *cs = gptr(d.csf + ((size_t)K * d.S + m) * 2);
+                caf = cs[0];
+                saf = cs[1];
+            }
+            xcs = gptr(d.xc)[s];
+        }
+        const double yq = d.y_first + (double)q * d.a_e;
+        for (int p0 = 0; p0 < d.N; p0 += kUnroll) {
+            PointBin<PREC> pb[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                pb[u].tile = -1;
+                if (vs && p0 + u < d.N) pb[u] = bin_point<PREC>(d, ca, sa, caf, saf, xcs, yq, K, p0 + u);
+            }
+            bool head[kUnroll];
+            int len[kUnroll], first[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) tile_runs(pb[u].tile, lane, head[u], len[u], first[u]);
+            if (!WRITE) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (head[u]) __hip_atomic_fetch_add(cnt + pb[u].tile, (uint32_t)len[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                uint32_t base[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    base[u] = head[u] ? __hip_atomic_fetch_add(cnt + pb[u].tile, (uint32_t)len[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t b0 = __shfl(base[u], first[u], 64);
+                    if (pb[u].tile >= 0) {
+                        const int64_t pos = (int64_t)b0 + (lane - first[u]);
+                        if (pos < cap) {
+                            bkey[pos] = pb[u].key;
+                            bix[pos] = pb[u].cell;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Exclusive scan of the tile counts in three launches: per-block sums of kScanSeg counts, a
+// one-block scan of those sums (also adds the slice total to the in-grid counter), and the
+// per-block scan that writes offsets and cursors.
+constexpr int kScanSeg = 4096;
+constexpr int kScanPer = kScanSeg / kBlock;   // counts per thread
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    uint32_t wo = 0;
+    for (int k = 0; k < w; ++k) wo += sh[k];
+    total = sh[0] + sh[1] + sh[2] + sh[3];
+    return wo + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_reduce(const uint32_t *counts, int64_t n, uint32_t *bsum)
+{
+    __shared__ uint32_t sh[4];
+    const int64_t a = (int64_t)blockIdx.x * kScanSeg + (int64_t)threadIdx.x * kScanPer;
+    uint32_t v = 0;
+    for (int k = 0; k < kScanPer; ++k)
+        if (a + k < n) v += counts[a + k];
+    uint32_t tot;
+    block_exclusive_scan(v, sh, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_top(uint32_t *bsum, int nb, uint32_t *offsets, int64_t n,
+                                                  uint64_t *binned)
+{
+    __shared__ uint32_t sh[4];
+    uint32_t carry = 0;
+    for (int c = 0; c < nb; c += kBlock) {
+        const int k = c + threadIdx.x;
+        const uint32_t v = k < nb ? bsum[k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(v, sh, tot);
+        if (k < nb) bsum[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        offsets[n] = carry;
+        if (binned) *binned += carry;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void scan_apply(const uint32_t *counts, int64_t n, const uint32_t *bsum,
+                                                    uint32_t *offsets, uint32_t *cursor)
+{
+    __shared__ uint32_t sh[4];
+    const int64_t a = (int64_t)blockIdx.x * kScanSeg + (int64_t)threadIdx.x * kScanPer;
+    uint32_t c[kScanPer];
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        c[k] = a + k < n ? counts[a + k] : 0u;
+        v += c[k];
+    }
+    uint32_t tot;
+    uint32_t run = bsum[blockIdx.x] + block_exclusive_scan(v, sh, tot);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (a + k < n) {
+            offsets[a + k] = run;
+            cursor[a + k] = run;
+        }
+        run += c[k];
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__ sims, int n_sims,
+                                                      const int64_t *__restrict__ tile_base,
+                                                      int64_t n_tiles, const uint32_t *__restrict__ offsets,
+                                                      const void *__restrict__ bkey_v,
+                                                      const uint16_t *__restrict__ bidx, int first_slice)
+{
+    using Key = typename KeyOf<PREC>::T;
+    __shared__ Key lds[kTile * kTile];
+    const FSM_GLOBAL Key *bkey = gptr(static_cast<const Key *>(bkey_v));
+    const FSM_GLOBAL uint16_t *bix = gptr(bidx);
+    const int tid = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
+        const DevSim d = sims[si];
+        const int64_t lt = t - d.tile_base;
+        const int tx = (int)(lt % d.tiles_x), ty = (int)(lt / d.tiles_x);
+        const int64_t i0 = (int64_t)tx << kTileShift, j0 = (int64_t)ty << kTileShift;
+        const int w = d.nx - i0 < kTile ? (int)(d.nx - i0) : kTile;
+        const int h = d.ny - j0 < kTile ? (int)(d.ny - j0) : kTile;
+        FSM_GLOBAL Key *Z = gptr(static_cast<Key *>(d.zmap)) + j0 * d.nx + i0;
+        for (int l = tid; l < kTile * kTile; l += kBlock) {
+            const int li = l & (kTile - 1), lj = l >> kTileShift;
+            Key v = KeyOf<PREC>::inf;
+            if (!first_slice && li < w && lj < h) {
+                const Key zb = Z[(int64_t)lj * d.nx + li];
+                v = PREC == FSM_F64 ? (Key)enc64((int64_t)zb) : (Key)enc32((int32_t)zb);
+            }
+            lds[l] = v;
+        }
+        __syncthreads();
+        const uint32_t e1 = offsets[t + 1];
+        for (uint32_t e = offsets[t] + tid; e < e1; e += kBlock)
+            __hip_atomic_fetch_min(&lds[bix[e]], bkey[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+        for (int l = tid; l < kTile * kTile; l += kBlock) {
+            const int li = l & (kTile - 1), lj = l >> kTileShift;
+            if (li < w && lj < h) {
+                const Key k = lds[l];
+                Z[(int64_t)lj * d.nx + li] = PREC == FSM_F64 ? (Key)enc64((int64_t)k) : (Key)enc32((int32_t)k);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void zero_u32(uint32_t *p, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) p[k] = 0u;
+}
+
 // ---- roughness -------------------------------------------------------------------------------
 
 // Height of one Z-map element; decodes the scatter's integer keys when `decode` is set.
@@ -569,6 +885,42 @@ int launch_decode(void *zmap, int64_t n, int precision, void *stream)
         hipLaunchKernelGGL(decode_only<FSM_F64>, dim3(blocks), dim3(kBlock), 0, s, zmap, n);
     else
         hipLaunchKernelGGL(decode_only<FSM_F32>, dim3(blocks), dim3(kBlock), 0, s, zmap, n);
+    return (int)hipGetLastError();
+}
+
+int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
+                        const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
+                        int64_t n_items, const BinBuffers &bb, bool first_slice,
+                        int precision, uint64_t *d_binned, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int zb = stream_blocks(n_tiles, kBlock, 4096);
+    hipLaunchKernelGGL(zero_u32, dim3(zb), dim3(kBlock), 0, s, bb.counts, n_tiles);
+    const int64_t cap_blocks = (int64_t)1 << 20;
+    const int ib = (int)(n_items < cap_blocks ? n_items : cap_blocks);
+    const int nb = (int)((n_tiles + kScanSeg - 1) / kScanSeg);
+    // block sums of the scan live after the cursor array
+    uint32_t *bsum = bb.cursor + n_tiles;
+    const int tb = (int)(n_tiles < cap_blocks ? n_tiles : cap_blocks);
+    if (precision == FSM_F64) {
+        if (ib > 0)
+            hipLaunchKernelGGL((bin_points<FSM_F64, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.counts, bb.bkey, bb.bidx, bb.cap);
+        hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bsum);
+        hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bsum, nb, bb.offsets, n_tiles, d_binned);
+        hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bsum, bb.offsets, bb.cursor);
+        if (ib > 0)
+            hipLaunchKernelGGL((bin_points<FSM_F64, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.cursor, bb.bkey, bb.bidx, bb.cap);
+        hipLaunchKernelGGL(tile_reduce<FSM_F64>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, (const uint32_t *)bb.offsets, (const void *)bb.bkey, (const uint16_t *)bb.bidx, first_slice ? 1 : 0);
+    } else {
+        if (ib > 0)
+            hipLaunchKernelGGL((bin_points<FSM_F32, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.counts, bb.bkey, bb.bidx, bb.cap);
+        hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bsum);
+        hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bsum, nb, bb.offsets, n_tiles, d_binned);
+        hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bsum, bb.offsets, bb.cursor);
+        if (ib > 0)
+            hipLaunchKernelGGL((bin_points<FSM_F32, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.cursor, bb.bkey, bb.bidx, bb.cap);
+        hipLaunchKernelGGL(tile_reduce<FSM_F32>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, (const uint32_t *)bb.offsets, (const void *)bb.bkey, (const uint16_t *)bb.bidx, first_slice ? 1 : 0);
+    }
     return (int)hipGetLastError();
 }
 

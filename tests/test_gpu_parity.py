@@ -34,6 +34,19 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(scope="module", params=["binned", "scatter"])
+def sctx(request):
+    """A context per Z-map strategy."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28160_amd import Context
+    c = Context(0)
+    c.set_strategy(request.param)
+    yield c
+    c.close()
+
+
 def run_gpu(ctx, sim, precision):
     print(f"[gpu] {sim.name or 'sim'} {precision} grid {sim.grid.nx}x{sim.grid.ny}", flush=True)
     z, r = ctx.fsm_simulate(sim, precision)
@@ -92,20 +105,33 @@ def check_f32(ctx, sim, zo=None, max_ambiguous=0.05):
 
 # --- double precision: bit-exact against the oracle ----------------------------------------
 
-def test_config1_f64_exact(ctx):
-    check_f64(ctx, W.config1())
+def test_config1_f64_exact(sctx):
+    check_f64(sctx, W.config1())
 
 
-def test_config2_reduced_f64_exact(ctx):
+def test_config2_reduced_f64_exact(sctx):
     # same tool and path rules as the 5000 x 5000 case on a ragged 777 x 613 grid
-    check_f64(ctx, W.config2(nx=777, ny=613, dd=0.004))
+    check_f64(sctx, W.config2(nx=777, ny=613, dd=0.004))
 
 
 @pytest.mark.parametrize("i", [0, 1, 2, 3, 5, 8])
-def test_mix_sims_f64_exact(ctx, i):
+def test_mix_sims_f64_exact(sctx, i):
     s = W.random_sim(3, i, side_max=300)
     s = s.replace(grid=dataclasses.replace(s.grid, dd=s.grid.dd * 4))
-    check_f64(ctx, s)
+    check_f64(sctx, s)
+
+
+def test_binned_slices_f64_exact(ctx):
+    # a 1 MiB bucket budget forces the evaluation range into many slices, each folding its
+    # tiles into the Z-map left by the previous one
+    from paper_2603_28160_amd import _abi
+    s = W.config2(nx=777, ny=613, dd=0.004)
+    ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 1 << 20)
+    try:
+        check_f64(ctx, s)
+        check_f32(ctx, s)
+    finally:
+        ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 2 << 30)
 
 
 def test_paper_case2_tool_f64_exact(ctx):
@@ -116,8 +142,9 @@ def test_paper_case2_tool_f64_exact(ctx):
     check_f64(ctx, s)
 
 
-@pytest.mark.parametrize("case", ["n1", "z1", "s1", "grid1x1", "nofeed", "odd", "sidetilt", "big_n"])
-def test_edge_cases_f64(ctx, case):
+@pytest.mark.parametrize("case", ["n1", "z1", "s1", "grid1x1", "nofeed", "odd", "sidetilt", "big_n",
+                                  "tile_edges"])
+def test_edge_cases_f64(sctx, case):
     base = W.config2(nx=90, ny=70, dd=0.02)
     t, c, g = base.tool, base.cut, base.grid
     if case == "n1":
@@ -136,10 +163,13 @@ def test_edge_cases_f64(ctx, case):
         t = dataclasses.replace(t, tilt_side=math.radians(-7.0), theta=(0.0, 1.5, 3.2, 4.6))
     elif case == "big_n":
         t = dataclasses.replace(t, n_edge=300, n_teeth=2)
-    check_f64(ctx, W.Sim(t, c, g, name=case))
+    elif case == "tile_edges":
+        g = W.centred_grid(129, 65, 0.02)      # one cell past whole tiles in both directions
+    check_f64(sctx, W.Sim(t, c, g, name=case))
 
 
-def test_empty_result(ctx):
+def test_empty_result(sctx):
+    ctx = sctx
     # the path never reaches the grid: every cell stays +inf and every parameter is NaN
     s = W.config1()
     s = s.replace(cut=dataclasses.replace(s.cut, y_first=50.0))
@@ -160,8 +190,8 @@ def test_deterministic(ctx):
 
 # --- single precision: tolerance against the oracle --------------------------------------------
 
-def test_config2_reduced_f32(ctx):
-    check_f32(ctx, W.config2(nx=777, ny=613, dd=0.004))
+def test_config2_reduced_f32(sctx):
+    check_f32(sctx, W.config2(nx=777, ny=613, dd=0.004))
 
 
 @pytest.mark.parametrize("i", [0, 2, 5])
@@ -206,6 +236,6 @@ def test_roughness_sinusoid_closed_form(ctx):
 # --- full-size workloads ------------------------------------------------------------------------------
 
 def test_config2_full_f64_exact(ctx):
-    # the 5000 x 5000 ball-end raster exactly as the benchmark runs it
+    # the 5000 x 5000 ball-end raster exactly as the benchmark runs it (default strategy)
     zo = check_f64(ctx, W.config2())
     check_f32(ctx, W.config2(), zo=zo)
