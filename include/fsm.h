@@ -176,8 +176,10 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
                                        cell tile, then min-reduce each tile in LDS and store it
                                        once; FSM_ZMAP_SCATTER: one global atomic min per point */
 #define FSM_OPT_BUCKET_BYTES 2    /* device bytes the binned strategy may use for its point
-                                       buckets (default 2 GiB); larger simulations run in
+                                       buckets (default 4 GiB); larger simulations run in
                                        slices of the evaluation range */
+#define FSM_OPT_GRAPHS 3           /* nonzero: capture batch launch sequences into HIP graphs
+                                       and replay them for batches of the same shape */
 #define FSM_ZMAP_BINNED 0
 #define FSM_ZMAP_SCATTER 1
 
@@ -197,6 +199,23 @@ int fsm_last_timings(const fsm_ctx *ctx, fsm_timings *out);
  * finished.  FSM_EINVAL on bad parameters, FSM_EDEVICE on a HIP error. */
 int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid,
                  int precision, void *zmap_dev, fsm_rough *out, void *stream);
+
+/* One simulation of a batch.  Every pointer is borrowed for the duration of the call. */
+typedef struct fsm_job {
+    const fsm_tool *tool;
+    const fsm_cut *cut;
+    const fsm_grid *grid;
+    void *zmap_dev;          /* caller-owned device Z-map of this job (precision of the batch) */
+} fsm_job;
+
+/* Many simulations of different shapes in one launch sequence: all their work items and
+ * tiles are numbered consecutively and every kernel of the pipeline covers the whole batch
+ * at once, so small and large simulations share the device (the batched form of the method,
+ * used for dataset generation).  out: n host records.  With FSM_OPT_GRAPHS on, the launch
+ * sequence is captured into a HIP graph keyed by its shape and replayed when a batch of the
+ * same shape comes again.  Returns after the work has finished. */
+int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision,
+                       fsm_rough *out, void *stream);
 
 /* Roughness of an existing Z-map in device memory (+inf = empty cell), same estimator as
  * fsm_simulate.  n_evals and n_binned of the result are zero. */

@@ -21,7 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ENOTSUP = 0, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
 TOOL_ROUND, TOOL_BALL = 0, 1
 FLAG_SQ_ZERO, FLAG_NO_HIT, FLAG_LOW_COVERAGE = 1, 2, 4
-OPT_ZMAP_STRATEGY, OPT_BUCKET_BYTES = 1, 2
+OPT_ZMAP_STRATEGY, OPT_BUCKET_BYTES, OPT_GRAPHS = 1, 2, 3
 ZMAP_BINNED, ZMAP_SCATTER = 0, 1
 
 
@@ -71,6 +71,11 @@ class FsmTimings(C.Structure):
                 ("rough_ms", C.c_float), ("total_ms", C.c_float), ("valid", C.c_int32)]
 
 
+class FsmJob(C.Structure):
+    _fields_ = [("tool", C.POINTER(FsmTool)), ("cut", C.POINTER(FsmCut)),
+                ("grid", C.POINTER(FsmGrid)), ("zmap_dev", C.c_void_p)]
+
+
 # every symbol include/fsm.h declares, with its ctypes signature
 P = C.POINTER
 SIGNATURES = {
@@ -88,6 +93,8 @@ SIGNATURES = {
                       P(FsmRough), C.c_void_p], C.c_int),
     "fsm_roughness": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, P(FsmRough), C.c_void_p],
                       C.c_int),
+    "fsm_simulate_batch": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmRough), C.c_void_p],
+                           C.c_int),
 }
 
 _lock = threading.Lock()

@@ -156,6 +156,35 @@ class Context:
         _check(rc, "fsm_roughness", self._h)
         return out.as_dict()
 
+    def fsm_simulate_batch(self, sims, precision="f64", zmaps=None, stream=None):
+        """Run many simulations in one launch sequence; returns (Z-map tensors, roughness
+        dicts), both in the order of `sims`."""
+        n = len(sims)
+        if n == 0:
+            return [], []
+        if zmaps is None:
+            zmaps = [self.new_zmap(s.grid, precision) for s in sims]
+        keep = []
+        jobs = (_abi.FsmJob * n)()
+        for k, (s, z) in enumerate(zip(sims, zmaps)):
+            self._check_zmap(s.grid, precision, z)
+            t, c, g = _abi.tool_struct(s.tool), _abi.cut_struct(s.cut), _abi.grid_struct(s.grid)
+            keep += [t, c, g]
+            jobs[k].tool = C.pointer(t)
+            jobs[k].cut = C.pointer(c)
+            jobs[k].grid = C.pointer(g)
+            jobs[k].zmap_dev = z.data_ptr()
+        out = (_abi.FsmRough * n)()
+        rc = self._lib.fsm_simulate_batch(self._h, n, jobs, _prec(precision), out,
+                                          C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_simulate_batch", self._h)
+        return list(zmaps), [o.as_dict() for o in out]
+
+    def set_graphs(self, on: bool = True):
+        """Capture launch sequences into HIP graphs and replay them per launch shape."""
+        self.fsm_ctx_set_option(_abi.OPT_GRAPHS, 1 if on else 0)
+
     # short aliases
     simulate = fsm_simulate
     roughness = fsm_roughness
+    simulate_batch = fsm_simulate_batch

@@ -1,16 +1,22 @@
-// fsm_api.cpp -- the C ABI of libfsm: context, plan, single simulation and roughness.
+// fsm_api.cpp -- the C ABI of libfsm: context, plan, simulations (one or a batch), roughness.
 //
-// A call builds the host plan (fsm_plan.cpp), packs it with the device descriptor into one
-// pinned staging image, copies that image to the context's device workspace with a single
-// stream-ordered transfer, launches fill -> scatter -> roughness on the caller's stream and
-// copies the ~100-byte result back.  The Z-map itself never leaves the device.
+// A call builds the host plan of every simulation (fsm_plan.cpp), packs the device
+// descriptors and tables into one pinned staging image, copies it to the context's device
+// workspace with a single stream-ordered transfer, launches the Z-map strategy and the tiled
+// roughness over the whole set at once, and copies the ~100-byte result records back.  The
+// Z-maps themselves never leave the device.
+//
+// Workspace layout: device-only scratch first (its offsets depend only on the launch shape, so
+// a captured graph stays valid for every set of that shape), then the uploaded image.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "fsm_internal.h"
 
@@ -21,12 +27,18 @@ struct fsm_ctx {
     size_t d_bytes = 0;
     void *h_ws = nullptr;     // pinned host staging
     size_t h_bytes = 0;
-    fsm_rough *h_out = nullptr;  // pinned result slot
+    fsm_rough *h_out = nullptr;  // pinned result records
+    size_t h_out_n = 0;
     bool profiling = false;
-    hipEvent_t ev[5] = {};       // upload, fill, scatter, rough, end
+    hipEvent_t ev[5] = {};       // upload, fill, z-map, roughness, end
     fsm_timings timings = {};
     int strategy = fsm::kStrategyBinned;
-    int64_t bucket_bytes = (int64_t)2 << 30;
+    int64_t bucket_bytes = (int64_t)4 << 30;
+    bool graphs = false;
+    hipStream_t own = nullptr;   // stream used for graph capture and replay
+    hipEvent_t join = nullptr;
+    std::map<std::string, hipGraphExec_t> graph_cache;
+    size_t max_lds = 65536;
 };
 
 namespace {
@@ -34,7 +46,10 @@ namespace {
 using fsm::DevSim;
 using fsm::Plan;
 
-constexpr int kItersPerItem = 16;   // steps each thread walks per work item and edge point
+constexpr int kItersPerItem = 16;   // steps each thread walks per scatter item and edge point
+constexpr int64_t kTargetRows = 4096;      // rows of the histogram mode per launch
+constexpr int kRowChunk = 32;              // rows per column-scan chunk
+constexpr int64_t kHistBudget = (int64_t)1 << 30;   // bytes of the row matrix
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -50,168 +65,409 @@ int hip_err(fsm_ctx *ctx, hipError_t e, const char *where)
     return set_err(ctx, FSM_EDEVICE, m);
 }
 
-// Byte layout of one simulation's workspace.  The first `upload` bytes are built on the host
-// and copied with one transfer; the rest is device-only scratch.
-struct Layout {
-    size_t sim, base, tbase, binned, pT, pTf, cs, csf, xc, upload;
-    size_t part1, part2, state, out, counts, offsets, cursor, bkey, bidx, total;
-    int64_t n_tiles = 0, cap = 0;
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Shape and layout of one launch over a set of simulations.
+struct SetLayout {
+    int n = 0, precision = 0, strategy = 0, sx = 7, sy = 6;
+    int64_t total_tiles = 0, total_items = 0, per_slice = 0, cap = 0;
+    int max_n = 1;
+    // histogram mode of the binned strategy (no global atomics)
+    bool hist = false;
+    int64_t total_rows = 0, rows_per_slice = 0, max_tiles = 0, items_per_row = 1;
+    // device-only region
+    size_t st1 = 0, st2 = 0, state = 0, out = 0, counts = 0, offsets = 0, cursor = 0, bsum = 0,
+           bkey = 0, bidx = 0, hist_m = 0, chunk = 0;
+    size_t scratch_end = 0;
+    // uploaded region
+    size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0;
+    std::vector<size_t> pT, pTf, cs, csf, xc;
+    size_t total = 0;
 };
 
-int64_t tiles_of(int64_t n) { return (n + fsm::kTile - 1) / fsm::kTile; }
-
-Layout layout_of(const Plan &P, int precision, bool binned, int64_t bucket_bytes)
+void choose_tiles(const fsm_ctx *ctx, int precision, int &sx, int &sy)
 {
-    Layout L{};
+    sx = fsm::tile_sx(precision);
+    sy = fsm::tile_sy(precision);
+    const size_t key = precision == FSM_F64 ? 8 : 4;
+    // leave room for the kernel's own small shared arrays
+    while (sy > 4 && (key << (sx + sy)) + 1024 > ctx->max_lds) --sy;
+}
+
+SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
+                      int strategy, std::vector<DevSim> &devs)
+{
+    SetLayout L;
+    L.n = (int)plans.size();
+    L.precision = precision;
+    L.strategy = strategy;
+    choose_tiles(ctx, precision, L.sx, L.sy);
+    devs.assign(L.n, DevSim{});
+    int64_t items = 0, bitems = 0, tiles = 0;
+    for (int k = 0; k < L.n; ++k) {
+        const Plan &P = plans[k];
+        DevSim &d = devs[k];
+        std::memset(&d, 0, sizeof d);
+        d.y_first = P.y_first;
+        d.a_e = P.a_e;
+        d.x_lo = P.x_lo;
+        d.y_lo = P.y_lo;
+        d.inv_dd = P.inv_dd;
+        d.nx_d = (double)P.nx;
+        d.ny_d = (double)P.ny;
+        d.nx = P.nx;
+        d.ny = P.ny;
+        d.tl_c = P.tl_c;
+        d.tl_s = P.tl_s;
+        d.ts_c = P.ts_c;
+        d.ts_s = P.ts_s;
+        d.tilt_lead = P.tilt_lead;
+        d.tilt_side = P.tilt_side;
+        d.z_n = P.z_n;
+        d.N = P.N;
+        d.S = P.S;
+        d.n_steps = (int32_t)P.n_steps;
+        d.n_passes = (int32_t)P.n_passes;
+        d.ppi = std::max(1, std::min(P.N, fsm::kBlock));
+        d.spi = fsm::kBlock / d.ppi;
+        d.chunk = d.spi * kItersPerItem;
+        d.n_chunks = (int32_t)ceil_div(P.n_steps, d.chunk);
+        d.n_items = P.n_passes * (int64_t)d.n_chunks * P.z_n;
+        d.item_base = items;
+        items += d.n_items;
+        d.n_sblocks = (int32_t)ceil_div(P.n_steps, fsm::kBlock);
+        d.n_bitems = P.n_passes * (int64_t)d.n_sblocks * P.z_n;
+        d.bitem_base = bitems;
+        bitems += d.n_bitems;
+        d.sx = L.sx;
+        d.sy = L.sy;
+        d.tiles_x = (int32_t)ceil_div(P.nx, (int64_t)1 << L.sx);
+        d.tiles_y = (int32_t)ceil_div(P.ny, (int64_t)1 << L.sy);
+        d.n_tiles = (int64_t)d.tiles_x * d.tiles_y;
+        d.tile_base = tiles;
+        tiles += d.n_tiles;
+        d.sim = k;
+        L.max_n = std::max(L.max_n, P.N);
+    }
+    L.total_tiles = tiles;
+    const bool binned = strategy == fsm::kStrategyBinned;
+    L.total_items = binned ? bitems : items;
+    if (binned) {
+        // histogram mode when every simulation's tile histogram fits in LDS and the row
+        // matrix fits its budget
+        L.items_per_row = std::max<int64_t>(1, ceil_div(bitems, kTargetRows));
+        int64_t rows = 0, hsize = 0;
+        for (DevSim &d : devs) {
+            L.max_tiles = std::max(L.max_tiles, d.n_tiles);
+            d.items_per_row = (int32_t)L.items_per_row;
+            d.n_rows = ceil_div(d.n_bitems, L.items_per_row);
+            d.row_base = rows;
+            d.hbase = hsize;
+            rows += d.n_rows;
+            hsize += d.n_rows * d.n_tiles;
+        }
+        L.total_rows = rows;
+        L.hist = L.max_tiles <= fsm::kMaxHistTiles && hsize * 4 <= kHistBudget;
+        if (!L.hist) L.max_tiles = 0;
+    }
+
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
-    L.sim = take(sizeof(DevSim));
-    L.base = take(sizeof(int64_t));
-    L.tbase = take(sizeof(int64_t));
-    L.binned = take(sizeof(uint64_t));
-    L.pT = take(sizeof(double) * P.pT.size());
-    L.pTf = take(sizeof(float) * 4 * (size_t)P.z_n * P.N);
-    L.cs = take(sizeof(double) * P.cs.size());
-    L.csf = take(sizeof(float) * P.cs.size());
-    L.xc = take(sizeof(double) * P.xc.size());
-    L.upload = o;
-    L.part1 = take(sizeof(fsm::RoughPart1) * fsm::kRoughBlocks);
-    L.part2 = take(sizeof(fsm::RoughPart2) * fsm::kRoughBlocks);
-    L.state = take(sizeof(fsm::RoughState));
-    L.out = take(sizeof(fsm_rough));
+    L.st1 = take(sizeof(fsm::TileStat1) * tiles);
+    L.st2 = take(sizeof(fsm::TileStat2) * tiles);
+    L.state = take(sizeof(fsm::RoughState) * L.n);
+    L.out = take(sizeof(fsm_rough) * L.n);
     if (binned) {
-        L.n_tiles = tiles_of(P.nx) * tiles_of(P.ny);
         const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
-        const int64_t per_item = (int64_t)fsm::kBlock * P.N;
-        int64_t cap = bucket_bytes / (key_bytes + 2);
-        if (cap > P.n_evals) cap = P.n_evals;
-        if (cap < per_item) cap = per_item;             // at least one item per slice
-        if (cap > (int64_t)UINT32_MAX) cap = UINT32_MAX; // offsets are 32-bit
+        const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
+        int64_t cap = ctx->bucket_bytes / (key_bytes + 2);
+        cap = std::min<int64_t>(cap, std::max<int64_t>(per_item, bitems * per_item));
+        cap = std::max<int64_t>(cap, per_item);
+        cap = std::min<int64_t>(cap, (int64_t)UINT32_MAX);
+        L.per_slice = std::max<int64_t>(1, cap / per_item);
+        L.per_slice = std::min<int64_t>(L.per_slice, std::max<int64_t>(1, bitems));
         L.cap = cap;
-        const int64_t nb = (L.n_tiles + 4095) / 4096;
-        L.counts = take(sizeof(uint32_t) * L.n_tiles);
-        L.offsets = take(sizeof(uint32_t) * (L.n_tiles + 1));
-        L.cursor = take(sizeof(uint32_t) * (L.n_tiles + nb));
+        const int64_t nb = ceil_div(tiles, 4096);
+        L.counts = take(sizeof(uint32_t) * tiles);
+        L.offsets = take(sizeof(uint32_t) * (tiles + 1));
+        L.cursor = take(sizeof(uint32_t) * tiles);
+        L.bsum = take(sizeof(uint32_t) * nb);
         L.bkey = take((size_t)key_bytes * cap);
         L.bidx = take(sizeof(uint16_t) * cap);
+        if (L.hist) {
+            const int64_t per_row = L.items_per_row * per_item;
+            L.rows_per_slice = std::max<int64_t>(1, cap / per_row);
+            L.rows_per_slice = std::min<int64_t>(L.rows_per_slice, std::max<int64_t>(1, L.total_rows));
+            int64_t hsize = 0;
+            for (const DevSim &d : devs) hsize += d.n_rows * d.n_tiles;
+            L.hist_m = take(sizeof(uint32_t) * std::max<int64_t>(1, hsize));
+            L.chunk = take(sizeof(uint32_t) * ceil_div(L.rows_per_slice, kRowChunk) * std::max<int64_t>(1, tiles));
+        }
+    }
+    L.scratch_end = o;
+    L.sims = take(sizeof(DevSim) * L.n);
+    L.ibase = take(sizeof(int64_t) * L.n);
+    L.bbase = take(sizeof(int64_t) * L.n);
+    L.tbase = take(sizeof(int64_t) * L.n);
+    L.binned = take(sizeof(uint64_t) * L.n);
+    L.evals = take(sizeof(int64_t) * L.n);
+    for (const Plan &P : plans) {
+        L.pT.push_back(take(sizeof(double) * P.pT.size()));
+        L.pTf.push_back(take(sizeof(float) * 4 * (size_t)P.z_n * P.N));
+        L.cs.push_back(take(sizeof(double) * P.cs.size()));
+        L.csf.push_back(take(sizeof(float) * P.cs.size()));
+        L.xc.push_back(take(sizeof(double) * P.xc.size()));
     }
     L.total = o;
     return L;
 }
 
-int ensure(fsm_ctx *ctx, size_t bytes)
+int ensure(fsm_ctx *ctx, size_t dev_bytes, size_t host_bytes, size_t n_out)
 {
-    if (ctx->d_bytes < bytes) {
-        if (ctx->d_ws) hipFree(ctx->d_ws);
+    if (ctx->d_bytes < dev_bytes) {
+        if (ctx->d_ws) {
+            hipFree(ctx->d_ws);
+            for (auto &g : ctx->graph_cache) hipGraphExecDestroy(g.second);
+            ctx->graph_cache.clear();
+        }
         ctx->d_ws = nullptr;
         ctx->d_bytes = 0;
-        hipError_t e = hipMalloc(&ctx->d_ws, bytes);
+        hipError_t e = hipMalloc(&ctx->d_ws, dev_bytes);
         if (e != hipSuccess) { ctx->d_ws = nullptr; return hip_err(ctx, e, "hipMalloc(workspace)"); }
-        ctx->d_bytes = bytes;
+        ctx->d_bytes = dev_bytes;
     }
-    if (ctx->h_bytes < bytes) {
+    if (ctx->h_bytes < host_bytes) {
         if (ctx->h_ws) hipHostFree(ctx->h_ws);
         ctx->h_ws = nullptr;
         ctx->h_bytes = 0;
-        hipError_t e = hipHostMalloc(&ctx->h_ws, bytes, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc(&ctx->h_ws, host_bytes, hipHostMallocDefault);
         if (e != hipSuccess) { ctx->h_ws = nullptr; return hip_err(ctx, e, "hipHostMalloc(staging)"); }
-        ctx->h_bytes = bytes;
+        ctx->h_bytes = host_bytes;
+    }
+    if (ctx->h_out_n < n_out) {
+        if (ctx->h_out) hipHostFree(ctx->h_out);
+        ctx->h_out = nullptr;
+        ctx->h_out_n = 0;
+        hipError_t e = hipHostMalloc((void **)&ctx->h_out, sizeof(fsm_rough) * n_out, hipHostMallocDefault);
+        if (e != hipSuccess) { ctx->h_out = nullptr; return hip_err(ctx, e, "hipHostMalloc(results)"); }
+        ctx->h_out_n = n_out;
     }
     return FSM_OK;
 }
 
-void fill_devsim(const Plan &P, const Layout &L, char *dev, void *zmap, DevSim &d)
+// Fill the uploaded part of the image (host offsets are relative to L.sims).
+void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<DevSim> &devs,
+                const std::vector<void *> &zmaps, char *dev, char *host)
 {
-    std::memset(&d, 0, sizeof d);
-    d.pT = reinterpret_cast<const double *>(dev + L.pT);
-    d.pTf = reinterpret_cast<const float *>(dev + L.pTf);
-    d.cs = reinterpret_cast<const double *>(dev + L.cs);
-    d.csf = reinterpret_cast<const float *>(dev + L.csf);
-    d.xc = reinterpret_cast<const double *>(dev + L.xc);
-    d.zmap = zmap;
-    d.y_first = P.y_first;
-    d.a_e = P.a_e;
-    d.x_lo = P.x_lo;
-    d.y_lo = P.y_lo;
-    d.inv_dd = P.inv_dd;
-    d.nx_d = (double)P.nx;
-    d.ny_d = (double)P.ny;
-    d.nx = P.nx;
-    d.ny = P.ny;
-    d.tl_c = P.tl_c;
-    d.tl_s = P.tl_s;
-    d.ts_c = P.ts_c;
-    d.ts_s = P.ts_s;
-    d.tilt_lead = P.tilt_lead;
-    d.tilt_side = P.tilt_side;
-    d.z_n = P.z_n;
-    d.N = P.N;
-    d.S = P.S;
-    d.n_steps = (int32_t)P.n_steps;
-    d.n_passes = (int32_t)P.n_passes;
-    d.ppi = std::min(P.N, fsm::kBlock);
-    d.spi = fsm::kBlock / d.ppi;
-    d.chunk = d.spi * kItersPerItem;
-    d.n_chunks = (int32_t)((P.n_steps + d.chunk - 1) / d.chunk);
-    d.n_items = P.n_passes * (int64_t)d.n_chunks * P.z_n;
-    d.item_base = 0;
-    d.tiles_x = (int32_t)tiles_of(P.nx);
-    d.tiles_y = (int32_t)tiles_of(P.ny);
-    d.n_sblocks = (int32_t)((P.n_steps + fsm::kBlock - 1) / fsm::kBlock);
-    d.n_bitems = P.n_passes * (int64_t)d.n_sblocks * P.z_n;
-    d.bitem_base = 0;
-    d.tile_base = 0;
-}
-
-void fill_image(const Plan &P, const Layout &L, char *host, const DevSim &d)
-{
-    std::memcpy(host + L.sim, &d, sizeof d);
-    const int64_t base0 = 0;
-    std::memcpy(host + L.base, &base0, sizeof base0);
-    std::memcpy(host + L.tbase, &base0, sizeof base0);
-    const uint64_t zero = 0;
-    std::memcpy(host + L.binned, &zero, sizeof zero);
-    std::memcpy(host + L.pT, P.pT.data(), sizeof(double) * P.pT.size());
-    float *pTf = reinterpret_cast<float *>(host + L.pTf);
-    for (size_t k = 0; k < (size_t)P.z_n * P.N; ++k) {
-        pTf[4 * k] = (float)P.pT[3 * k];
-        pTf[4 * k + 1] = (float)P.pT[3 * k + 1];
-        pTf[4 * k + 2] = (float)P.pT[3 * k + 2];
-        pTf[4 * k + 3] = 0.0f;
+    auto H = [&](size_t off) { return host + (off - L.sims); };
+    std::vector<int64_t> ib(L.n), bb(L.n), tb(L.n), ev(L.n), rbase(L.n);
+    std::vector<uint64_t> zero(L.n, 0);
+    for (int k = 0; k < L.n; ++k) {
+        const Plan &P = plans[k];
+        DevSim &d = devs[k];
+        d.pT = reinterpret_cast<const double *>(dev + L.pT[k]);
+        d.pTf = reinterpret_cast<const float *>(dev + L.pTf[k]);
+        d.cs = reinterpret_cast<const double *>(dev + L.cs[k]);
+        d.csf = reinterpret_cast<const float *>(dev + L.csf[k]);
+        d.xc = reinterpret_cast<const double *>(dev + L.xc[k]);
+        d.zmap = zmaps[k];
+        ib[k] = d.item_base;
+        bb[k] = d.bitem_base;
+        tb[k] = d.tile_base;
+        rbase[k] = d.row_base;
+        ev[k] = P.n_evals;
+        if (!P.pT.empty()) std::memcpy(H(L.pT[k]), P.pT.data(), sizeof(double) * P.pT.size());
+        float *pTf = reinterpret_cast<float *>(H(L.pTf[k]));
+        for (size_t q = 0; q < (size_t)P.z_n * P.N && 3 * q + 2 < P.pT.size(); ++q) {
+            pTf[4 * q] = (float)P.pT[3 * q];
+            pTf[4 * q + 1] = (float)P.pT[3 * q + 1];
+            pTf[4 * q + 2] = (float)P.pT[3 * q + 2];
+            pTf[4 * q + 3] = 0.0f;
+        }
+        if (!P.cs.empty()) std::memcpy(H(L.cs[k]), P.cs.data(), sizeof(double) * P.cs.size());
+        float *csf = reinterpret_cast<float *>(H(L.csf[k]));
+        for (size_t q = 0; q < P.cs.size(); ++q) csf[q] = (float)P.cs[q];
+        if (!P.xc.empty()) std::memcpy(H(L.xc[k]), P.xc.data(), sizeof(double) * P.xc.size());
     }
-    std::memcpy(host + L.cs, P.cs.data(), sizeof(double) * P.cs.size());
-    float *csf = reinterpret_cast<float *>(host + L.csf);
-    for (size_t k = 0; k < P.cs.size(); ++k) csf[k] = (float)P.cs[k];
-    std::memcpy(host + L.xc, P.xc.data(), sizeof(double) * P.xc.size());
+    std::memcpy(H(L.sims), devs.data(), sizeof(DevSim) * L.n);
+    std::memcpy(H(L.ibase), ib.data(), sizeof(int64_t) * L.n);
+    std::memcpy(H(L.bbase), (L.hist ? rbase : bb).data(), sizeof(int64_t) * L.n);
+    std::memcpy(H(L.tbase), tb.data(), sizeof(int64_t) * L.n);
+    std::memcpy(H(L.binned), zero.data(), sizeof(uint64_t) * L.n);
+    std::memcpy(H(L.evals), ev.data(), sizeof(int64_t) * L.n);
 }
 
-bool valid_precision(int p) { return p == FSM_F64 || p == FSM_F32; }
-
-void mark(fsm_ctx *ctx, int k, hipStream_t s)
+void mark(fsm_ctx *ctx, int k, hipStream_t s, bool capturing)
 {
-    if (ctx->profiling) hipEventRecord(ctx->ev[k], s);
+    if (ctx->profiling && !capturing) hipEventRecord(ctx->ev[k], s);
 }
 
 // Read the events of a finished call into ctx->timings (phases that did not run read 0).
-void collect(fsm_ctx *ctx, bool have_upload, bool have_scatter)
+void collect(fsm_ctx *ctx, bool phases)
 {
     if (!ctx->profiling) return;
     float t[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 4; ++k) {
-        if ((k == 0 && !have_upload) || ((k == 1 || k == 2) && !have_scatter)) continue;
-        int a = k, b = k + 1;
-        if (hipEventElapsedTime(&t[k], ctx->ev[a], ctx->ev[b]) != hipSuccess) t[k] = 0.0f;
-    }
+    if (phases)
+        for (int k = 0; k < 4; ++k)
+            if (hipEventElapsedTime(&t[k], ctx->ev[k], ctx->ev[k + 1]) != hipSuccess) t[k] = 0.0f;
     ctx->timings.upload_ms = t[0];
     ctx->timings.fill_ms = t[1];
     ctx->timings.scatter_ms = t[2];
     ctx->timings.rough_ms = t[3];
     float tot = 0.0f;
-    const int first = have_upload ? 0 : 3;
-    if (hipEventElapsedTime(&tot, ctx->ev[first], ctx->ev[4]) != hipSuccess) tot = 0.0f;
+    if (hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[4]) != hipSuccess) tot = 0.0f;
     ctx->timings.total_ms = tot;
     ctx->timings.valid = 1;
 }
+
+// Every kernel of one set launch, in order (the part a graph captures).
+int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs,
+               const std::vector<Plan> &plans, char *dev, hipStream_t s, bool capturing)
+{
+    const DevSim *d_sims = reinterpret_cast<const DevSim *>(dev + L.sims);
+    const int64_t *d_ibase = reinterpret_cast<const int64_t *>(dev + L.ibase);
+    const int64_t *d_bbase = reinterpret_cast<const int64_t *>(dev + L.bbase);
+    const int64_t *d_tbase = reinterpret_cast<const int64_t *>(dev + L.tbase);
+    uint64_t *d_binned = reinterpret_cast<uint64_t *>(dev + L.binned);
+    const int64_t *d_evals = reinterpret_cast<const int64_t *>(dev + L.evals);
+    auto *st1 = reinterpret_cast<fsm::TileStat1 *>(dev + L.st1);
+    auto *st2 = reinterpret_cast<fsm::TileStat2 *>(dev + L.st2);
+    auto *state = reinterpret_cast<fsm::RoughState *>(dev + L.state);
+    auto *d_out = reinterpret_cast<fsm_rough *>(dev + L.out);
+    const bool binned = L.strategy == fsm::kStrategyBinned;
+    int he = 0;
+    mark(ctx, 1, s, capturing);
+    if (!binned) {
+        for (int k = 0; k < L.n; ++k) {
+            he = fsm::launch_fill(devs[k].zmap, plans[k].nx * plans[k].ny, L.precision, s);
+            if (he) return hip_err(ctx, (hipError_t)he, "fill kernel");
+        }
+    }
+    mark(ctx, 2, s, capturing);
+    if (binned) {
+        fsm::BinBuffers bb;
+        bb.counts = reinterpret_cast<uint32_t *>(dev + L.counts);
+        bb.offsets = reinterpret_cast<uint32_t *>(dev + L.offsets);
+        bb.cursor = reinterpret_cast<uint32_t *>(dev + L.cursor);
+        bb.bsum = reinterpret_cast<uint32_t *>(dev + L.bsum);
+        bb.bkey = dev + L.bkey;
+        bb.bidx = reinterpret_cast<uint16_t *>(dev + L.bidx);
+        bb.cap = L.cap;
+        bb.hist = L.hist ? reinterpret_cast<uint32_t *>(dev + L.hist_m) : nullptr;
+        bb.chunk = L.hist ? reinterpret_cast<uint32_t *>(dev + L.chunk) : nullptr;
+        bb.max_tiles = (int32_t)L.max_tiles;
+        bb.row_chunk = kRowChunk;
+        if (L.hist) {
+            // d_bbase holds each simulation's first row in this mode
+            int64_t r0 = 0;
+            do {
+                const int64_t r1 = std::min<int64_t>(L.total_rows, r0 + L.rows_per_slice);
+                he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, r0, r1, bb,
+                                            r0 == 0, r1 >= L.total_rows, L.precision, L.sx, L.sy,
+                                            st1, d_binned, s);
+                if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
+                r0 = r1;
+            } while (r0 < L.total_rows);
+        } else if (L.total_items == 0) {
+            // nothing to bin: the maps are still initialised and the first pass still runs
+            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, 0, 0, bb,
+                                          true, true, L.precision, L.sx, L.sy, st1, d_binned, s);
+            if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
+        }
+        for (int64_t b0 = 0; !L.hist && b0 < L.total_items; b0 += L.per_slice) {
+            const int64_t nit = std::min<int64_t>(L.per_slice, L.total_items - b0);
+            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, b0, nit, bb,
+                                          b0 == 0, b0 + nit >= L.total_items, L.precision, L.sx,
+                                          L.sy, st1, d_binned, s);
+            if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
+        }
+    } else {
+        he = fsm::launch_scatter(d_sims, L.n, d_ibase, L.total_items, L.precision, d_binned, s);
+        if (he) return hip_err(ctx, (hipError_t)he, "scatter kernel");
+    }
+    mark(ctx, 3, s, capturing);
+    he = fsm::launch_rough(d_sims, L.n, d_tbase, L.total_tiles, L.precision, L.sx, L.sy, !binned,
+                           !binned, st1, st2, state, d_binned, d_evals, d_out, s);
+    if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
+    return FSM_OK;
+}
+
+// Plan, upload, launch and wait for a set of simulations; results to out[0..n).
+int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void *> &zmaps,
+            int precision, fsm_rough *out, hipStream_t user)
+{
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
+    std::vector<DevSim> devs;
+    const SetLayout L = make_layout(ctx, plans, precision, ctx->strategy, devs);
+    int rc = ensure(ctx, L.total, L.total - L.sims, (size_t)L.n);
+    if (rc != FSM_OK) return rc;
+    char *dev = static_cast<char *>(ctx->d_ws);
+    char *host = static_cast<char *>(ctx->h_ws);
+    fill_image(L, plans, devs, zmaps, dev, host);
+
+    hipStream_t s = user;
+    if (ctx->graphs) {
+        // graphs are captured and replayed on the context's own stream, after the caller's
+        if (!ctx->own) {
+            e = hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_err(ctx, e, "hipStreamCreate");
+            e = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_err(ctx, e, "hipEventCreate");
+        }
+        e = hipEventRecord(ctx->join, user);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipEventRecord");
+        e = hipStreamWaitEvent(ctx->own, ctx->join, 0);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipStreamWaitEvent");
+        s = ctx->own;
+    }
+    ctx->timings.valid = 0;
+    mark(ctx, 0, s, false);
+    e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
+    if (ctx->graphs) {
+        char key[256];
+        std::snprintf(key, sizeof key, "%d/%d/%d/%lld/%lld/%lld/%lld/%d/%d/%d/%lld/%lld/%p", L.precision,
+                      L.strategy, L.n, (long long)L.total_tiles, (long long)L.total_items,
+                      (long long)L.per_slice, (long long)L.cap, L.sx, L.sy, (int)L.hist,
+                      (long long)L.total_rows, (long long)L.rows_per_slice, ctx->d_ws);
+        std::string k(key);
+        for (int i = 0; i < L.n; ++i) k += "/" + std::to_string(plans[i].nx) + "x" + std::to_string(plans[i].ny);
+        auto it = ctx->graph_cache.find(k);
+        if (it == ctx->graph_cache.end()) {
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_err(ctx, e, "hipStreamBeginCapture");
+            rc = launch_set(ctx, L, devs, plans, dev, s, true);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (rc != FSM_OK) { if (g) hipGraphDestroy(g); return rc; }
+            if (e2 != hipSuccess) return hip_err(ctx, e2, "hipStreamEndCapture");
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_err(ctx, e, "hipGraphInstantiate");
+            it = ctx->graph_cache.emplace(k, x).first;
+        }
+        mark(ctx, 1, s, false);
+        e = hipGraphLaunch(it->second, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipGraphLaunch");
+        mark(ctx, 2, s, false);
+        mark(ctx, 3, s, false);
+    } else {
+        rc = launch_set(ctx, L, devs, plans, dev, s, false);
+        if (rc != FSM_OK) return rc;
+    }
+    e = hipMemcpyAsync(ctx->h_out, dev + L.out, sizeof(fsm_rough) * L.n, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
+    mark(ctx, 4, s, false);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+    collect(ctx, !ctx->graphs);
+    if (out) std::memcpy(out, ctx->h_out, sizeof(fsm_rough) * L.n);
+    return FSM_OK;
+}
+
+bool valid_precision(int p) { return p == FSM_F64 || p == FSM_F32; }
 
 }  // namespace
 
@@ -252,7 +508,10 @@ int fsm_plan(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, int
         P.pT.resize((size_t)P.z_n * P.N * 3);
         P.cs.resize((size_t)P.z_n * P.S * 2);
         P.xc.resize((size_t)P.n_steps);
-        out->workspace_bytes = (int64_t)layout_of(P, precision, true, (int64_t)2 << 30).total;
+        fsm_ctx probe;
+        std::vector<Plan> one{P};
+        std::vector<DevSim> devs;
+        out->workspace_bytes = (int64_t)make_layout(&probe, one, precision, fsm::kStrategyBinned, devs).total;
         return FSM_OK;
     } catch (const std::bad_alloc &) {
         return FSM_ENOMEM;
@@ -289,11 +548,32 @@ int fsm_ctx_create(fsm_ctx **out, int device)
     fsm_ctx *c = new (std::nothrow) fsm_ctx;
     if (!c) return FSM_ENOMEM;
     c->device = device;
-    if (hipHostMalloc((void **)&c->h_out, sizeof(fsm_rough), hipHostMallocDefault) != hipSuccess) {
-        delete c;
-        return FSM_ENOMEM;
-    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_lds = (size_t)lds;
     *out = c;
+    return FSM_OK;
+}
+
+void fsm_ctx_destroy(fsm_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    for (auto &g : ctx->graph_cache) hipGraphExecDestroy(g.second);
+    for (auto &ev : ctx->ev)
+        if (ev) hipEventDestroy(ev);
+    if (ctx->join) hipEventDestroy(ctx->join);
+    if (ctx->own) hipStreamDestroy(ctx->own);
+    if (ctx->d_ws) hipFree(ctx->d_ws);
+    if (ctx->h_ws) hipHostFree(ctx->h_ws);
+    if (ctx->h_out) hipHostFree(ctx->h_out);
+    delete ctx;
+}
+
+int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n)
+{
+    if (!ctx || !buf || n == 0) return FSM_EINVAL;
+    std::snprintf(buf, n, "%s", ctx->err.c_str());
     return FSM_OK;
 }
 
@@ -309,6 +589,9 @@ int fsm_ctx_set_option(fsm_ctx *ctx, int option, int64_t value)
     case FSM_OPT_BUCKET_BYTES:
         if (value < ((int64_t)1 << 20)) return set_err(ctx, FSM_EINVAL, "bucket budget below 1 MiB");
         ctx->bucket_bytes = value;
+        return FSM_OK;
+    case FSM_OPT_GRAPHS:
+        ctx->graphs = value != 0;
         return FSM_OK;
     default:
         return set_err(ctx, FSM_EINVAL, "unknown option");
@@ -337,25 +620,6 @@ int fsm_last_timings(const fsm_ctx *ctx, fsm_timings *out)
     return FSM_OK;
 }
 
-void fsm_ctx_destroy(fsm_ctx *ctx)
-{
-    if (!ctx) return;
-    hipSetDevice(ctx->device);
-    for (auto &ev : ctx->ev)
-        if (ev) hipEventDestroy(ev);
-    if (ctx->d_ws) hipFree(ctx->d_ws);
-    if (ctx->h_ws) hipHostFree(ctx->h_ws);
-    if (ctx->h_out) hipHostFree(ctx->h_out);
-    delete ctx;
-}
-
-int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n)
-{
-    if (!ctx || !buf || n == 0) return FSM_EINVAL;
-    std::snprintf(buf, n, "%s", ctx->err.c_str());
-    return FSM_OK;
-}
-
 int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid,
                  int precision, void *zmap_dev, fsm_rough *out, void *stream)
 {
@@ -363,78 +627,38 @@ int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const f
     if (!tool || !cut || !grid || !zmap_dev || !valid_precision(precision))
         return set_err(ctx, FSM_EINVAL, "null argument or invalid precision");
     try {
-        Plan P;
+        std::vector<Plan> plans(1);
         std::string err;
-        int rc = fsm::build_plan(*tool, *cut, *grid, P, err, true);
+        int rc = fsm::build_plan(*tool, *cut, *grid, plans[0], err, true);
         if (rc != FSM_OK) return set_err(ctx, rc, err);
-        hipError_t e = hipSetDevice(ctx->device);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
-        const bool binned = ctx->strategy == fsm::kStrategyBinned;
-        const Layout L = layout_of(P, precision, binned, ctx->bucket_bytes);
-        rc = ensure(ctx, L.total);
-        if (rc != FSM_OK) return rc;
-        char *dev = static_cast<char *>(ctx->d_ws);
-        char *host = static_cast<char *>(ctx->h_ws);
-        DevSim d;
-        fill_devsim(P, L, dev, zmap_dev, d);
-        fill_image(P, L, host, d);
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        ctx->timings.valid = 0;
-        mark(ctx, 0, s);
-        e = hipMemcpyAsync(dev, host, L.upload, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
-        const int64_t n = grid->nx * grid->ny;
-        uint64_t *d_binned = reinterpret_cast<uint64_t *>(dev + L.binned);
-        const DevSim *d_sim = reinterpret_cast<const DevSim *>(dev + L.sim);
-        mark(ctx, 1, s);
-        int he;
-        if (!binned) {
-            he = fsm::launch_fill(zmap_dev, n, precision, stream);
-            if (he) return hip_err(ctx, (hipError_t)he, "fill kernel");
+        std::vector<void *> zmaps{zmap_dev};
+        return run_set(ctx, plans, zmaps, precision, out, static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, FSM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_err(ctx, FSM_EINVAL, "unexpected host exception");
+    }
+}
+
+int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_rough *out,
+                       void *stream)
+{
+    if (!ctx) return FSM_EINVAL;
+    if (n < 1 || !jobs || !out || !valid_precision(precision))
+        return set_err(ctx, FSM_EINVAL, "empty batch, null argument or invalid precision");
+    try {
+        std::vector<Plan> plans((size_t)n);
+        std::vector<void *> zmaps((size_t)n);
+        for (int k = 0; k < n; ++k) {
+            const fsm_job &j = jobs[k];
+            if (!j.tool || !j.cut || !j.grid || !j.zmap_dev)
+                return set_err(ctx, FSM_EINVAL, "job " + std::to_string(k) + ": null pointer");
+            std::string err;
+            int rc = fsm::build_plan(*j.tool, *j.cut, *j.grid, plans[k], err, true);
+            if (rc != FSM_OK) return set_err(ctx, rc, "job " + std::to_string(k) + ": " + err);
+            zmaps[k] = j.zmap_dev;
         }
-        mark(ctx, 2, s);
-        if (binned) {
-            fsm::BinBuffers bb;
-            bb.counts = reinterpret_cast<uint32_t *>(dev + L.counts);
-            bb.offsets = reinterpret_cast<uint32_t *>(dev + L.offsets);
-            bb.cursor = reinterpret_cast<uint32_t *>(dev + L.cursor);
-            bb.bkey = dev + L.bkey;
-            bb.bidx = reinterpret_cast<uint16_t *>(dev + L.bidx);
-            bb.cap = L.cap;
-            const int64_t per_slice = std::max<int64_t>(1, L.cap / ((int64_t)fsm::kBlock * P.N));
-            for (int64_t b0 = 0; b0 < d.n_bitems; b0 += per_slice) {
-                const int64_t nit = std::min<int64_t>(per_slice, d.n_bitems - b0);
-                he = fsm::launch_binned_slice(d_sim, 1, reinterpret_cast<const int64_t *>(dev + L.base),
-                                              reinterpret_cast<const int64_t *>(dev + L.tbase), L.n_tiles,
-                                              b0, nit, bb, b0 == 0, precision, d_binned, stream);
-                if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
-            }
-        } else {
-            he = fsm::launch_scatter(d_sim, d, d.n_items, 1, reinterpret_cast<const int64_t *>(dev + L.base),
-                                     precision, d_binned, stream);
-            if (he) return hip_err(ctx, (hipError_t)he, "scatter kernel");
-        }
-        mark(ctx, 3, s);
-        if (out) {
-            he = fsm::launch_rough(zmap_dev, grid->nx, grid->ny, precision, !binned,
-                                   reinterpret_cast<fsm::RoughPart1 *>(dev + L.part1),
-                                   reinterpret_cast<fsm::RoughPart2 *>(dev + L.part2),
-                                   reinterpret_cast<fsm::RoughState *>(dev + L.state),
-                                   reinterpret_cast<fsm_rough *>(dev + L.out), d_binned,
-                                   P.n_evals, stream);
-            if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
-            e = hipMemcpyAsync(ctx->h_out, dev + L.out, sizeof(fsm_rough), hipMemcpyDeviceToHost, s);
-            if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
-        } else if (!binned) {
-            he = fsm::launch_decode(zmap_dev, n, precision, stream);
-            if (he) return hip_err(ctx, (hipError_t)he, "decode kernel");
-        }
-        mark(ctx, 4, s);
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
-        collect(ctx, true, true);
-        if (out) *out = *ctx->h_out;
-        return FSM_OK;
+        return run_set(ctx, plans, zmaps, precision, out, static_cast<hipStream_t>(stream));
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");
     } catch (...) {
@@ -447,32 +671,53 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
 {
     if (!ctx) return FSM_EINVAL;
     if (!grid || !zmap_dev || !out || !valid_precision(precision) || grid->nx < 1 || grid->ny < 1 ||
-        grid->nx > INT64_MAX / grid->ny)
+        grid->nx > INT32_MAX || grid->ny > INT32_MAX || grid->nx > INT64_MAX / grid->ny)
         return set_err(ctx, FSM_EINVAL, "invalid grid, pointer or precision");
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
-    Plan P;   // empty tables: only the reduction part of the layout is used
-    const Layout L = layout_of(P, precision, false, 0);
-    int rc = ensure(ctx, L.total);
-    if (rc != FSM_OK) return rc;
-    char *dev = static_cast<char *>(ctx->d_ws);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    ctx->timings.valid = 0;
-    mark(ctx, 3, s);
-    int he = fsm::launch_rough(const_cast<void *>(zmap_dev), grid->nx, grid->ny, precision, false,
-                               reinterpret_cast<fsm::RoughPart1 *>(dev + L.part1),
-                               reinterpret_cast<fsm::RoughPart2 *>(dev + L.part2),
-                               reinterpret_cast<fsm::RoughState *>(dev + L.state),
-                               reinterpret_cast<fsm_rough *>(dev + L.out), nullptr, 0, stream);
-    if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
-    e = hipMemcpyAsync(ctx->h_out, dev + L.out, sizeof(fsm_rough), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
-    mark(ctx, 4, s);
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
-    collect(ctx, false, false);
-    *out = *ctx->h_out;
-    return FSM_OK;
+    try {
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
+        // a set of one pseudo-simulation carrying only the grid: the tiled roughness passes
+        std::vector<Plan> plans(1);
+        plans[0].nx = grid->nx;
+        plans[0].ny = grid->ny;
+        plans[0].N = 1;
+        std::vector<DevSim> devs;
+        const SetLayout L = make_layout(ctx, plans, precision, fsm::kStrategyScatter, devs);
+        int rc = ensure(ctx, L.total, L.total - L.sims, 1);
+        if (rc != FSM_OK) return rc;
+        char *dev = static_cast<char *>(ctx->d_ws);
+        char *host = static_cast<char *>(ctx->h_ws);
+        std::vector<void *> zmaps{const_cast<void *>(zmap_dev)};
+        fill_image(L, plans, devs, zmaps, dev, host);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        ctx->timings.valid = 0;
+        mark(ctx, 0, s, false);
+        e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
+        mark(ctx, 1, s, false);
+        mark(ctx, 2, s, false);
+        mark(ctx, 3, s, false);
+        int he = fsm::launch_rough(reinterpret_cast<const DevSim *>(dev + L.sims), 1,
+                                   reinterpret_cast<const int64_t *>(dev + L.tbase), L.total_tiles,
+                                   precision, L.sx, L.sy, true, false,
+                                   reinterpret_cast<fsm::TileStat1 *>(dev + L.st1),
+                                   reinterpret_cast<fsm::TileStat2 *>(dev + L.st2),
+                                   reinterpret_cast<fsm::RoughState *>(dev + L.state), nullptr, nullptr,
+                                   reinterpret_cast<fsm_rough *>(dev + L.out), s);
+        if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
+        e = hipMemcpyAsync(ctx->h_out, dev + L.out, sizeof(fsm_rough), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
+        mark(ctx, 4, s, false);
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+        collect(ctx, true);
+        *out = *ctx->h_out;
+        return FSM_OK;
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, FSM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_err(ctx, FSM_EINVAL, "unexpected host exception");
+    }
 }
 
 }  // extern "C"

@@ -30,6 +30,21 @@ struct Plan {
 int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &out,
                std::string &err, bool tables = true);
 
+constexpr int kBlock = 256;            // threads per block of every kernel
+constexpr int kWaves = kBlock / 64;    // waves per block
+
+// Tile shapes of the binned Z-map and of the tiled roughness passes: (1 << sx) x (1 << sy)
+// cells.  The keys of one tile live in LDS during the reduction (32 KiB: several blocks per
+// compute unit).
+inline int tile_sx(int precision) { return precision == FSM_F64 ? 6 : 7; }
+inline int tile_sy(int precision) { (void)precision; return 6; }
+// Largest per-simulation tile count whose per-block histogram fits in LDS (64 KiB).
+constexpr int64_t kMaxHistTiles = 16384;
+
+// Z-map strategies
+constexpr int kStrategyBinned = 0;     // bucket points by tile, reduce each tile in LDS
+constexpr int kStrategyScatter = 1;    // global atomic min per point
+
 // Device-side description of one simulation (plain data, copied to device memory).
 struct DevSim {
     const double *pT;        // [z_n][N][3]
@@ -37,7 +52,7 @@ struct DevSim {
     const double *cs;        // [z_n][S][2]
     const float *csf;        // [z_n][S][2]
     const double *xc;        // [n_steps]
-    void *zmap;              // encoded keys during the scatter, heights afterwards
+    void *zmap;              // the caller's Z-map
     double y_first, a_e;
     double x_lo, y_lo, inv_dd;
     double nx_d, ny_d;       // nx, ny as doubles for the in-grid test
@@ -47,68 +62,85 @@ struct DevSim {
     int32_t z_n, N, S;
     int32_t n_steps;
     int32_t n_passes;
-    int32_t chunk;           // steps per work item
-    int32_t n_chunks;        // work items per (pass, tooth)
+    // scatter strategy: one item = (pass, chunk of steps, tooth), threads over edge points
+    int32_t chunk;           // steps per item
+    int32_t n_chunks;        // items per (pass, tooth)
     int32_t ppi, spi;        // edge points per step slot, steps in flight per block
-    int64_t n_items;         // n_passes * n_chunks * z_n
-    int64_t item_base;       // first global work item of this simulation
-    // binned Z-map: the grid is cut into kTile x kTile cell tiles
-    int32_t tiles_x, tiles_y;
-    int32_t n_sblocks;       // step blocks of kBlock steps per (pass, tooth)
+    int64_t n_items;
+    int64_t item_base;       // first global scatter item of this simulation
+    // binned strategy: one item = (pass, block of kBlock steps, tooth), threads over steps
+    int32_t n_sblocks;       // step blocks per (pass, tooth)
     int32_t pad0;
     int64_t n_bitems;        // n_passes * n_sblocks * z_n
     int64_t bitem_base;      // first global binning item of this simulation
+    // tiles (binned Z-map and tiled roughness)
+    int32_t sx, sy;          // tile = (1 << sx) x (1 << sy) cells
+    int32_t tiles_x, tiles_y;
+    int64_t n_tiles;
     int64_t tile_base;       // first global tile of this simulation
+    int32_t sim;             // index of this simulation in its launch
+    int32_t items_per_row;   // histogram binning: binning items per row
+    int64_t n_rows;          // histogram binning: rows of this simulation
+    int64_t row_base;        // first global row of this simulation
+    int64_t hbase;           // offset of this simulation's first row in the row matrix
 };
 
-// Reduction partials and results of the roughness kernels (device memory).
-struct RoughPart1 {
-    double sum, mn, mx;
+// Per-tile partial sums of the roughness passes (device memory).  Row ny/2 and column nx/2
+// carry the two profiles.
+struct TileStat1 {
+    double sum, mn, mx, row_sum, col_sum;
     int64_t n;
+    int32_t row_n, col_n;
 };
-struct RoughPart2 {
-    double s1, s2, s3, s4;
+struct TileStat2 {
+    double s1, s2, s3, s4, row_abs, col_abs;
 };
 struct RoughState {
-    double mean;
-    double row_mean, col_mean;
+    double mean, row_mean, col_mean, mn, mx;
     int64_t n, n_row, n_col;
-    double mn, mx;
 };
 
-constexpr int kBlock = 256;            // threads per block of every kernel
-constexpr int kRoughBlocks = 1024;     // blocks of the roughness passes (fixed: determinism)
-constexpr int kTileShift = 6;
-constexpr int kTile = 1 << kTileShift; // cells per tile side of the binned Z-map
-constexpr int kScanThreads = 1024;
-
-// Z-map strategies
-constexpr int kStrategyBinned = 0;     // bucket points by tile, reduce each tile in LDS
-constexpr int kStrategyScatter = 1;    // global atomic min per point
-
-// Buffers of the binned Z-map path (device memory).
+// Buffers of the binned strategy (device memory).
 struct BinBuffers {
-    uint32_t *counts;        // [n_tiles]
-    uint32_t *offsets;       // [n_tiles + 1]
-    uint32_t *cursor;        // [n_tiles]
+    uint32_t *counts;        // [n_tiles] points per tile
+    uint32_t *offsets;       // [n_tiles + 1] bucket starts
+    uint32_t *cursor;        // [n_tiles] write cursors (run mode)
+    uint32_t *bsum;          // [ceil(n_tiles / scan segment)] scan block sums
     void *bkey;              // [cap] int64 (FP64) or int32 (FP32) height keys
     uint16_t *bidx;          // [cap] cell index inside the tile
     int64_t cap;             // bucket capacity (points)
+    // histogram mode
+    uint32_t *hist;          // row matrix: per row, the points of each tile of its simulation
+    uint32_t *chunk;         // [n_chunks][n_tiles] column-scan partials
+    int32_t max_tiles;       // largest tile count of a simulation in the launch
+    int32_t row_chunk;       // rows per column-scan chunk
 };
 
-// Launch wrappers (fsm_kernels.hip).  All return a hipError_t as int.
+// Launch wrappers (fsm_kernels.hip).  All return a hipError_t as int.  `sims`/`d_*base`
+// describe n_sims simulations whose items and tiles are numbered consecutively.
 int launch_fill(void *zmap, int64_t n, int precision, void *stream);
-int launch_scatter(const DevSim *d_sims, const DevSim &h_sim0, int64_t n_items, int n_sims,
-                   const int64_t *d_item_base, int precision, uint64_t *d_binned, void *stream);
-int launch_rough(void *zmap, int64_t nx, int64_t ny, int precision, bool decode,
-                 RoughPart1 *p1, RoughPart2 *p2, RoughState *st, fsm_rough *d_out,
-                 const uint64_t *d_binned, int64_t n_evals, void *stream);
-int launch_decode(void *zmap, int64_t n, int precision, void *stream);
-// One slice of binning items [item_begin, item_begin + n_items) of the binned path:
-// count -> scan -> bucket write -> per-tile LDS reduction into the Z-map.
+int launch_scatter(const DevSim *d_sims, int n_sims, const int64_t *d_item_base,
+                   int64_t n_items, int precision, uint64_t *d_binned, void *stream);
+// One slice [item_begin, item_begin + n_items) of binning items: count -> scan -> write ->
+// per-tile LDS reduction into the Z-maps (with the first roughness pass on the last slice).
 int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
                         const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
                         int64_t n_items, const BinBuffers &bb, bool first_slice,
-                        int precision, uint64_t *d_binned, void *stream);
+                        bool last_slice, int precision, int sx, int sy, TileStat1 *st1,
+                        uint64_t *d_binned, void *stream);
+// Histogram mode of the binned strategy, one slice of rows [row_begin, row_end): per-block
+// LDS histograms written as rows, a chunked column scan into per-(row, tile) offsets, a write
+// pass that claims slots with LDS atomics only, then the per-tile LDS reduction.
+int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
+                      const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
+                      int64_t row_end, const BinBuffers &bb, bool first_slice, bool last_slice,
+                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                      void *stream);
+// Tiled roughness.  with_pass1: run the first pass (decoding scatter keys if `decode`);
+// otherwise its tile partials are already in st1.  out: one record per simulation.
+int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, int64_t n_tiles,
+                 int precision, int sx, int sy, bool with_pass1, bool decode, TileStat1 *st1,
+                 TileStat2 *st2, RoughState *state, const uint64_t *d_binned,
+                 const int64_t *d_evals, fsm_rough *d_out, void *stream);
 
 }  // namespace fsm

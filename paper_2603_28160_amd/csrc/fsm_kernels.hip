@@ -1,18 +1,29 @@
 // fsm_kernels.hip -- gfx950 kernels of libfsm.
 //
-//   fill      : Z-map <- +inf (the empty-cell value) with 16-byte stores.
-//   scatter   : the hot loop of the method (Sec. 2.3, Sec. 3.2 "surface computation"): every
-//               (pass, step, tooth, edge point) is turned into the workpiece frame (Eq. (3)-(5)
-//               plus tilt) on the fly, binned into its half-open sampling boundary (Eq. (7)) and
-//               min-reduced into the Z-map with an integer atomic min on an order-preserving
-//               encoding of the height.  One block owns one (pass, step chunk, tooth) item.
-//   rough     : two passes over the Z-map (count/sum/min/max, then central moments) with
-//               wave64 shuffles and a fixed-order combine; a one-block finalize computes the
-//               ISO 25178-2 amplitude parameters and the two profile Ra values.
+// The hot loop of the method (Sec. 2.3; the "surface computation" module of Sec. 3.2): every
+// (pass, step, tooth, edge point) is turned into the workpiece frame on the fly (Eq. (3),
+// tilt, Eq. (4)), binned into its half-open sampling boundary (Eq. (7)) and min-reduced into
+// the Z-map.  Two strategies reach the Z-map:
+//
+//   scatter : one global integer atomic min per point on an order-preserving encoding of the
+//             height.  Each point touches its own cache line of the map.
+//   binned  : points are sorted by cell tile first and every tile is min-reduced in LDS.
+//             count  - per point its tile; lanes are consecutive time steps, so equal tiles
+//                      come in runs and one atomic add per run counts them;
+//             scan   - exclusive prefix sum of the tile counts (three launches);
+//             write  - the same points again; one atomic add per run on the tile's cursor
+//                      claims the run's slots and each lane stores (height key, cell inside
+//                      the tile);
+//             reduce - one block per tile: keys in LDS, integer ds_min of every bucket entry,
+//                      one coalesced store of the decoded tile, and the first roughness pass
+//                      on the fly.
+//
+// Roughness is tiled as well: per-tile partial sums (count, sum, min, max and the two profile
+// lines; then the central moments), combined per simulation in a fixed order by one block.
 //
 // Double precision: only +, -, * run on the device (no contraction: -ffp-contract=off), in
 // the order the host planner documents, so binning decisions equal those of the plain
-// definition bit for bit.  Single precision: rotation and tilt in float with fused
+// definition bit for bit.  Single precision: rotation and tilt in float with explicit fused
 // multiply-adds; the tool-centre offset and the binning stay in double.
 #include <hip/hip_runtime.h>
 
@@ -39,6 +50,20 @@ constexpr int32_t kInf32 = 0x7F800000;             // bits of +inf (float)
 __device__ __forceinline__ int64_t enc64(int64_t b) { return b >= 0 ? b : (b ^ 0x7FFFFFFFFFFFFFFFLL); }
 __device__ __forceinline__ int32_t enc32(int32_t b) { return b >= 0 ? b : (b ^ 0x7FFFFFFF); }
 
+template <int PREC> struct KeyOf;
+template <> struct KeyOf<FSM_F64> {
+    using T = int64_t;
+    static constexpr int64_t inf = kInf64;
+    __device__ static int64_t enc(int64_t k) { return enc64(k); }
+    __device__ static double height(int64_t k) { return __longlong_as_double(k); }
+};
+template <> struct KeyOf<FSM_F32> {
+    using T = int32_t;
+    static constexpr int32_t inf = kInf32;
+    __device__ static int32_t enc(int32_t k) { return enc32(k); }
+    __device__ static double height(int32_t k) { return (double)__int_as_float(k); }
+};
+
 // Block b of a launch runs on XCD (b mod 8).  Give every XCD a contiguous range of items so
 // that the items sharing one XCD's L2 are neighbours along the tool path.
 __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t G)
@@ -46,6 +71,14 @@ __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t G)
     const int64_t g8 = G >> 3;
     if (b >= (g8 << 3)) return b;
     return (b & 7) * g8 + (b >> 3);
+}
+
+// Global item handled by block-loop index b of a grid-stride loop over n items.
+__device__ __forceinline__ int64_t loop_item(int64_t b, int64_t n)
+{
+    const int64_t round0 = b - blockIdx.x;
+    const int64_t rn = n - round0 < (int64_t)gridDim.x ? n - round0 : (int64_t)gridDim.x;
+    return round0 + xcd_item(b - round0, rn);
 }
 
 template <typename T>
@@ -68,8 +101,8 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Block-wide reductions of kBlock (= 4 waves) threads; the result is valid in every thread.
-// `buf` must hold 4 values.  Fixed order: lanes by butterfly, waves 0..3 left to right.
+// Block-wide reduction of kBlock (= 4 waves) threads, valid in every thread.  Fixed order:
+// lanes by butterfly, then waves 0..3 left to right.  `buf` holds 4 values.
 template <typename T, typename Op>
 __device__ __forceinline__ T block_reduce(T v, T *buf, Op op)
 {
@@ -79,6 +112,32 @@ __device__ __forceinline__ T block_reduce(T v, T *buf, Op op)
     __syncthreads();
     return op(op(buf[0], buf[1]), op(buf[2], buf[3]));
 }
+struct Add { template <typename T> __device__ T operator()(T a, T b) const { return a + b; } };
+struct Min { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+struct Max { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *buf) { return block_reduce(wave_sum(v), buf, Add()); }
+
+// Index of the simulation owning global item / tile `x` (base ascending, base[0] == 0).
+__device__ __forceinline__ int find_sim(const int64_t *__restrict__ base, int n, int64_t x)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+int stream_blocks(int64_t work, int64_t per_block, int cap)
+{
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    return (int)(b < cap ? b : cap);
+}
+
+constexpr int64_t kMaxGrid = (int64_t)1 << 20;
 
 // ---- fill ------------------------------------------------------------------------------------
 
@@ -102,33 +161,92 @@ __global__ __launch_bounds__(kBlock) void fill32(int32_t *z, int64_t n)
     if (blockIdx.x == 0 && threadIdx.x < (n & 3)) z[(n4 << 2) + threadIdx.x] = kInf32;
 }
 
-// ---- scatter ---------------------------------------------------------------------------------
-
-// Index of the simulation that owns global work item `item` (item_base is ascending, with
-// item_base[0] == 0).
-__device__ __forceinline__ int find_sim(const int64_t *__restrict__ base, int n, int64_t item)
+__global__ __launch_bounds__(kBlock) void zero_u32(uint32_t *p, int64_t n)
 {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (base[mid] <= item) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) p[k] = 0u;
 }
+
+// ---- kinematics of one point -----------------------------------------------------------------
+
+// Workpiece-frame horizontal offsets (xs, ys) from the tool centre and the height key of edge
+// point p of tooth K at spindle angle (ca, sa), single or double precision.
+template <int PREC>
+__device__ __forceinline__ void turn_point(const DevSim &d, double ca, double sa, float caf,
+                                           float saf, int K, int p, double &xs, double &ys,
+                                           typename KeyOf<PREC>::T &key)
+{
+    if (PREC == FSM_F64) {
+        const FSM_GLOBAL double *pt = gptr(d.pT + ((size_t)K * d.N + p) * 3);
+        const double xT = pt[0], yT = pt[1], zT = pt[2];
+        // Eq. (3): [[c, s], [-s, c]] applied to the tool-frame point, then the tilt
+        double x = ca * xT + sa * yT;
+        double y = ca * yT - sa * xT;
+        double z = zT;
+        if (d.tilt_lead) {
+            const double x1 = d.tl_c * x + d.tl_s * z;
+            z = d.tl_c * z - d.tl_s * x;
+            x = x1;
+        }
+        if (d.tilt_side) {
+            const double y1 = d.ts_c * y - d.ts_s * z;
+            z = d.ts_s * y + d.ts_c * z;
+            y = y1;
+        }
+        xs = x;
+        ys = y;
+        key = (typename KeyOf<PREC>::T)enc64(__double_as_longlong(z));
+    } else {
+        const FSM_GLOBAL float *pt = gptr(d.pTf + ((size_t)K * d.N + p) * 4);
+        const float px = pt[0], py = pt[1], pz = pt[2];
+        float x = fmaf(caf, px, saf * py);
+        float y = fmaf(caf, py, -(saf * px));
+        float z = pz;
+        if (d.tilt_lead) {
+            const float c = (float)d.tl_c, s = (float)d.tl_s;
+            const float x1 = fmaf(c, x, s * z);
+            z = fmaf(c, z, -(s * x));
+            x = x1;
+        }
+        if (d.tilt_side) {
+            const float c = (float)d.ts_c, s = (float)d.ts_s;
+            const float y1 = fmaf(c, y, -(s * z));
+            z = fmaf(s, y, c * z);
+            y = y1;
+        }
+        xs = (double)x;
+        ys = (double)y;
+        key = (typename KeyOf<PREC>::T)enc32(__float_as_int(z));
+    }
+}
+
+// Eq. (4) tool-centre offset and Eq. (7) half-open sampling boundaries: the cell (i, j), or
+// false outside the grid.
+__device__ __forceinline__ bool bin_cell(const DevSim &d, double xcs, double yq, double xs,
+                                         double ys, int32_t &i, int32_t &j)
+{
+    const double fx = ((xcs + xs) - d.x_lo) * d.inv_dd;
+    const double fy = ((yq + ys) - d.y_lo) * d.inv_dd;
+    if (fx >= 0.0 && fx < d.nx_d && fy >= 0.0 && fy < d.ny_d) {
+        i = (int32_t)fx;
+        j = (int32_t)fy;
+        return true;
+    }
+    return false;
+}
+
+// ---- scatter strategy ------------------------------------------------------------------------
 
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sims, int n_sims,
                                                   const int64_t *__restrict__ item_base,
                                                   int64_t n_items, uint64_t *__restrict__ binned)
 {
-    __shared__ uint32_t red[4];
-    uint32_t cnt = 0;
+    using KT = KeyOf<PREC>;
+    using Key = typename KT::T;
     const int tid = threadIdx.x;
     for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
-        // items of one round of the grid, spread over the XCDs in contiguous ranges
-        const int64_t round0 = b - blockIdx.x;
-        const int64_t rn = n_items - round0 < (int64_t)gridDim.x ? n_items - round0 : (int64_t)gridDim.x;
-        const int64_t item = round0 + xcd_item(b - round0, rn);
+        const int64_t item = loop_item(b, n_items);
         const int si = n_sims == 1 ? 0 : find_sim(item_base, n_sims, item);
         const DevSim d = sims[si];
         int64_t local = item - d.item_base;
@@ -136,83 +254,36 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
         local /= d.z_n;
         const int chunk = (int)(local % d.n_chunks);
         const int q = (int)(local / d.n_chunks);
-
         const int ppi = d.ppi, spi = d.spi;
         const int lane_p = tid % ppi, lane_s = tid / ppi;
-        if (lane_s >= spi) continue;
-        const int s0 = chunk * d.chunk;
-        const int s1 = s0 + d.chunk < d.n_steps ? s0 + d.chunk : d.n_steps;
-        const double yq = d.y_first + (double)q * d.a_e;
-        const int S = d.S;
-        const double x_lo = d.x_lo, y_lo = d.y_lo, inv = d.inv_dd;
-        const double nxd = d.nx_d, nyd = d.ny_d;
-        const int64_t nx = d.nx;
-        const FSM_GLOBAL double *__restrict__ xc = gptr(d.xc);
-
-        for (int p = lane_p; p < d.N; p += ppi) {
-            int s = s0 + lane_s;
-            int m = s % S;
-            if (PREC == FSM_F64) {
-                const FSM_GLOBAL double *__restrict__ cs = gptr(d.cs + (size_t)K * S * 2);
-                const FSM_GLOBAL double *pt = gptr(d.pT + ((size_t)K * d.N + p) * 3);
-                const double xT = pt[0], yT = pt[1], zT = pt[2];
-                FSM_GLOBAL int64_t *__restrict__ zk = gptr(static_cast<int64_t *>(d.zmap));
+        uint32_t cnt = 0;
+        if (lane_s < spi) {
+            const int s0 = chunk * d.chunk;
+            const int s1 = s0 + d.chunk < d.n_steps ? s0 + d.chunk : d.n_steps;
+            const double yq = d.y_first + (double)q * d.a_e;
+            const int S = d.S;
+            FSM_GLOBAL Key *zk = gptr(static_cast<Key *>(d.zmap));
+            for (int p = lane_p; p < d.N; p += ppi) {
+                int s = s0 + lane_s;
+                int m = s % S;
                 for (; s < s1; s += spi) {
-                    const double ca = cs[2 * m], sa = cs[2 * m + 1];
-                    // Eq. (3): [[c, s], [-s, c]] applied to the tool-frame point
-                    double xs = ca * xT + sa * yT;
-                    double ys = ca * yT - sa * xT;
-                    double zs = zT;
-                    if (d.tilt_lead) {
-                        const double x1 = d.tl_c * xs + d.tl_s * zs;
-                        zs = d.tl_c * zs - d.tl_s * xs;
-                        xs = x1;
+                    double ca = 0, sa = 0;
+                    float caf = 0, saf = 0;
+                    if (PREC == FSM_F64) {
+                        const FSM_GLOBAL double *cs = gptr(d.cs + ((size_t)K * S + m) * 2);
+                        ca = cs[0];
+                        sa = cs[1];
+                    } else {
+                        const FSM_GLOBAL float *cs = gptr(d.csf + ((size_t)K * S + m) * 2);
+                        caf = cs[0];
+                        saf = cs[1];
                     }
-                    if (d.tilt_side) {
-                        const double y1 = d.ts_c * ys - d.ts_s * zs;
-                        zs = d.ts_s * ys + d.ts_c * zs;
-                        ys = y1;
-                    }
-                    // Eq. (4): tool-centre offset; Eq. (7): half-open sampling boundaries
-                    const double fx = ((xc[s] + xs) - x_lo) * inv;
-                    const double fy = ((yq + ys) - y_lo) * inv;
-                    if (fx >= 0.0 && fx < nxd && fy >= 0.0 && fy < nyd) {
-                        const int64_t idx = (int64_t)(int32_t)fy * nx + (int32_t)fx;
-                        const int64_t key = enc64(__double_as_longlong(zs));
-                        if (key < __hip_atomic_load(zk + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                            __hip_atomic_fetch_min(zk + idx, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        ++cnt;
-                    }
-                    m += spi;
-                    while (m >= S) m -= S;
-                }
-            } else {
-                const FSM_GLOBAL float *__restrict__ cs = gptr(d.csf + (size_t)K * S * 2);
-                const FSM_GLOBAL float *ptf = gptr(d.pTf + ((size_t)K * d.N + p) * 4);
-                const float px = ptf[0], py = ptf[1], pz = ptf[2];
-                FSM_GLOBAL int32_t *__restrict__ zk = gptr(static_cast<int32_t *>(d.zmap));
-                const float tlc = (float)d.tl_c, tls = (float)d.tl_s;
-                const float tsc = (float)d.ts_c, tss = (float)d.ts_s;
-                for (; s < s1; s += spi) {
-                    const float ca = cs[2 * m], sa = cs[2 * m + 1];
-                    float xs = fmaf(ca, px, sa * py);
-                    float ys = fmaf(ca, py, -(sa * px));
-                    float zs = pz;
-                    if (d.tilt_lead) {
-                        const float x1 = fmaf(tlc, xs, tls * zs);
-                        zs = fmaf(tlc, zs, -(tls * xs));
-                        xs = x1;
-                    }
-                    if (d.tilt_side) {
-                        const float y1 = fmaf(tsc, ys, -(tss * zs));
-                        zs = fmaf(tss, ys, tsc * zs);
-                        ys = y1;
-                    }
-                    const double fx = ((xc[s] + (double)xs) - x_lo) * inv;
-                    const double fy = ((yq + (double)ys) - y_lo) * inv;
-                    if (fx >= 0.0 && fx < nxd && fy >= 0.0 && fy < nyd) {
-                        const int64_t idx = (int64_t)(int32_t)fy * nx + (int32_t)fx;
-                        const int32_t key = enc32(__float_as_int(zs));
+                    double xs, ys;
+                    Key key;
+                    turn_point<PREC>(d, ca, sa, caf, saf, K, p, xs, ys, key);
+                    int32_t i, j;
+                    if (bin_cell(d, gptr(d.xc)[s], yq, xs, ys, i, j)) {
+                        const int64_t idx = (int64_t)j * d.nx + i;
                         if (key < __hip_atomic_load(zk + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                             __hip_atomic_fetch_min(zk + idx, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ++cnt;
@@ -222,135 +293,56 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
                 }
             }
         }
+        const uint32_t w = wave_sum(cnt);
+        if ((tid & 63) == 0 && w) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)w);
     }
-    const uint32_t tot = block_reduce(wave_sum(cnt), red, [](uint32_t a, uint32_t b) { return a + b; });
-    if (tid == 0 && tot) atomicAdd((unsigned long long *)binned, (unsigned long long)tot);
 }
 
-// ---- binned Z-map ----------------------------------------------------------------------------
-//
-// The scatter form above touches one random cache line of the Z-map per binned point.  The
-// binned form sorts the points by kTile x kTile cell tile first and reduces every tile in LDS:
-//   count : per point, the tile it falls in; lanes are consecutive time steps, so equal tiles
-//           come in runs and one atomic add per run counts them;
-//   scan  : exclusive prefix sum of the counts -> bucket offsets (and write cursors);
-//   write : the same points again, each run claiming its slots with one atomic add and every
-//           lane storing (height key, cell index inside the tile);
-//   reduce: one block per tile: keys in LDS, integer ds_min of every bucket entry, then one
-//           coalesced store of the decoded tile (the Z-map is touched once per slice).
-
-template <int PREC> struct KeyOf;
-template <> struct KeyOf<FSM_F64> { using T = int64_t; static constexpr int64_t inf = kInf64; };
-template <> struct KeyOf<FSM_F32> { using T = int32_t; static constexpr int32_t inf = kInf32; };
+// ---- binned strategy ---------------------------------------------------------------------------
 
 constexpr int kUnroll = 4;   // edge points in flight per lane
 
-// Position of one edge point of the current (pass, step, tooth) in the workpiece frame and its
-// bin.  Returns the global tile (or -1 outside the grid), the cell inside the tile and the key.
-template <int PREC>
-struct PointBin {
-    int32_t tile;
-    uint16_t cell;
-    typename KeyOf<PREC>::T key;
+struct Runs {
+    bool head;               // first lane of a run of equal tiles
+    int len;                 // run length (head lanes)
+    int first;               // head lane of this lane's run
 };
 
-template <int PREC>
-__device__ __forceinline__ PointBin<PREC> bin_point(const DevSim &d, double ca, double sa,
-                                                    float caf, float saf, double xcs, double yq,
-                                                    int K, int p)
+// Runs of equal tiles over the 64 lanes of a wave (t < 0: no tile).  Lanes hold consecutive
+// time steps of one edge point, so a point's neighbours in time share its tile for a while.
+__device__ __forceinline__ Runs tile_runs(int32_t t, int lane)
 {
-    PointBin<PREC> r;
-    r.tile = -1;
-    r.cell = 0;
-    r.key = 0;
-    double xs, ys;
-    typename KeyOf<PREC>::T key;
-    if (PREC == FSM_F64) {
-        const FSM_GLOBAL double *pt = gptr(d.pT + ((size_t)K * d.N + p) * 3);
-        const double xT = pt[0], yT = pt[1], zT = pt[2];
-        // Eq. (3): [[c, s], [-s, c]] applied to the tool-frame point, then the tilt
-        xs = ca * xT + sa * yT;
-        ys = ca * yT - sa * xT;
-        double zs = zT;
-        if (d.tilt_lead) {
-            const double x1 = d.tl_c * xs + d.tl_s * zs;
-            zs = d.tl_c * zs - d.tl_s * xs;
-            xs = x1;
-        }
-        if (d.tilt_side) {
-            const double y1 = d.ts_c * ys - d.ts_s * zs;
-            zs = d.ts_s * ys + d.ts_c * zs;
-            ys = y1;
-        }
-        key = (typename KeyOf<PREC>::T)enc64(__double_as_longlong(zs));
-    } else {
-        const FSM_GLOBAL float *pt = gptr(d.pTf + ((size_t)K * d.N + p) * 4);
-        const float px = pt[0], py = pt[1], pz = pt[2];
-        float xf = fmaf(caf, px, saf * py);
-        float yf = fmaf(caf, py, -(saf * px));
-        float zf = pz;
-        if (d.tilt_lead) {
-            const float c = (float)d.tl_c, s = (float)d.tl_s;
-            const float x1 = fmaf(c, xf, s * zf);
-            zf = fmaf(c, zf, -(s * xf));
-            xf = x1;
-        }
-        if (d.tilt_side) {
-            const float c = (float)d.ts_c, s = (float)d.ts_s;
-            const float y1 = fmaf(c, yf, -(s * zf));
-            zf = fmaf(s, yf, c * zf);
-            yf = y1;
-        }
-        xs = (double)xf;
-        ys = (double)yf;
-        key = (typename KeyOf<PREC>::T)enc32(__float_as_int(zf));
-    }
-    // Eq. (4): tool-centre offset; Eq. (7): half-open sampling boundaries
-    const double fx = ((xcs + xs) - d.x_lo) * d.inv_dd;
-    const double fy = ((yq + ys) - d.y_lo) * d.inv_dd;
-    if (fx >= 0.0 && fx < d.nx_d && fy >= 0.0 && fy < d.ny_d) {
-        const int32_t i = (int32_t)fx, j = (int32_t)fy;
-        r.tile = (int32_t)d.tile_base + (j >> kTileShift) * d.tiles_x + (i >> kTileShift);
-        r.cell = (uint16_t)(((j & (kTile - 1)) << kTileShift) | (i & (kTile - 1)));
-        r.key = key;
-    }
-    return r;
-}
-
-// Runs of equal tiles over the 64 lanes of a wave.  head: first lane of a run; len: run
-// length (valid in head lanes); first: head lane of this lane's run.
-__device__ __forceinline__ void tile_runs(int32_t t, int lane, bool &head, int &len, int &first)
-{
+    Runs r;
     int32_t prev = __shfl_up(t, 1, 64);
     if (lane == 0) prev = -2;
-    head = t >= 0 && t != prev;
-    const uint64_t heads = __ballot(head);
+    r.head = t >= 0 && t != prev;
+    const uint64_t heads = __ballot(r.head);
     const uint64_t ends = heads | __ballot(t < 0);
     const uint64_t le = (2ull << lane) - 1ull;
     const uint64_t above = ends & ~le;
     const int nxt = above ? __ffsll((unsigned long long)above) - 1 : 64;
-    len = nxt - lane;
+    r.len = nxt - lane;
     const uint64_t mine = heads & le;
-    first = mine ? 63 - __clzll((long long)mine) : lane;
+    r.first = mine ? 63 - __clzll((long long)mine) : lane;
+    return r;
 }
 
+// Counting (WRITE = false): one atomic add per run, its result unused.  Writing (WRITE =
+// true): one atomic add per run on the tile's cursor claims the run's slots; every lane of the
+// run stores (height key, cell inside the tile) at the head's slot plus its distance to it.
 template <int PREC, bool WRITE>
 __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ sims, int n_sims,
                                                      const int64_t *__restrict__ bitem_base,
                                                      int64_t item_begin, int64_t n_items,
-                                                     uint32_t *__restrict__ counter,
-                                                     void *__restrict__ bkey_v,
-                                                     uint16_t *__restrict__ bidx, int64_t cap)
+                                                     BinBuffers bb)
 {
     using Key = typename KeyOf<PREC>::T;
     const int tid = threadIdx.x, lane = tid & 63;
-    FSM_GLOBAL uint32_t *cnt = gptr(counter);
-    FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bkey_v));
-    FSM_GLOBAL uint16_t *bix = gptr(bidx);
+    FSM_GLOBAL uint32_t *counter = gptr(WRITE ? bb.cursor : bb.counts);
+    FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bb.bkey));
+    FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
     for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
-        const int64_t round0 = b - blockIdx.x;
-        const int64_t rn = n_items - round0 < (int64_t)gridDim.x ? n_items - round0 : (int64_t)gridDim.x;
-        const int64_t item = item_begin + round0 + xcd_item(b - round0, rn);
+        const int64_t item = item_begin + loop_item(b, n_items);
         const int si = n_sims == 1 ? 0 : find_sim(bitem_base, n_sims, item);
         const DevSim d = sims[si];
         int64_t local = item - d.bitem_base;
@@ -376,34 +368,48 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
             xcs = gptr(d.xc)[s];
         }
         const double yq = d.y_first + (double)q * d.a_e;
+        const int sx = d.sx, sy = d.sy;
+        const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
         for (int p0 = 0; p0 < d.N; p0 += kUnroll) {
-            PointBin<PREC> pb[kUnroll];
+            int32_t tile[kUnroll];
+            uint16_t cell[kUnroll];
+            Key key[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-                pb[u].tile = -1;
-                if (vs && p0 + u < d.N) pb[u] = bin_point<PREC>(d, ca, sa, caf, saf, xcs, yq, K, p0 + u);
+                tile[u] = -1;
+                cell[u] = 0;
+                key[u] = 0;
+                if (vs && p0 + u < d.N) {
+                    double xs, ys;
+                    turn_point<PREC>(d, ca, sa, caf, saf, K, p0 + u, xs, ys, key[u]);
+                    int32_t i, j;
+                    if (bin_cell(d, xcs, yq, xs, ys, i, j)) {
+                        tile[u] = (int32_t)d.tile_base + (j >> sy) * d.tiles_x + (i >> sx);
+                        cell[u] = (uint16_t)(((j & my) << sx) | (i & mx));
+                    }
+                }
             }
-            bool head[kUnroll];
-            int len[kUnroll], first[kUnroll];
+            Runs r[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) tile_runs(pb[u].tile, lane, head[u], len[u], first[u]);
+            for (int u = 0; u < kUnroll; ++u) r[u] = tile_runs(tile[u], lane);
             if (!WRITE) {
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
-                    if (head[u]) __hip_atomic_fetch_add(cnt + pb[u].tile, (uint32_t)len[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (r[u].head)
+                        __hip_atomic_fetch_add(counter + tile[u], (uint32_t)r[u].len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 uint32_t base[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
-                    base[u] = head[u] ? __hip_atomic_fetch_add(cnt + pb[u].tile, (uint32_t)len[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+                    base[u] = r[u].head ? __hip_atomic_fetch_add(counter + tile[u], (uint32_t)r[u].len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t b0 = __shfl(base[u], first[u], 64);
-                    if (pb[u].tile >= 0) {
-                        const int64_t pos = (int64_t)b0 + (lane - first[u]);
-                        if (pos < cap) {
-                            bkey[pos] = pb[u].key;
-                            bix[pos] = pb[u].cell;
+                    const uint32_t b0 = __shfl(base[u], r[u].first, 64);
+                    if (tile[u] >= 0) {
+                        const int64_t pos = (int64_t)b0 + (lane - r[u].first);
+                        if (pos < bb.cap) {
+                            bkey[pos] = key[u];
+                            bix[pos] = cell[u];
                         }
                     }
                 }
@@ -412,11 +418,189 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
     }
 }
 
-// Exclusive scan of the tile counts in three launches: per-block sums of kScanSeg counts, a
-// one-block scan of those sums (also adds the slice total to the in-grid counter), and the
-// per-block scan that writes offsets and cursors.
+// ---- binned strategy, histogram mode ------------------------------------------------------------
+//
+// Without global atomics.  A block owns a row of consecutive binning items of one simulation
+// and counts its points per tile in an LDS histogram over all tiles of that simulation; the
+// histogram is stored as the row's entry of a row matrix.  A chunked column scan turns the
+// matrix into the offset of every (row, tile) inside the tile's bucket, and the write pass
+// recomputes the points, claiming slots with LDS atomics on the row's cursors.
+
+// Visit every in-grid point of binning items [i0, i1) of simulation d: f(tile, cell, key) with
+// the tile numbered inside the simulation.
+template <int PREC, typename F>
+__device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t i1, F &&f)
+{
+    using Key = typename KeyOf<PREC>::T;
+    const int tid = threadIdx.x;
+    const int sx = d.sx, sy = d.sy;
+    const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
+    for (int64_t it = i0; it < i1; ++it) {
+        int64_t local = it;
+        const int K = (int)(local % d.z_n);
+        local /= d.z_n;
+        const int sb = (int)(local % d.n_sblocks);
+        const int q = (int)(local / d.n_sblocks);
+        const int s = sb * kBlock + tid;
+        if (s >= d.n_steps) continue;
+        const int m = s % d.S;
+        double ca = 0.0, sa = 0.0;
+        float caf = 0.0f, saf = 0.0f;
+        if (PREC == FSM_F64) {
+            const FSM_GLOBAL double *cs = gptr(d.cs + ((size_t)K * d.S + m) * 2);
+            ca = cs[0];
+            sa = cs[1];
+        } else {
+            const FSM_GLOBAL float *cs = gptr(d.csf + ((size_t)K * d.S + m) * 2);
+            caf = cs[0];
+            saf = cs[1];
+        }
+        const double xcs = gptr(d.xc)[s];
+        const double yq = d.y_first + (double)q * d.a_e;
+        for (int p = 0; p < d.N; ++p) {
+            double xs, ys;
+            Key key;
+            turn_point<PREC>(d, ca, sa, caf, saf, K, p, xs, ys, key);
+            int32_t i, j;
+            if (bin_cell(d, xcs, yq, xs, ys, i, j))
+                f((j >> sy) * d.tiles_x + (i >> sx), (uint16_t)(((j & my) << sx) | (i & mx)), key);
+        }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void hist_count(const DevSim *__restrict__ sims, int n_sims,
+                                                     const int64_t *__restrict__ row_base,
+                                                     int64_t r0, int64_t n_rows, BinBuffers bb)
+{
+    using Key = typename KeyOf<PREC>::T;
+    extern __shared__ uint32_t hist[];
+    const int tid = threadIdx.x;
+    for (int64_t b = blockIdx.x; b < n_rows; b += gridDim.x) {
+        const int64_t r = r0 + loop_item(b, n_rows);
+        const int si = n_sims == 1 ? 0 : find_sim(row_base, n_sims, r);
+        const DevSim d = sims[si];
+        const int64_t lr = r - d.row_base;
+        const int64_t i0 = lr * d.items_per_row;
+        const int64_t i1 = i0 + d.items_per_row < d.n_bitems ? i0 + d.items_per_row : d.n_bitems;
+        const int T = (int)d.n_tiles;
+        for (int t = tid; t < T; t += kBlock) hist[t] = 0u;
+        __syncthreads();
+        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t, Key) {
+            __hip_atomic_fetch_add(&hist[lt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        });
+        __syncthreads();
+        FSM_GLOBAL uint32_t *row = gptr(bb.hist) + d.hbase + lr * T;
+        for (int t = tid; t < T; t += kBlock) row[t] = hist[t];
+        __syncthreads();
+    }
+}
+
+// Rows of simulation d inside [lo, hi): clipped to its own rows.
+__device__ __forceinline__ void sim_rows(const DevSim &d, int64_t lo, int64_t hi, int64_t &a, int64_t &b)
+{
+    a = lo > d.row_base ? lo : d.row_base;
+    const int64_t e = d.row_base + d.n_rows;
+    b = hi < e ? hi : e;
+}
+
+// Column sums of the row matrix over chunks of row_chunk rows of the slice [r0, r1).
+__global__ __launch_bounds__(kBlock) void hist_colsum(const DevSim *__restrict__ sims, int n_sims,
+                                                      const int64_t *__restrict__ tile_base,
+                                                      int64_t n_tiles, int64_t r0, int64_t r1,
+                                                      int64_t n_chunks, BinBuffers bb)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n_chunks * n_tiles; x += stride) {
+        const int64_t c = x / n_tiles, t = x - c * n_tiles;
+        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
+        const DevSim &d = sims[si];
+        int64_t a, b;
+        sim_rows(d, r0 + c * bb.row_chunk, r0 + (c + 1) * bb.row_chunk < r1 ? r0 + (c + 1) * bb.row_chunk : r1, a, b);
+        const int64_t lt = t - d.tile_base;
+        uint32_t sum = 0;
+        for (int64_t r = a; r < b; ++r) sum += bb.hist[d.hbase + (r - d.row_base) * d.n_tiles + lt];
+        bb.chunk[x] = sum;
+    }
+}
+
+// Exclusive scan of the chunk sums down every column; the column totals become the tile counts.
+__global__ __launch_bounds__(kBlock) void hist_chunkscan(int64_t n_tiles, int64_t n_chunks, BinBuffers bb)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tiles; t += stride) {
+        uint32_t run = 0;
+        for (int64_t c = 0; c < n_chunks; ++c) {
+            const uint32_t v = bb.chunk[c * n_tiles + t];
+            bb.chunk[c * n_tiles + t] = run;
+            run += v;
+        }
+        bb.counts[t] = run;
+    }
+}
+
+// Rows within a chunk: the matrix entries become offsets inside their tile's bucket.
+__global__ __launch_bounds__(kBlock) void hist_apply(const DevSim *__restrict__ sims, int n_sims,
+                                                     const int64_t *__restrict__ tile_base,
+                                                     int64_t n_tiles, int64_t r0, int64_t r1,
+                                                     int64_t n_chunks, BinBuffers bb)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n_chunks * n_tiles; x += stride) {
+        const int64_t c = x / n_tiles, t = x - c * n_tiles;
+        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
+        const DevSim &d = sims[si];
+        int64_t a, b;
+        sim_rows(d, r0 + c * bb.row_chunk, r0 + (c + 1) * bb.row_chunk < r1 ? r0 + (c + 1) * bb.row_chunk : r1, a, b);
+        const int64_t lt = t - d.tile_base;
+        uint32_t run = bb.chunk[x];
+        for (int64_t r = a; r < b; ++r) {
+            uint32_t *e = bb.hist + d.hbase + (r - d.row_base) * d.n_tiles + lt;
+            const uint32_t v = *e;
+            *e = run;
+            run += v;
+        }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ sims, int n_sims,
+                                                     const int64_t *__restrict__ row_base,
+                                                     int64_t r0, int64_t n_rows, BinBuffers bb)
+{
+    using Key = typename KeyOf<PREC>::T;
+    extern __shared__ uint32_t cur[];
+    const int tid = threadIdx.x;
+    FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bb.bkey));
+    FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
+    for (int64_t b = blockIdx.x; b < n_rows; b += gridDim.x) {
+        const int64_t r = r0 + loop_item(b, n_rows);
+        const int si = n_sims == 1 ? 0 : find_sim(row_base, n_sims, r);
+        const DevSim d = sims[si];
+        const int64_t lr = r - d.row_base;
+        const int64_t i0 = lr * d.items_per_row;
+        const int64_t i1 = i0 + d.items_per_row < d.n_bitems ? i0 + d.items_per_row : d.n_bitems;
+        const int T = (int)d.n_tiles;
+        const FSM_GLOBAL uint32_t *row = gptr(bb.hist) + d.hbase + lr * T;
+        const FSM_GLOBAL uint32_t *off = gptr(bb.offsets) + d.tile_base;
+        for (int t = tid; t < T; t += kBlock) cur[t] = off[t] + row[t];
+        __syncthreads();
+        const int64_t cap = bb.cap;
+        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t cell, Key key) {
+            const uint32_t pos = __hip_atomic_fetch_add(&cur[lt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if ((int64_t)pos < cap) {
+                bkey[pos] = key;
+                bix[pos] = cell;
+            }
+        });
+        __syncthreads();
+    }
+}
+
+// Exclusive scan of the tile counts in three launches: per-block sums of kScanSeg tiles, a
+// one-block scan of those sums, and the per-block scan that writes offsets and cursors.
 constexpr int kScanSeg = 4096;
-constexpr int kScanPer = kScanSeg / kBlock;   // counts per thread
+constexpr int kScanPer = kScanSeg / kBlock;   // tiles per thread
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
 {
@@ -448,8 +632,7 @@ __global__ __launch_bounds__(kBlock) void scan_reduce(const uint32_t *counts, in
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void scan_top(uint32_t *bsum, int nb, uint32_t *offsets, int64_t n,
-                                                  uint64_t *binned)
+__global__ __launch_bounds__(kBlock) void scan_top(uint32_t *bsum, int nb, uint32_t *offsets, int64_t n)
 {
     __shared__ uint32_t sh[4];
     uint32_t carry = 0;
@@ -461,10 +644,7 @@ __global__ __launch_bounds__(kBlock) void scan_top(uint32_t *bsum, int nb, uint3
         if (k < nb) bsum[k] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) {
-        offsets[n] = carry;
-        if (binned) *binned += carry;
-    }
+    if (threadIdx.x == 0) offsets[n] = carry;
 }
 
 __global__ __launch_bounds__(kBlock) void scan_apply(const uint32_t *counts, int64_t n, const uint32_t *bsum,
@@ -491,345 +671,294 @@ __global__ __launch_bounds__(kBlock) void scan_apply(const uint32_t *counts, int
     }
 }
 
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__ sims, int n_sims,
-                                                      const int64_t *__restrict__ tile_base,
-                                                      int64_t n_tiles, const uint32_t *__restrict__ offsets,
-                                                      const void *__restrict__ bkey_v,
-                                                      const uint16_t *__restrict__ bidx, int first_slice)
-{
-    using Key = typename KeyOf<PREC>::T;
-    __shared__ Key lds[kTile * kTile];
-    const FSM_GLOBAL Key *bkey = gptr(static_cast<const Key *>(bkey_v));
-    const FSM_GLOBAL uint16_t *bix = gptr(bidx);
-    const int tid = threadIdx.x;
-    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
-        const DevSim d = sims[si];
-        const int64_t lt = t - d.tile_base;
-        const int tx = (int)(lt % d.tiles_x), ty = (int)(lt / d.tiles_x);
-        const int64_t i0 = (int64_t)tx << kTileShift, j0 = (int64_t)ty << kTileShift;
-        const int w = d.nx - i0 < kTile ? (int)(d.nx - i0) : kTile;
-        const int h = d.ny - j0 < kTile ? (int)(d.ny - j0) : kTile;
-        FSM_GLOBAL Key *Z = gptr(static_cast<Key *>(d.zmap)) + j0 * d.nx + i0;
-        for (int l = tid; l < kTile * kTile; l += kBlock) {
-            const int li = l & (kTile - 1), lj = l >> kTileShift;
-            Key v = KeyOf<PREC>::inf;
-            if (!first_slice && li < w && lj < h) {
-                const Key zb = Z[(int64_t)lj * d.nx + li];
-                v = PREC == FSM_F64 ? (Key)enc64((int64_t)zb) : (Key)enc32((int32_t)zb);
-            }
-            lds[l] = v;
-        }
-        __syncthreads();
-        const uint32_t e1 = offsets[t + 1];
-        for (uint32_t e = offsets[t] + tid; e < e1; e += kBlock)
-            __hip_atomic_fetch_min(&lds[bix[e]], bkey[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __syncthreads();
-        for (int l = tid; l < kTile * kTile; l += kBlock) {
-            const int li = l & (kTile - 1), lj = l >> kTileShift;
-            if (li < w && lj < h) {
-                const Key k = lds[l];
-                Z[(int64_t)lj * d.nx + li] = PREC == FSM_F64 ? (Key)enc64((int64_t)k) : (Key)enc32((int32_t)k);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void zero_u32(uint32_t *p, int64_t n)
-{
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) p[k] = 0u;
-}
-
-// ---- roughness -------------------------------------------------------------------------------
-
-// Height of one Z-map element; decodes the scatter's integer keys when `decode` is set.
-__device__ __forceinline__ double height64(int64_t k, bool decode)
-{
-    return __longlong_as_double(decode ? enc64(k) : k);
-}
-__device__ __forceinline__ double height32(int32_t k, bool decode)
-{
-    return (double)__int_as_float(decode ? enc32(k) : k);
-}
-
-struct Acc1 {
-    double sum = 0.0, mn = INFINITY, mx = -INFINITY;
+// Accumulator of the first roughness pass over one tile.
+struct Stat1Acc {
+    double sum = 0.0, mn = INFINITY, mx = -INFINITY, row_sum = 0.0, col_sum = 0.0;
     int64_t n = 0;
-    __device__ void add(double v)
+    int32_t row_n = 0, col_n = 0;
+    __device__ void add(double v, bool on_row, bool on_col)
     {
         if (v < INFINITY) {
             sum += v;
             mn = fmin(mn, v);
             mx = fmax(mx, v);
             ++n;
+            if (on_row) { row_sum += v; ++row_n; }
+            if (on_col) { col_sum += v; ++col_n; }
         }
     }
-};
-
-__device__ void store_part1(Acc1 a, RoughPart1 *part)
-{
-    __shared__ double bd[4];
-    __shared__ int64_t bn[4];
-    const double s = block_reduce(wave_sum(a.sum), bd, [](double x, double y) { return x + y; });
-    const double mn = block_reduce(wave_min(a.mn), bd, [](double x, double y) { return fmin(x, y); });
-    const double mx = block_reduce(wave_max(a.mx), bd, [](double x, double y) { return fmax(x, y); });
-    const int64_t n = block_reduce(wave_sum(a.n), bn, [](int64_t x, int64_t y) { return x + y; });
-    if (threadIdx.x == 0) part[blockIdx.x] = RoughPart1{s, mn, mx, n};
-}
-
-// Pass 1: count, sum, min, max of the reached cells.  With `decode`, integer keys left by the
-// scatter become heights; only negative heights change bits, so only those are written back.
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void rough1(void *zmap, int64_t n, bool decode, RoughPart1 *part)
-{
-    Acc1 a;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (PREC == FSM_F64) {
-        int64_t *z = static_cast<int64_t *>(zmap);
-        const int64_t n2 = n >> 1;
-        for (int64_t k = gid; k < n2; k += stride) {
-            longlong2 v = reinterpret_cast<longlong2 *>(z)[k];
-            if (decode && (v.x < 0 || v.y < 0)) {
-                reinterpret_cast<longlong2 *>(z)[k] = longlong2{enc64(v.x), enc64(v.y)};
-            }
-            a.add(height64(v.x, decode));
-            a.add(height64(v.y, decode));
-        }
-        if ((n & 1) && gid == 0) {
-            const int64_t v = z[n - 1];
-            if (decode && v < 0) z[n - 1] = enc64(v);
-            a.add(height64(v, decode));
-        }
-    } else {
-        int32_t *z = static_cast<int32_t *>(zmap);
-        const int64_t n4 = n >> 2;
-        for (int64_t k = gid; k < n4; k += stride) {
-            int4 v = reinterpret_cast<int4 *>(z)[k];
-            if (decode && (v.x < 0 || v.y < 0 || v.z < 0 || v.w < 0)) {
-                reinterpret_cast<int4 *>(z)[k] = int4{enc32(v.x), enc32(v.y), enc32(v.z), enc32(v.w)};
-            }
-            a.add(height32(v.x, decode));
-            a.add(height32(v.y, decode));
-            a.add(height32(v.z, decode));
-            a.add(height32(v.w, decode));
-        }
-        if (gid < (n & 3)) {
-            const int64_t k = (n4 << 2) + gid;
-            const int32_t v = z[k];
-            if (decode && v < 0) z[k] = enc32(v);
-            a.add(height32(v, decode));
-        }
-    }
-    store_part1(a, part);
-}
-
-__device__ __forceinline__ double load_height(const void *zmap, int64_t k, int prec)
-{
-    return prec == FSM_F64 ? static_cast<const double *>(zmap)[k]
-                           : (double)static_cast<const float *>(zmap)[k];
-}
-
-// Sum and count of the reached cells along a line (start, stride, count), block-wide.
-__device__ void line_sum(const void *zmap, int prec, int64_t start, int64_t stride, int64_t cnt,
-                         double &sum, int64_t &n)
-{
-    __shared__ double bd[4];
-    __shared__ int64_t bn[4];
-    double s = 0.0;
-    int64_t m = 0;
-    for (int64_t k = threadIdx.x; k < cnt; k += kBlock) {
-        const double v = load_height(zmap, start + k * stride, prec);
-        if (v < INFINITY) { s += v; ++m; }
-    }
-    sum = block_reduce(wave_sum(s), bd, [](double x, double y) { return x + y; });
-    n = block_reduce(wave_sum(m), bn, [](int64_t x, int64_t y) { return x + y; });
-}
-
-__device__ double line_absdev(const void *zmap, int prec, int64_t start, int64_t stride,
-                              int64_t cnt, double mu)
-{
-    __shared__ double bd[4];
-    double s = 0.0;
-    for (int64_t k = threadIdx.x; k < cnt; k += kBlock) {
-        const double v = load_height(zmap, start + k * stride, prec);
-        if (v < INFINITY) s += fabs(v - mu);
-    }
-    return block_reduce(wave_sum(s), bd, [](double x, double y) { return x + y; });
-}
-
-// One block: combine the pass-1 partials in a fixed order and the two profile means.
-__global__ __launch_bounds__(kBlock) void rough1_final(const void *zmap, int prec, int64_t nx, int64_t ny,
-                                                      const RoughPart1 *part, int nparts, RoughState *st)
-{
-    Acc1 a;
-    for (int k = threadIdx.x; k < nparts; k += kBlock) {
-        const RoughPart1 p = part[k];
-        a.sum += p.sum;
-        a.mn = fmin(a.mn, p.mn);
-        a.mx = fmax(a.mx, p.mx);
-        a.n += p.n;
-    }
-    __shared__ double bd[4];
-    __shared__ int64_t bn[4];
-    const double sum = block_reduce(wave_sum(a.sum), bd, [](double x, double y) { return x + y; });
-    const double mn = block_reduce(wave_min(a.mn), bd, [](double x, double y) { return fmin(x, y); });
-    const double mx = block_reduce(wave_max(a.mx), bd, [](double x, double y) { return fmax(x, y); });
-    const int64_t n = block_reduce(wave_sum(a.n), bn, [](int64_t x, int64_t y) { return x + y; });
-    double rs, cs;
-    int64_t rn, cn;
-    line_sum(zmap, prec, (ny / 2) * nx, 1, nx, rs, rn);
-    line_sum(zmap, prec, nx / 2, nx, ny, cs, cn);
-    if (threadIdx.x == 0) {
-        st->n = n;
-        st->mean = n ? sum / (double)n : NAN;
-        st->mn = mn;
-        st->mx = mx;
-        st->n_row = rn;
-        st->row_mean = rn ? rs / (double)rn : NAN;
-        st->n_col = cn;
-        st->col_mean = cn ? cs / (double)cn : NAN;
-    }
-}
-
-struct Acc2 {
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-    __device__ void add(double v, double mu)
+    __device__ TileStat1 reduce()
     {
-        if (v < INFINITY) {
-            const double d = v - mu;
-            const double d2 = d * d;
-            s1 += fabs(d);
-            s2 += d2;
-            s3 += d2 * d;
-            s4 += d2 * d2;
-        }
+        __shared__ double bd[4];
+        __shared__ int64_t bl[4];
+        __shared__ int32_t bi[4];
+        TileStat1 t;
+        t.sum = block_sum(sum, bd);
+        t.mn = block_reduce(wave_min(mn), bd, Min());
+        t.mx = block_reduce(wave_max(mx), bd, Max());
+        t.row_sum = block_sum(row_sum, bd);
+        t.col_sum = block_sum(col_sum, bd);
+        t.n = block_sum(n, bl);
+        t.row_n = block_sum(row_n, bi);
+        t.col_n = block_sum(col_n, bi);
+        return t;
     }
 };
 
-// Pass 2: central moments about the mean of pass 1.
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void rough2(const void *zmap, int64_t n, const RoughState *st, RoughPart2 *part)
+// Geometry of tile t of simulation d: origin (i0, j0) and extent w x h (ragged at the edges).
+struct TileGeom {
+    int64_t i0, j0;
+    int w, h;
+};
+__device__ __forceinline__ TileGeom tile_geom(const DevSim &d, int64_t t)
 {
-    const double mu = st->mean;
-    Acc2 a;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (PREC == FSM_F64) {
-        const double *z = static_cast<const double *>(zmap);
-        const int64_t n2 = n >> 1;
-        for (int64_t k = gid; k < n2; k += stride) {
-            const double2 v = reinterpret_cast<const double2 *>(z)[k];
-            a.add(v.x, mu);
-            a.add(v.y, mu);
-        }
-        if ((n & 1) && gid == 0) a.add(z[n - 1], mu);
-    } else {
-        const float *z = static_cast<const float *>(zmap);
-        const int64_t n4 = n >> 2;
-        for (int64_t k = gid; k < n4; k += stride) {
-            const float4 v = reinterpret_cast<const float4 *>(z)[k];
-            a.add(v.x, mu);
-            a.add(v.y, mu);
-            a.add(v.z, mu);
-            a.add(v.w, mu);
-        }
-        if (gid < (n & 3)) a.add(z[(n4 << 2) + gid], mu);
-    }
-    __shared__ double bd[4];
-    const double s1 = block_reduce(wave_sum(a.s1), bd, [](double x, double y) { return x + y; });
-    const double s2 = block_reduce(wave_sum(a.s2), bd, [](double x, double y) { return x + y; });
-    const double s3 = block_reduce(wave_sum(a.s3), bd, [](double x, double y) { return x + y; });
-    const double s4 = block_reduce(wave_sum(a.s4), bd, [](double x, double y) { return x + y; });
-    if (threadIdx.x == 0) part[blockIdx.x] = RoughPart2{s1, s2, s3, s4};
+    const int64_t lt = t - d.tile_base;
+    const int tx = (int)(lt % d.tiles_x), ty = (int)(lt / d.tiles_x);
+    TileGeom g;
+    g.i0 = (int64_t)tx << d.sx;
+    g.j0 = (int64_t)ty << d.sy;
+    const int TX = 1 << d.sx, TY = 1 << d.sy;
+    g.w = d.nx - g.i0 < TX ? (int)(d.nx - g.i0) : TX;
+    g.h = d.ny - g.j0 < TY ? (int)(d.ny - g.j0) : TY;
+    return g;
 }
 
-// One block: combine the pass-2 partials and write the result record.
-__global__ __launch_bounds__(kBlock) void rough2_final(const void *zmap, int prec, int64_t nx, int64_t ny,
-                                                      const RoughPart2 *part, int nparts,
-                                                      const RoughState *st, const uint64_t *binned,
-                                                      int64_t n_evals, fsm_rough *out)
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__ sims, int n_sims,
+                                                      const int64_t *__restrict__ tile_base,
+                                                      int64_t n_tiles, BinBuffers bb, int first_slice,
+                                                      int last_slice, TileStat1 *__restrict__ st1,
+                                                      uint64_t *__restrict__ binned)
 {
-    Acc2 a;
-    for (int k = threadIdx.x; k < nparts; k += kBlock) {
-        const RoughPart2 p = part[k];
-        a.s1 += p.s1;
-        a.s2 += p.s2;
-        a.s3 += p.s3;
-        a.s4 += p.s4;
-    }
-    __shared__ double bd[4];
-    const double s1 = block_reduce(wave_sum(a.s1), bd, [](double x, double y) { return x + y; });
-    const double s2 = block_reduce(wave_sum(a.s2), bd, [](double x, double y) { return x + y; });
-    const double s3 = block_reduce(wave_sum(a.s3), bd, [](double x, double y) { return x + y; });
-    const double s4 = block_reduce(wave_sum(a.s4), bd, [](double x, double y) { return x + y; });
-    const double ra_row = line_absdev(zmap, prec, (ny / 2) * nx, 1, nx, st->row_mean);
-    const double ra_col = line_absdev(zmap, prec, nx / 2, nx, ny, st->col_mean);
-    if (threadIdx.x == 0) {
-        fsm_rough r;
-        const int64_t n = st->n;
-        const double dn = (double)n;
-        const double mu = st->mean;
-        r.n_hit = n;
-        r.n_evals = n_evals;
-        r.n_binned = binned ? (int64_t)*binned : 0;
-        r.n_feed = st->n_row;
-        r.n_pick = st->n_col;
-        r.flags = 0;
-        r.reserved = 0;
-        r.mean = mu;
-        if (n == 0) {
-            r.Sa = r.Sq = r.Sp = r.Sv = r.Sz = r.Ssk = r.Sku = NAN;
-            r.flags |= FSM_FLAG_NO_HIT;
-        } else {
-            r.Sa = s1 / dn;
-            r.Sq = sqrt(s2 / dn);
-            r.Sp = st->mx - mu;
-            r.Sv = mu - st->mn;
-            r.Sz = r.Sp + r.Sv;
-            if (r.Sq > 0.0) {
-                r.Ssk = (s3 / dn) / (r.Sq * r.Sq * r.Sq);
-                r.Sku = (s4 / dn) / (r.Sq * r.Sq * r.Sq * r.Sq);
-            } else {
-                r.Ssk = r.Sku = NAN;
-                r.flags |= FSM_FLAG_SQ_ZERO;
+    using KT = KeyOf<PREC>;
+    using Key = typename KT::T;
+    extern __shared__ unsigned char smem[];
+    Key *lds = reinterpret_cast<Key *>(smem);
+    const FSM_GLOBAL Key *bkey = gptr(static_cast<const Key *>(bb.bkey));
+    const FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
+    const FSM_GLOBAL uint32_t *offsets = gptr(bb.offsets);
+    const int tid = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
+        const DevSim d = sims[si];
+        const TileGeom g = tile_geom(d, t);
+        const int sx = d.sx, TX = 1 << sx, TC = TX << d.sy;
+        FSM_GLOBAL Key *Z = gptr(static_cast<Key *>(d.zmap)) + g.j0 * d.nx + g.i0;
+        for (int l = tid; l < TC; l += kBlock) {
+            const int li = l & (TX - 1), lj = l >> sx;
+            Key v = KT::inf;
+            if (!first_slice && li < g.w && lj < g.h) v = KT::enc(Z[(int64_t)lj * d.nx + li]);
+            lds[l] = v;
+        }
+        __syncthreads();
+        const uint32_t e0 = offsets[t], e1 = offsets[t + 1];
+        for (uint32_t e = e0 + tid; e < e1; e += kBlock)
+            __hip_atomic_fetch_min(&lds[bix[e]], bkey[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (tid == 0 && e1 > e0) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)(e1 - e0));
+        __syncthreads();
+        Stat1Acc acc;
+        const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
+        for (int l = tid; l < TC; l += kBlock) {
+            const int li = l & (TX - 1), lj = l >> sx;
+            if (li < g.w && lj < g.h) {
+                const Key k = KT::enc(lds[l]);
+                Z[(int64_t)lj * d.nx + li] = k;
+                if (last_slice) acc.add(KT::height(k), lj == rj, li == ci);
             }
         }
-        if ((double)n < 0.99 * (double)nx * (double)ny) r.flags |= FSM_FLAG_LOW_COVERAGE;
-        r.Ra_feed = st->n_row ? ra_row / (double)st->n_row : NAN;
-        r.Ra_pick = st->n_col ? ra_col / (double)st->n_col : NAN;
-        *out = r;
-    }
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void decode_only(void *zmap, int64_t n)
-{
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) {
-        if (PREC == FSM_F64) {
-            int64_t *z = static_cast<int64_t *>(zmap);
-            const int64_t v = z[k];
-            if (v < 0) z[k] = enc64(v);
-        } else {
-            int32_t *z = static_cast<int32_t *>(zmap);
-            const int32_t v = z[k];
-            if (v < 0) z[k] = enc32(v);
+        if (last_slice) {
+            const TileStat1 s = acc.reduce();
+            if (tid == 0) st1[t] = s;
         }
+        __syncthreads();
     }
 }
 
-int stream_blocks(int64_t work, int64_t per_block, int cap)
+// ---- tiled roughness ---------------------------------------------------------------------------
+
+// First pass over tiles of finished Z-maps: optional decoding of scatter keys (only negative
+// heights change bits, so only those are written back) and the tile partial sums.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void tile_stats1(const DevSim *__restrict__ sims, int n_sims,
+                                                      const int64_t *__restrict__ tile_base,
+                                                      int64_t n_tiles, int decode, TileStat1 *st1)
 {
-    int64_t b = (work + per_block - 1) / per_block;
-    if (b < 1) b = 1;
-    return (int)(b < cap ? b : cap);
+    using KT = KeyOf<PREC>;
+    using Key = typename KT::T;
+    const int tid = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
+        const DevSim d = sims[si];
+        const TileGeom g = tile_geom(d, t);
+        const int TX = 1 << d.sx, TC = TX << d.sy;
+        FSM_GLOBAL Key *Z = gptr(static_cast<Key *>(d.zmap)) + g.j0 * d.nx + g.i0;
+        const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
+        Stat1Acc acc;
+        for (int l = tid; l < TC; l += kBlock) {
+            const int li = l & (TX - 1), lj = l >> d.sx;
+            if (li < g.w && lj < g.h) {
+                Key k = Z[(int64_t)lj * d.nx + li];
+                if (decode && k < 0) {
+                    k = KT::enc(k);
+                    Z[(int64_t)lj * d.nx + li] = k;
+                }
+                acc.add(KT::height(k), lj == rj, li == ci);
+            }
+        }
+        const TileStat1 s = acc.reduce();
+        if (tid == 0) st1[t] = s;
+    }
+}
+
+// One block per simulation: combine its tiles' first-pass partials in a fixed order.
+__global__ __launch_bounds__(kBlock) void rough_final1(const DevSim *__restrict__ sims,
+                                                       const TileStat1 *__restrict__ st1,
+                                                       RoughState *state)
+{
+    const DevSim d = sims[blockIdx.x];
+    Stat1Acc a;
+    for (int64_t k = threadIdx.x; k < d.n_tiles; k += kBlock) {
+        const TileStat1 s = st1[d.tile_base + k];
+        a.sum += s.sum;
+        a.mn = fmin(a.mn, s.mn);
+        a.mx = fmax(a.mx, s.mx);
+        a.row_sum += s.row_sum;
+        a.col_sum += s.col_sum;
+        a.n += s.n;
+        a.row_n += s.row_n;
+        a.col_n += s.col_n;
+    }
+    const TileStat1 r = a.reduce();
+    if (threadIdx.x == 0) {
+        RoughState st;
+        st.n = r.n;
+        st.mean = r.n ? r.sum / (double)r.n : NAN;
+        st.mn = r.mn;
+        st.mx = r.mx;
+        st.n_row = r.row_n;
+        st.row_mean = r.row_n ? r.row_sum / (double)r.row_n : NAN;
+        st.n_col = r.col_n;
+        st.col_mean = r.col_n ? r.col_sum / (double)r.col_n : NAN;
+        state[d.sim] = st;
+    }
+}
+
+struct Stat2Acc {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, row_abs = 0.0, col_abs = 0.0;
+    __device__ TileStat2 reduce()
+    {
+        __shared__ double bd[4];
+        TileStat2 t;
+        t.s1 = block_sum(s1, bd);
+        t.s2 = block_sum(s2, bd);
+        t.s3 = block_sum(s3, bd);
+        t.s4 = block_sum(s4, bd);
+        t.row_abs = block_sum(row_abs, bd);
+        t.col_abs = block_sum(col_abs, bd);
+        return t;
+    }
+};
+
+// Second pass: central moments about each simulation's mean, and the profile deviations.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__ sims, int n_sims,
+                                                      const int64_t *__restrict__ tile_base,
+                                                      int64_t n_tiles, const RoughState *__restrict__ state,
+                                                      TileStat2 *st2)
+{
+    using KT = KeyOf<PREC>;
+    using Key = typename KT::T;
+    const int tid = threadIdx.x;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
+        const DevSim d = sims[si];
+        const RoughState st = state[d.sim];
+        const TileGeom g = tile_geom(d, t);
+        const int TX = 1 << d.sx, TC = TX << d.sy;
+        const FSM_GLOBAL Key *Z = gptr(static_cast<const Key *>(d.zmap)) + g.j0 * d.nx + g.i0;
+        const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
+        Stat2Acc a;
+        for (int l = tid; l < TC; l += kBlock) {
+            const int li = l & (TX - 1), lj = l >> d.sx;
+            if (li < g.w && lj < g.h) {
+                const double v = KT::height(Z[(int64_t)lj * d.nx + li]);
+                if (v < INFINITY) {
+                    const double dv = v - st.mean;
+                    const double d2 = dv * dv;
+                    a.s1 += fabs(dv);
+                    a.s2 += d2;
+                    a.s3 += d2 * dv;
+                    a.s4 += d2 * d2;
+                    if (lj == rj) a.row_abs += fabs(v - st.row_mean);
+                    if (li == ci) a.col_abs += fabs(v - st.col_mean);
+                }
+            }
+        }
+        const TileStat2 s = a.reduce();
+        if (tid == 0) st2[t] = s;
+    }
+}
+
+// One block per simulation: combine the second-pass partials and write the result record.
+__global__ __launch_bounds__(kBlock) void rough_final2(const DevSim *__restrict__ sims,
+                                                       const TileStat2 *__restrict__ st2,
+                                                       const RoughState *__restrict__ state,
+                                                       const uint64_t *__restrict__ binned,
+                                                       const int64_t *__restrict__ evals,
+                                                       fsm_rough *out)
+{
+    const DevSim d = sims[blockIdx.x];
+    Stat2Acc a;
+    for (int64_t k = threadIdx.x; k < d.n_tiles; k += kBlock) {
+        const TileStat2 s = st2[d.tile_base + k];
+        a.s1 += s.s1;
+        a.s2 += s.s2;
+        a.s3 += s.s3;
+        a.s4 += s.s4;
+        a.row_abs += s.row_abs;
+        a.col_abs += s.col_abs;
+    }
+    const TileStat2 r = a.reduce();
+    if (threadIdx.x == 0) {
+        const RoughState st = state[d.sim];
+        fsm_rough o;
+        const int64_t n = st.n;
+        const double dn = (double)n;
+        o.n_hit = n;
+        o.n_evals = evals ? evals[d.sim] : 0;
+        o.n_binned = binned ? (int64_t)binned[d.sim] : 0;
+        o.n_feed = st.n_row;
+        o.n_pick = st.n_col;
+        o.flags = 0;
+        o.reserved = 0;
+        o.mean = st.mean;
+        if (n == 0) {
+            o.Sa = o.Sq = o.Sp = o.Sv = o.Sz = o.Ssk = o.Sku = NAN;
+            o.flags |= FSM_FLAG_NO_HIT;
+        } else {
+            o.Sa = r.s1 / dn;
+            o.Sq = sqrt(r.s2 / dn);
+            o.Sp = st.mx - st.mean;
+            o.Sv = st.mean - st.mn;
+            o.Sz = o.Sp + o.Sv;
+            if (o.Sq > 0.0) {
+                o.Ssk = (r.s3 / dn) / (o.Sq * o.Sq * o.Sq);
+                o.Sku = (r.s4 / dn) / (o.Sq * o.Sq * o.Sq * o.Sq);
+            } else {
+                o.Ssk = o.Sku = NAN;
+                o.flags |= FSM_FLAG_SQ_ZERO;
+            }
+        }
+        if ((double)n < 0.99 * (double)d.nx * (double)d.ny) o.flags |= FSM_FLAG_LOW_COVERAGE;
+        o.Ra_feed = st.n_row ? r.row_abs / (double)st.n_row : NAN;
+        o.Ra_pick = st.n_col ? r.col_abs / (double)st.n_col : NAN;
+        out[d.sim] = o;
+    }
 }
 
 }  // namespace
+
+// ---- launch wrappers ---------------------------------------------------------------------------
 
 int launch_fill(void *zmap, int64_t n, int precision, void *stream)
 {
@@ -842,12 +971,11 @@ int launch_fill(void *zmap, int64_t n, int precision, void *stream)
     return (int)hipGetLastError();
 }
 
-int launch_scatter(const DevSim *d_sims, const DevSim &, int64_t n_items, int n_sims,
-                   const int64_t *d_item_base, int precision, uint64_t *d_binned, void *stream)
+int launch_scatter(const DevSim *d_sims, int n_sims, const int64_t *d_item_base, int64_t n_items,
+                   int precision, uint64_t *d_binned, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t cap = (int64_t)1 << 20;
-    const int blocks = (int)(n_items < cap ? n_items : cap);
+    const int blocks = (int)(n_items < kMaxGrid ? n_items : kMaxGrid);
     if (blocks <= 0) return 0;
     if (precision == FSM_F64)
         hipLaunchKernelGGL(scatter<FSM_F64>, dim3(blocks), dim3(kBlock), 0, s, d_sims, n_sims, d_item_base, n_items, d_binned);
@@ -856,71 +984,105 @@ int launch_scatter(const DevSim *d_sims, const DevSim &, int64_t n_items, int n_
     return (int)hipGetLastError();
 }
 
-int launch_rough(void *zmap, int64_t nx, int64_t ny, int precision, bool decode,
-                 RoughPart1 *p1, RoughPart2 *p2, RoughState *st, fsm_rough *d_out,
-                 const uint64_t *d_binned, int64_t n_evals, void *stream)
-{
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t n = nx * ny;
-    const int blocks = stream_blocks(n, (int64_t)kBlock * 4, kRoughBlocks);
-    if (precision == FSM_F64) {
-        hipLaunchKernelGGL(rough1<FSM_F64>, dim3(blocks), dim3(kBlock), 0, s, zmap, n, decode, p1);
-        hipLaunchKernelGGL(rough1_final, dim3(1), dim3(kBlock), 0, s, (const void *)zmap, precision, nx, ny, (const RoughPart1 *)p1, blocks, st);
-        hipLaunchKernelGGL(rough2<FSM_F64>, dim3(blocks), dim3(kBlock), 0, s, (const void *)zmap, n, (const RoughState *)st, p2);
-    } else {
-        hipLaunchKernelGGL(rough1<FSM_F32>, dim3(blocks), dim3(kBlock), 0, s, zmap, n, decode, p1);
-        hipLaunchKernelGGL(rough1_final, dim3(1), dim3(kBlock), 0, s, (const void *)zmap, precision, nx, ny, (const RoughPart1 *)p1, blocks, st);
-        hipLaunchKernelGGL(rough2<FSM_F32>, dim3(blocks), dim3(kBlock), 0, s, (const void *)zmap, n, (const RoughState *)st, p2);
-    }
-    hipLaunchKernelGGL(rough2_final, dim3(1), dim3(kBlock), 0, s, (const void *)zmap, precision, nx, ny,
-                       (const RoughPart2 *)p2, blocks, (const RoughState *)st, d_binned, n_evals, d_out);
-    return (int)hipGetLastError();
-}
-
-int launch_decode(void *zmap, int64_t n, int precision, void *stream)
-{
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int blocks = stream_blocks(n, (int64_t)kBlock * 8, 8192);
-    if (precision == FSM_F64)
-        hipLaunchKernelGGL(decode_only<FSM_F64>, dim3(blocks), dim3(kBlock), 0, s, zmap, n);
-    else
-        hipLaunchKernelGGL(decode_only<FSM_F32>, dim3(blocks), dim3(kBlock), 0, s, zmap, n);
-    return (int)hipGetLastError();
-}
-
 int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
                         const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
-                        int64_t n_items, const BinBuffers &bb, bool first_slice,
-                        int precision, uint64_t *d_binned, void *stream)
+                        int64_t n_items, const BinBuffers &bb, bool first_slice, bool last_slice,
+                        int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                        void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int zb = stream_blocks(n_tiles, kBlock, 4096);
     hipLaunchKernelGGL(zero_u32, dim3(zb), dim3(kBlock), 0, s, bb.counts, n_tiles);
-    const int64_t cap_blocks = (int64_t)1 << 20;
-    const int ib = (int)(n_items < cap_blocks ? n_items : cap_blocks);
+    const int ib = (int)(n_items < kMaxGrid ? n_items : kMaxGrid);
     const int nb = (int)((n_tiles + kScanSeg - 1) / kScanSeg);
-    // block sums of the scan live after the cursor array
-    uint32_t *bsum = bb.cursor + n_tiles;
-    const int tb = (int)(n_tiles < cap_blocks ? n_tiles : cap_blocks);
+    const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
+    const size_t lds = (size_t)(precision == FSM_F64 ? 8 : 4) << (sx + sy);
     if (precision == FSM_F64) {
         if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F64, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.counts, bb.bkey, bb.bidx, bb.cap);
-        hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bsum);
-        hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bsum, nb, bb.offsets, n_tiles, d_binned);
-        hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bsum, bb.offsets, bb.cursor);
-        if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F64, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.cursor, bb.bkey, bb.bidx, bb.cap);
-        hipLaunchKernelGGL(tile_reduce<FSM_F64>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, (const uint32_t *)bb.offsets, (const void *)bb.bkey, (const uint16_t *)bb.bidx, first_slice ? 1 : 0);
+            hipLaunchKernelGGL((bin_points<FSM_F64, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
     } else {
         if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F32, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.counts, bb.bkey, bb.bidx, bb.cap);
-        hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bsum);
-        hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bsum, nb, bb.offsets, n_tiles, d_binned);
-        hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bsum, bb.offsets, bb.cursor);
-        if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F32, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb.cursor, bb.bkey, bb.bidx, bb.cap);
-        hipLaunchKernelGGL(tile_reduce<FSM_F32>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, (const uint32_t *)bb.offsets, (const void *)bb.bkey, (const uint16_t *)bb.bidx, first_slice ? 1 : 0);
+            hipLaunchKernelGGL((bin_points<FSM_F32, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
     }
+    hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bb.bsum);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bb.bsum, nb, bb.offsets, n_tiles);
+    hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bb.bsum, bb.offsets, bb.cursor);
+    if (precision == FSM_F64) {
+        if (ib > 0)
+            hipLaunchKernelGGL((bin_points<FSM_F64, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
+        hipLaunchKernelGGL(tile_reduce<FSM_F64>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    } else {
+        if (ib > 0)
+            hipLaunchKernelGGL((bin_points<FSM_F32, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
+        hipLaunchKernelGGL(tile_reduce<FSM_F32>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
+                      const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
+                      int64_t row_end, const BinBuffers &bb, bool first_slice, bool last_slice,
+                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                      void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t nr = row_end - row_begin;
+    const int rb = (int)(nr < kMaxGrid ? nr : kMaxGrid);
+    const size_t hist_lds = sizeof(uint32_t) * (size_t)(bb.max_tiles > 0 ? bb.max_tiles : 1);
+    const int64_t n_chunks = (nr + bb.row_chunk - 1) / bb.row_chunk;
+    const int cb = stream_blocks(n_chunks * n_tiles, kBlock, 16384);
+    const int tb1 = stream_blocks(n_tiles, kBlock, 16384);
+    const int nb = (int)((n_tiles + kScanSeg - 1) / kScanSeg);
+    const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
+    const size_t lds = (size_t)(precision == FSM_F64 ? 8 : 4) << (sx + sy);
+    if (rb > 0) {
+        if (precision == FSM_F64)
+            hipLaunchKernelGGL(hist_count<FSM_F64>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+        else
+            hipLaunchKernelGGL(hist_count<FSM_F32>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+    }
+    if (n_chunks > 0) {
+        hipLaunchKernelGGL(hist_colsum, dim3(cb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, row_begin, row_end, n_chunks, bb);
+        hipLaunchKernelGGL(hist_chunkscan, dim3(tb1), dim3(kBlock), 0, s, n_tiles, n_chunks, bb);
+        hipLaunchKernelGGL(hist_apply, dim3(cb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, row_begin, row_end, n_chunks, bb);
+    } else {
+        hipLaunchKernelGGL(zero_u32, dim3(tb1), dim3(kBlock), 0, s, bb.counts, n_tiles);
+    }
+    hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bb.bsum);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bb.bsum, nb, bb.offsets, n_tiles);
+    hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bb.bsum, bb.offsets, bb.cursor);
+    if (precision == FSM_F64) {
+        if (rb > 0)
+            hipLaunchKernelGGL(hist_write<FSM_F64>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+        hipLaunchKernelGGL(tile_reduce<FSM_F64>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    } else {
+        if (rb > 0)
+            hipLaunchKernelGGL(hist_write<FSM_F32>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+        hipLaunchKernelGGL(tile_reduce<FSM_F32>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    }
+    return (int)hipGetLastError();
+}
+
+
+int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, int64_t n_tiles,
+                 int precision, int, int, bool with_pass1, bool decode, TileStat1 *st1,
+                 TileStat2 *st2, RoughState *state, const uint64_t *d_binned,
+                 const int64_t *d_evals, fsm_rough *d_out, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
+    if (with_pass1) {
+        if (precision == FSM_F64)
+            hipLaunchKernelGGL(tile_stats1<FSM_F64>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, decode ? 1 : 0, st1);
+        else
+            hipLaunchKernelGGL(tile_stats1<FSM_F32>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, decode ? 1 : 0, st1);
+    }
+    hipLaunchKernelGGL(rough_final1, dim3(n_sims), dim3(kBlock), 0, s, d_sims, (const TileStat1 *)st1, state);
+    if (precision == FSM_F64)
+        hipLaunchKernelGGL(tile_stats2<FSM_F64>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, (const RoughState *)state, st2);
+    else
+        hipLaunchKernelGGL(tile_stats2<FSM_F32>, dim3(tb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, (const RoughState *)state, st2);
+    hipLaunchKernelGGL(rough_final2, dim3(n_sims), dim3(kBlock), 0, s, d_sims, (const TileStat2 *)st2, (const RoughState *)state, d_binned, d_evals, d_out);
     return (int)hipGetLastError();
 }
 
