@@ -354,14 +354,26 @@ int or_simulate_window(const or_tool *t, const or_cut *c, const or_grid *g,
     return 0;
 }
 
-int or_ambiguous_cells(const or_tool *t, const or_cut *c, const or_grid *g,
-                       const double *Z, double delta, double tol, unsigned char *mask)
+/* Interval of each cell's minimum when every evaluation's workpiece position (x, y) may move by
+ * up to `delta` along each axis: the cell-assignment rule of Eq. (7) applied to every position
+ * in the square [x - delta, x + delta] x [y - delta, y + delta].  lo: least height of an
+ * evaluation that can reach the cell; hi: least height of one that reaches it wherever it
+ * moves (+inf if none); top: greatest height of one that can reach it (-inf if none).  Any
+ * per-cell minimum over moved positions is +inf or lies in [lo, min(hi, top)], and is finite
+ * whenever hi is.  With delta = 0, lo and hi equal the Z-map. */
+int or_cell_bounds(const or_tool *t, const or_cut *c, const or_grid *g, double delta,
+                   double *lo, double *hi, double *top)
 {
-    if (!Z || !mask || !(delta >= 0.0)) return -1;
+    if (!lo || !hi || !top || !(delta >= 0.0)) return -1;
     chain ch;
     int rc = chain_init(t, c, g, &ch);
     if (rc) return rc;
-    memset(mask, 0, (size_t)(g->nx * g->ny));
+    const long long cells = g->nx * g->ny;
+    for (long long k = 0; k < cells; ++k) {
+        lo[k] = INFINITY;
+        hi[k] = INFINITY;
+        top[k] = -INFINITY;
+    }
     const double x_lo = g->x0 - 0.5 * g->dd, y_lo = g->y0 - 0.5 * g->dd, inv = 1.0 / g->dd;
     const double dr = delta * inv;
     const int Zt = t->n_teeth, N = t->n_edge;
@@ -378,13 +390,15 @@ int or_ambiguous_cells(const or_tool *t, const or_cut *c, const or_grid *g,
                     const double fx = (w[0] - x_lo) * inv, fy = (w[1] - y_lo) * inv;
                     const double ia = floor(fx - dr), ib = floor(fx + dr);
                     const double ja = floor(fy - dr), jb = floor(fy + dr);
-                    if (ia == ib && ja == jb) continue;      /* far from every boundary */
+                    const int sure = ia == ib && ja == jb;
                     for (double fj = ja; fj <= jb; fj += 1.0) {
                         for (double fi = ia; fi <= ib; fi += 1.0) {
                             if (fi < 0.0 || fj < 0.0 || fi >= (double)g->nx || fj >= (double)g->ny)
                                 continue;
                             const long long k = (long long)fj * g->nx + (long long)fi;
-                            if (w[2] <= Z[k] + tol) mask[k] = 1;
+                            if (w[2] < lo[k]) lo[k] = w[2];
+                            if (w[2] > top[k]) top[k] = w[2];
+                            if (sure && w[2] < hi[k]) hi[k] = w[2];
                         }
                     }
                 }

@@ -98,11 +98,12 @@ int or_simulate_window(const or_tool *t, const or_cut *c, const or_grid *g,
                        long long i0, long long i1, long long j0, long long j1,
                        double *Zw, long long *win, or_counts *cnt);
 
-/* Cells whose single-precision result may legitimately differ from the double one: a cell is
- * marked when an evaluation lying within `delta` of a cell boundary could land in it (or leave
- * it) with a height at most `tol` above the cell's double-precision value Z (full grid). */
-int or_ambiguous_cells(const or_tool *t, const or_cut *c, const or_grid *g,
-                       const double *Z, double delta, double tol, unsigned char *mask);
+/* Per-cell interval of the minimum when every evaluation may move by up to `delta` in x and
+ * y (Eq. (7) applied to the whole square of positions): lo = least reachable height, hi = least
+ * height of the evaluations that land in the cell wherever they move (+inf if none), top =
+ * greatest reachable height (-inf if none).  Full grid, nx*ny doubles each. */
+int or_cell_bounds(const or_tool *t, const or_cut *c, const or_grid *g, double delta,
+                   double *lo, double *hi, double *top);
 
 /* Areal and profile roughness of a Z-map (+inf = empty cell). */
 int or_roughness(const double *Z, long long nx, long long ny, or_rough *out);

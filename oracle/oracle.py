@@ -91,8 +91,8 @@ def lib() -> C.CDLL:
             L.or_simulate_window.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_longlong,
                                              C.c_longlong, C.c_longlong, C.c_longlong,
                                              P(C.c_double), P(C.c_longlong), P(OrCounts)]
-            L.or_ambiguous_cells.argtypes = [P(OrTool), P(OrCut), P(OrGrid), P(C.c_double),
-                                             C.c_double, C.c_double, P(C.c_ubyte)]
+            L.or_cell_bounds.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_double,
+                                         P(C.c_double), P(C.c_double), P(C.c_double)]
             L.or_roughness.argtypes = [P(C.c_double), C.c_longlong, C.c_longlong, P(OrRough)]
             L.or_paper_trajectory_points.argtypes = [C.c_double, C.c_double, C.c_int,
                                                      C.c_double, C.c_double, C.c_double]
@@ -187,17 +187,17 @@ def simulate(sim, window=None, winners: bool = False):
     return (Z, counts, W) if winners else (Z, counts)
 
 
-def ambiguous_cells(sim, Z: np.ndarray, delta: float, tol: float) -> np.ndarray:
+def cell_bounds(sim, delta: float):
+    """(lo, hi, top) per cell when every evaluation may move by up to delta in x and y."""
     g = sim.grid
-    Z = np.ascontiguousarray(Z, dtype=np.float64)
-    assert Z.shape == (g.ny, g.nx)
-    mask = np.zeros((g.ny, g.nx), dtype=np.uint8)
-    rc = lib().or_ambiguous_cells(C.byref(_tool(sim.tool)), C.byref(_cut(sim.cut)),
-                                  C.byref(_grid(g)), _dp(Z), delta, tol,
-                                  mask.ctypes.data_as(C.POINTER(C.c_ubyte)))
+    lo = np.empty((g.ny, g.nx))
+    hi = np.empty((g.ny, g.nx))
+    top = np.empty((g.ny, g.nx))
+    rc = lib().or_cell_bounds(C.byref(_tool(sim.tool)), C.byref(_cut(sim.cut)),
+                              C.byref(_grid(g)), float(delta), _dp(lo), _dp(hi), _dp(top))
     if rc:
-        raise ValueError(f"or_ambiguous_cells: invalid parameters ({rc})")
-    return mask.astype(bool)
+        raise ValueError(f"or_cell_bounds: invalid parameters ({rc})")
+    return lo, hi, top
 
 
 def roughness(Z: np.ndarray) -> dict:
@@ -214,5 +214,5 @@ def paper_trajectory_points(v_c: float, f_z: float, z_n: int, D: float, L: float
     return int(lib().or_paper_trajectory_points(v_c, f_z, z_n, D, L, dt))
 
 
-__all__ = ["build", "lib", "edge_points", "plan", "point", "simulate", "ambiguous_cells",
+__all__ = ["build", "lib", "edge_points", "plan", "point", "simulate", "cell_bounds",
            "roughness", "paper_trajectory_points"]

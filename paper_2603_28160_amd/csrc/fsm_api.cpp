@@ -67,6 +67,16 @@ int hip_err(fsm_ctx *ctx, hipError_t e, const char *where)
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Bucket capacity in points: the context's bucket budget over the bytes of one entry (key and
+// cell index), at least one binning item's worst case and at most what 32-bit offsets address.
+int64_t bucket_cap(const fsm_ctx *ctx, int precision, int64_t per_item)
+{
+    const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
+    int64_t cap = ctx->bucket_bytes / (key_bytes + 2);
+    cap = std::max<int64_t>(cap, per_item);
+    return std::min<int64_t>(cap, (int64_t)UINT32_MAX);
+}
+
 // Shape and layout of one launch over a set of simulations.
 struct SetLayout {
     int n = 0, precision = 0, strategy = 0, sx = 7, sy = 6;
@@ -155,7 +165,10 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     if (binned) {
         // histogram mode when every simulation's tile histogram fits in LDS and the row
         // matrix fits its budget
-        L.items_per_row = std::max<int64_t>(1, ceil_div(bitems, kTargetRows));
+        // a row never holds more points than one bucket slice can take
+        const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
+        const int64_t row_items = std::max<int64_t>(1, bucket_cap(ctx, precision, per_item) / per_item);
+        L.items_per_row = std::max<int64_t>(1, std::min(ceil_div(bitems, kTargetRows), row_items));
         int64_t rows = 0, hsize = 0;
         for (DevSim &d : devs) {
             L.max_tiles = std::max(L.max_tiles, d.n_tiles);
@@ -180,10 +193,8 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     if (binned) {
         const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
         const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
-        int64_t cap = ctx->bucket_bytes / (key_bytes + 2);
+        int64_t cap = bucket_cap(ctx, precision, per_item);
         cap = std::min<int64_t>(cap, std::max<int64_t>(per_item, bitems * per_item));
-        cap = std::max<int64_t>(cap, per_item);
-        cap = std::min<int64_t>(cap, (int64_t)UINT32_MAX);
         L.per_slice = std::max<int64_t>(1, cap / per_item);
         L.per_slice = std::min<int64_t>(L.per_slice, std::max<int64_t>(1, bitems));
         L.cap = cap;

@@ -24,7 +24,9 @@
 // Double precision: only +, -, * run on the device (no contraction: -ffp-contract=off), in
 // the order the host planner documents, so binning decisions equal those of the plain
 // definition bit for bit.  Single precision: rotation and tilt in float with explicit fused
-// multiply-adds; the tool-centre offset and the binning stay in double.
+// multiply-adds on tool-local coordinates; the tool-centre position is formed in double and
+// split into an integer cell plus a fraction once per step, and each point bins from its
+// float offset.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -235,6 +237,81 @@ __device__ __forceinline__ bool bin_cell(const DevSim &d, double xcs, double yq,
     return false;
 }
 
+// Single precision: the tool centre's cell coordinates are formed in double precision once per
+// step and split into an integer cell and a fraction; every point then bins from its float
+// tool-local offset with one fused multiply-add per axis.
+struct Centre32 {
+    int32_t ix, iy;
+    float fx, fy;
+    bool near;               // false: the centre is too far from the grid for any point to land
+};
+__device__ __forceinline__ Centre32 centre32(const DevSim &d, double xcs, double yq)
+{
+    Centre32 c;
+    const double gx = (xcs - d.x_lo) * d.inv_dd, gy = (yq - d.y_lo) * d.inv_dd;
+    c.near = gx > -1073741824.0 && gx < 1073741824.0 && gy > -1073741824.0 && gy < 1073741824.0;
+    const double fx = floor(gx), fy = floor(gy);
+    c.ix = c.near ? (int32_t)fx : 0;
+    c.iy = c.near ? (int32_t)fy : 0;
+    c.fx = (float)(gx - fx);
+    c.fy = (float)(gy - fy);
+    return c;
+}
+__device__ __forceinline__ bool bin_cell32(const DevSim &d, const Centre32 &c, float xs, float ys,
+                                           int32_t &i, int32_t &j)
+{
+    const float inv = (float)d.inv_dd;
+    i = c.ix + __float2int_rd(fmaf(xs, inv, c.fx));
+    j = c.iy + __float2int_rd(fmaf(ys, inv, c.fy));
+    return c.near && (uint32_t)i < (uint32_t)d.nx && (uint32_t)j < (uint32_t)d.ny;
+}
+
+// Single-precision kinematics of one point: float offsets from the tool centre and the key.
+__device__ __forceinline__ void turn_point32(const DevSim &d, float caf, float saf, int K, int p,
+                                             float &xs, float &ys, int32_t &key)
+{
+    const FSM_GLOBAL float *pt = gptr(d.pTf + ((size_t)K * d.N + p) * 4);
+    const float px = pt[0], py = pt[1], pz = pt[2];
+    float x = fmaf(caf, px, saf * py);
+    float y = fmaf(caf, py, -(saf * px));
+    float z = pz;
+    if (d.tilt_lead) {
+        const float c = (float)d.tl_c, s = (float)d.tl_s;
+        const float x1 = fmaf(c, x, s * z);
+        z = fmaf(c, z, -(s * x));
+        x = x1;
+    }
+    if (d.tilt_side) {
+        const float c = (float)d.ts_c, s = (float)d.ts_s;
+        const float y1 = fmaf(c, y, -(s * z));
+        z = fmaf(s, y, c * z);
+        y = y1;
+    }
+    xs = x;
+    ys = y;
+    key = enc32(__float_as_int(z));
+}
+
+// One point of either precision: its cell (i, j) and key; false outside the grid.
+template <int PREC>
+__device__ __forceinline__ bool place_point(const DevSim &d, double ca, double sa, float caf,
+                                            float saf, double xcs, double yq, const Centre32 &c32,
+                                            int K, int p, int32_t &i, int32_t &j,
+                                            typename KeyOf<PREC>::T &key)
+{
+    if (PREC == FSM_F64) {
+        double xs, ys;
+        turn_point<PREC>(d, ca, sa, caf, saf, K, p, xs, ys, key);
+        return bin_cell(d, xcs, yq, xs, ys, i, j);
+    } else {
+        float xs, ys;
+        int32_t k32;
+        turn_point32(d, caf, saf, K, p, xs, ys, k32);
+        key = (typename KeyOf<PREC>::T)k32;
+        return bin_cell32(d, c32, xs, ys, i, j);
+    }
+}
+
 // ---- scatter strategy ------------------------------------------------------------------------
 
 template <int PREC>
@@ -278,11 +355,12 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
                         caf = cs[0];
                         saf = cs[1];
                     }
-                    double xs, ys;
+                    const double xcs = gptr(d.xc)[s];
+                    Centre32 c32 = {};
+                    if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
                     Key key;
-                    turn_point<PREC>(d, ca, sa, caf, saf, K, p, xs, ys, key);
                     int32_t i, j;
-                    if (bin_cell(d, gptr(d.xc)[s], yq, xs, ys, i, j)) {
+                    if (place_point<PREC>(d, ca, sa, caf, saf, xcs, yq, c32, K, p, i, j, key)) {
                         const int64_t idx = (int64_t)j * d.nx + i;
                         if (key < __hip_atomic_load(zk + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                             __hip_atomic_fetch_min(zk + idx, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -368,6 +446,8 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
             xcs = gptr(d.xc)[s];
         }
         const double yq = d.y_first + (double)q * d.a_e;
+        Centre32 c32 = {};
+        if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
         const int sx = d.sx, sy = d.sy;
         const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
         for (int p0 = 0; p0 < d.N; p0 += kUnroll) {
@@ -380,10 +460,8 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
                 cell[u] = 0;
                 key[u] = 0;
                 if (vs && p0 + u < d.N) {
-                    double xs, ys;
-                    turn_point<PREC>(d, ca, sa, caf, saf, K, p0 + u, xs, ys, key[u]);
                     int32_t i, j;
-                    if (bin_cell(d, xcs, yq, xs, ys, i, j)) {
+                    if (place_point<PREC>(d, ca, sa, caf, saf, xcs, yq, c32, K, p0 + u, i, j, key[u])) {
                         tile[u] = (int32_t)d.tile_base + (j >> sy) * d.tiles_x + (i >> sx);
                         cell[u] = (uint16_t)(((j & my) << sx) | (i & mx));
                     }
@@ -427,7 +505,8 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
 // recomputes the points, claiming slots with LDS atomics on the row's cursors.
 
 // Visit every in-grid point of binning items [i0, i1) of simulation d: f(tile, cell, key) with
-// the tile numbered inside the simulation.
+// the tile numbered inside the simulation.  Lanes hold consecutive time steps; the edge points
+// are walked one at a time (the compiler overlaps consecutive iterations).
 template <int PREC, typename F>
 __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t i1, F &&f)
 {
@@ -457,12 +536,12 @@ __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t 
         }
         const double xcs = gptr(d.xc)[s];
         const double yq = d.y_first + (double)q * d.a_e;
+        Centre32 c32 = {};
+        if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
         for (int p = 0; p < d.N; ++p) {
-            double xs, ys;
             Key key;
-            turn_point<PREC>(d, ca, sa, caf, saf, K, p, xs, ys, key);
             int32_t i, j;
-            if (bin_cell(d, xcs, yq, xs, ys, i, j))
+            if (place_point<PREC>(d, ca, sa, caf, saf, xcs, yq, c32, K, p, i, j, key))
                 f((j >> sy) * d.tiles_x + (i >> sx), (uint16_t)(((j & my) << sx) | (i & mx)), key);
         }
     }
@@ -751,8 +830,25 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
             lds[l] = v;
         }
         __syncthreads();
-        const uint32_t e0 = offsets[t], e1 = offsets[t + 1];
-        for (uint32_t e = e0 + tid; e < e1; e += kBlock)
+        // entries past the capacity were never written (the planner sizes slices so that none
+        // are dropped); the clamp keeps the reads inside the bucket arrays regardless
+        const int64_t cap = bb.cap;
+        const uint32_t e0 = (int64_t)offsets[t] < cap ? offsets[t] : (uint32_t)cap;
+        const uint32_t e1 = (int64_t)offsets[t + 1] < cap ? offsets[t + 1] : (uint32_t)cap;
+        uint32_t e = e0 + tid;
+        for (; e + 3 * kBlock < e1; e += 4 * kBlock) {
+            Key k4[4];
+            uint16_t c4[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                k4[v] = bkey[e + v * kBlock];
+                c4[v] = bix[e + v * kBlock];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                __hip_atomic_fetch_min(&lds[c4[v]], k4[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        for (; e < e1; e += kBlock)
             __hip_atomic_fetch_min(&lds[bix[e]], bkey[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (tid == 0 && e1 > e0) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)(e1 - e0));
         __syncthreads();

@@ -148,6 +148,7 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     const double x_hi = x_lo + (double)g.nx * g.dd, y_hi = y_lo + (double)g.ny * g.dd;
     const double fpr = (double)Z * c.f_z;
     P.r_reach = reach;
+    if (!(reach / g.dd < 536870912.0)) { err = "tool reach spans more than 2^29 cells"; return FSM_EINVAL; }
     P.x_start = std::isnan(c.x_start) ? x_lo - reach : c.x_start;
     if (c.n_steps > 0) {
         P.n_steps = c.n_steps;
