@@ -3,10 +3,11 @@ per-cell minimum, roughness) on the 5000 x 5000 ball-end raster workload, one MI
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-A step is one fsm_simulate call: plan tables to the device, Z-map fill, scatter kernel,
-two roughness passes and the result back on the host; the Z-map stays resident in HBM.
-Prints one JSON line.  The dominant kernel's duration comes from HIP events the library
-records on the stream it launches on.
+A step is one fsm_simulate call: plan tables to the device, the binned Z-map (count, scan,
+write, per-tile reduction), the roughness passes and the result back on the host; the Z-map
+stays resident in HBM.  Prints one JSON line.  The value comes from unprofiled steps; a second
+set of steps with the library's HIP events on (recorded on the stream it launches on) gives
+the per-stage kernel times and the roofline of the longest stage.
 """
 from __future__ import annotations
 
@@ -22,9 +23,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Z-map cells/s and simulations/s (p50/p99 latency), FP32 batched vs FP64 plain"
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP64_PEAK_TFLOPS = 78.6        # MI355X vector FP64
-BYTES_PER_UPDATE = {"f64": 8, "f32": 4}   # one encoded-height compare/min-update per binned point
+HBM_PEAK_GBS = 8000.0                          # MI355X HBM3E, GB/s
+VALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}  # MI355X vector FP64 / FP32
+KEY_BYTES = {"f64": 8, "f32": 4}
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_28160_amd", "csrc", "fsm_kernels.hip")
+STAGE_KERNEL = {"count": "hist_count", "write": "hist_write", "reduce": "tile_reduce"}
 
 
 def pct(xs, q):
@@ -35,29 +39,95 @@ def pct(xs, q):
     return xs[k]
 
 
-def run_precision(ctx, sim, prec, steps, warmup):
+def flop_per_eval(tool):
+    """Algorithmic floating-point operations of one edge-point evaluation: the spindle rotation
+    (4 mul + 2 add), the tilt rotations (lead or side alone: 4 mul + 2 add; both: a 3x3 product,
+    9 mul + 6 add), the tool-centre offset (2 add) and the cell index (2 sub + 2 mul + 2 floor).
+    Compares and integer index arithmetic are not counted."""
+    lead, side = tool.tilt_lead != 0.0, tool.tilt_side != 0.0
+    tilt = 15 if (lead and side) else (6 if (lead or side) else 0)
+    return 6 + tilt + 2 + 6
+
+
+def stored_traffic(kernel, prec):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
+    summary is missing or was taken on a different kernel source."""
+    import hashlib
+    import re
+    path = os.path.join(PROFILES, f"{kernel}_{prec}_ball_r3_5000x5000_pmc.md")
+    try:
+        text = open(path).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_source_sha256") != src:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_precision(ctx, sim, prec, steps, warmup, profile):
     import torch
     zmap = ctx.new_zmap(sim.grid, prec)
-    ctx.fsm_ctx_set_profiling(True)
+    ctx.fsm_ctx_set_profiling(profile)
     for _ in range(warmup):
         ctx.fsm_simulate(sim, prec, zmap)
     torch.cuda.synchronize()
-    lat, scat, rough_ms, fill_ms = [], [], [], []
+    lat, tim = [], []
     t0 = time.perf_counter()
     r = None
     for _ in range(steps):
         a = time.perf_counter()
         _, r = ctx.fsm_simulate(sim, prec, zmap)
         lat.append((time.perf_counter() - a) * 1e3)
-        t = ctx.fsm_last_timings()
-        scat.append(t["scatter_ms"])
-        rough_ms.append(t["rough_ms"])
-        fill_ms.append(t["fill_ms"])
+        if profile:
+            tim.append(ctx.fsm_last_timings())
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    return {"elapsed_s": el, "ms_per_step": el / steps * 1e3, "lat": lat,
-            "scatter_ms": statistics.mean(scat), "rough_ms": statistics.mean(rough_ms),
-            "fill_ms": statistics.mean(fill_ms), "rough": r}
+    ctx.fsm_ctx_set_profiling(False)
+    out = {"elapsed_s": el, "ms_per_step": el / steps * 1e3, "lat": lat, "rough": r}
+    if profile:
+        for k in ("fill_ms", "scatter_ms", "rough_ms", "count_ms", "index_ms", "write_ms",
+                  "reduce_ms"):
+            out[k] = statistics.mean(t[k] for t in tim)
+        out["n_slices"] = tim[-1]["n_slices"]
+    return out
+
+
+def roofline(sim, plan, prec, prof):
+    """Roofline of the longest stage of the Z-map, timed with HIP events on the stream the
+    library launches on (mean over the profiled steps, per launch)."""
+    stages = {k: prof[f"{k}_ms"] for k in ("count", "write", "reduce")}
+    stage = max(stages, key=stages.get)
+    n_launch = max(1, prof["n_slices"])
+    ms = stages[stage] / n_launch
+    kernel = STAGE_KERNEL[stage]
+    if ms <= 0.0:
+        # scatter strategy: one kernel does kinematics, binning and the minimum
+        stage, kernel, n_launch, ms = "count", "scatter", 1, prof["scatter_ms"]
+    r = prof["rough"]
+    if stage in ("count", "write"):
+        fpe = flop_per_eval(sim.tool)
+        work = fpe * plan["n_evals"] / n_launch
+        achieved = work / (ms * 1e-3) / 1e12
+        peak = VALU_PEAK_TFLOPS[prec]
+        out = {"bound": "alu", "unit": "TFLOP/s", "flop_per_eval": fpe,
+               "evals_per_launch": plan["n_evals"] // n_launch}
+    else:
+        # bucket entries read (key + 16-bit cell), Z-map read-free first slice, Z-map written
+        work = (r["n_binned"] * (KEY_BYTES[prec] + 2) + sim.grid.nx * sim.grid.ny * KEY_BYTES[prec]) / n_launch
+        achieved = work / (ms * 1e-3) / 1e9
+        peak = HBM_PEAK_GBS
+        out = {"bound": "hbm", "unit": "GB/s", "bytes_per_launch": work}
+    traffic = stored_traffic(kernel, prec)
+    out.update({"kernel": f"{kernel}<{prec}>", "achieved": achieved, "peak": peak,
+                "frac": achieved / peak, "traffic": traffic, "launch_ms": ms,
+                "launches_per_step": n_launch, "stage_ms": stages,
+                "index_ms": prof["index_ms"]})
+    return out
 
 
 def main():
@@ -102,23 +172,30 @@ def main():
             alt = "scatter" if args.strategy == "binned" else "binned"
             ctx.set_strategy(alt)
             for prec in precs:
-                o = run_precision(ctx, sim, prec, args.steps, args.warmup)
+                o = run_precision(ctx, sim, prec, args.steps, args.warmup, profile=True)
                 other[prec] = {"ms_per_step": o["ms_per_step"], "zmap_ms": o["scatter_ms"]}
                 print(f"[bench] {alt} {prec}: {o['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         ctx.set_strategy(args.strategy)
         for prec in precs:
             print(f"[bench] {sim.name} {prec}: warmup {args.warmup}, steps {args.steps}",
                   file=sys.stderr, flush=True)
-            res[prec] = run_precision(ctx, sim, prec, args.steps, args.warmup)
-            print(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, scatter "
-                  f"{res[prec]['scatter_ms']:.3f} ms", file=sys.stderr, flush=True)
+            res[prec] = run_precision(ctx, sim, prec, args.steps, args.warmup, profile=False)
+            res[prec]["prof"] = run_precision(ctx, sim, prec, args.steps, 1, profile=True)
+            p = res[prec]["prof"]
+            print(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step; z-map {p['scatter_ms']:.3f} ms "
+                  f"(count {p['count_ms']:.3f}, index {p['index_ms']:.3f}, write {p['write_ms']:.3f}, "
+                  f"reduce {p['reduce_ms']:.3f}), roughness {p['rough_ms']:.3f} ms",
+                  file=sys.stderr, flush=True)
 
     main_prec = "f64" if "f64" in res else precs[0]
     m = res[main_prec]
     r = m["rough"]
-    n_binned = r["n_binned"]
-    upd_bytes = n_binned * BYTES_PER_UPDATE[main_prec]
-    achieved = upd_bytes / (m["scatter_ms"] * 1e-3) / 1e9
+
+    def kernel_ms(p):
+        return {"fill": p["fill_ms"], "zmap": p["scatter_ms"], "zmap_count": p["count_ms"],
+                "zmap_index": p["index_ms"], "zmap_write": p["write_ms"],
+                "zmap_reduce": p["reduce_ms"], "roughness": p["rough_ms"]}
+
     out = {
         "metric": METRIC,
         "value": n_cells * args.steps / m["elapsed_s"],
@@ -141,12 +218,10 @@ def main():
         "sims_per_s": args.steps / m["elapsed_s"],
         "latency_ms": {"p50": pct(m["lat"], 50), "p99": pct(m["lat"], 99)},
         "evals_per_s": plan["n_evals"] * args.steps / m["elapsed_s"],
+        "binned_per_s": r["n_binned"] * args.steps / m["elapsed_s"],
         "coverage": r["n_hit"] / n_cells,
-        "kernel_ms": {"fill": m["fill_ms"], "zmap": m["scatter_ms"], "roughness": m["rough_ms"]},
-        "roofline": {"bound": "hbm", "kernel": "scatter", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
-                     "algorithmic_bytes": upd_bytes, "n_binned": n_binned},
+        "kernel_ms": kernel_ms(m["prof"]),
+        "roofline": roofline(sim, plan, main_prec, m["prof"]),
     }
     for prec in res:
         if prec == main_prec:
@@ -155,8 +230,8 @@ def main():
         out[prec] = {"value": n_cells * args.steps / o["elapsed_s"], "unit": "cells/s",
                      "ms_per_step": o["ms_per_step"],
                      "latency_ms": {"p50": pct(o["lat"], 50), "p99": pct(o["lat"], 99)},
-                     "kernel_ms": {"fill": o["fill_ms"], "zmap": o["scatter_ms"],
-                                   "roughness": o["rough_ms"]},
+                     "kernel_ms": kernel_ms(o["prof"]),
+                     "roofline": roofline(sim, plan, prec, o["prof"]),
                      "Sa": o["rough"]["Sa"], "Sa_f64": r["Sa"]}
     if other:
         out["other_strategy"] = other

@@ -140,6 +140,12 @@ typedef struct fsm_timings {
     float scatter_ms;        /* kinematics + binning + per-cell minimum (all slices) */
     float rough_ms;          /* roughness passes (or the decode pass) */
     float total_ms;          /* first event to last event */
+    /* stages of the binned Z-map, summed over its slices (0 for the scatter strategy) */
+    float count_ms;          /* kinematics + binning, points counted per tile */
+    float index_ms;          /* scans of the counts into bucket offsets */
+    float write_ms;          /* kinematics + binning again, points written to their buckets */
+    float reduce_ms;         /* per-tile minimum in LDS (+ first roughness pass) */
+    int32_t n_slices;        /* slices of the binned Z-map */
     int32_t valid;           /* 1 once a profiled call has completed */
 } fsm_timings;
 

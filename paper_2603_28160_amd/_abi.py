@@ -68,7 +68,9 @@ class FsmRough(C.Structure):
 
 class FsmTimings(C.Structure):
     _fields_ = [("upload_ms", C.c_float), ("fill_ms", C.c_float), ("scatter_ms", C.c_float),
-                ("rough_ms", C.c_float), ("total_ms", C.c_float), ("valid", C.c_int32)]
+                ("rough_ms", C.c_float), ("total_ms", C.c_float), ("count_ms", C.c_float),
+                ("index_ms", C.c_float), ("write_ms", C.c_float), ("reduce_ms", C.c_float),
+                ("n_slices", C.c_int32), ("valid", C.c_int32)]
 
 
 class FsmJob(C.Structure):

@@ -31,6 +31,8 @@ struct fsm_ctx {
     size_t h_out_n = 0;
     bool profiling = false;
     hipEvent_t ev[5] = {};       // upload, fill, z-map, roughness, end
+    std::vector<fsm::StageEvents> stage_ev;   // per binned slice: the five stage events
+    int stages_used = 0;                      // slices of the last profiled call
     fsm_timings timings = {};
     int strategy = fsm::kStrategyBinned;
     int64_t bucket_bytes = (int64_t)4 << 30;
@@ -313,6 +315,23 @@ void mark(fsm_ctx *ctx, int k, hipStream_t s, bool capturing)
     if (ctx->profiling && !capturing) hipEventRecord(ctx->ev[k], s);
 }
 
+// Stage events of binned slice k of a profiled eager call (nullptr otherwise).
+const fsm::StageEvents *stage_marks(fsm_ctx *ctx, size_t k, bool capturing)
+{
+    if (!ctx->profiling || capturing) return nullptr;
+    while (ctx->stage_ev.size() <= k) {
+        fsm::StageEvents m = {};
+        for (void *&e : m.ev) {
+            hipEvent_t h = nullptr;
+            if (hipEventCreate(&h) != hipSuccess) return nullptr;
+            e = h;
+        }
+        ctx->stage_ev.push_back(m);
+    }
+    ctx->stages_used = (int)k + 1;
+    return &ctx->stage_ev[k];
+}
+
 // Read the events of a finished call into ctx->timings (phases that did not run read 0).
 void collect(fsm_ctx *ctx, bool phases)
 {
@@ -325,6 +344,19 @@ void collect(fsm_ctx *ctx, bool phases)
     ctx->timings.fill_ms = t[1];
     ctx->timings.scatter_ms = t[2];
     ctx->timings.rough_ms = t[3];
+    float st[4] = {0, 0, 0, 0};
+    for (int k = 0; phases && k < ctx->stages_used; ++k)
+        for (int j = 0; j < 4; ++j) {
+            float v = 0.0f;
+            if (hipEventElapsedTime(&v, static_cast<hipEvent_t>(ctx->stage_ev[k].ev[j]),
+                                    static_cast<hipEvent_t>(ctx->stage_ev[k].ev[j + 1])) == hipSuccess)
+                st[j] += v;
+        }
+    ctx->timings.count_ms = st[0];
+    ctx->timings.index_ms = st[1];
+    ctx->timings.write_ms = st[2];
+    ctx->timings.reduce_ms = st[3];
+    ctx->timings.n_slices = phases ? ctx->stages_used : 0;
     float tot = 0.0f;
     if (hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[4]) != hipSuccess) tot = 0.0f;
     ctx->timings.total_ms = tot;
@@ -368,6 +400,8 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
         bb.chunk = L.hist ? reinterpret_cast<uint32_t *>(dev + L.chunk) : nullptr;
         bb.max_tiles = (int32_t)L.max_tiles;
         bb.row_chunk = kRowChunk;
+        ctx->stages_used = 0;
+        size_t slice = 0;
         if (L.hist) {
             // d_bbase holds each simulation's first row in this mode
             int64_t r0 = 0;
@@ -375,21 +409,22 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
                 const int64_t r1 = std::min<int64_t>(L.total_rows, r0 + L.rows_per_slice);
                 he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, r0, r1, bb,
                                             r0 == 0, r1 >= L.total_rows, L.precision, L.sx, L.sy,
-                                            st1, d_binned, s);
+                                            st1, d_binned, s, stage_marks(ctx, slice++, capturing));
                 if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
                 r0 = r1;
             } while (r0 < L.total_rows);
         } else if (L.total_items == 0) {
             // nothing to bin: the maps are still initialised and the first pass still runs
             he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, 0, 0, bb,
-                                          true, true, L.precision, L.sx, L.sy, st1, d_binned, s);
+                                          true, true, L.precision, L.sx, L.sy, st1, d_binned, s,
+                                          stage_marks(ctx, slice++, capturing));
             if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
         }
         for (int64_t b0 = 0; !L.hist && b0 < L.total_items; b0 += L.per_slice) {
             const int64_t nit = std::min<int64_t>(L.per_slice, L.total_items - b0);
             he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, b0, nit, bb,
                                           b0 == 0, b0 + nit >= L.total_items, L.precision, L.sx,
-                                          L.sy, st1, d_binned, s);
+                                          L.sy, st1, d_binned, s, stage_marks(ctx, slice++, capturing));
             if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
         }
     } else {
@@ -433,6 +468,7 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
         s = ctx->own;
     }
     ctx->timings.valid = 0;
+    ctx->stages_used = 0;
     mark(ctx, 0, s, false);
     e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
@@ -573,6 +609,9 @@ void fsm_ctx_destroy(fsm_ctx *ctx)
     for (auto &g : ctx->graph_cache) hipGraphExecDestroy(g.second);
     for (auto &ev : ctx->ev)
         if (ev) hipEventDestroy(ev);
+    for (auto &m : ctx->stage_ev)
+        for (void *e : m.ev)
+            if (e) hipEventDestroy(static_cast<hipEvent_t>(e));
     if (ctx->join) hipEventDestroy(ctx->join);
     if (ctx->own) hipStreamDestroy(ctx->own);
     if (ctx->d_ws) hipFree(ctx->d_ws);
@@ -702,6 +741,7 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
         fill_image(L, plans, devs, zmaps, dev, host);
         hipStream_t s = static_cast<hipStream_t>(stream);
         ctx->timings.valid = 0;
+        ctx->stages_used = 0;
         mark(ctx, 0, s, false);
         e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");

@@ -116,6 +116,12 @@ struct BinBuffers {
     int32_t row_chunk;       // rows per column-scan chunk
 };
 
+// Optional stage events of one binned slice (hipEvent_t handles, recorded on the launch
+// stream): before counting, after counting, after the scans, after writing, after reducing.
+struct StageEvents {
+    void *ev[5];
+};
+
 // Launch wrappers (fsm_kernels.hip).  All return a hipError_t as int.  `sims`/`d_*base`
 // describe n_sims simulations whose items and tiles are numbered consecutively.
 int launch_fill(void *zmap, int64_t n, int precision, void *stream);
@@ -127,7 +133,7 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
                         const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
                         int64_t n_items, const BinBuffers &bb, bool first_slice,
                         bool last_slice, int precision, int sx, int sy, TileStat1 *st1,
-                        uint64_t *d_binned, void *stream);
+                        uint64_t *d_binned, void *stream, const StageEvents *marks = nullptr);
 // Histogram mode of the binned strategy, one slice of rows [row_begin, row_end): per-block
 // LDS histograms written as rows, a chunked column scan into per-(row, tile) offsets, a write
 // pass that claims slots with LDS atomics only, then the per-tile LDS reduction.
@@ -135,7 +141,7 @@ int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_bas
                       const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
                       int64_t row_end, const BinBuffers &bb, bool first_slice, bool last_slice,
                       int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                      void *stream);
+                      void *stream, const StageEvents *marks = nullptr);
 // Tiled roughness.  with_pass1: run the first pass (decoding scatter keys if `decode`);
 // otherwise its tile partials are already in st1.  out: one record per simulation.
 int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, int64_t n_tiles,

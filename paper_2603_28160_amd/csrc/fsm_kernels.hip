@@ -1080,63 +1080,63 @@ int launch_scatter(const DevSim *d_sims, int n_sims, const int64_t *d_item_base,
     return (int)hipGetLastError();
 }
 
-int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
-                        const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
-                        int64_t n_items, const BinBuffers &bb, bool first_slice, bool last_slice,
-                        int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                        void *stream)
+namespace {
+
+void stage(const StageEvents *marks, int k, hipStream_t s)
 {
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int zb = stream_blocks(n_tiles, kBlock, 4096);
-    hipLaunchKernelGGL(zero_u32, dim3(zb), dim3(kBlock), 0, s, bb.counts, n_tiles);
-    const int ib = (int)(n_items < kMaxGrid ? n_items : kMaxGrid);
+    if (marks) hipEventRecord(static_cast<hipEvent_t>(marks->ev[k]), s);
+}
+
+// Exclusive scan of counts[0, n) into offsets and cursors.
+void launch_scan(int64_t n_tiles, const BinBuffers &bb, hipStream_t s)
+{
     const int nb = (int)((n_tiles + kScanSeg - 1) / kScanSeg);
-    const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
-    const size_t lds = (size_t)(precision == FSM_F64 ? 8 : 4) << (sx + sy);
-    if (precision == FSM_F64) {
-        if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F64, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
-    } else {
-        if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F32, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
-    }
     hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bb.bsum);
     hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bb.bsum, nb, bb.offsets, n_tiles);
     hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bb.bsum, bb.offsets, bb.cursor);
-    if (precision == FSM_F64) {
-        if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F64, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
-        hipLaunchKernelGGL(tile_reduce<FSM_F64>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
-    } else {
-        if (ib > 0)
-            hipLaunchKernelGGL((bin_points<FSM_F32, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
-        hipLaunchKernelGGL(tile_reduce<FSM_F32>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
-    }
-    return (int)hipGetLastError();
 }
 
-int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
-                      const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
-                      int64_t row_end, const BinBuffers &bb, bool first_slice, bool last_slice,
-                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                      void *stream)
+template <int PREC>
+void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
+                  const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin, int64_t n_items,
+                  const BinBuffers &bb, bool first_slice, bool last_slice, int sx, int sy,
+                  TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
 {
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int ib = (int)(n_items < kMaxGrid ? n_items : kMaxGrid);
+    const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
+    const size_t lds = sizeof(typename KeyOf<PREC>::T) << (sx + sy);
+    stage(marks, 0, s);
+    hipLaunchKernelGGL(zero_u32, dim3(stream_blocks(n_tiles, kBlock, 4096)), dim3(kBlock), 0, s, bb.counts, n_tiles);
+    if (ib > 0)
+        hipLaunchKernelGGL((bin_points<PREC, false>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
+    stage(marks, 1, s);
+    launch_scan(n_tiles, bb, s);
+    stage(marks, 2, s);
+    if (ib > 0)
+        hipLaunchKernelGGL((bin_points<PREC, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
+    stage(marks, 3, s);
+    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    stage(marks, 4, s);
+}
+
+template <int PREC>
+void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
+                const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin, int64_t row_end,
+                const BinBuffers &bb, bool first_slice, bool last_slice, int sx, int sy,
+                TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
+{
     const int64_t nr = row_end - row_begin;
     const int rb = (int)(nr < kMaxGrid ? nr : kMaxGrid);
     const size_t hist_lds = sizeof(uint32_t) * (size_t)(bb.max_tiles > 0 ? bb.max_tiles : 1);
     const int64_t n_chunks = (nr + bb.row_chunk - 1) / bb.row_chunk;
     const int cb = stream_blocks(n_chunks * n_tiles, kBlock, 16384);
     const int tb1 = stream_blocks(n_tiles, kBlock, 16384);
-    const int nb = (int)((n_tiles + kScanSeg - 1) / kScanSeg);
     const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
-    const size_t lds = (size_t)(precision == FSM_F64 ? 8 : 4) << (sx + sy);
-    if (rb > 0) {
-        if (precision == FSM_F64)
-            hipLaunchKernelGGL(hist_count<FSM_F64>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
-        else
-            hipLaunchKernelGGL(hist_count<FSM_F32>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
-    }
+    const size_t lds = sizeof(typename KeyOf<PREC>::T) << (sx + sy);
+    stage(marks, 0, s);
+    if (rb > 0)
+        hipLaunchKernelGGL(hist_count<PREC>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+    stage(marks, 1, s);
     if (n_chunks > 0) {
         hipLaunchKernelGGL(hist_colsum, dim3(cb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, row_begin, row_end, n_chunks, bb);
         hipLaunchKernelGGL(hist_chunkscan, dim3(tb1), dim3(kBlock), 0, s, n_tiles, n_chunks, bb);
@@ -1144,18 +1144,42 @@ int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_bas
     } else {
         hipLaunchKernelGGL(zero_u32, dim3(tb1), dim3(kBlock), 0, s, bb.counts, n_tiles);
     }
-    hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bb.bsum);
-    hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bb.bsum, nb, bb.offsets, n_tiles);
-    hipLaunchKernelGGL(scan_apply, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, (const uint32_t *)bb.bsum, bb.offsets, bb.cursor);
-    if (precision == FSM_F64) {
-        if (rb > 0)
-            hipLaunchKernelGGL(hist_write<FSM_F64>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
-        hipLaunchKernelGGL(tile_reduce<FSM_F64>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
-    } else {
-        if (rb > 0)
-            hipLaunchKernelGGL(hist_write<FSM_F32>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
-        hipLaunchKernelGGL(tile_reduce<FSM_F32>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
-    }
+    launch_scan(n_tiles, bb, s);
+    stage(marks, 2, s);
+    if (rb > 0)
+        hipLaunchKernelGGL(hist_write<PREC>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+    stage(marks, 3, s);
+    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    stage(marks, 4, s);
+}
+
+}  // namespace
+
+int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
+                        const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
+                        int64_t n_items, const BinBuffers &bb, bool first_slice, bool last_slice,
+                        int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                        void *stream, const StageEvents *marks)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == FSM_F64)
+        binned_slice<FSM_F64>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+    else
+        binned_slice<FSM_F32>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+    return (int)hipGetLastError();
+}
+
+int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
+                      const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
+                      int64_t row_end, const BinBuffers &bb, bool first_slice, bool last_slice,
+                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                      void *stream, const StageEvents *marks)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == FSM_F64)
+        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+    else
+        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
     return (int)hipGetLastError();
 }
 
