@@ -93,7 +93,7 @@ struct SetLayout {
     size_t scratch_end = 0;
     // uploaded region
     size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0;
-    std::vector<size_t> pT, pTf, cs, csf, xc;
+    std::vector<size_t> pT, pTf, cs, csf, xc, gm;
     size_t total = 0;
 };
 
@@ -129,6 +129,10 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         d.ny_d = (double)P.ny;
         d.nx = P.nx;
         d.ny = P.ny;
+        d.n_groups = P.n_groups;
+        d.x_hi = P.x_hi;
+        d.y_hi = P.y_hi;
+        d.cull_reach = P.cull_reach;
         d.tl_c = P.tl_c;
         d.tl_s = P.tl_s;
         d.ts_c = P.ts_c;
@@ -230,6 +234,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         L.cs.push_back(take(sizeof(double) * P.cs.size()));
         L.csf.push_back(take(sizeof(float) * P.cs.size()));
         L.xc.push_back(take(sizeof(double) * P.xc.size()));
+        L.gm.push_back(take(sizeof(double) * P.gm.size()));
     }
     L.total = o;
     return L;
@@ -283,6 +288,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         d.cs = reinterpret_cast<const double *>(dev + L.cs[k]);
         d.csf = reinterpret_cast<const float *>(dev + L.csf[k]);
         d.xc = reinterpret_cast<const double *>(dev + L.xc[k]);
+        d.gm = reinterpret_cast<const double *>(dev + L.gm[k]);
         d.zmap = zmaps[k];
         ib[k] = d.item_base;
         bb[k] = d.bitem_base;
@@ -301,6 +307,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         float *csf = reinterpret_cast<float *>(H(L.csf[k]));
         for (size_t q = 0; q < P.cs.size(); ++q) csf[q] = (float)P.cs[q];
         if (!P.xc.empty()) std::memcpy(H(L.xc[k]), P.xc.data(), sizeof(double) * P.xc.size());
+        if (!P.gm.empty()) std::memcpy(H(L.gm[k]), P.gm.data(), sizeof(double) * P.gm.size());
     }
     std::memcpy(H(L.sims), devs.data(), sizeof(DevSim) * L.n);
     std::memcpy(H(L.ibase), ib.data(), sizeof(int64_t) * L.n);

@@ -24,7 +24,20 @@ struct Plan {
     std::vector<double> pT;   // [z_n][N][3] tool-frame edge points
     std::vector<double> cs;   // [z_n][S][2] cos, sin of the spindle angle alpha
     std::vector<double> xc;   // [n_steps] tool-centre x per step
+    // swept-box culling: per tooth and group of kGroup consecutive edge points, a margin that
+    // bounds every point of the group over one wave of steps around its reference point's arc
+    int n_groups = 0;
+    double x_hi = 0, y_hi = 0, cull_reach = 0;
+    std::vector<double> gm;   // [z_n][n_groups]
 };
+
+// Edge points per culling group, and the group's reference point (its middle point).
+constexpr int kGroup = 16;
+constexpr int group_ref(int g, int N)
+{
+    const int n = N - g * kGroup < kGroup ? N - g * kGroup : kGroup;
+    return g * kGroup + n / 2;
+}
 
 // Validate and build the plan.  Returns FSM_OK or FSM_EINVAL with a message in `err`.
 int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &out,
@@ -83,6 +96,12 @@ struct DevSim {
     int64_t n_rows;          // histogram binning: rows of this simulation
     int64_t row_base;        // first global row of this simulation
     int64_t hbase;           // offset of this simulation's first row in the row matrix
+    // swept-box culling
+    const double *gm;        // [z_n][n_groups] group margins
+    int32_t n_groups;
+    int32_t pad1;
+    double x_hi, y_hi;       // upper grid boundaries
+    double cull_reach;       // bound on any point's horizontal distance from the tool centre
 };
 
 // Per-tile partial sums of the roughness passes (device memory).  Row ny/2 and column nx/2

@@ -83,6 +83,25 @@ __device__ __forceinline__ int64_t loop_item(int64_t b, int64_t n)
     return round0 + xcd_item(b - round0, rn);
 }
 
+// Work whose cost varies along the item order (binning rows: passes and steps far from the
+// grid are culled) goes to the XCDs in interleaved chunks of kXcdChunk consecutive items, so
+// every XCD gets a share of the heavy and the light parts while neighbouring items, which
+// write into the same tiles' buckets, still share an L2.
+constexpr int64_t kXcdChunk = 16;
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t G)
+{
+    const int64_t span = 8 * kXcdChunk;
+    if (b >= G / span * span) return b;
+    const int64_t k = b >> 3;
+    return (k / kXcdChunk) * span + (b & 7) * kXcdChunk + (k % kXcdChunk);
+}
+__device__ __forceinline__ int64_t loop_chunk(int64_t b, int64_t n)
+{
+    const int64_t round0 = b - blockIdx.x;
+    const int64_t rn = n - round0 < (int64_t)gridDim.x ? n - round0 : (int64_t)gridDim.x;
+    return round0 + xcd_chunk(b - round0, rn);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
@@ -171,55 +190,96 @@ __global__ __launch_bounds__(kBlock) void zero_u32(uint32_t *p, int64_t n)
 
 // ---- kinematics of one point -----------------------------------------------------------------
 
-// Workpiece-frame horizontal offsets (xs, ys) from the tool centre and the height key of edge
-// point p of tooth K at spindle angle (ca, sa), single or double precision.
+// A tool-frame edge point and a spindle angle (cos, sin) in the kernel's precision.  Points are
+// loaded once per edge point and reused over the lanes' steps.
+template <int PREC> struct Edge;
+template <> struct Edge<FSM_F64> { double x, y, z; };
+template <> struct Edge<FSM_F32> { float x, y, z; };
+template <int PREC> struct Turn;
+template <> struct Turn<FSM_F64> { double c, s; };
+template <> struct Turn<FSM_F32> { float c, s; };
+
 template <int PREC>
-__device__ __forceinline__ void turn_point(const DevSim &d, double ca, double sa, float caf,
-                                           float saf, int K, int p, double &xs, double &ys,
-                                           typename KeyOf<PREC>::T &key)
+__device__ __forceinline__ Edge<PREC> edge_point(const DevSim &d, int K, int p)
 {
-    if (PREC == FSM_F64) {
+    Edge<PREC> e;
+    if constexpr (PREC == FSM_F64) {
         const FSM_GLOBAL double *pt = gptr(d.pT + ((size_t)K * d.N + p) * 3);
-        const double xT = pt[0], yT = pt[1], zT = pt[2];
-        // Eq. (3): [[c, s], [-s, c]] applied to the tool-frame point, then the tilt
-        double x = ca * xT + sa * yT;
-        double y = ca * yT - sa * xT;
-        double z = zT;
-        if (d.tilt_lead) {
-            const double x1 = d.tl_c * x + d.tl_s * z;
-            z = d.tl_c * z - d.tl_s * x;
-            x = x1;
-        }
-        if (d.tilt_side) {
-            const double y1 = d.ts_c * y - d.ts_s * z;
-            z = d.ts_s * y + d.ts_c * z;
-            y = y1;
-        }
-        xs = x;
-        ys = y;
-        key = (typename KeyOf<PREC>::T)enc64(__double_as_longlong(z));
+        e.x = pt[0];
+        e.y = pt[1];
+        e.z = pt[2];
     } else {
         const FSM_GLOBAL float *pt = gptr(d.pTf + ((size_t)K * d.N + p) * 4);
-        const float px = pt[0], py = pt[1], pz = pt[2];
-        float x = fmaf(caf, px, saf * py);
-        float y = fmaf(caf, py, -(saf * px));
-        float z = pz;
-        if (d.tilt_lead) {
-            const float c = (float)d.tl_c, s = (float)d.tl_s;
-            const float x1 = fmaf(c, x, s * z);
-            z = fmaf(c, z, -(s * x));
-            x = x1;
-        }
-        if (d.tilt_side) {
-            const float c = (float)d.ts_c, s = (float)d.ts_s;
-            const float y1 = fmaf(c, y, -(s * z));
-            z = fmaf(s, y, c * z);
-            y = y1;
-        }
-        xs = (double)x;
-        ys = (double)y;
-        key = (typename KeyOf<PREC>::T)enc32(__float_as_int(z));
+        e.x = pt[0];
+        e.y = pt[1];
+        e.z = pt[2];
     }
+    return e;
+}
+
+template <int PREC>
+__device__ __forceinline__ Turn<PREC> spindle_turn(const DevSim &d, int K, int m)
+{
+    Turn<PREC> t;
+    if constexpr (PREC == FSM_F64) {
+        const FSM_GLOBAL double *cs = gptr(d.cs + ((size_t)K * d.S + m) * 2);
+        t.c = cs[0];
+        t.s = cs[1];
+    } else {
+        const FSM_GLOBAL float *cs = gptr(d.csf + ((size_t)K * d.S + m) * 2);
+        t.c = cs[0];
+        t.s = cs[1];
+    }
+    return t;
+}
+
+// Workpiece-frame horizontal offsets (xs, ys) of an edge point from the tool centre, and its
+// height key.  Double precision: Eq. (3) [[c, s], [-s, c]] then the tilt rotations, in the
+// oracle's operation order with no contraction.  Single precision: the same with fused
+// multiply-adds.
+__device__ __forceinline__ void turn_point(const DevSim &d, const Turn<FSM_F64> &a,
+                                           const Edge<FSM_F64> &e, double &xs, double &ys,
+                                           int64_t &key)
+{
+    double x = a.c * e.x + a.s * e.y;
+    double y = a.c * e.y - a.s * e.x;
+    double z = e.z;
+    if (d.tilt_lead) {
+        const double x1 = d.tl_c * x + d.tl_s * z;
+        z = d.tl_c * z - d.tl_s * x;
+        x = x1;
+    }
+    if (d.tilt_side) {
+        const double y1 = d.ts_c * y - d.ts_s * z;
+        z = d.ts_s * y + d.ts_c * z;
+        y = y1;
+    }
+    xs = x;
+    ys = y;
+    key = enc64(__double_as_longlong(z));
+}
+__device__ __forceinline__ void turn_point(const DevSim &d, const Turn<FSM_F32> &a,
+                                           const Edge<FSM_F32> &e, float &xs, float &ys,
+                                           int32_t &key)
+{
+    float x = fmaf(a.c, e.x, a.s * e.y);
+    float y = fmaf(a.c, e.y, -(a.s * e.x));
+    float z = e.z;
+    if (d.tilt_lead) {
+        const float c = (float)d.tl_c, s = (float)d.tl_s;
+        const float x1 = fmaf(c, x, s * z);
+        z = fmaf(c, z, -(s * x));
+        x = x1;
+    }
+    if (d.tilt_side) {
+        const float c = (float)d.ts_c, s = (float)d.ts_s;
+        const float y1 = fmaf(c, y, -(s * z));
+        z = fmaf(s, y, c * z);
+        y = y1;
+    }
+    xs = x;
+    ys = y;
+    key = enc32(__float_as_int(z));
 }
 
 // Eq. (4) tool-centre offset and Eq. (7) half-open sampling boundaries: the cell (i, j), or
@@ -266,50 +326,85 @@ __device__ __forceinline__ bool bin_cell32(const DevSim &d, const Centre32 &c, f
     return c.near && (uint32_t)i < (uint32_t)d.nx && (uint32_t)j < (uint32_t)d.ny;
 }
 
-// Single-precision kinematics of one point: float offsets from the tool centre and the key.
-__device__ __forceinline__ void turn_point32(const DevSim &d, float caf, float saf, int K, int p,
-                                             float &xs, float &ys, int32_t &key)
+// One point of either precision: its cell (i, j) and key; false outside the grid.
+__device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F64> &a,
+                                            const Edge<FSM_F64> &e, double xcs, double yq,
+                                            const Centre32 &, int32_t &i, int32_t &j, int64_t &key)
 {
-    const FSM_GLOBAL float *pt = gptr(d.pTf + ((size_t)K * d.N + p) * 4);
-    const float px = pt[0], py = pt[1], pz = pt[2];
-    float x = fmaf(caf, px, saf * py);
-    float y = fmaf(caf, py, -(saf * px));
-    float z = pz;
-    if (d.tilt_lead) {
-        const float c = (float)d.tl_c, s = (float)d.tl_s;
-        const float x1 = fmaf(c, x, s * z);
-        z = fmaf(c, z, -(s * x));
-        x = x1;
-    }
-    if (d.tilt_side) {
-        const float c = (float)d.ts_c, s = (float)d.ts_s;
-        const float y1 = fmaf(c, y, -(s * z));
-        z = fmaf(s, y, c * z);
-        y = y1;
-    }
-    xs = x;
-    ys = y;
-    key = enc32(__float_as_int(z));
+    double xs, ys;
+    turn_point(d, a, e, xs, ys, key);
+    return bin_cell(d, xcs, yq, xs, ys, i, j);
+}
+__device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F32> &a,
+                                            const Edge<FSM_F32> &e, double, double,
+                                            const Centre32 &c32, int32_t &i, int32_t &j,
+                                            int32_t &key)
+{
+    float xs, ys;
+    turn_point(d, a, e, xs, ys, key);
+    return bin_cell32(d, c32, xs, ys, i, j);
 }
 
-// One point of either precision: its cell (i, j) and key; false outside the grid.
-template <int PREC>
-__device__ __forceinline__ bool place_point(const DevSim &d, double ca, double sa, float caf,
-                                            float saf, double xcs, double yq, const Centre32 &c32,
-                                            int K, int p, int32_t &i, int32_t &j,
-                                            typename KeyOf<PREC>::T &key)
+// ---- swept-box culling -------------------------------------------------------------------------
+//
+// A wave of a binning item covers 64 consecutive steps of one pass and tooth.  Most of the
+// auto path's evaluations land outside the grid (the path overshoots the grid by the tool
+// reach on every side), so whole waves, and then groups of kGroup edge points, are skipped
+// when a conservative box around their positions misses the grid.  The skipped points would
+// have been dropped by the in-grid test, so results do not change.
+
+// Value of v in lane l (l uniform over the wave).
+__device__ __forceinline__ double lane_value(double v, int l)
 {
-    if (PREC == FSM_F64) {
-        double xs, ys;
-        turn_point<PREC>(d, ca, sa, caf, saf, K, p, xs, ys, key);
-        return bin_cell(d, xcs, yq, xs, ys, i, j);
-    } else {
-        float xs, ys;
-        int32_t k32;
-        turn_point32(d, caf, saf, K, p, xs, ys, k32);
-        key = (typename KeyOf<PREC>::T)k32;
-        return bin_cell32(d, c32, xs, ys, i, j);
-    }
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// The steps of this thread's wave in step block sb: the first step, the last active lane and
+// the tool-centre x at both ends (x grows with the step).  False past the pass's last step.
+struct WaveSteps {
+    int s0, last;
+    double xc0, xc1;
+};
+__device__ __forceinline__ bool wave_steps(const DevSim &d, int sb, WaveSteps &w)
+{
+    const int s0 = __builtin_amdgcn_readfirstlane(sb * kBlock + (int)(threadIdx.x & ~63u));
+    if (s0 >= d.n_steps) return false;
+    const int rem = d.n_steps - 1 - s0;
+    w.s0 = s0;
+    w.last = rem < 63 ? rem : 63;
+    w.xc0 = gptr(d.xc)[s0];
+    w.xc1 = gptr(d.xc)[s0 + w.last];
+    return true;
+}
+
+// False when the tool centre's path over the wave, widened by the reach, misses the grid.
+__device__ __forceinline__ bool wave_near(const DevSim &d, const WaveSteps &w, double yq)
+{
+    return w.xc1 + d.cull_reach >= d.x_lo && w.xc0 - d.cull_reach < d.x_hi &&
+           yq + d.cull_reach >= d.y_lo && yq - d.cull_reach < d.y_hi;
+}
+
+// False when no point of edge-point group g can land in the grid during the wave: every lane
+// places the group's reference point at its own step, the first and last lanes' offsets span
+// a box that the group's margin widens (arc sagitta, group spread, rounding slack).  Called in
+// uniform control flow with every lane up to w.last active.
+template <int PREC>
+__device__ __forceinline__ bool group_near(const DevSim &d, const Turn<PREC> &a,
+                                           const Edge<PREC> &ref, int K, int g,
+                                           const WaveSteps &w, double yq)
+{
+    typename KeyOf<PREC>::T k;
+    decltype(ref.x) fx, fy;
+    turn_point(d, a, ref, fx, fy, k);
+    const double ax = (double)fx, ay = (double)fy;
+    const double ax0 = lane_value(ax, 0), ax1 = lane_value(ax, w.last);
+    const double ay0 = lane_value(ay, 0), ay1 = lane_value(ay, w.last);
+    const double m = gptr(d.gm)[K * d.n_groups + g];
+    return w.xc1 + fmax(ax0, ax1) + m >= d.x_lo && w.xc0 + fmin(ax0, ax1) - m < d.x_hi &&
+           yq + fmax(ay0, ay1) + m >= d.y_lo && yq + fmin(ay0, ay1) - m < d.y_hi;
 }
 
 // ---- scatter strategy ------------------------------------------------------------------------
@@ -341,26 +436,17 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
             const int S = d.S;
             FSM_GLOBAL Key *zk = gptr(static_cast<Key *>(d.zmap));
             for (int p = lane_p; p < d.N; p += ppi) {
+                const Edge<PREC> e = edge_point<PREC>(d, K, p);
                 int s = s0 + lane_s;
                 int m = s % S;
                 for (; s < s1; s += spi) {
-                    double ca = 0, sa = 0;
-                    float caf = 0, saf = 0;
-                    if (PREC == FSM_F64) {
-                        const FSM_GLOBAL double *cs = gptr(d.cs + ((size_t)K * S + m) * 2);
-                        ca = cs[0];
-                        sa = cs[1];
-                    } else {
-                        const FSM_GLOBAL float *cs = gptr(d.csf + ((size_t)K * S + m) * 2);
-                        caf = cs[0];
-                        saf = cs[1];
-                    }
+                    const Turn<PREC> a = spindle_turn<PREC>(d, K, m);
                     const double xcs = gptr(d.xc)[s];
                     Centre32 c32 = {};
                     if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
                     Key key;
                     int32_t i, j;
-                    if (place_point<PREC>(d, ca, sa, caf, saf, xcs, yq, c32, K, p, i, j, key)) {
+                    if (place_point(d, a, e, xcs, yq, c32, i, j, key)) {
                         const int64_t idx = (int64_t)j * d.nx + i;
                         if (key < __hip_atomic_load(zk + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                             __hip_atomic_fetch_min(zk + idx, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -420,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
     FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bb.bkey));
     FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
     for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
-        const int64_t item = item_begin + loop_item(b, n_items);
+        const int64_t item = item_begin + loop_chunk(b, n_items);
         const int si = n_sims == 1 ? 0 : find_sim(bitem_base, n_sims, item);
         const DevSim d = sims[si];
         int64_t local = item - d.bitem_base;
@@ -428,66 +514,64 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
         local /= d.z_n;
         const int sb = (int)(local % d.n_sblocks);
         const int q = (int)(local / d.n_sblocks);
-        const int s = sb * kBlock + tid;
-        const bool vs = s < d.n_steps;
-        double ca = 0.0, sa = 0.0, xcs = 0.0;
-        float caf = 0.0f, saf = 0.0f;
-        if (vs) {
-            const int m = s % d.S;
-            if (PREC == FSM_F64) {
-                const FSM_GLOBAL double *cs = gptr(d.cs + ((size_t)K * d.S + m) * 2);
-                ca = cs[0];
-                sa = cs[1];
-            } else {
-                const FSM_GLOBAL float *cs = gptr(d.csf + ((size_t)K * d.S + m) * 2);
-                caf = cs[0];
-                saf = cs[1];
-            }
-            xcs = gptr(d.xc)[s];
-        }
+        WaveSteps w;
+        if (!wave_steps(d, sb, w)) continue;
         const double yq = d.y_first + (double)q * d.a_e;
+        if (!wave_near(d, w, yq)) continue;
+        const bool vs = lane <= w.last;
+        const int s = w.s0 + (vs ? lane : w.last);
+        const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
+        const double xcs = gptr(d.xc)[s];
         Centre32 c32 = {};
         if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
         const int sx = d.sx, sy = d.sy;
         const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
-        for (int p0 = 0; p0 < d.N; p0 += kUnroll) {
-            int32_t tile[kUnroll];
-            uint16_t cell[kUnroll];
-            Key key[kUnroll];
+        for (int g = 0; g < d.n_groups; ++g) {
+            if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
+            const int pg = g * kGroup;
+            Edge<PREC> ep[kGroup];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                tile[u] = -1;
-                cell[u] = 0;
-                key[u] = 0;
-                if (vs && p0 + u < d.N) {
-                    int32_t i, j;
-                    if (place_point<PREC>(d, ca, sa, caf, saf, xcs, yq, c32, K, p0 + u, i, j, key[u])) {
-                        tile[u] = (int32_t)d.tile_base + (j >> sy) * d.tiles_x + (i >> sx);
-                        cell[u] = (uint16_t)(((j & my) << sx) | (i & mx));
-                    }
-                }
-            }
-            Runs r[kUnroll];
+            for (int u = 0; u < kGroup; ++u) ep[u] = edge_point<PREC>(d, K, pg + u < d.N ? pg + u : d.N - 1);
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) r[u] = tile_runs(tile[u], lane);
-            if (!WRITE) {
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (r[u].head)
-                        __hip_atomic_fetch_add(counter + tile[u], (uint32_t)r[u].len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                uint32_t base[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    base[u] = r[u].head ? __hip_atomic_fetch_add(counter + tile[u], (uint32_t)r[u].len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+            for (int h = 0; h < kGroup; h += kUnroll) {
+                int32_t tile[kUnroll];
+                uint16_t cell[kUnroll];
+                Key key[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t b0 = __shfl(base[u], r[u].first, 64);
-                    if (tile[u] >= 0) {
-                        const int64_t pos = (int64_t)b0 + (lane - r[u].first);
-                        if (pos < bb.cap) {
-                            bkey[pos] = key[u];
-                            bix[pos] = cell[u];
+                    tile[u] = -1;
+                    cell[u] = 0;
+                    key[u] = 0;
+                    if (vs && pg + h + u < d.N) {
+                        int32_t i, j;
+                        if (place_point(d, a, ep[h + u], xcs, yq, c32, i, j, key[u])) {
+                            tile[u] = (int32_t)d.tile_base + (j >> sy) * d.tiles_x + (i >> sx);
+                            cell[u] = (uint16_t)(((j & my) << sx) | (i & mx));
+                        }
+                    }
+                }
+                Runs r[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) r[u] = tile_runs(tile[u], lane);
+                if (!WRITE) {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (r[u].head)
+                            __hip_atomic_fetch_add(counter + tile[u], (uint32_t)r[u].len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    uint32_t base[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        base[u] = r[u].head ? __hip_atomic_fetch_add(counter + tile[u], (uint32_t)r[u].len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        const uint32_t b0 = __shfl(base[u], r[u].first, 64);
+                        if (tile[u] >= 0) {
+                            const int64_t pos = (int64_t)b0 + (lane - r[u].first);
+                            if (pos < bb.cap) {
+                                bkey[pos] = key[u];
+                                bix[pos] = cell[u];
+                            }
                         }
                     }
                 }
@@ -511,7 +595,7 @@ template <int PREC, typename F>
 __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t i1, F &&f)
 {
     using Key = typename KeyOf<PREC>::T;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int sx = d.sx, sy = d.sy;
     const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
     for (int64_t it = i0; it < i1; ++it) {
@@ -520,29 +604,27 @@ __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t 
         local /= d.z_n;
         const int sb = (int)(local % d.n_sblocks);
         const int q = (int)(local / d.n_sblocks);
-        const int s = sb * kBlock + tid;
-        if (s >= d.n_steps) continue;
-        const int m = s % d.S;
-        double ca = 0.0, sa = 0.0;
-        float caf = 0.0f, saf = 0.0f;
-        if (PREC == FSM_F64) {
-            const FSM_GLOBAL double *cs = gptr(d.cs + ((size_t)K * d.S + m) * 2);
-            ca = cs[0];
-            sa = cs[1];
-        } else {
-            const FSM_GLOBAL float *cs = gptr(d.csf + ((size_t)K * d.S + m) * 2);
-            caf = cs[0];
-            saf = cs[1];
-        }
-        const double xcs = gptr(d.xc)[s];
+        WaveSteps w;
+        if (!wave_steps(d, sb, w)) continue;
         const double yq = d.y_first + (double)q * d.a_e;
+        if (!wave_near(d, w, yq)) continue;
+        // lanes past the last step repeat it (they take part in the culling test only)
+        const bool act = lane <= w.last;
+        const int s = w.s0 + (act ? lane : w.last);
+        const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
+        const double xcs = gptr(d.xc)[s];
         Centre32 c32 = {};
         if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
-        for (int p = 0; p < d.N; ++p) {
-            Key key;
-            int32_t i, j;
-            if (place_point<PREC>(d, ca, sa, caf, saf, xcs, yq, c32, K, p, i, j, key))
-                f((j >> sy) * d.tiles_x + (i >> sx), (uint16_t)(((j & my) << sx) | (i & mx)), key);
+        for (int g = 0; g < d.n_groups; ++g) {
+            if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
+            const int pg = g * kGroup;
+            const int pe = pg + kGroup < d.N ? pg + kGroup : d.N;
+            for (int p = pg; p < pe; ++p) {
+                Key key;
+                int32_t i, j;
+                if (act && place_point(d, a, edge_point<PREC>(d, K, p), xcs, yq, c32, i, j, key))
+                    f((j >> sy) * d.tiles_x + (i >> sx), (uint16_t)(((j & my) << sx) | (i & mx)), key);
+            }
         }
     }
 }
@@ -556,7 +638,7 @@ __global__ __launch_bounds__(kBlock) void hist_count(const DevSim *__restrict__ 
     extern __shared__ uint32_t hist[];
     const int tid = threadIdx.x;
     for (int64_t b = blockIdx.x; b < n_rows; b += gridDim.x) {
-        const int64_t r = r0 + loop_item(b, n_rows);
+        const int64_t r = r0 + loop_chunk(b, n_rows);
         const int si = n_sims == 1 ? 0 : find_sim(row_base, n_sims, r);
         const DevSim d = sims[si];
         const int64_t lr = r - d.row_base;
@@ -653,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ 
     FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bb.bkey));
     FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
     for (int64_t b = blockIdx.x; b < n_rows; b += gridDim.x) {
-        const int64_t r = r0 + loop_item(b, n_rows);
+        const int64_t r = r0 + loop_chunk(b, n_rows);
         const int si = n_sims == 1 ? 0 : find_sim(row_base, n_sims, r);
         const DevSim d = sims[si];
         const int64_t lr = r - d.row_base;
@@ -1084,7 +1166,7 @@ namespace {
 
 void stage(const StageEvents *marks, int k, hipStream_t s)
 {
-    if (marks) hipEventRecord(static_cast<hipEvent_t>(marks->ev[k]), s);
+    if (marks) (void)hipEventRecord(static_cast<hipEvent_t>(marks->ev[k]), s);
 }
 
 // Exclusive scan of counts[0, n) into offsets and cursors.

@@ -6,6 +6,7 @@
 // add, subtract and multiply.  The operation order of each expression is fixed (the build
 // turns off contraction into fused multiply-adds), which makes the double-precision path
 // reproduce the plain definition of the method bit for bit.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -205,6 +206,34 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     P.xc.resize((size_t)P.n_steps);
     for (int64_t s = 0; s < P.n_steps; ++s)
         P.xc[(size_t)s] = P.x_start + ((double)s * fpr) / (double)S;
+
+    // --- culling margins.  Over the 64 consecutive steps of one wave the reference point of a
+    // group turns by at most 63 steps about the tool axis (a circular arc of radius r_m, tilted
+    // as a whole) while the centre moves along a line, so every position lies within the
+    // arc's sagitta of the box spanned by the first and last positions; every other point of
+    // the group stays within its distance rho from the reference point under any rigid motion.
+    // The slack eps covers rounding of the box and of single-precision points.
+    const double eps = 1e-5 * (reach + 1.0);
+    const double half = 63.0 * M_PI / (double)S;
+    P.n_groups = (N + kGroup - 1) / kGroup;
+    P.gm.assign((size_t)Z * P.n_groups, 0.0);
+    for (int K = 0; K < Z; ++K) {
+        for (int gi = 0; gi < P.n_groups; ++gi) {
+            const double *m = &P.pT[((size_t)K * N + group_ref(gi, N)) * 3];
+            double rho = 0.0;
+            for (int p = gi * kGroup; p < N && p < (gi + 1) * kGroup; ++p) {
+                const double *q = &P.pT[((size_t)K * N + p) * 3];
+                const double dx = q[0] - m[0], dy = q[1] - m[1], dz = q[2] - m[2];
+                rho = std::max(rho, std::sqrt(dx * dx + dy * dy + dz * dz));
+            }
+            const double rm = std::sqrt(m[0] * m[0] + m[1] * m[1]);
+            const double sag = half <= 0.5 * M_PI ? rm * (1.0 - std::cos(half)) : 2.0 * rm;
+            P.gm[(size_t)K * P.n_groups + gi] = rho + sag + eps;
+        }
+    }
+    P.x_hi = x_hi;
+    P.y_hi = y_hi;
+    P.cull_reach = reach + eps;
     return FSM_OK;
 }
 
