@@ -97,6 +97,62 @@ def run_precision(ctx, sim, prec, steps, warmup, profile):
     return out
 
 
+def batch_leg(ctx, n_sims):
+    """Configuration 3 (n_sims seeded simulations, sides up to 2048): every simulation once,
+    batched (one fsm_simulate_batch) and plain (one fsm_simulate per simulation, each waited
+    for), in both precisions.  Z-maps resident in HBM."""
+    import torch
+    from paper_2603_28160_amd import workloads
+    sims = workloads.config3(n_sims)
+    cells = sum(s.grid.nx * s.grid.ny for s in sims)
+    out = {"workload": f"config3_mix_{n_sims}", "sims": n_sims, "cells": cells}
+    for prec in ("f32", "f64"):
+        zmaps = [ctx.new_zmap(s.grid, prec) for s in sims]
+        ctx.fsm_simulate_batch(sims[:2], prec, zmaps=zmaps[:2])       # warm the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.fsm_simulate_batch(sims, prec, zmaps=zmaps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for s, z in zip(sims, zmaps):
+            ctx.fsm_simulate(s, prec, z)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        del zmaps
+        torch.cuda.empty_cache()
+        out[prec] = {"batched": {"s": tb, "sims_per_s": n_sims / tb, "cells_per_s": cells / tb},
+                     "plain": {"s": tp, "sims_per_s": n_sims / tp, "cells_per_s": cells / tp}}
+        print(f"[bench] config3 x{n_sims} {prec}: batched {tb:.3f} s, plain {tp:.3f} s",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def serve_leg(ctx, n_req, rate, max_batch=16, n_slots=2):
+    """Configuration 4: n_req requests drawn like configuration 3 with sides up to 4096,
+    Poisson arrivals at `rate` per second, served with continuous batching (server-held
+    Z-maps in a device arena), in both precisions.  Latency = arrival to result on the host."""
+    from paper_2603_28160_amd import workloads
+    reqs = workloads.config4_requests(n_req, rate)
+    out = {"workload": f"config4_poisson_{rate:g}_per_s", "requests": n_req, "rate_per_s": rate,
+           "n_slots": n_slots, "max_batch": max_batch}
+    for prec in ("f32", "f64"):
+        res = ctx.fsm_serve_run([(s, a, None) for a, s in reqs], prec, n_slots=n_slots,
+                                max_batch=max_batch, arena_bytes=8 << 30, slot_bytes=2 << 30)
+        ok = [(r, a) for r, (a, _) in zip(res, reqs) if r["status"] == 0]
+        lat = [(r["done_s"] - a) * 1e3 for r, a in ok]
+        span = max(r["done_s"] for r, _ in ok) - min(a for _, a in ok)
+        sizes = {}
+        for r, _ in ok:
+            sizes[r["batch"]] = sizes.get(r["batch"], 0) + 1
+        out[prec] = {"sims_per_s": len(ok) / span, "latency_ms": {"p50": pct(lat, 50),
+                     "p99": pct(lat, 99)}, "completed": len(ok),
+                     "mean_batch": len(ok) / max(1, len(sizes))}
+        print(f"[bench] serving {prec}: {len(ok)}/{n_req} done, {len(ok) / span:.1f} sims/s, "
+              f"p50 {pct(lat, 50):.2f} ms, p99 {pct(lat, 99):.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def roofline(sim, plan, prec, prof):
     """Roofline of the longest stage of the Z-map, timed with HIP events on the stream the
     library launches on (mean over the profiled steps, per launch)."""
@@ -140,6 +196,11 @@ def main():
     ap.add_argument("--strategy", choices=["binned", "scatter"], default="binned")
     ap.add_argument("--compare-strategies", action="store_true",
                     help="also time the other Z-map strategy (reported, not the value)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batch (configuration 3) and serving (configuration 4) legs")
+    ap.add_argument("--batch-sims", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-rate", type=float, default=500.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reads 1 GiB, writes "
                          "1 GiB) five times, to scale HBM byte counters")
@@ -186,6 +247,10 @@ def main():
                   f"(count {p['count_ms']:.3f}, index {p['index_ms']:.3f}, write {p['write_ms']:.3f}, "
                   f"reduce {p['reduce_ms']:.3f}), roughness {p['rough_ms']:.3f} ms",
                   file=sys.stderr, flush=True)
+        extras = {}
+        if not args.no_extras:
+            extras["batch"] = batch_leg(ctx, args.batch_sims)
+            extras["serving"] = serve_leg(ctx, args.serve_requests, args.serve_rate)
 
     main_prec = "f64" if "f64" in res else precs[0]
     m = res[main_prec]
@@ -235,6 +300,7 @@ def main():
                      "Sa": o["rough"]["Sa"], "Sa_f64": r["Sa"]}
     if other:
         out["other_strategy"] = other
+    out.update(extras)
     if not args.no_cpu_baseline:
         import oracle
         print("[bench] cpu baseline: FP64 oracle on the full workload, 1 thread",

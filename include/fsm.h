@@ -228,6 +228,72 @@ int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision,
 int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_dev,
                   fsm_rough *out, void *stream);
 
+/* ---- serving loop --------------------------------------------------------------------------
+ *
+ * Simulations of different sizes and parameters arriving over time, the way a surrogate-model
+ * dataset generator calls the method (Sec. 4.3 names dataset generation as the use of the
+ * speed-up).  The caller's thread runs the loop: requests arrive at their stated times, are
+ * admitted first come, first served as soon as their Z-map fits the device arena, and are
+ * gathered into batches that run on n_slots streams at once, each with its own workspace, so
+ * requests that arrive while others are on the device join it as soon as a slot frees up
+ * (continuous batching).  Every batch is one fsm_simulate_batch launch sequence, so each
+ * result equals the same simulation run alone. */
+
+typedef struct fsm_request {
+    const fsm_tool *tool;
+    const fsm_cut *cut;
+    const fsm_grid *grid;
+    double arrival_s;        /* arrival time, seconds after the start of the run */
+    void *zmap_dev;          /* caller-owned device Z-map (kept), or NULL: the server holds the
+                                map in its arena while the request is in flight and returns
+                                only the roughness */
+} fsm_request;
+
+typedef struct fsm_request_result {
+    fsm_rough rough;
+    double admit_s;          /* seconds after the start: admitted (arena range taken) */
+    double start_s;          /* its batch was queued on the device */
+    double done_s;           /* its batch was seen finished by the loop */
+    int32_t status;          /* FSM_OK, FSM_EINVAL (bad parameters) or FSM_ENOMEM (larger
+                                than the arena or than one slot's workspace) */
+    int32_t batch;           /* index of its batch, -1 if it never ran */
+    int32_t slot;            /* slot (stream) its batch ran on, -1 if it never ran */
+    int32_t pad;
+} fsm_request_result;
+
+typedef struct fsm_serve_config {
+    int32_t precision;       /* FSM_F64 or FSM_F32, for every request */
+    int32_t n_slots;         /* batches in flight at once, 1..16 */
+    int32_t max_batch;       /* simulations per batch, >= 1 */
+    int32_t realtime;        /* 1: requests arrive at arrival_s on the wall clock; 0: all at 0 */
+    int64_t arena_bytes;     /* device bytes for server-held Z-maps (allocated once per run) */
+    int64_t slot_bytes;      /* device workspace per slot (allocated once per run); batches are
+                                sized, and their buckets sliced, to fit it */
+} fsm_serve_config;
+
+/* Serve n requests to completion on ctx's device.  out: n records, written for every request
+ * (a rejected request carries its status; the call still returns FSM_OK).  The call allocates
+ * the arena and the slot workspaces once at the start and frees them at the end; nothing is
+ * allocated while requests are served.  Returns FSM_EINVAL for a bad configuration, FSM_ENOMEM
+ * if the arena or workspaces cannot be allocated, FSM_EDEVICE on a HIP error. */
+int fsm_serve_run(fsm_ctx *ctx, const fsm_serve_config *cfg, int n, const fsm_request *req,
+                  fsm_request_result *out);
+
+/* Device model of the dry run: a batch occupies its slot for launch_s plus, for every
+ * simulation, per_eval_s per edge-point evaluation and per_cell_s per Z-map cell. */
+typedef struct fsm_serve_model {
+    double launch_s;
+    double per_eval_s;
+    double per_cell_s;
+} fsm_serve_model;
+
+/* Host only: the same scheduler as fsm_serve_run (arrivals, admission, batching, the slot
+ * workspace rule) against a simulated clock and the device model; zmap_dev is ignored except
+ * for NULL (server-held) versus non-NULL (caller-owned).  The roughness records are zero.
+ * arena_peak (nullable) receives the most arena bytes held at once. */
+int fsm_serve_dry_run(const fsm_serve_config *cfg, const fsm_serve_model *model, int n,
+                      const fsm_request *req, fsm_request_result *out, int64_t *arena_peak);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,27 @@ class FsmJob(C.Structure):
                 ("grid", C.POINTER(FsmGrid)), ("zmap_dev", C.c_void_p)]
 
 
+class FsmRequest(C.Structure):
+    _fields_ = [("tool", C.POINTER(FsmTool)), ("cut", C.POINTER(FsmCut)),
+                ("grid", C.POINTER(FsmGrid)), ("arrival_s", C.c_double),
+                ("zmap_dev", C.c_void_p)]
+
+
+class FsmRequestResult(C.Structure):
+    _fields_ = [("rough", FsmRough), ("admit_s", C.c_double), ("start_s", C.c_double),
+                ("done_s", C.c_double), ("status", C.c_int32), ("batch", C.c_int32),
+                ("slot", C.c_int32), ("pad", C.c_int32)]
+
+
+class FsmServeConfig(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("n_slots", C.c_int32), ("max_batch", C.c_int32),
+                ("realtime", C.c_int32), ("arena_bytes", C.c_int64), ("slot_bytes", C.c_int64)]
+
+
+class FsmServeModel(C.Structure):
+    _fields_ = [("launch_s", C.c_double), ("per_eval_s", C.c_double), ("per_cell_s", C.c_double)]
+
+
 # every symbol include/fsm.h declares, with its ctypes signature
 P = C.POINTER
 SIGNATURES = {
@@ -97,6 +118,10 @@ SIGNATURES = {
                       C.c_int),
     "fsm_simulate_batch": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmRough), C.c_void_p],
                            C.c_int),
+    "fsm_serve_run": ([C.c_void_p, P(FsmServeConfig), C.c_int, P(FsmRequest),
+                       P(FsmRequestResult)], C.c_int),
+    "fsm_serve_dry_run": ([P(FsmServeConfig), P(FsmServeModel), C.c_int, P(FsmRequest),
+                           P(FsmRequestResult), P(C.c_int64)], C.c_int),
 }
 
 _lock = threading.Lock()

@@ -70,6 +70,48 @@ def _stream_handle(stream, device: int) -> int:
     return int(stream.cuda_stream)
 
 
+def _requests(requests, precision, ctx=None):
+    n = len(requests)
+    reqs = (_abi.FsmRequest * n)()
+    keep = []
+    for k, (s, arrival, z) in enumerate(requests):
+        if z is not None and ctx is not None:
+            ctx._check_zmap(s.grid, precision, z)
+        t, c, g = _abi.tool_struct(s.tool), _abi.cut_struct(s.cut), _abi.grid_struct(s.grid)
+        keep += [t, c, g]
+        reqs[k].tool = C.pointer(t)
+        reqs[k].cut = C.pointer(c)
+        reqs[k].grid = C.pointer(g)
+        reqs[k].arrival_s = float(arrival)
+        reqs[k].zmap_dev = None if z is None else (z if isinstance(z, int) else z.data_ptr())
+    return reqs, keep
+
+
+def _result(o) -> dict:
+    return {"rough": o.rough.as_dict(), "status": o.status, "batch": o.batch, "slot": o.slot,
+            "admit_s": o.admit_s, "start_s": o.start_s, "done_s": o.done_s}
+
+
+def fsm_serve_dry_run(requests, precision="f32", n_slots=2, max_batch=16, realtime=True,
+                      arena_bytes=1 << 30, slot_bytes=1 << 30, launch_s=50e-6,
+                      per_eval_s=5e-12, per_cell_s=5e-11):
+    """The serving scheduler on the host against a modelled device (no GPU): requests are
+    (sim, arrival_s, zmap) with zmap None (server-held) or any non-None marker (caller-owned).
+    Returns (per-request dicts, most arena bytes held at once)."""
+    n = len(requests)
+    cfg = _abi.FsmServeConfig(_prec(precision), n_slots, max_batch, 1 if realtime else 0,
+                              int(arena_bytes), int(slot_bytes))
+    model = _abi.FsmServeModel(launch_s, per_eval_s, per_cell_s)
+    marked = [(s, a, None if z is None else 1) for s, a, z in requests]
+    reqs, keep = _requests(marked, precision)
+    out = (_abi.FsmRequestResult * max(n, 1))()
+    peak = C.c_int64(0)
+    rc = _abi.load().fsm_serve_dry_run(C.byref(cfg), C.byref(model), n, reqs, out, C.byref(peak))
+    _check(rc, "fsm_serve_dry_run")
+    del keep
+    return [_result(out[k]) for k in range(n)], peak.value
+
+
 class Context:
     """One libfsm context on one HIP device (fsm_ctx_create / fsm_ctx_destroy)."""
 
@@ -180,6 +222,29 @@ class Context:
         _check(rc, "fsm_simulate_batch", self._h)
         return list(zmaps), [o.as_dict() for o in out]
 
+    def fsm_serve_run(self, requests, precision="f32", n_slots=2, max_batch=16, realtime=True,
+                      arena_bytes=None, slot_bytes=1 << 30):
+        """Serve requests [(sim, arrival_s, zmap tensor or None), ...] to completion with
+        continuous batching; returns one dict per request (roughness, status, batch, slot and
+        admit/start/done times in seconds after the start).  Requests without a Z-map tensor
+        are held in a device arena sized to the largest of them times n_slots * max_batch
+        unless arena_bytes is given."""
+        n = len(requests)
+        if n == 0:
+            return []
+        key = 8 if _prec(precision) == _abi.F64 else 4
+        if arena_bytes is None:
+            own = [int(s.grid.nx) * int(s.grid.ny) * key for s, _, z in requests if z is None]
+            arena_bytes = 0 if not own else min(sum(own), max(own) * n_slots * max_batch) + (1 << 20)
+        cfg = _abi.FsmServeConfig(_prec(precision), n_slots, max_batch, 1 if realtime else 0,
+                                  int(arena_bytes), int(slot_bytes))
+        reqs, keep = _requests(requests, precision, self)
+        out = (_abi.FsmRequestResult * n)()
+        rc = self._lib.fsm_serve_run(self._h, C.byref(cfg), n, reqs, out)
+        _check(rc, "fsm_serve_run", self._h)
+        del keep
+        return [_result(o) for o in out]
+
     def set_graphs(self, on: bool = True):
         """Capture launch sequences into HIP graphs and replay them per launch shape."""
         self.fsm_ctx_set_option(_abi.OPT_GRAPHS, 1 if on else 0)
@@ -188,3 +253,4 @@ class Context:
     simulate = fsm_simulate
     roughness = fsm_roughness
     simulate_batch = fsm_simulate_batch
+    serve = fsm_serve_run

@@ -42,10 +42,14 @@ def build(verbose: bool = False) -> str:
     o = os.path.join(BUILD, "fsm_plan.o")
     _run(["g++", *COMMON, "-fno-builtin", "-c", os.path.join(CSRC, "fsm_plan.cpp"), "-o", o])
     objs.append(o)
-    o = os.path.join(BUILD, "fsm_api.o")
-    _run([HIPCC, *COMMON, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
-          os.path.join(CSRC, "fsm_api.cpp"), "-o", o])
+    o = os.path.join(BUILD, "fsm_sched.o")
+    _run(["g++", *COMMON, "-c", os.path.join(CSRC, "fsm_sched.cpp"), "-o", o])
     objs.append(o)
+    for name in ("fsm_api", "fsm_serve"):
+        o = os.path.join(BUILD, name + ".o")
+        _run([HIPCC, *COMMON, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
+              os.path.join(CSRC, name + ".cpp"), "-o", o])
+        objs.append(o)
     o = os.path.join(BUILD, "fsm_kernels.o")
     _run([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, "fsm_kernels.hip"), "-o", o])
     objs.append(o)

@@ -18,39 +18,15 @@
 #include <string>
 #include <vector>
 
-#include "fsm_internal.h"
+#include "fsm_runtime.h"
 
-struct fsm_ctx {
-    int device = 0;
-    std::string err;
-    void *d_ws = nullptr;     // device workspace
-    size_t d_bytes = 0;
-    void *h_ws = nullptr;     // pinned host staging
-    size_t h_bytes = 0;
-    fsm_rough *h_out = nullptr;  // pinned result records
-    size_t h_out_n = 0;
-    bool profiling = false;
-    hipEvent_t ev[5] = {};       // upload, fill, z-map, roughness, end
-    std::vector<fsm::StageEvents> stage_ev;   // per binned slice: the five stage events
-    int stages_used = 0;                      // slices of the last profiled call
-    fsm_timings timings = {};
-    int strategy = fsm::kStrategyBinned;
-    int64_t bucket_bytes = (int64_t)4 << 30;
-    bool graphs = false;
-    hipStream_t own = nullptr;   // stream used for graph capture and replay
-    hipEvent_t join = nullptr;
-    std::map<std::string, hipGraphExec_t> graph_cache;
-    size_t max_lds = 65536;
-};
-
-namespace {
-
-using fsm::DevSim;
-using fsm::Plan;
+namespace fsm {
+namespace rt {
 
 constexpr int kItersPerItem = 16;   // steps each thread walks per scatter item and edge point
 constexpr int64_t kTargetRows = 4096;      // rows of the histogram mode per launch
 constexpr int kRowChunk = 32;              // rows per column-scan chunk
+constexpr int64_t kMinSliceRows = 2048;    // rows (blocks) a slice of the histogram mode keeps
 constexpr int64_t kHistBudget = (int64_t)1 << 30;   // bytes of the row matrix
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -69,33 +45,15 @@ int hip_err(fsm_ctx *ctx, hipError_t e, const char *where)
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Bucket capacity in points: the context's bucket budget over the bytes of one entry (key and
-// cell index), at least one binning item's worst case and at most what 32-bit offsets address.
-int64_t bucket_cap(const fsm_ctx *ctx, int precision, int64_t per_item)
+// Bucket capacity in points: the bucket budget over the bytes of one entry (key and cell
+// index), at least one binning item's worst case and at most what 32-bit offsets address.
+int64_t bucket_cap(int64_t bucket_bytes, int precision, int64_t per_item)
 {
     const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
-    int64_t cap = ctx->bucket_bytes / (key_bytes + 2);
+    int64_t cap = bucket_bytes / (key_bytes + 2);
     cap = std::max<int64_t>(cap, per_item);
     return std::min<int64_t>(cap, (int64_t)UINT32_MAX);
 }
-
-// Shape and layout of one launch over a set of simulations.
-struct SetLayout {
-    int n = 0, precision = 0, strategy = 0, sx = 7, sy = 6;
-    int64_t total_tiles = 0, total_items = 0, per_slice = 0, cap = 0;
-    int max_n = 1;
-    // histogram mode of the binned strategy (no global atomics)
-    bool hist = false;
-    int64_t total_rows = 0, rows_per_slice = 0, max_tiles = 0, items_per_row = 1;
-    // device-only region
-    size_t st1 = 0, st2 = 0, state = 0, out = 0, counts = 0, offsets = 0, cursor = 0, bsum = 0,
-           bkey = 0, bidx = 0, hist_m = 0, chunk = 0;
-    size_t scratch_end = 0;
-    // uploaded region
-    size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0;
-    std::vector<size_t> pT, pTf, cs, csf, xc, gm;
-    size_t total = 0;
-};
 
 void choose_tiles(const fsm_ctx *ctx, int precision, int &sx, int &sy)
 {
@@ -107,7 +65,7 @@ void choose_tiles(const fsm_ctx *ctx, int precision, int &sx, int &sy)
 }
 
 SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
-                      int strategy, std::vector<DevSim> &devs)
+                      int strategy, int64_t bucket_bytes, std::vector<DevSim> &devs)
 {
     SetLayout L;
     L.n = (int)plans.size();
@@ -170,21 +128,30 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     L.total_items = binned ? bitems : items;
     if (binned) {
         // histogram mode when every simulation's tile histogram fits in LDS and the row
-        // matrix fits its budget
-        // a row never holds more points than one bucket slice can take
+        // matrix fits its budget.  Rows: about kTargetRows per launch, but never more items
+        // than one bucket slice can take, and small enough that a slice still holds
+        // kMinSliceRows rows (blocks) when the work runs in many slices; coarser only when the
+        // row matrix would outgrow its budget.
         const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
-        const int64_t row_items = std::max<int64_t>(1, bucket_cap(ctx, precision, per_item) / per_item);
-        L.items_per_row = std::max<int64_t>(1, std::min(ceil_div(bitems, kTargetRows), row_items));
+        const int64_t slice_items = std::max<int64_t>(
+            1, std::min(bucket_cap(bucket_bytes, precision, per_item), std::max(per_item, bitems * per_item)) / per_item);
+        int64_t ipr = std::max<int64_t>(1, std::min(ceil_div(bitems, kTargetRows), slice_items / kMinSliceRows));
         int64_t rows = 0, hsize = 0;
-        for (DevSim &d : devs) {
-            L.max_tiles = std::max(L.max_tiles, d.n_tiles);
-            d.items_per_row = (int32_t)L.items_per_row;
-            d.n_rows = ceil_div(d.n_bitems, L.items_per_row);
-            d.row_base = rows;
-            d.hbase = hsize;
-            rows += d.n_rows;
-            hsize += d.n_rows * d.n_tiles;
+        for (;;) {
+            rows = hsize = 0;
+            for (DevSim &d : devs) {
+                L.max_tiles = std::max(L.max_tiles, d.n_tiles);
+                d.items_per_row = (int32_t)ipr;
+                d.n_rows = ceil_div(d.n_bitems, ipr);
+                d.row_base = rows;
+                d.hbase = hsize;
+                rows += d.n_rows;
+                hsize += d.n_rows * d.n_tiles;
+            }
+            if (hsize * 4 <= kHistBudget || ipr >= slice_items) break;
+            ipr = std::min(slice_items, ipr * 2);
         }
+        L.items_per_row = ipr;
         L.total_rows = rows;
         L.hist = L.max_tiles <= fsm::kMaxHistTiles && hsize * 4 <= kHistBudget;
         if (!L.hist) L.max_tiles = 0;
@@ -199,7 +166,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     if (binned) {
         const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
         const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
-        int64_t cap = bucket_cap(ctx, precision, per_item);
+        int64_t cap = bucket_cap(bucket_bytes, precision, per_item);
         cap = std::min<int64_t>(cap, std::max<int64_t>(per_item, bitems * per_item));
         L.per_slice = std::max<int64_t>(1, cap / per_item);
         L.per_slice = std::min<int64_t>(L.per_slice, std::max<int64_t>(1, bitems));
@@ -228,49 +195,63 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     L.tbase = take(sizeof(int64_t) * L.n);
     L.binned = take(sizeof(uint64_t) * L.n);
     L.evals = take(sizeof(int64_t) * L.n);
+    // table sizes follow from the plan's shape, so a plan built without its tables lays out
+    // the same image
     for (const Plan &P : plans) {
-        L.pT.push_back(take(sizeof(double) * P.pT.size()));
-        L.pTf.push_back(take(sizeof(float) * 4 * (size_t)P.z_n * P.N));
-        L.cs.push_back(take(sizeof(double) * P.cs.size()));
-        L.csf.push_back(take(sizeof(float) * P.cs.size()));
-        L.xc.push_back(take(sizeof(double) * P.xc.size()));
-        L.gm.push_back(take(sizeof(double) * P.gm.size()));
+        const size_t pts = (size_t)P.z_n * P.N, angles = (size_t)P.z_n * P.S;
+        L.pT.push_back(take(sizeof(double) * 3 * pts));
+        L.pTf.push_back(take(sizeof(float) * 4 * pts));
+        L.cs.push_back(take(sizeof(double) * 2 * angles));
+        L.csf.push_back(take(sizeof(float) * 2 * angles));
+        L.xc.push_back(take(sizeof(double) * (size_t)P.n_steps));
+        L.gm.push_back(take(sizeof(double) * (size_t)P.z_n * P.n_groups));
     }
     L.total = o;
     return L;
 }
 
-int ensure(fsm_ctx *ctx, size_t dev_bytes, size_t host_bytes, size_t n_out)
+int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size_t n_out)
 {
-    if (ctx->d_bytes < dev_bytes) {
-        if (ctx->d_ws) {
-            hipFree(ctx->d_ws);
-            for (auto &g : ctx->graph_cache) hipGraphExecDestroy(g.second);
-            ctx->graph_cache.clear();
+    if (w.d_bytes < dev_bytes) {
+        if (w.d_ws) {
+            hipFree(w.d_ws);
+            if (&w == &ctx->ws) {
+                // captured graphs point into the old workspace
+                for (auto &g : ctx->graph_cache) hipGraphExecDestroy(g.second);
+                ctx->graph_cache.clear();
+            }
         }
-        ctx->d_ws = nullptr;
-        ctx->d_bytes = 0;
-        hipError_t e = hipMalloc(&ctx->d_ws, dev_bytes);
-        if (e != hipSuccess) { ctx->d_ws = nullptr; return hip_err(ctx, e, "hipMalloc(workspace)"); }
-        ctx->d_bytes = dev_bytes;
+        w.d_ws = nullptr;
+        w.d_bytes = 0;
+        hipError_t e = hipMalloc(&w.d_ws, dev_bytes);
+        if (e != hipSuccess) { w.d_ws = nullptr; return hip_err(ctx, e, "hipMalloc(workspace)"); }
+        w.d_bytes = dev_bytes;
     }
-    if (ctx->h_bytes < host_bytes) {
-        if (ctx->h_ws) hipHostFree(ctx->h_ws);
-        ctx->h_ws = nullptr;
-        ctx->h_bytes = 0;
-        hipError_t e = hipHostMalloc(&ctx->h_ws, host_bytes, hipHostMallocDefault);
-        if (e != hipSuccess) { ctx->h_ws = nullptr; return hip_err(ctx, e, "hipHostMalloc(staging)"); }
-        ctx->h_bytes = host_bytes;
+    if (w.h_bytes < host_bytes) {
+        if (w.h_ws) hipHostFree(w.h_ws);
+        w.h_ws = nullptr;
+        w.h_bytes = 0;
+        hipError_t e = hipHostMalloc(&w.h_ws, host_bytes, hipHostMallocDefault);
+        if (e != hipSuccess) { w.h_ws = nullptr; return hip_err(ctx, e, "hipHostMalloc(staging)"); }
+        w.h_bytes = host_bytes;
     }
-    if (ctx->h_out_n < n_out) {
-        if (ctx->h_out) hipHostFree(ctx->h_out);
-        ctx->h_out = nullptr;
-        ctx->h_out_n = 0;
-        hipError_t e = hipHostMalloc((void **)&ctx->h_out, sizeof(fsm_rough) * n_out, hipHostMallocDefault);
-        if (e != hipSuccess) { ctx->h_out = nullptr; return hip_err(ctx, e, "hipHostMalloc(results)"); }
-        ctx->h_out_n = n_out;
+    if (w.h_out_n < n_out) {
+        if (w.h_out) hipHostFree(w.h_out);
+        w.h_out = nullptr;
+        w.h_out_n = 0;
+        hipError_t e = hipHostMalloc((void **)&w.h_out, sizeof(fsm_rough) * n_out, hipHostMallocDefault);
+        if (e != hipSuccess) { w.h_out = nullptr; return hip_err(ctx, e, "hipHostMalloc(results)"); }
+        w.h_out_n = n_out;
     }
     return FSM_OK;
+}
+
+void release(Workspace &w)
+{
+    if (w.d_ws) hipFree(w.d_ws);
+    if (w.h_ws) hipHostFree(w.h_ws);
+    if (w.h_out) hipHostFree(w.h_out);
+    w = Workspace();
 }
 
 // Fill the uploaded part of the image (host offsets are relative to L.sims).
@@ -403,6 +384,7 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
         bb.bkey = dev + L.bkey;
         bb.bidx = reinterpret_cast<uint16_t *>(dev + L.bidx);
         bb.cap = L.cap;
+        bb.tile0 = 0;
         bb.hist = L.hist ? reinterpret_cast<uint32_t *>(dev + L.hist_m) : nullptr;
         bb.chunk = L.hist ? reinterpret_cast<uint32_t *>(dev + L.chunk) : nullptr;
         bb.max_tiles = (int32_t)L.max_tiles;
@@ -410,13 +392,29 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
         ctx->stages_used = 0;
         size_t slice = 0;
         if (L.hist) {
-            // d_bbase holds each simulation's first row in this mode
+            // d_bbase holds each simulation's first row in this mode.  A slice works on the
+            // tiles of the simulations its rows belong to (every simulation has a row).
+            auto sim_of_row = [&](int64_t r) {
+                int lo = 0, hi = L.n - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) / 2;
+                    if (devs[mid].row_base <= r) lo = mid; else hi = mid - 1;
+                }
+                return lo;
+            };
             int64_t r0 = 0;
             do {
                 const int64_t r1 = std::min<int64_t>(L.total_rows, r0 + L.rows_per_slice);
-                he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, r0, r1, bb,
-                                            r0 == 0, r1 >= L.total_rows, L.precision, L.sx, L.sy,
-                                            st1, d_binned, s, stage_marks(ctx, slice++, capturing));
+                const DevSim &da = devs[sim_of_row(r0)], &db = devs[sim_of_row(r1 - 1)];
+                const int64_t t0 = da.tile_base, t1 = db.tile_base + db.n_tiles;
+                fsm::BinBuffers bs = bb;
+                bs.tile0 = t0;
+                bs.counts += t0;
+                bs.offsets += t0;
+                bs.cursor += t0;
+                he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, t1 - t0, r0, r1, bs,
+                                            L.precision, L.sx, L.sy, st1, d_binned, s,
+                                            stage_marks(ctx, slice++, capturing));
                 if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
                 r0 = r1;
             } while (r0 < L.total_rows);
@@ -445,6 +443,23 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
     return FSM_OK;
 }
 
+int enqueue_set(fsm_ctx *ctx, Workspace &w, const SetLayout &L, const std::vector<Plan> &plans,
+                std::vector<DevSim> &devs, const std::vector<void *> &zmaps, hipStream_t s,
+                bool profile)
+{
+    char *dev = static_cast<char *>(w.d_ws);
+    char *host = static_cast<char *>(w.h_ws);
+    fill_image(L, plans, devs, zmaps, dev, host);
+    hipError_t e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
+    // the profiling events are the context's: only the synchronous calls record them
+    int rc = launch_set(ctx, L, devs, plans, dev, s, !profile);
+    if (rc != FSM_OK) return rc;
+    e = hipMemcpyAsync(w.h_out, dev + L.out, sizeof(fsm_rough) * L.n, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
+    return FSM_OK;
+}
+
 // Plan, upload, launch and wait for a set of simulations; results to out[0..n).
 int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void *> &zmaps,
             int precision, fsm_rough *out, hipStream_t user)
@@ -452,12 +467,12 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
     std::vector<DevSim> devs;
-    const SetLayout L = make_layout(ctx, plans, precision, ctx->strategy, devs);
-    int rc = ensure(ctx, L.total, L.total - L.sims, (size_t)L.n);
+    const SetLayout L = make_layout(ctx, plans, precision, ctx->strategy, ctx->bucket_bytes, devs);
+    Workspace &w = ctx->ws;
+    int rc = ensure(ctx, w, L.total, L.total - L.sims, (size_t)L.n);
     if (rc != FSM_OK) return rc;
-    char *dev = static_cast<char *>(ctx->d_ws);
-    char *host = static_cast<char *>(ctx->h_ws);
-    fill_image(L, plans, devs, zmaps, dev, host);
+    char *dev = static_cast<char *>(w.d_ws);
+    char *host = static_cast<char *>(w.h_ws);
 
     hipStream_t s = user;
     if (ctx->graphs) {
@@ -477,14 +492,15 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
     ctx->timings.valid = 0;
     ctx->stages_used = 0;
     mark(ctx, 0, s, false);
-    e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
     if (ctx->graphs) {
+        fill_image(L, plans, devs, zmaps, dev, host);
+        e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
         char key[256];
         std::snprintf(key, sizeof key, "%d/%d/%d/%lld/%lld/%lld/%lld/%d/%d/%d/%lld/%lld/%p", L.precision,
                       L.strategy, L.n, (long long)L.total_tiles, (long long)L.total_items,
                       (long long)L.per_slice, (long long)L.cap, L.sx, L.sy, (int)L.hist,
-                      (long long)L.total_rows, (long long)L.rows_per_slice, ctx->d_ws);
+                      (long long)L.total_rows, (long long)L.rows_per_slice, w.d_ws);
         std::string k(key);
         for (int i = 0; i < L.n; ++i) k += "/" + std::to_string(plans[i].nx) + "x" + std::to_string(plans[i].ny);
         auto it = ctx->graph_cache.find(k);
@@ -507,23 +523,28 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
         if (e != hipSuccess) return hip_err(ctx, e, "hipGraphLaunch");
         mark(ctx, 2, s, false);
         mark(ctx, 3, s, false);
+        e = hipMemcpyAsync(w.h_out, dev + L.out, sizeof(fsm_rough) * L.n, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
     } else {
-        rc = launch_set(ctx, L, devs, plans, dev, s, false);
+        rc = enqueue_set(ctx, w, L, plans, devs, zmaps, s, true);
         if (rc != FSM_OK) return rc;
     }
-    e = hipMemcpyAsync(ctx->h_out, dev + L.out, sizeof(fsm_rough) * L.n, hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
     mark(ctx, 4, s, false);
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
     collect(ctx, !ctx->graphs);
-    if (out) std::memcpy(out, ctx->h_out, sizeof(fsm_rough) * L.n);
+    if (out) std::memcpy(out, w.h_out, sizeof(fsm_rough) * L.n);
     return FSM_OK;
 }
 
 bool valid_precision(int p) { return p == FSM_F64 || p == FSM_F32; }
 
-}  // namespace
+}  // namespace rt
+}  // namespace fsm
+
+using namespace fsm::rt;
+using fsm::DevSim;
+using fsm::Plan;
 
 extern "C" {
 
@@ -559,13 +580,11 @@ int fsm_plan(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, int
         out->n_evals = P.n_evals;
         out->n_cells = grid->nx * grid->ny;
         out->zmap_bytes = out->n_cells * (precision == FSM_F64 ? 8 : 4);
-        P.pT.resize((size_t)P.z_n * P.N * 3);
-        P.cs.resize((size_t)P.z_n * P.S * 2);
-        P.xc.resize((size_t)P.n_steps);
         fsm_ctx probe;
         std::vector<Plan> one{P};
         std::vector<DevSim> devs;
-        out->workspace_bytes = (int64_t)make_layout(&probe, one, precision, fsm::kStrategyBinned, devs).total;
+        out->workspace_bytes = (int64_t)make_layout(&probe, one, precision, fsm::kStrategyBinned,
+                                                    probe.bucket_bytes, devs).total;
         return FSM_OK;
     } catch (const std::bad_alloc &) {
         return FSM_ENOMEM;
@@ -621,9 +640,7 @@ void fsm_ctx_destroy(fsm_ctx *ctx)
             if (e) hipEventDestroy(static_cast<hipEvent_t>(e));
     if (ctx->join) hipEventDestroy(ctx->join);
     if (ctx->own) hipStreamDestroy(ctx->own);
-    if (ctx->d_ws) hipFree(ctx->d_ws);
-    if (ctx->h_ws) hipHostFree(ctx->h_ws);
-    if (ctx->h_out) hipHostFree(ctx->h_out);
+    release(ctx->ws);
     delete ctx;
 }
 
@@ -739,11 +756,12 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
         plans[0].ny = grid->ny;
         plans[0].N = 1;
         std::vector<DevSim> devs;
-        const SetLayout L = make_layout(ctx, plans, precision, fsm::kStrategyScatter, devs);
-        int rc = ensure(ctx, L.total, L.total - L.sims, 1);
+        const SetLayout L = make_layout(ctx, plans, precision, fsm::kStrategyScatter,
+                                        ctx->bucket_bytes, devs);
+        int rc = ensure(ctx, ctx->ws, L.total, L.total - L.sims, 1);
         if (rc != FSM_OK) return rc;
-        char *dev = static_cast<char *>(ctx->d_ws);
-        char *host = static_cast<char *>(ctx->h_ws);
+        char *dev = static_cast<char *>(ctx->ws.d_ws);
+        char *host = static_cast<char *>(ctx->ws.h_ws);
         std::vector<void *> zmaps{const_cast<void *>(zmap_dev)};
         fill_image(L, plans, devs, zmaps, dev, host);
         hipStream_t s = static_cast<hipStream_t>(stream);
@@ -763,13 +781,13 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
                                    reinterpret_cast<fsm::RoughState *>(dev + L.state), nullptr, nullptr,
                                    reinterpret_cast<fsm_rough *>(dev + L.out), s);
         if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
-        e = hipMemcpyAsync(ctx->h_out, dev + L.out, sizeof(fsm_rough), hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(ctx->ws.h_out, dev + L.out, sizeof(fsm_rough), hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
         mark(ctx, 4, s, false);
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
         collect(ctx, true);
-        *out = *ctx->h_out;
+        *out = *ctx->ws.h_out;
         return FSM_OK;
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");

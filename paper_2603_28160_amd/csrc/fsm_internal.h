@@ -121,6 +121,9 @@ struct RoughState {
 
 // Buffers of the binned strategy (device memory).
 struct BinBuffers {
+    // counts, offsets and cursor are indexed by (global tile - tile0): a slice of the histogram
+    // mode covers only the tiles of the simulations its rows belong to
+    int64_t tile0;
     uint32_t *counts;        // [n_tiles] points per tile
     uint32_t *offsets;       // [n_tiles + 1] bucket starts
     uint32_t *cursor;        // [n_tiles] write cursors (run mode)
@@ -155,12 +158,15 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
                         uint64_t *d_binned, void *stream, const StageEvents *marks = nullptr);
 // Histogram mode of the binned strategy, one slice of rows [row_begin, row_end): per-block
 // LDS histograms written as rows, a chunked column scan into per-(row, tile) offsets, a write
-// pass that claims slots with LDS atomics only, then the per-tile LDS reduction.
+// pass that claims slots with LDS atomics only, then the per-tile LDS reduction.  The slice
+// touches only the n_tiles tiles from bb.tile0 on (those of the simulations its rows belong
+// to); a simulation's tiles are initialised in the slice holding its first row and their
+// first roughness pass runs in the slice holding its last row.
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
                       const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
-                      int64_t row_end, const BinBuffers &bb, bool first_slice, bool last_slice,
-                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                      void *stream, const StageEvents *marks = nullptr);
+                      int64_t row_end, const BinBuffers &bb, int precision, int sx, int sy,
+                      TileStat1 *st1, uint64_t *d_binned, void *stream,
+                      const StageEvents *marks = nullptr);
 // Tiled roughness.  with_pass1: run the first pass (decoding scatter keys if `decode`);
 // otherwise its tile partials are already in st1.  out: one record per simulation.
 int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, int64_t n_tiles,

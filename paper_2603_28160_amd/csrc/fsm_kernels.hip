@@ -665,7 +665,8 @@ __device__ __forceinline__ void sim_rows(const DevSim &d, int64_t lo, int64_t hi
     b = hi < e ? hi : e;
 }
 
-// Column sums of the row matrix over chunks of row_chunk rows of the slice [r0, r1).
+// Column sums of the row matrix over chunks of row_chunk rows of the slice [r0, r1), for the
+// n_tiles tiles from bb.tile0 on.
 __global__ __launch_bounds__(kBlock) void hist_colsum(const DevSim *__restrict__ sims, int n_sims,
                                                       const int64_t *__restrict__ tile_base,
                                                       int64_t n_tiles, int64_t r0, int64_t r1,
@@ -673,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void hist_colsum(const DevSim *__restrict__
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n_chunks * n_tiles; x += stride) {
-        const int64_t c = x / n_tiles, t = x - c * n_tiles;
+        const int64_t c = x / n_tiles, t = bb.tile0 + (x - c * n_tiles);
         const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
         const DevSim &d = sims[si];
         int64_t a, b;
@@ -708,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void hist_apply(const DevSim *__restrict__ 
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n_chunks * n_tiles; x += stride) {
-        const int64_t c = x / n_tiles, t = x - c * n_tiles;
+        const int64_t c = x / n_tiles, t = bb.tile0 + (x - c * n_tiles);
         const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
         const DevSim &d = sims[si];
         int64_t a, b;
@@ -743,7 +744,7 @@ __global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ 
         const int64_t i1 = i0 + d.items_per_row < d.n_bitems ? i0 + d.items_per_row : d.n_bitems;
         const int T = (int)d.n_tiles;
         const FSM_GLOBAL uint32_t *row = gptr(bb.hist) + d.hbase + lr * T;
-        const FSM_GLOBAL uint32_t *off = gptr(bb.offsets) + d.tile_base;
+        const FSM_GLOBAL uint32_t *off = gptr(bb.offsets) + (d.tile_base - bb.tile0);
         for (int t = tid; t < T; t += kBlock) cur[t] = off[t] + row[t];
         __syncthreads();
         const int64_t cap = bb.cap;
@@ -884,11 +885,15 @@ __device__ __forceinline__ TileGeom tile_geom(const DevSim &d, int64_t t)
     return g;
 }
 
+// Tiles [bb.tile0, bb.tile0 + n_tiles).  first_slice / last_slice: whether the tiles start
+// from +inf (else from the Z-map) and whether the first roughness pass runs; -1 takes both per
+// simulation from the slice's rows [r0, r1) (histogram mode).
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__ sims, int n_sims,
                                                       const int64_t *__restrict__ tile_base,
                                                       int64_t n_tiles, BinBuffers bb, int first_slice,
-                                                      int last_slice, TileStat1 *__restrict__ st1,
+                                                      int last_slice, int64_t r0, int64_t r1,
+                                                      TileStat1 *__restrict__ st1,
                                                       uint64_t *__restrict__ binned)
 {
     using KT = KeyOf<PREC>;
@@ -899,24 +904,27 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
     const FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
     const FSM_GLOBAL uint32_t *offsets = gptr(bb.offsets);
     const int tid = threadIdx.x;
-    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
+        const int64_t t = bb.tile0 + tl;
         const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
         const DevSim d = sims[si];
+        const bool first = first_slice >= 0 ? first_slice != 0 : d.row_base >= r0;
+        const bool last = last_slice >= 0 ? last_slice != 0 : d.row_base + d.n_rows <= r1;
         const TileGeom g = tile_geom(d, t);
         const int sx = d.sx, TX = 1 << sx, TC = TX << d.sy;
         FSM_GLOBAL Key *Z = gptr(static_cast<Key *>(d.zmap)) + g.j0 * d.nx + g.i0;
         for (int l = tid; l < TC; l += kBlock) {
             const int li = l & (TX - 1), lj = l >> sx;
             Key v = KT::inf;
-            if (!first_slice && li < g.w && lj < g.h) v = KT::enc(Z[(int64_t)lj * d.nx + li]);
+            if (!first && li < g.w && lj < g.h) v = KT::enc(Z[(int64_t)lj * d.nx + li]);
             lds[l] = v;
         }
         __syncthreads();
         // entries past the capacity were never written (the planner sizes slices so that none
         // are dropped); the clamp keeps the reads inside the bucket arrays regardless
         const int64_t cap = bb.cap;
-        const uint32_t e0 = (int64_t)offsets[t] < cap ? offsets[t] : (uint32_t)cap;
-        const uint32_t e1 = (int64_t)offsets[t + 1] < cap ? offsets[t + 1] : (uint32_t)cap;
+        const uint32_t e0 = (int64_t)offsets[tl] < cap ? offsets[tl] : (uint32_t)cap;
+        const uint32_t e1 = (int64_t)offsets[tl + 1] < cap ? offsets[tl + 1] : (uint32_t)cap;
         uint32_t e = e0 + tid;
         for (; e + 3 * kBlock < e1; e += 4 * kBlock) {
             Key k4[4];
@@ -941,10 +949,10 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
             if (li < g.w && lj < g.h) {
                 const Key k = KT::enc(lds[l]);
                 Z[(int64_t)lj * d.nx + li] = k;
-                if (last_slice) acc.add(KT::height(k), lj == rj, li == ci);
+                if (last) acc.add(KT::height(k), lj == rj, li == ci);
             }
         }
-        if (last_slice) {
+        if (last) {
             const TileStat1 s = acc.reduce();
             if (tid == 0) st1[t] = s;
         }
@@ -1197,15 +1205,15 @@ void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
     if (ib > 0)
         hipLaunchKernelGGL((bin_points<PREC, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
     stage(marks, 3, s);
-    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
     stage(marks, 4, s);
 }
 
 template <int PREC>
 void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
                 const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin, int64_t row_end,
-                const BinBuffers &bb, bool first_slice, bool last_slice, int sx, int sy,
-                TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
+                const BinBuffers &bb, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                hipStream_t s, const StageEvents *marks)
 {
     const int64_t nr = row_end - row_begin;
     const int rb = (int)(nr < kMaxGrid ? nr : kMaxGrid);
@@ -1231,7 +1239,7 @@ void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
     if (rb > 0)
         hipLaunchKernelGGL(hist_write<PREC>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
     stage(marks, 3, s);
-    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, st1, d_binned);
+    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, -1, -1, row_begin, row_end, st1, d_binned);
     stage(marks, 4, s);
 }
 
@@ -1253,15 +1261,14 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
 
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
                       const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
-                      int64_t row_end, const BinBuffers &bb, bool first_slice, bool last_slice,
-                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                      void *stream, const StageEvents *marks)
+                      int64_t row_end, const BinBuffers &bb, int precision, int sx, int sy,
+                      TileStat1 *st1, uint64_t *d_binned, void *stream, const StageEvents *marks)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64)
-        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     else
-        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     return (int)hipGetLastError();
 }
 

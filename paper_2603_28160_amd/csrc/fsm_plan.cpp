@@ -189,6 +189,9 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     P.tl_s = std::sin(t.tilt_lead);
     P.ts_c = std::cos(t.tilt_side);
     P.ts_s = std::sin(t.tilt_side);
+    P.n_groups = (N + kGroup - 1) / kGroup;
+    P.x_hi = x_hi;
+    P.y_hi = y_hi;
     if (!tables) return FSM_OK;
 
     // --- spindle angle of Eq. (3), alpha = phi + theta_K - omega t with omega t = 2 pi m / S,
@@ -215,7 +218,6 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     // The slack eps covers rounding of the box and of single-precision points.
     const double eps = 1e-5 * (reach + 1.0);
     const double half = 63.0 * M_PI / (double)S;
-    P.n_groups = (N + kGroup - 1) / kGroup;
     P.gm.assign((size_t)Z * P.n_groups, 0.0);
     for (int K = 0; K < Z; ++K) {
         for (int gi = 0; gi < P.n_groups; ++gi) {
@@ -231,8 +233,6 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
             P.gm[(size_t)K * P.n_groups + gi] = rho + sag + eps;
         }
     }
-    P.x_hi = x_hi;
-    P.y_hi = y_hi;
     P.cull_reach = reach + eps;
     return FSM_OK;
 }

@@ -1,0 +1,87 @@
+// fsm_runtime.h -- the context and the launch machinery shared by the C ABI (fsm_api.cpp) and
+// the serving loop (fsm_serve.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fsm_internal.h"
+
+namespace fsm {
+namespace rt {
+
+// Device workspace, pinned host staging and pinned result records of one stream of work.
+struct Workspace {
+    void *d_ws = nullptr;
+    size_t d_bytes = 0;
+    void *h_ws = nullptr;
+    size_t h_bytes = 0;
+    fsm_rough *h_out = nullptr;
+    size_t h_out_n = 0;
+};
+
+// Shape and layout of one launch over a set of simulations.
+struct SetLayout {
+    int n = 0, precision = 0, strategy = 0, sx = 7, sy = 6;
+    int64_t total_tiles = 0, total_items = 0, per_slice = 0, cap = 0;
+    int max_n = 1;
+    // histogram mode of the binned strategy (no global atomics)
+    bool hist = false;
+    int64_t total_rows = 0, rows_per_slice = 0, max_tiles = 0, items_per_row = 1;
+    // device-only region
+    size_t st1 = 0, st2 = 0, state = 0, out = 0, counts = 0, offsets = 0, cursor = 0, bsum = 0,
+           bkey = 0, bidx = 0, hist_m = 0, chunk = 0;
+    size_t scratch_end = 0;
+    // uploaded region
+    size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0;
+    std::vector<size_t> pT, pTf, cs, csf, xc, gm;
+    size_t total = 0;
+};
+
+}  // namespace rt
+}  // namespace fsm
+
+struct fsm_ctx {
+    int device = 0;
+    std::string err;
+    fsm::rt::Workspace ws;       // workspace of the synchronous calls
+    bool profiling = false;
+    hipEvent_t ev[5] = {};       // upload, fill, z-map, roughness, end
+    std::vector<fsm::StageEvents> stage_ev;   // per binned slice: the five stage events
+    int stages_used = 0;                      // slices of the last profiled call
+    fsm_timings timings = {};
+    int strategy = fsm::kStrategyBinned;
+    int64_t bucket_bytes = (int64_t)4 << 30;
+    bool graphs = false;
+    hipStream_t own = nullptr;   // stream used for graph capture and replay
+    hipEvent_t join = nullptr;
+    std::map<std::string, hipGraphExec_t> graph_cache;
+    size_t max_lds = 65536;
+};
+
+
+namespace fsm {
+namespace rt {
+
+int set_err(fsm_ctx *ctx, int code, const std::string &msg);
+int hip_err(fsm_ctx *ctx, hipError_t e, const char *where);
+bool valid_precision(int p);
+// Layout of one launch over `plans`; bucket_bytes bounds the bucket arrays (slices beyond).
+SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
+                      int strategy, int64_t bucket_bytes, std::vector<DevSim> &devs);
+// Grow w to at least the given sizes (device workspace, host staging, result records).
+int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size_t n_out);
+void release(Workspace &w);
+// Upload the image of L from w's staging, launch every kernel and queue the copy of the
+// result records into w.h_out, all on stream s; returns without waiting.  profile: record the
+// context's timing events (synchronous calls only).
+int enqueue_set(fsm_ctx *ctx, Workspace &w, const SetLayout &L, const std::vector<Plan> &plans,
+                std::vector<DevSim> &devs, const std::vector<void *> &zmaps, hipStream_t s,
+                bool profile);
+
+}  // namespace rt
+}  // namespace fsm

@@ -1,0 +1,81 @@
+"""GPU tests of the serving loop (fsm_serve_run): requests of different sizes arriving over time
+are batched and overlapped on several streams, and each result must equal the same simulation
+run alone, bit for bit in both precisions (every kernel treats a simulation of a batch exactly
+as it treats it alone)."""
+import numpy as np
+import pytest
+
+from paper_2603_28160_amd import _abi, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28160_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def mix(n, side_max=512, spread=0.02):
+    rng = np.random.default_rng([28160, 44, n])
+    arrivals = np.sort(rng.uniform(0.0, spread, n))
+    return [(W.random_sim(4, 500 + i, side_max=side_max), float(a)) for i, a in enumerate(arrivals)]
+
+
+def same_rough(a, b):
+    for k, v in a.items():
+        w = b[k]
+        if isinstance(v, float) and np.isnan(v):
+            assert np.isnan(w), k
+        else:
+            assert v == w, (k, v, w)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_served_results_equal_alone(ctx, prec):
+    reqs = mix(16)
+    zmaps = [ctx.new_zmap(s.grid, prec) for s, _ in reqs]
+    print(f"[gpu] serve {len(reqs)} requests {prec}", flush=True)
+    res = ctx.fsm_serve_run([(s, a, z) for (s, a), z in zip(reqs, zmaps)], prec,
+                            n_slots=3, max_batch=4)
+    assert all(r["status"] == 0 for r in res)
+    # the mix really mixed: some batch held several requests or batches overlapped in time
+    b = {}
+    for r in res:
+        b.setdefault(r["batch"], []).append(r)
+    iv = sorted((v[0]["start_s"], v[0]["done_s"]) for v in b.values())
+    overlapped = any(iv[k + 1][0] < iv[k][1] for k in range(len(iv) - 1))
+    assert overlapped or max(len(v) for v in b.values()) > 1
+    for k, ((s, a), z) in enumerate(zip(reqs, zmaps)):
+        assert res[k]["start_s"] >= a - 1e-6
+        z1, r1 = ctx.fsm_simulate(s, prec)
+        assert np.array_equal(z.cpu().numpy(), z1.cpu().numpy()), k
+        same_rough(res[k]["rough"], r1)
+
+
+def test_server_held_maps_return_the_same_roughness(ctx):
+    reqs = mix(10, spread=0.005)
+    print("[gpu] serve with server-held maps", flush=True)
+    res = ctx.fsm_serve_run([(s, a, None) for s, a in reqs], "f32", n_slots=2, max_batch=3)
+    for k, (s, _) in enumerate(reqs):
+        assert res[k]["status"] == 0
+        _, r1 = ctx.fsm_simulate(s, "f32")
+        same_rough(res[k]["rough"], r1)
+
+
+def test_rejected_request_does_not_stall_others(ctx):
+    reqs = mix(4, side_max=256)
+    huge = reqs[0][0].replace(grid=W.centred_grid(8192, 8192, reqs[0][0].grid.dd))
+    items = [(s, a, None) for s, a in reqs] + [(huge, 0.0, None)]
+    print("[gpu] serve with an oversized request", flush=True)
+    res = ctx.fsm_serve_run(items, "f32", n_slots=2, max_batch=2, arena_bytes=64 << 20)
+    assert res[-1]["status"] == _abi.ENOMEM and res[-1]["batch"] == -1
+    for k, (s, _) in enumerate(reqs):
+        assert res[k]["status"] == 0
+        _, r1 = ctx.fsm_simulate(s, "f32")
+        same_rough(res[k]["rough"], r1)
