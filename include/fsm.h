@@ -186,6 +186,15 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
                                        slices of the evaluation range */
 #define FSM_OPT_GRAPHS 3           /* nonzero: capture batch launch sequences into HIP graphs
                                        and replay them for batches of the same shape */
+#define FSM_OPT_TILE_SHAPE 4      /* cell tile of the binned Z-map and of the roughness partials:
+                                       16 * log2(width) + log2(height), both 16..256 cells and the
+                                       tile's keys at most 64 KiB; 0 (default): 64 x 64 cells in
+                                       double precision, 128 x 64 in single */
+#define FSM_OPT_TARGET_ROWS 5     /* binning rows (one workgroup each) per launch of the
+                                       histogram mode, 256..65536; 0 (default): 4096 */
+#define FSM_OPT_AUTOTUNED 6       /* nonzero (default): a call whose workload class fsm_autotune
+                                       has measured uses the parameters it kept; zero: the
+                                       context's own options */
 #define FSM_ZMAP_BINNED 0
 #define FSM_ZMAP_SCATTER 1
 
@@ -222,6 +231,28 @@ typedef struct fsm_job {
  * same shape comes again.  Returns after the work has finished. */
 int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision,
                        fsm_rough *out, void *stream);
+
+/* Launch parameters chosen by fsm_autotune. */
+typedef struct fsm_tune_result {
+    int32_t strategy;        /* FSM_ZMAP_BINNED or FSM_ZMAP_SCATTER */
+    int32_t tile_shape;      /* FSM_OPT_TILE_SHAPE encoding */
+    int32_t target_rows;     /* FSM_OPT_TARGET_ROWS value */
+    int32_t n_tried;         /* candidates timed */
+    float best_ms;           /* time of one launch sequence with the kept parameters */
+    float default_ms;        /* the same with the default parameters */
+} fsm_tune_result;
+
+/* The project's autotuner for the batched launch.  Times candidate launch parameters (Z-map
+ * strategy, cell tile shape, histogram rows per launch) on the n jobs run as one batch, by
+ * coordinate search from the defaults, each candidate the best of two timed runs after one
+ * untimed one, and keeps the fastest for the jobs' workload class (precision, number of
+ * simulations, and the binary orders of magnitude of their total cells and edge-point
+ * evaluations).  Later fsm_simulate / fsm_simulate_batch / fsm_serve_run calls of the same
+ * class use them while FSM_OPT_AUTOTUNED is on.  Parameters change only the launch, not the
+ * Z-maps; roughness sums may differ in the last bits with the tile shape.  The jobs' Z-maps
+ * are overwritten.  out: the kept parameters and timings. */
+int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tune_result *out,
+                 void *stream);
 
 /* Roughness of an existing Z-map in device memory (+inf = empty cell), same estimator as
  * fsm_simulate.  n_evals and n_binned of the result are zero. */

@@ -361,14 +361,16 @@ int or_simulate_window(const or_tool *t, const or_cut *c, const or_grid *g,
  * moves (+inf if none); top: greatest height of one that can reach it (-inf if none).  Any
  * per-cell minimum over moved positions is +inf or lies in [lo, min(hi, top)], and is finite
  * whenever hi is.  With delta = 0, lo and hi equal the Z-map. */
-int or_cell_bounds(const or_tool *t, const or_cut *c, const or_grid *g, double delta,
-                   double *lo, double *hi, double *top)
+int or_cell_bounds_window(const or_tool *t, const or_cut *c, const or_grid *g, double delta,
+                          long long i0, long long i1, long long j0, long long j1,
+                          double *lo, double *hi, double *top)
 {
     if (!lo || !hi || !top || !(delta >= 0.0)) return -1;
+    if (i0 < 0 || j0 < 0 || i1 > g->nx || j1 > g->ny || i0 >= i1 || j0 >= j1) return -1;
     chain ch;
     int rc = chain_init(t, c, g, &ch);
     if (rc) return rc;
-    const long long cells = g->nx * g->ny;
+    const long long wx = i1 - i0, cells = wx * (j1 - j0);
     for (long long k = 0; k < cells; ++k) {
         lo[k] = INFINITY;
         hi[k] = INFINITY;
@@ -393,9 +395,9 @@ int or_cell_bounds(const or_tool *t, const or_cut *c, const or_grid *g, double d
                     const int sure = ia == ib && ja == jb;
                     for (double fj = ja; fj <= jb; fj += 1.0) {
                         for (double fi = ia; fi <= ib; fi += 1.0) {
-                            if (fi < 0.0 || fj < 0.0 || fi >= (double)g->nx || fj >= (double)g->ny)
+                            if (fi < (double)i0 || fj < (double)j0 || fi >= (double)i1 || fj >= (double)j1)
                                 continue;
-                            const long long k = (long long)fj * g->nx + (long long)fi;
+                            const long long k = ((long long)fj - j0) * wx + ((long long)fi - i0);
                             if (w[2] < lo[k]) lo[k] = w[2];
                             if (w[2] > top[k]) top[k] = w[2];
                             if (sure && w[2] < hi[k]) hi[k] = w[2];
@@ -407,6 +409,12 @@ int or_cell_bounds(const or_tool *t, const or_cut *c, const or_grid *g, double d
     }
     free(ch.pT);
     return 0;
+}
+
+int or_cell_bounds(const or_tool *t, const or_cut *c, const or_grid *g, double delta,
+                   double *lo, double *hi, double *top)
+{
+    return or_cell_bounds_window(t, c, g, delta, 0, g->nx, 0, g->ny, lo, hi, top);
 }
 
 /* ---- roughness --------------------------------------------------------------------------- */

@@ -105,6 +105,11 @@ int or_simulate_window(const or_tool *t, const or_cut *c, const or_grid *g,
 int or_cell_bounds(const or_tool *t, const or_cut *c, const or_grid *g, double delta,
                    double *lo, double *hi, double *top);
 
+/* The same restricted to the cell window [i0,i1) x [j0,j1) (row-major window arrays). */
+int or_cell_bounds_window(const or_tool *t, const or_cut *c, const or_grid *g, double delta,
+                          long long i0, long long i1, long long j0, long long j1,
+                          double *lo, double *hi, double *top);
+
 /* Areal and profile roughness of a Z-map (+inf = empty cell). */
 int or_roughness(const double *Z, long long nx, long long ny, or_rough *out);
 

@@ -93,6 +93,10 @@ def lib() -> C.CDLL:
                                              P(C.c_double), P(C.c_longlong), P(OrCounts)]
             L.or_cell_bounds.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_double,
                                          P(C.c_double), P(C.c_double), P(C.c_double)]
+            L.or_cell_bounds_window.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_double,
+                                                C.c_longlong, C.c_longlong, C.c_longlong,
+                                                C.c_longlong, P(C.c_double), P(C.c_double),
+                                                P(C.c_double)]
             L.or_roughness.argtypes = [P(C.c_double), C.c_longlong, C.c_longlong, P(OrRough)]
             L.or_paper_trajectory_points.argtypes = [C.c_double, C.c_double, C.c_int,
                                                      C.c_double, C.c_double, C.c_double]
@@ -187,14 +191,16 @@ def simulate(sim, window=None, winners: bool = False):
     return (Z, counts, W) if winners else (Z, counts)
 
 
-def cell_bounds(sim, delta: float):
-    """(lo, hi, top) per cell when every evaluation may move by up to delta in x and y."""
+def cell_bounds(sim, delta: float, window=None):
+    """(lo, hi, top) per cell when every evaluation may move by up to delta in x and y, over
+    the whole grid or the cell window (i0, i1, j0, j1)."""
     g = sim.grid
-    lo = np.empty((g.ny, g.nx))
-    hi = np.empty((g.ny, g.nx))
-    top = np.empty((g.ny, g.nx))
-    rc = lib().or_cell_bounds(C.byref(_tool(sim.tool)), C.byref(_cut(sim.cut)),
-                              C.byref(_grid(g)), float(delta), _dp(lo), _dp(hi), _dp(top))
+    i0, i1, j0, j1 = window if window is not None else (0, g.nx, 0, g.ny)
+    shape = (j1 - j0, i1 - i0)
+    lo, hi, top = np.empty(shape), np.empty(shape), np.empty(shape)
+    rc = lib().or_cell_bounds_window(C.byref(_tool(sim.tool)), C.byref(_cut(sim.cut)),
+                                     C.byref(_grid(g)), float(delta), i0, i1, j0, j1,
+                                     _dp(lo), _dp(hi), _dp(top))
     if rc:
         raise ValueError(f"or_cell_bounds: invalid parameters ({rc})")
     return lo, hi, top

@@ -22,6 +22,7 @@ F64, F32 = 0, 1
 TOOL_ROUND, TOOL_BALL = 0, 1
 FLAG_SQ_ZERO, FLAG_NO_HIT, FLAG_LOW_COVERAGE = 1, 2, 4
 OPT_ZMAP_STRATEGY, OPT_BUCKET_BYTES, OPT_GRAPHS = 1, 2, 3
+OPT_TILE_SHAPE, OPT_TARGET_ROWS, OPT_AUTOTUNED = 4, 5, 6
 ZMAP_BINNED, ZMAP_SCATTER = 0, 1
 
 
@@ -78,6 +79,11 @@ class FsmJob(C.Structure):
                 ("grid", C.POINTER(FsmGrid)), ("zmap_dev", C.c_void_p)]
 
 
+class FsmTuneResult(C.Structure):
+    _fields_ = [("strategy", C.c_int32), ("tile_shape", C.c_int32), ("target_rows", C.c_int32),
+                ("n_tried", C.c_int32), ("best_ms", C.c_float), ("default_ms", C.c_float)]
+
+
 class FsmRequest(C.Structure):
     _fields_ = [("tool", C.POINTER(FsmTool)), ("cut", C.POINTER(FsmCut)),
                 ("grid", C.POINTER(FsmGrid)), ("arrival_s", C.c_double),
@@ -118,6 +124,8 @@ SIGNATURES = {
                       C.c_int),
     "fsm_simulate_batch": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmRough), C.c_void_p],
                            C.c_int),
+    "fsm_autotune": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmTuneResult), C.c_void_p],
+                     C.c_int),
     "fsm_serve_run": ([C.c_void_p, P(FsmServeConfig), C.c_int, P(FsmRequest),
                        P(FsmRequestResult)], C.c_int),
     "fsm_serve_dry_run": ([P(FsmServeConfig), P(FsmServeModel), C.c_int, P(FsmRequest),

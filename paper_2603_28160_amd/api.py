@@ -245,6 +245,27 @@ class Context:
         del keep
         return [_result(o) for o in out]
 
+    def fsm_autotune(self, sims, precision="f64", zmaps=None, stream=None) -> dict:
+        """Time candidate launch parameters on `sims` run as one batch and keep the fastest for
+        their workload class (later calls of that class use them).  Returns the kept
+        parameters with the best and the default timings (ms)."""
+        n = len(sims)
+        if zmaps is None:
+            zmaps = [self.new_zmap(s.grid, precision) for s in sims]
+        keep = []
+        jobs = (_abi.FsmJob * n)()
+        for k, (s, z) in enumerate(zip(sims, zmaps)):
+            self._check_zmap(s.grid, precision, z)
+            t, c, g = _abi.tool_struct(s.tool), _abi.cut_struct(s.cut), _abi.grid_struct(s.grid)
+            keep += [t, c, g]
+            jobs[k].tool, jobs[k].cut, jobs[k].grid = C.pointer(t), C.pointer(c), C.pointer(g)
+            jobs[k].zmap_dev = z.data_ptr()
+        out = _abi.FsmTuneResult()
+        rc = self._lib.fsm_autotune(self._h, n, jobs, _prec(precision), C.byref(out),
+                                    C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_autotune", self._h)
+        return {k: getattr(out, k) for k, _ in out._fields_}
+
     def set_graphs(self, on: bool = True):
         """Capture launch sequences into HIP graphs and replay them per launch shape."""
         self.fsm_ctx_set_option(_abi.OPT_GRAPHS, 1 if on else 0)
@@ -254,3 +275,4 @@ class Context:
     roughness = fsm_roughness
     simulate_batch = fsm_simulate_batch
     serve = fsm_serve_run
+    autotune = fsm_autotune

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -24,7 +26,6 @@ namespace fsm {
 namespace rt {
 
 constexpr int kItersPerItem = 16;   // steps each thread walks per scatter item and edge point
-constexpr int64_t kTargetRows = 4096;      // rows of the histogram mode per launch
 constexpr int kRowChunk = 32;              // rows per column-scan chunk
 constexpr int64_t kMinSliceRows = 2048;    // rows (blocks) a slice of the histogram mode keeps
 constexpr int64_t kHistBudget = (int64_t)1 << 30;   // bytes of the row matrix
@@ -55,8 +56,22 @@ int64_t bucket_cap(int64_t bucket_bytes, int precision, int64_t per_item)
     return std::min<int64_t>(cap, (int64_t)UINT32_MAX);
 }
 
-void choose_tiles(const fsm_ctx *ctx, int precision, int &sx, int &sy)
+bool valid_tile_shape(const fsm_ctx *ctx, int precision, int code)
 {
+    const int sx = code >> 4, sy = code & 15;
+    const size_t key = precision == FSM_F64 ? 8 : 4;
+    const size_t lds = std::min<size_t>(ctx->max_lds, 65536);
+    return code >= 0 && (code >> 8) == 0 && sx >= 4 && sx <= 8 && sy >= 4 && sy <= 8 &&
+           (key << (sx + sy)) <= lds;
+}
+
+void choose_tiles(const fsm_ctx *ctx, int precision, int code, int &sx, int &sy)
+{
+    if (code != 0 && valid_tile_shape(ctx, precision, code)) {
+        sx = code >> 4;
+        sy = code & 15;
+        return;
+    }
     sx = fsm::tile_sx(precision);
     sy = fsm::tile_sy(precision);
     const size_t key = precision == FSM_F64 ? 8 : 4;
@@ -64,14 +79,48 @@ void choose_tiles(const fsm_ctx *ctx, int precision, int &sx, int &sy)
     while (sy > 4 && (key << (sx + sy)) + 1024 > ctx->max_lds) --sy;
 }
 
-SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
-                      int strategy, int64_t bucket_bytes, std::vector<DevSim> &devs)
+// binary order of magnitude, for the workload class
+int order2(double v) { return v < 1.0 ? 0 : (int)std::floor(std::log2(v) + 0.5); }
+
+std::string tune_key(const std::vector<Plan> &plans, int precision)
 {
+    double cells = 0.0, evals = 0.0;
+    for (const Plan &P : plans) {
+        cells += (double)P.nx * (double)P.ny;
+        evals += (double)P.n_evals;
+    }
+    return std::to_string(precision) + "/" + std::to_string(order2((double)plans.size())) + "/" +
+           std::to_string(order2(cells)) + "/" + std::to_string(order2(evals));
+}
+
+LaunchParams params_for(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision)
+{
+    LaunchParams lp;
+    lp.strategy = ctx->strategy;
+    lp.tile_shape = ctx->tile_shape;
+    lp.target_rows = ctx->target_rows;
+    lp.bucket_bytes = ctx->bucket_bytes;
+    if (ctx->use_tuned && !ctx->tuned.empty()) {
+        auto it = ctx->tuned.find(tune_key(plans, precision));
+        if (it != ctx->tuned.end()) {
+            lp.strategy = it->second.strategy;
+            lp.tile_shape = it->second.tile_shape;
+            lp.target_rows = it->second.target_rows;
+        }
+    }
+    return lp;
+}
+
+SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
+                      const LaunchParams &lp, std::vector<DevSim> &devs)
+{
+    const int strategy = lp.strategy;
+    const int64_t bucket_bytes = lp.bucket_bytes;
     SetLayout L;
     L.n = (int)plans.size();
     L.precision = precision;
     L.strategy = strategy;
-    choose_tiles(ctx, precision, L.sx, L.sy);
+    choose_tiles(ctx, precision, lp.tile_shape, L.sx, L.sy);
     devs.assign(L.n, DevSim{});
     int64_t items = 0, bitems = 0, tiles = 0;
     for (int k = 0; k < L.n; ++k) {
@@ -128,14 +177,14 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     L.total_items = binned ? bitems : items;
     if (binned) {
         // histogram mode when every simulation's tile histogram fits in LDS and the row
-        // matrix fits its budget.  Rows: about kTargetRows per launch, but never more items
+        // matrix fits its budget.  Rows: about target_rows per launch, but never more items
         // than one bucket slice can take, and small enough that a slice still holds
         // kMinSliceRows rows (blocks) when the work runs in many slices; coarser only when the
         // row matrix would outgrow its budget.
         const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
         const int64_t slice_items = std::max<int64_t>(
             1, std::min(bucket_cap(bucket_bytes, precision, per_item), std::max(per_item, bitems * per_item)) / per_item);
-        int64_t ipr = std::max<int64_t>(1, std::min(ceil_div(bitems, kTargetRows), slice_items / kMinSliceRows));
+        int64_t ipr = std::max<int64_t>(1, std::min(ceil_div(bitems, std::max<int64_t>(1, lp.target_rows)), slice_items / kMinSliceRows));
         int64_t rows = 0, hsize = 0;
         for (;;) {
             rows = hsize = 0;
@@ -261,7 +310,8 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
     auto H = [&](size_t off) { return host + (off - L.sims); };
     std::vector<int64_t> ib(L.n), bb(L.n), tb(L.n), ev(L.n), rbase(L.n);
     std::vector<uint64_t> zero(L.n, 0);
-    for (int k = 0; k < L.n; ++k) {
+    // every simulation writes its own descriptor and table ranges of the staging image
+    parallel_for(L.n, [&](int k) {
         const Plan &P = plans[k];
         DevSim &d = devs[k];
         d.pT = reinterpret_cast<const double *>(dev + L.pT[k]);
@@ -289,7 +339,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         for (size_t q = 0; q < P.cs.size(); ++q) csf[q] = (float)P.cs[q];
         if (!P.xc.empty()) std::memcpy(H(L.xc[k]), P.xc.data(), sizeof(double) * P.xc.size());
         if (!P.gm.empty()) std::memcpy(H(L.gm[k]), P.gm.data(), sizeof(double) * P.gm.size());
-    }
+    });
     std::memcpy(H(L.sims), devs.data(), sizeof(DevSim) * L.n);
     std::memcpy(H(L.ibase), ib.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.bbase), (L.hist ? rbase : bb).data(), sizeof(int64_t) * L.n);
@@ -467,7 +517,7 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
     std::vector<DevSim> devs;
-    const SetLayout L = make_layout(ctx, plans, precision, ctx->strategy, ctx->bucket_bytes, devs);
+    const SetLayout L = make_layout(ctx, plans, precision, params_for(ctx, plans, precision), devs);
     Workspace &w = ctx->ws;
     int rc = ensure(ctx, w, L.total, L.total - L.sims, (size_t)L.n);
     if (rc != FSM_OK) return rc;
@@ -583,8 +633,7 @@ int fsm_plan(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, int
         fsm_ctx probe;
         std::vector<Plan> one{P};
         std::vector<DevSim> devs;
-        out->workspace_bytes = (int64_t)make_layout(&probe, one, precision, fsm::kStrategyBinned,
-                                                    probe.bucket_bytes, devs).total;
+        out->workspace_bytes = (int64_t)make_layout(&probe, one, precision, LaunchParams(), devs).total;
         return FSM_OK;
     } catch (const std::bad_alloc &) {
         return FSM_ENOMEM;
@@ -667,6 +716,19 @@ int fsm_ctx_set_option(fsm_ctx *ctx, int option, int64_t value)
     case FSM_OPT_GRAPHS:
         ctx->graphs = value != 0;
         return FSM_OK;
+    case FSM_OPT_TILE_SHAPE:
+        if (value != 0 && !(valid_tile_shape(ctx, FSM_F64, (int)value) || valid_tile_shape(ctx, FSM_F32, (int)value)))
+            return set_err(ctx, FSM_EINVAL, "tile shape out of range");
+        ctx->tile_shape = (int)value;
+        return FSM_OK;
+    case FSM_OPT_TARGET_ROWS:
+        if (value != 0 && (value < 256 || value > 65536))
+            return set_err(ctx, FSM_EINVAL, "target rows out of range");
+        ctx->target_rows = value ? value : 4096;
+        return FSM_OK;
+    case FSM_OPT_AUTOTUNED:
+        ctx->use_tuned = value != 0;
+        return FSM_OK;
     default:
         return set_err(ctx, FSM_EINVAL, "unknown option");
     }
@@ -727,12 +789,128 @@ int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, 
             const fsm_job &j = jobs[k];
             if (!j.tool || !j.cut || !j.grid || !j.zmap_dev)
                 return set_err(ctx, FSM_EINVAL, "job " + std::to_string(k) + ": null pointer");
-            std::string err;
-            int rc = fsm::build_plan(*j.tool, *j.cut, *j.grid, plans[k], err, true);
-            if (rc != FSM_OK) return set_err(ctx, rc, "job " + std::to_string(k) + ": " + err);
             zmaps[k] = j.zmap_dev;
         }
+        // the host plans (tables included) are independent: build them on several threads
+        std::vector<int> rcs((size_t)n, FSM_OK);
+        std::vector<std::string> errs((size_t)n);
+        parallel_for(n, [&](int k) {
+            rcs[k] = fsm::build_plan(*jobs[k].tool, *jobs[k].cut, *jobs[k].grid, plans[k], errs[k], true);
+        });
+        for (int k = 0; k < n; ++k)
+            if (rcs[k] != FSM_OK) return set_err(ctx, rcs[k], "job " + std::to_string(k) + ": " + errs[k]);
         return run_set(ctx, plans, zmaps, precision, out, static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, FSM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_err(ctx, FSM_EINVAL, "unexpected host exception");
+    }
+}
+
+int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tune_result *out,
+                 void *stream)
+{
+    if (!ctx) return FSM_EINVAL;
+    if (n < 1 || !jobs || !out || !valid_precision(precision))
+        return set_err(ctx, FSM_EINVAL, "empty job list, null argument or invalid precision");
+    try {
+        std::vector<Plan> plans((size_t)n);
+        std::vector<void *> zmaps((size_t)n);
+        for (int k = 0; k < n; ++k) {
+            if (!jobs[k].tool || !jobs[k].cut || !jobs[k].grid || !jobs[k].zmap_dev)
+                return set_err(ctx, FSM_EINVAL, "job " + std::to_string(k) + ": null pointer");
+            zmaps[k] = jobs[k].zmap_dev;
+        }
+        std::vector<int> rcs((size_t)n, FSM_OK);
+        std::vector<std::string> errs((size_t)n);
+        parallel_for(n, [&](int k) {
+            rcs[k] = fsm::build_plan(*jobs[k].tool, *jobs[k].cut, *jobs[k].grid, plans[k], errs[k], true);
+        });
+        for (int k = 0; k < n; ++k)
+            if (rcs[k] != FSM_OK) return set_err(ctx, rcs[k], "job " + std::to_string(k) + ": " + errs[k]);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+
+        // the candidates run eagerly through the tuned-table slot of this class; the guard
+        // puts the context back however the search ends
+        const std::string key = tune_key(plans, precision);
+        struct Guard {
+            fsm_ctx *c;
+            std::map<std::string, LaunchParams> tuned;
+            bool use, graphs;
+            ~Guard() { c->tuned = tuned; c->use_tuned = use; c->graphs = graphs; }
+        };
+        LaunchParams best;
+        float best_ms = 0.0f, base_ms = 0.0f;
+        int tried = 0;
+        {
+        Guard guard{ctx, ctx->tuned, ctx->use_tuned, ctx->graphs};
+        ctx->use_tuned = true;
+        ctx->graphs = false;
+        auto time_of = [&](const LaunchParams &lp, float &ms) -> int {
+            ctx->tuned[key] = lp;
+            double best = 1e300;
+            for (int rep = 0; rep < 3; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                const int rc = run_set(ctx, plans, zmaps, precision, nullptr, s);
+                if (rc != FSM_OK) return rc;
+                const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                if (rep > 0) best = std::min(best, el);
+            }
+            ms = (float)best;
+            ++tried;
+            return FSM_OK;
+        };
+        LaunchParams base;
+        base.strategy = fsm::kStrategyBinned;
+        base.tile_shape = 0;
+        base.target_rows = 4096;
+        base.bucket_bytes = ctx->bucket_bytes;
+        int rc = time_of(base, base_ms);
+        if (rc != FSM_OK) return rc;
+        best = base;
+        best_ms = base_ms;
+        // 1. tile shape with the default rows
+        static const int shapes[] = {0x55, 0x65, 0x56, 0x66, 0x75, 0x76, 0x67, 0x77, 0x86};
+        for (int code : shapes) {
+            int dsx = 0, dsy = 0;
+            choose_tiles(ctx, precision, 0, dsx, dsy);
+            if (!valid_tile_shape(ctx, precision, code) || code == ((dsx << 4) | dsy)) continue;
+            LaunchParams lp = base;
+            lp.tile_shape = code;
+            float ms = 0.0f;
+            rc = time_of(lp, ms);
+            if (rc != FSM_OK) return rc;
+            if (ms < best_ms) { best_ms = ms; best = lp; }
+        }
+        // 2. rows per launch with the best tile
+        for (int64_t rows : {1024, 2048, 8192, 16384}) {
+            LaunchParams lp = best;
+            lp.target_rows = rows;
+            float ms = 0.0f;
+            rc = time_of(lp, ms);
+            if (rc != FSM_OK) return rc;
+            if (ms < best_ms) { best_ms = ms; best = lp; }
+        }
+        // 3. the global-atomic strategy with the best tile (its roughness tiles)
+        {
+            LaunchParams lp = best;
+            lp.strategy = fsm::kStrategyScatter;
+            float ms = 0.0f;
+            rc = time_of(lp, ms);
+            if (rc != FSM_OK) return rc;
+            if (ms < best_ms) { best_ms = ms; best = lp; }
+        }
+        }
+        ctx->tuned[key] = best;
+        out->strategy = best.strategy == fsm::kStrategyScatter ? FSM_ZMAP_SCATTER : FSM_ZMAP_BINNED;
+        int bsx = 0, bsy = 0;
+        choose_tiles(ctx, precision, best.tile_shape, bsx, bsy);
+        out->tile_shape = (bsx << 4) | bsy;
+        out->target_rows = (int32_t)best.target_rows;
+        out->n_tried = tried;
+        out->best_ms = best_ms;
+        out->default_ms = base_ms;
+        return FSM_OK;
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");
     } catch (...) {
@@ -756,8 +934,10 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
         plans[0].ny = grid->ny;
         plans[0].N = 1;
         std::vector<DevSim> devs;
-        const SetLayout L = make_layout(ctx, plans, precision, fsm::kStrategyScatter,
-                                        ctx->bucket_bytes, devs);
+        LaunchParams lp;
+        lp.strategy = fsm::kStrategyScatter;
+        lp.tile_shape = ctx->tile_shape;
+        const SetLayout L = make_layout(ctx, plans, precision, lp, devs);
         int rc = ensure(ctx, ctx->ws, L.total, L.total - L.sims, 1);
         if (rc != FSM_OK) return rc;
         char *dev = static_cast<char *>(ctx->ws.d_ws);

@@ -4,9 +4,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <exception>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fsm_internal.h"
@@ -22,6 +27,15 @@ struct Workspace {
     size_t h_bytes = 0;
     fsm_rough *h_out = nullptr;
     size_t h_out_n = 0;
+};
+
+// Launch parameters of one set: strategy, tile shape (0: default), histogram rows per launch,
+// bucket budget.
+struct LaunchParams {
+    int strategy = kStrategyBinned;
+    int tile_shape = 0;
+    int64_t target_rows = 4096;
+    int64_t bucket_bytes = (int64_t)4 << 30;
 };
 
 // Shape and layout of one launch over a set of simulations.
@@ -57,6 +71,10 @@ struct fsm_ctx {
     int strategy = fsm::kStrategyBinned;
     int64_t bucket_bytes = (int64_t)4 << 30;
     bool graphs = false;
+    int tile_shape = 0;          // FSM_OPT_TILE_SHAPE (0: default)
+    int64_t target_rows = 4096;  // FSM_OPT_TARGET_ROWS
+    bool use_tuned = true;       // FSM_OPT_AUTOTUNED
+    std::map<std::string, fsm::rt::LaunchParams> tuned;   // per workload class (fsm_autotune)
     hipStream_t own = nullptr;   // stream used for graph capture and replay
     hipEvent_t join = nullptr;
     std::map<std::string, hipGraphExec_t> graph_cache;
@@ -67,12 +85,48 @@ struct fsm_ctx {
 namespace fsm {
 namespace rt {
 
+// f(k) for k in [0, n) on up to 16 host threads (the caller's included); the first exception
+// thrown by any f is rethrown here.
+template <typename F>
+void parallel_for(int n, F &&f)
+{
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int T = std::min({n, hw, 16});
+    if (T <= 1 || n < 4) {
+        for (int k = 0; k < n; ++k) f(k);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex m;
+    auto work = [&]() {
+        try {
+            for (int k; (k = next.fetch_add(1)) < n;) f(k);
+        } catch (...) {
+            std::lock_guard<std::mutex> g(m);
+            if (!err) err = std::current_exception();
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < T; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    if (err) std::rethrow_exception(err);
+}
+
 int set_err(fsm_ctx *ctx, int code, const std::string &msg);
 int hip_err(fsm_ctx *ctx, hipError_t e, const char *where);
 bool valid_precision(int p);
-// Layout of one launch over `plans`; bucket_bytes bounds the bucket arrays (slices beyond).
+// Layout of one launch over `plans` with parameters lp (its bucket budget bounds the bucket
+// arrays; the work runs in slices beyond).
 SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
-                      int strategy, int64_t bucket_bytes, std::vector<DevSim> &devs);
+                      const LaunchParams &lp, std::vector<DevSim> &devs);
+// Workload class of a set (the key of the autotuner's table) and the parameters a call on it
+// uses: the context's options, or what fsm_autotune kept for the class.
+std::string tune_key(const std::vector<Plan> &plans, int precision);
+LaunchParams params_for(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision);
+// Whether a tile shape code is valid for the precision (and the context's LDS).
+bool valid_tile_shape(const fsm_ctx *ctx, int precision, int code);
 // Grow w to at least the given sizes (device workspace, host staging, result records).
 int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size_t n_out);
 void release(Workspace &w);

@@ -77,11 +77,13 @@ Book book_requests(const fsm_serve_config &cfg, int n, const fsm_request *req,
 bool fit_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
                 int64_t slot_bytes, SetLayout &L, std::vector<DevSim> &devs, int64_t &bucket)
 {
-    bucket = ctx->bucket_bytes;
+    LaunchParams lp = params_for(ctx, plans, precision);
+    bucket = lp.bucket_bytes;
     const int64_t entry = precision == FSM_F64 ? 10 : 6;
     for (int it = 0; it < 8; ++it) {
         devs.clear();
-        L = make_layout(ctx, plans, precision, ctx->strategy, bucket, devs);
+        lp.bucket_bytes = bucket;
+        L = make_layout(ctx, plans, precision, lp, devs);
         if ((int64_t)L.total <= slot_bytes) return true;
         const int64_t floor_bytes = (int64_t)fsm::kBlock * L.max_n * entry;
         const int64_t used = L.cap * entry;
@@ -174,13 +176,18 @@ public:
     int submit(int slot, const std::vector<int> &batch, const std::vector<fsm::SchedResult> &res) override
     {
         Slot &s = slots_[slot];
-        std::vector<Plan> plans(batch.size());
-        std::vector<void *> zmaps(batch.size());
-        for (size_t k = 0; k < batch.size(); ++k) {
+        const int nb = (int)batch.size();
+        std::vector<Plan> plans((size_t)nb);
+        std::vector<void *> zmaps((size_t)nb);
+        std::vector<int> rcs((size_t)nb, FSM_OK);
+        std::vector<std::string> errs((size_t)nb);
+        parallel_for(nb, [&](int k) {
             const fsm_request &r = req_[book_.index[batch[k]]];
-            std::string err;
-            int rc = fsm::build_plan(*r.tool, *r.cut, *r.grid, plans[k], err, true);
-            if (rc != FSM_OK) return set_err(ctx_, rc, err);
+            rcs[k] = fsm::build_plan(*r.tool, *r.cut, *r.grid, plans[k], errs[k], true);
+        });
+        for (int k = 0; k < nb; ++k) {
+            if (rcs[k] != FSM_OK) return set_err(ctx_, rcs[k], errs[k]);
+            const fsm_request &r = req_[book_.index[batch[k]]];
             zmaps[k] = r.zmap_dev ? r.zmap_dev
                                   : static_cast<void *>(static_cast<char *>(arena_) + res[batch[k]].arena_offset);
         }

@@ -22,10 +22,11 @@ def f32_delta(sim):
     return 16.0 * 2.0 ** -24 * (pl["r_reach"] + sim.cut.a_p + 1.0)
 
 
-def f32_intervals(sim, delta=None, tol=F32_TOL):
+def f32_intervals(sim, delta=None, tol=F32_TOL, window=None):
     """Per-cell acceptance interval [low, high] (mm), the cells that must be hit and the cells
-    that must stay empty, for a single-precision Z-map of `sim`."""
-    lo, hi, top = oracle.cell_bounds(sim, f32_delta(sim) if delta is None else delta)
+    that must stay empty, for a single-precision Z-map of `sim` (or its cell window
+    (i0, i1, j0, j1))."""
+    lo, hi, top = oracle.cell_bounds(sim, f32_delta(sim) if delta is None else delta, window)
     must_hit = np.isfinite(hi)
     must_miss = ~np.isfinite(lo)
     low = lo - tol

@@ -91,3 +91,12 @@ def test_moment_bounds_are_tight_for_a_shift():
     rp = oracle.roughness(Z + 1e-3)
     assert abs(rp["mean"] - r["mean"]) == pytest.approx(b["mean"], rel=1e-9)
     assert abs(rp["Sq"] - r["Sq"]) <= 1e-15
+
+
+def test_window_equals_full_grid_slice():
+    s = small_sim()
+    delta = 0.3 * s.grid.dd
+    full = oracle.cell_bounds(s, delta)
+    win = oracle.cell_bounds(s, delta, window=(7, 40, 5, 31))
+    for a, b in zip(full, win):
+        assert np.array_equal(a[5:31, 7:40], b)
