@@ -156,6 +156,42 @@ def large_leg(ctx, steps=3):
             "coverage": r["n_hit"] / cells, "steps": steps}
 
 
+# EFSM wall times (s) of the paper's nine performance conditions on its laptop CPU, from the
+# computation-time table of Sec. 4.3: context for the paper-mode leg, not a target
+PAPER_EFSM_S = {1: 0.81, 2: 0.68, 3: 0.55, 4: 0.65, 5: 0.52, 6: 0.45, 7: 0.59, 8: 0.46, 9: 0.43}
+
+
+def paper_leg(ctx, steps=3):
+    """The paper's nine performance conditions in its fixed-time-step mode (Case-2 tool, 10 x 5
+    mm at 5 um, dt = 0.4 us), one plain simulation each, both precisions: time per simulation,
+    trajectory points/s and edge-point evaluations/s."""
+    import torch
+    from paper_2603_28160_amd import fsm_plan, workloads
+    out = {"workload": "paper_conditions_10x5mm_dt0.4us", "conditions": {}}
+    for no in range(1, 10):
+        sim = workloads.paper_mode(no)
+        plan = fsm_plan(sim)
+        traj = sim.tool.n_teeth * plan["n_steps"]
+        row = {"trajectory_points": traj, "evals": plan["n_evals"],
+               "paper_efsm_s": PAPER_EFSM_S[no]}
+        for prec in ("f64", "f32"):
+            z = ctx.new_zmap(sim.grid, prec)
+            ctx.fsm_simulate(sim, prec, z)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.fsm_simulate(sim, prec, z)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / steps
+            row[prec] = {"ms": el * 1e3, "trajectory_points_per_s": traj / el,
+                         "evals_per_s": plan["n_evals"] / el}
+        out["conditions"][no] = row
+    ms = [out["conditions"][k]["f64"]["ms"] for k in out["conditions"]]
+    print(f"[bench] paper conditions f64: {min(ms):.2f}..{max(ms):.2f} ms per simulation",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def serve_leg(ctx, n_req, rate, max_batch=16, n_slots=2):
     """Configuration 4: n_req requests drawn like configuration 3 with sides up to 4096,
     Poisson arrivals at `rate` per second, served with continuous batching (server-held
@@ -280,6 +316,7 @@ def main():
             extras["batch"] = batch_leg(ctx, args.batch_sims)
             extras["serving"] = serve_leg(ctx, args.serve_requests, args.serve_rate)
             extras["large_field"] = large_leg(ctx)
+            extras["paper_mode"] = paper_leg(ctx)
 
     main_prec = "f64" if "f64" in res else precs[0]
     m = res[main_prec]

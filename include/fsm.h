@@ -93,13 +93,24 @@ typedef struct fsm_cut {
     double a_p;              /* axial depth of cut, > 0 (sets the engaged edge length) */
     double a_e;              /* stepover between parallel passes; <= 0: one pass */
     double phi0;             /* initial phase angle phi of Eq. (3) */
-    int32_t steps_per_rev;   /* S, time steps per spindle revolution, >= 1 */
+    int32_t steps_per_rev;   /* S, time steps per spindle revolution, >= 1 (FSM_TIME_PER_REV) */
     int32_t n_passes;        /* parallel passes; 0: enough to cover the grid */
     int64_t n_steps;         /* time steps per pass; 0: whole revolutions covering the grid */
     double x_start;          /* tool-centre x at step 0; NaN: a full reach before the grid */
     double y_first;          /* tool-centre y of pass 0; NaN: a full reach below the grid
                                 (or the grid centre line for a single pass) */
+    int32_t time_mode;       /* FSM_TIME_PER_REV: steps_per_rev steps per revolution;
+                                FSM_TIME_FIXED_DT: the paper's fixed time step dt at cutting
+                                speed v_c (Sec. 4.3), spindle speed 1000 v_c / (pi D) */
+    int32_t reserved;
+    double v_c;              /* cutting speed, m/min (FSM_TIME_FIXED_DT) */
+    double dt;               /* time step, s (FSM_TIME_FIXED_DT) */
+    double x_end;            /* end of the travel the automatic step count covers; NaN: a full
+                                reach past the grid */
 } fsm_cut;
+
+#define FSM_TIME_PER_REV 0
+#define FSM_TIME_FIXED_DT 1
 
 typedef struct fsm_grid {
     double x0, y0;           /* position of node (0, 0) */

@@ -63,9 +63,21 @@ static int check_tool(const or_tool *t)
 static int check_cut(const or_cut *c)
 {
     if (!c) return -1;
-    if (c->S < 1 || !(c->f_z >= 0.0) || !(c->a_p > 0.0)) return -1;
+    if (!(c->f_z >= 0.0) || !(c->a_p > 0.0)) return -1;
     if (c->n_passes < 0 || c->n_steps < 0) return -1;
-    return 0;
+    if (c->time_mode == 0) return c->S < 1 ? -1 : 0;
+    if (c->time_mode == 1) return (c->v_c > 0.0 && c->dt > 0.0) ? 0 : -1;
+    return -1;
+}
+
+/* Fixed-time-step mode (the paper's own time discretisation, Sec. 4.3): spindle speed
+ * n = 1000 v_c / (pi D) rev/min from the cutting speed, angular speed omega = 2 pi n / 60,
+ * feed speed v_f = f_z z_n n / 60 (mm/s); step s sits at time t = s dt. */
+static double spindle_rpm(const or_tool *t, const or_cut *c) { return (1000.0 * c->v_c) / (M_PI * t->D); }
+static double omega_of(const or_tool *t, const or_cut *c) { return ((2.0 * M_PI) * spindle_rpm(t, c)) / 60.0; }
+static double feed_speed(const or_tool *t, const or_cut *c)
+{
+    return (c->f_z * (double)t->n_teeth * spindle_rpm(t, c)) / 60.0;
 }
 
 static int check_grid(const or_grid *g)
@@ -204,10 +216,17 @@ int or_plan(const or_tool *t, const or_cut *c, const or_grid *g, or_plan_out *ou
 
     out->r_reach = reach;
     out->x_start = isnan(c->x_start) ? x_lo - reach : c->x_start;
+    const double x_end = isnan(c->x_end) ? x_hi + reach : c->x_end;
     if (c->n_steps > 0) {
         out->n_steps = c->n_steps;
+    } else if (c->time_mode == 1) {
+        /* time over the travel at the feed speed, in whole time steps */
+        const double v_f = feed_speed(t, c);
+        double steps = v_f > 0.0 ? ceil(((x_end - out->x_start) / v_f) / c->dt) : 1.0;
+        if (steps < 1.0) steps = 1.0;
+        out->n_steps = (long long)steps;
     } else if (fpr > 0.0) {
-        double revs = ceil(((x_hi + reach) - out->x_start) / fpr);
+        double revs = ceil((x_end - out->x_start) / fpr);
         if (revs < 1.0) revs = 1.0;
         out->n_steps = (long long)revs * c->S;
     } else {
@@ -234,6 +253,7 @@ typedef struct chain {
     double *pT;          /* [Z][N][3] */
     m4 Ry, Rx;           /* tilt */
     double fpr;
+    double omega, v_f;   /* fixed-time-step mode */
 } chain;
 
 static int chain_init(const or_tool *t, const or_cut *c, const or_grid *g, chain *ch)
@@ -252,22 +272,33 @@ static int chain_init(const or_tool *t, const or_cut *c, const or_grid *g, chain
     ch->Rx[1][1] = cs; ch->Rx[1][2] = -ss;
     ch->Rx[2][1] = ss; ch->Rx[2][2] = cs;
     ch->fpr = (double)t->n_teeth * c->f_z;
+    ch->omega = c->time_mode == 1 ? omega_of(t, c) : 0.0;
+    ch->v_f = c->time_mode == 1 ? feed_speed(t, c) : 0.0;
     return 0;
 }
 
-/* Eq. (4) read with the feed along X: tool centre at step s of pass q. */
+/* Eq. (4) read with the feed along X: tool centre at step s of pass q (v_f t at t = s dt in
+ * the fixed-time-step mode). */
 static void m_spindle_to_work(const or_cut *c, const chain *ch, long long q, long long s, m4 W)
 {
     m_identity(W);
-    W[0][3] = ch->plan.x_start + ((double)s * ch->fpr) / (double)c->S;
+    if (c->time_mode == 1)
+        W[0][3] = ch->plan.x_start + ch->v_f * ((double)s * c->dt);
+    else
+        W[0][3] = ch->plan.x_start + ((double)s * ch->fpr) / (double)c->S;
     W[1][3] = ch->plan.y_first + (double)q * c->a_e;
 }
 
-/* Eq. (3): alpha = phi + 2 pi (K-1)/z_n - omega t with omega t = 2 pi (s mod S) / S. */
-static void m_tool_to_spindle(const or_tool *t, const or_cut *c, long long s, int K, m4 T)
+/* Eq. (3): alpha = phi + 2 pi (K-1)/z_n - omega t, with omega t = 2 pi (s mod S) / S, or
+ * omega (s dt) in the fixed-time-step mode. */
+static void m_tool_to_spindle(const or_tool *t, const or_cut *c, const chain *ch, long long s,
+                              int K, m4 T)
 {
-    const double alpha = (c->phi0 + tooth_angle(t, K))
-                       - ((2.0 * M_PI) * (double)(s % c->S)) / (double)c->S;
+    double alpha;
+    if (c->time_mode == 1)
+        alpha = (c->phi0 + tooth_angle(t, K)) - ch->omega * ((double)s * c->dt);
+    else
+        alpha = (c->phi0 + tooth_angle(t, K)) - ((2.0 * M_PI) * (double)(s % c->S)) / (double)c->S;
     m_rot_z(alpha, T);
 }
 
@@ -288,7 +319,7 @@ int or_point(const or_tool *t, const or_cut *c, const or_grid *g,
     if (rc) return rc;
     if (K < 0 || K >= t->n_teeth || p < 0 || p >= t->n_edge) { free(ch.pT); return -1; }
     m4 T, W;
-    m_tool_to_spindle(t, c, s, K, T);
+    m_tool_to_spindle(t, c, &ch, s, K, T);
     m_spindle_to_work(c, &ch, q, s, W);
     double w[4];
     transform(&ch, T, W, ch.pT + 3 * ((long long)K * t->n_edge + p), w);
@@ -332,7 +363,7 @@ int or_simulate_window(const or_tool *t, const or_cut *c, const or_grid *g,
             m_spindle_to_work(c, &ch, q, s, W);
             for (int K = 0; K < Zt; ++K) {
                 m4 T;
-                m_tool_to_spindle(t, c, s, K, T);
+                m_tool_to_spindle(t, c, &ch, s, K, T);
                 for (int p = 0; p < N; ++p) {
                     double w[4];
                     transform(&ch, T, W, ch.pT + 3 * ((long long)K * N + p), w);
@@ -385,7 +416,7 @@ int or_cell_bounds_window(const or_tool *t, const or_cut *c, const or_grid *g, d
             m_spindle_to_work(c, &ch, q, s, W);
             for (int K = 0; K < Zt; ++K) {
                 m4 T;
-                m_tool_to_spindle(t, c, s, K, T);
+                m_tool_to_spindle(t, c, &ch, s, K, T);
                 for (int p = 0; p < N; ++p) {
                     double w[4];
                     transform(&ch, T, W, ch.pT + 3 * ((long long)K * N + p), w);

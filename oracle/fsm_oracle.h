@@ -51,6 +51,10 @@ typedef struct or_cut {
     long long n_steps;   /* steps per pass, 0: enough whole revolutions to cover the grid */
     double x_start;      /* tool-centre x at step 0 (NaN: auto) */
     double y_first;      /* tool-centre y of pass 0 (NaN: auto) */
+    int time_mode;       /* 0: S steps per revolution; 1: fixed time step dt at cutting speed v_c */
+    double v_c;          /* cutting speed, m/min (time_mode 1) */
+    double dt;           /* time step, s (time_mode 1) */
+    double x_end;        /* end of travel for the automatic step count (NaN: a reach past the grid) */
 } or_cut;
 
 /* Workpiece grid (Sec. 2.2): node (i, j) sits at (x0 + i*dd, y0 + j*dd). */

@@ -38,7 +38,9 @@ class OrTool(C.Structure):
 class OrCut(C.Structure):
     _fields_ = [("f_z", C.c_double), ("a_p", C.c_double), ("a_e", C.c_double),
                 ("phi0", C.c_double), ("S", C.c_int), ("n_passes", C.c_int),
-                ("n_steps", C.c_longlong), ("x_start", C.c_double), ("y_first", C.c_double)]
+                ("n_steps", C.c_longlong), ("x_start", C.c_double), ("y_first", C.c_double),
+                ("time_mode", C.c_int), ("v_c", C.c_double), ("dt", C.c_double),
+                ("x_end", C.c_double)]
 
 
 class OrGrid(C.Structure):
@@ -133,7 +135,8 @@ def _tool(t) -> OrTool:
 def _cut(c) -> OrCut:
     return OrCut(f_z=c.f_z, a_p=c.a_p, a_e=c.a_e, phi0=c.phi0, S=int(c.steps_per_rev),
                  n_passes=int(c.n_passes), n_steps=int(c.n_steps), x_start=c.x_start,
-                 y_first=c.y_first)
+                 y_first=c.y_first, time_mode=int(c.time_mode), v_c=c.v_c, dt=c.dt,
+                 x_end=c.x_end)
 
 
 def _grid(g) -> OrGrid:

@@ -39,7 +39,9 @@ class FsmTool(C.Structure):
 class FsmCut(C.Structure):
     _fields_ = [("f_z", C.c_double), ("a_p", C.c_double), ("a_e", C.c_double),
                 ("phi0", C.c_double), ("steps_per_rev", C.c_int32), ("n_passes", C.c_int32),
-                ("n_steps", C.c_int64), ("x_start", C.c_double), ("y_first", C.c_double)]
+                ("n_steps", C.c_int64), ("x_start", C.c_double), ("y_first", C.c_double),
+                ("time_mode", C.c_int32), ("reserved", C.c_int32), ("v_c", C.c_double),
+                ("dt", C.c_double), ("x_end", C.c_double)]
 
 
 class FsmGrid(C.Structure):
@@ -191,7 +193,8 @@ def tool_struct(t) -> FsmTool:
 def cut_struct(c) -> FsmCut:
     return FsmCut(f_z=c.f_z, a_p=c.a_p, a_e=c.a_e, phi0=c.phi0,
                   steps_per_rev=int(c.steps_per_rev), n_passes=int(c.n_passes),
-                  n_steps=int(c.n_steps), x_start=c.x_start, y_first=c.y_first)
+                  n_steps=int(c.n_steps), x_start=c.x_start, y_first=c.y_first,
+                  time_mode=int(c.time_mode), v_c=c.v_c, dt=c.dt, x_end=c.x_end)
 
 
 def grid_struct(g) -> FsmGrid:

@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     o = os.path.join(BUILD, "fsm_plan.o")
-    _run(["g++", *COMMON, "-fno-builtin", "-c", os.path.join(CSRC, "fsm_plan.cpp"), "-o", o])
+    _run(["g++", *COMMON, "-pthread", "-fno-builtin", "-c", os.path.join(CSRC, "fsm_plan.cpp"), "-o", o])
     objs.append(o)
     o = os.path.join(BUILD, "fsm_sched.o")
     _run(["g++", *COMMON, "-c", os.path.join(CSRC, "fsm_sched.cpp"), "-o", o])
@@ -54,7 +54,7 @@ def build(verbose: bool = False) -> str:
     _run([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, "fsm_kernels.hip"), "-o", o])
     objs.append(o)
     tmp = LIB + f".tmp{os.getpid()}"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

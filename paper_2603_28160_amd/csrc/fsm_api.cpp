@@ -250,8 +250,9 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         const size_t pts = (size_t)P.z_n * P.N, angles = (size_t)P.z_n * P.S;
         L.pT.push_back(take(sizeof(double) * 3 * pts));
         L.pTf.push_back(take(sizeof(float) * 4 * pts));
-        L.cs.push_back(take(sizeof(double) * 2 * angles));
-        L.csf.push_back(take(sizeof(float) * 2 * angles));
+        // only the precision's own angle table travels (it is per step in the fixed-step mode)
+        L.cs.push_back(take(precision == FSM_F64 ? sizeof(double) * 2 * angles : 0));
+        L.csf.push_back(take(precision == FSM_F32 ? sizeof(float) * 2 * angles : 0));
         L.xc.push_back(take(sizeof(double) * (size_t)P.n_steps));
         L.gm.push_back(take(sizeof(double) * (size_t)P.z_n * P.n_groups));
     }
@@ -334,9 +335,12 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
             pTf[4 * q + 2] = (float)P.pT[3 * q + 2];
             pTf[4 * q + 3] = 0.0f;
         }
-        if (!P.cs.empty()) std::memcpy(H(L.cs[k]), P.cs.data(), sizeof(double) * P.cs.size());
-        float *csf = reinterpret_cast<float *>(H(L.csf[k]));
-        for (size_t q = 0; q < P.cs.size(); ++q) csf[q] = (float)P.cs[q];
+        if (L.precision == FSM_F64) {
+            if (!P.cs.empty()) std::memcpy(H(L.cs[k]), P.cs.data(), sizeof(double) * P.cs.size());
+        } else {
+            float *csf = reinterpret_cast<float *>(H(L.csf[k]));
+            for (size_t q = 0; q < P.cs.size(); ++q) csf[q] = (float)P.cs[q];
+        }
         if (!P.xc.empty()) std::memcpy(H(L.xc[k]), P.xc.data(), sizeof(double) * P.xc.size());
         if (!P.gm.empty()) std::memcpy(H(L.gm[k]), P.gm.data(), sizeof(double) * P.gm.size());
     });
@@ -593,6 +597,7 @@ bool valid_precision(int p) { return p == FSM_F64 || p == FSM_F32; }
 }  // namespace fsm
 
 using namespace fsm::rt;
+using fsm::parallel_for;
 using fsm::DevSim;
 using fsm::Plan;
 

@@ -2,8 +2,13 @@
 // C ABI).  Not part of the public interface.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <exception>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fsm.h"
@@ -42,6 +47,35 @@ constexpr int group_ref(int g, int N)
 // Validate and build the plan.  Returns FSM_OK or FSM_EINVAL with a message in `err`.
 int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &out,
                std::string &err, bool tables = true);
+
+// f(k) for k in [0, n) on up to 16 host threads (the caller's included); the first exception
+// thrown by any f is rethrown here.
+template <typename F>
+void parallel_for(int n, F &&f)
+{
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int T = std::min({n, hw, 16});
+    if (T <= 1 || n < 4) {
+        for (int k = 0; k < n; ++k) f(k);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::exception_ptr err;
+    std::mutex m;
+    auto work = [&]() {
+        try {
+            for (int k; (k = next.fetch_add(1)) < n;) f(k);
+        } catch (...) {
+            std::lock_guard<std::mutex> g(m);
+            if (!err) err = std::current_exception();
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < T; ++t) pool.emplace_back(work);
+    work();
+    for (auto &t : pool) t.join();
+    if (err) std::rethrow_exception(err);
+}
 
 constexpr int kBlock = 256;            // threads per block of every kernel
 constexpr int kWaves = kBlock / 64;    // waves per block

@@ -81,7 +81,11 @@ int validate(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, std::string
     if (!finite(c.a_p) || !(c.a_p > 0.0)) return bad("cut.a_p must be finite and > 0");
     if (!finite(c.a_e)) return bad("cut.a_e must be finite");
     if (!finite(c.phi0)) return bad("cut.phi0 must be finite");
-    if (c.steps_per_rev < 1) return bad("cut.steps_per_rev must be >= 1");
+    if (c.time_mode != FSM_TIME_PER_REV && c.time_mode != FSM_TIME_FIXED_DT) return bad("cut.time_mode unknown");
+    if (c.time_mode == FSM_TIME_PER_REV && c.steps_per_rev < 1) return bad("cut.steps_per_rev must be >= 1");
+    if (c.time_mode == FSM_TIME_FIXED_DT && (!finite(c.v_c) || !(c.v_c > 0.0) || !finite(c.dt) || !(c.dt > 0.0)))
+        return bad("cut.v_c and cut.dt must be finite and > 0 in the fixed-time-step mode");
+    if (std::isinf(c.x_end)) return bad("cut.x_end must be finite or NaN");
     if (c.n_passes < 0) return bad("cut.n_passes must be >= 0");
     if (c.n_steps < 0 || c.n_steps > (int64_t)INT32_MAX) return bad("cut.n_steps must be in [0, 2^31)");
     if (std::isinf(c.x_start) || std::isinf(c.y_first)) return bad("cut.x_start / y_first must be finite or NaN");
@@ -100,11 +104,11 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
 {
     int rc = validate(t, c, g, err);
     if (rc != FSM_OK) return rc;
-    const int Z = t.n_teeth, N = t.n_edge, S = c.steps_per_rev;
+    const int Z = t.n_teeth, N = t.n_edge;
+    const bool fixed_dt = c.time_mode == FSM_TIME_FIXED_DT;
     P.kind = t.kind;
     P.z_n = Z;
     P.N = N;
-    P.S = S;
 
     // --- edge points in the tool frame: Eq. (2), then the helix lag turn, then the
     // eccentric offset.  Each line is the matrix-vector product of that transformation
@@ -151,16 +155,34 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     P.r_reach = reach;
     if (!(reach / g.dd < 536870912.0)) { err = "tool reach spans more than 2^29 cells"; return FSM_EINVAL; }
     P.x_start = std::isnan(c.x_start) ? x_lo - reach : c.x_start;
+    const double x_end = std::isnan(c.x_end) ? x_hi + reach : c.x_end;
+    // fixed-time-step mode (Sec. 4.3): spindle speed from the cutting speed, then the angular
+    // and feed speeds; a step sits at time s dt
+    const double n_rpm = fixed_dt ? (1000.0 * c.v_c) / (M_PI * t.D) : 0.0;
+    const double omega = fixed_dt ? ((2.0 * M_PI) * n_rpm) / 60.0 : 0.0;
+    const double v_f = fixed_dt ? (c.f_z * (double)Z * n_rpm) / 60.0 : 0.0;
     if (c.n_steps > 0) {
         P.n_steps = c.n_steps;
+    } else if (fixed_dt) {
+        double steps = v_f > 0.0 ? std::ceil(((x_end - P.x_start) / v_f) / c.dt) : 1.0;
+        if (steps < 1.0) steps = 1.0;
+        if (!(steps < (double)INT32_MAX)) { err = "path needs more than 2^31 steps per pass"; return FSM_EINVAL; }
+        P.n_steps = (int64_t)steps;
     } else if (fpr > 0.0) {
-        double revs = std::ceil(((x_hi + reach) - P.x_start) / fpr);
+        double revs = std::ceil((x_end - P.x_start) / fpr);
         if (revs < 1.0) revs = 1.0;
-        if (!(revs * (double)S < (double)INT32_MAX)) { err = "path needs more than 2^31 steps per pass"; return FSM_EINVAL; }
-        P.n_steps = (int64_t)revs * S;
+        if (!(revs * (double)c.steps_per_rev < (double)INT32_MAX)) { err = "path needs more than 2^31 steps per pass"; return FSM_EINVAL; }
+        P.n_steps = (int64_t)revs * c.steps_per_rev;
     } else {
-        P.n_steps = S;
+        P.n_steps = c.steps_per_rev;
     }
+    // the angle table's period: a revolution, or every step of a pass in the fixed-step mode
+    if (fixed_dt && (double)Z * (double)P.n_steps > (double)(1 << 26)) {
+        err = "fixed-time-step angle table above 2^26 entries";
+        return FSM_EINVAL;
+    }
+    const int S = fixed_dt ? (int)P.n_steps : c.steps_per_rev;
+    P.S = S;
     if (c.n_passes > 0) {
         P.n_passes = c.n_passes;
     } else if (c.a_e > 0.0) {
@@ -195,20 +217,33 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     if (!tables) return FSM_OK;
 
     // --- spindle angle of Eq. (3), alpha = phi + theta_K - omega t with omega t = 2 pi m / S,
-    // m = step mod S: one (cos, sin) pair per tooth and step of a revolution
+    // m = step mod S: one (cos, sin) pair per tooth and step of a revolution.  Fixed-step
+    // mode: omega t = omega (s dt) for every step s of a pass.
+    // (large tables, as in the fixed-step mode, are filled in chunks on several threads)
+    constexpr int kChunk = 16384;
     P.cs.assign((size_t)Z * S * 2, 0.0);
-    for (int K = 0; K < Z; ++K) {
+    const int n_chunks = (S + kChunk - 1) / kChunk;
+    parallel_for(Z * n_chunks, [&](int job) {
+        const int K = job / n_chunks, m0 = (job % n_chunks) * kChunk;
+        const int m1 = std::min(S, m0 + kChunk);
         const double a = c.phi0 + tooth_angle(t, K);
-        for (int m = 0; m < S; ++m) {
-            const double alpha = a - ((2.0 * M_PI) * (double)m) / (double)S;
+        for (int m = m0; m < m1; ++m) {
+            const double alpha = fixed_dt ? a - omega * ((double)m * c.dt)
+                                          : a - ((2.0 * M_PI) * (double)m) / (double)S;
             P.cs[((size_t)K * S + m) * 2] = std::cos(alpha);
             P.cs[((size_t)K * S + m) * 2 + 1] = std::sin(alpha);
         }
-    }
-    // --- tool-centre x per step (Eq. (4) with the feed along X): z_n f_z per revolution
+    });
+    // --- tool-centre x per step (Eq. (4) with the feed along X): z_n f_z per revolution, or
+    // v_f (s dt) in the fixed-step mode
     P.xc.resize((size_t)P.n_steps);
-    for (int64_t s = 0; s < P.n_steps; ++s)
-        P.xc[(size_t)s] = P.x_start + ((double)s * fpr) / (double)S;
+    const int x_chunks = (int)((P.n_steps + kChunk - 1) / kChunk);
+    parallel_for(x_chunks, [&](int job) {
+        const int64_t s0 = (int64_t)job * kChunk, s1 = std::min<int64_t>(P.n_steps, s0 + kChunk);
+        for (int64_t s = s0; s < s1; ++s)
+            P.xc[(size_t)s] = fixed_dt ? P.x_start + v_f * ((double)s * c.dt)
+                                       : P.x_start + ((double)s * fpr) / (double)S;
+    });
 
     // --- culling margins.  Over the 64 consecutive steps of one wave the reference point of a
     // group turns by at most 63 steps about the tool axis (a circular arc of radius r_m, tilted
@@ -217,7 +252,8 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     // the group stays within its distance rho from the reference point under any rigid motion.
     // The slack eps covers rounding of the box and of single-precision points.
     const double eps = 1e-5 * (reach + 1.0);
-    const double half = 63.0 * M_PI / (double)S;
+    // half the angle the spindle turns over 63 steps
+    const double half = fixed_dt ? 0.5 * (63.0 * (omega * c.dt)) : 63.0 * M_PI / (double)S;
     P.gm.assign((size_t)Z * P.n_groups, 0.0);
     for (int K = 0; K < Z; ++K) {
         for (int gi = 0; gi < P.n_groups; ++gi) {

@@ -85,35 +85,6 @@ struct fsm_ctx {
 namespace fsm {
 namespace rt {
 
-// f(k) for k in [0, n) on up to 16 host threads (the caller's included); the first exception
-// thrown by any f is rethrown here.
-template <typename F>
-void parallel_for(int n, F &&f)
-{
-    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-    const int T = std::min({n, hw, 16});
-    if (T <= 1 || n < 4) {
-        for (int k = 0; k < n; ++k) f(k);
-        return;
-    }
-    std::atomic<int> next{0};
-    std::exception_ptr err;
-    std::mutex m;
-    auto work = [&]() {
-        try {
-            for (int k; (k = next.fetch_add(1)) < n;) f(k);
-        } catch (...) {
-            std::lock_guard<std::mutex> g(m);
-            if (!err) err = std::current_exception();
-        }
-    };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < T; ++t) pool.emplace_back(work);
-    work();
-    for (auto &t : pool) t.join();
-    if (err) std::rethrow_exception(err);
-}
-
 int set_err(fsm_ctx *ctx, int code, const std::string &msg);
 int hip_err(fsm_ctx *ctx, hipError_t e, const char *where);
 bool valid_precision(int p);

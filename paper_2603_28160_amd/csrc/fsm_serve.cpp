@@ -18,6 +18,7 @@
 #include "fsm_sched.h"
 
 using namespace fsm::rt;
+using fsm::parallel_for;
 using fsm::DevSim;
 using fsm::Plan;
 

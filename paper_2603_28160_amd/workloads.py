@@ -55,6 +55,10 @@ class Cut:
     n_steps: int = 0           # steps per pass, 0: auto
     x_start: float = math.nan  # NaN: auto
     y_first: float = math.nan  # NaN: auto
+    time_mode: int = 0         # 0: steps_per_rev steps per revolution; 1: fixed time step dt
+    v_c: float = math.nan      # cutting speed, m/min (time_mode 1)
+    dt: float = math.nan       # time step, s (time_mode 1)
+    x_end: float = math.nan    # end of travel for the automatic step count; NaN: auto
 
 
 @dataclass
@@ -181,6 +185,29 @@ def paper_case2_tool(eps_r: float = 0.0, eps_a: float = 0.0, n_edge: int = 40) -
     return Tool(kind=ROUND, n_teeth=2, n_edge=n_edge, D=10.0, R_edge=5.0,
                 rake_radial=math.radians(0.6), rake_axial=0.0,
                 eps_r=(0.0, eps_r), eps_a=(0.0, eps_a))
+
+
+# --- the paper's computational-performance conditions (Sec. 4.3) -------------------------------
+
+# (number, v_c m/min, f_z mm/tooth, a_p mm) of the paper's table of selected milling parameters
+PAPER_CONDITIONS = ((1, 170, 0.4, 0.3), (2, 170, 0.5, 0.4), (3, 170, 0.6, 0.5),
+                    (4, 200, 0.4, 0.3), (5, 200, 0.5, 0.4), (6, 200, 0.6, 0.5),
+                    (7, 230, 0.4, 0.3), (8, 230, 0.5, 0.4), (9, 230, 0.6, 0.5))
+PAPER_DT = 0.4e-6          # s: the time step that reproduces the paper's trajectory-point counts
+
+
+def paper_mode(no: int, dd: float = 0.005, n_edge: int = 40, travel: float = 10.0) -> Sim:
+    """Condition `no` of the paper's performance study: the Case-2 tool without runout, one
+    straight pass along the 10 mm length of a 10 x 5 mm surface at the paper's fixed time step,
+    the surface sampled at dd (the paper does not state its grid; 5 um by default)."""
+    _, vc, fz, ap = PAPER_CONDITIONS[no - 1]
+    tool = paper_case2_tool(n_edge=n_edge)
+    nx, ny = int(round(10.0 / dd)), int(round(5.0 / dd))
+    grid = centred_grid(nx, ny, dd)
+    x_lo = grid.x0 - 0.5 * dd
+    cut = Cut(f_z=fz, a_p=ap, n_passes=1, y_first=0.0, time_mode=1, v_c=float(vc), dt=PAPER_DT,
+              x_start=x_lo, x_end=x_lo + travel)
+    return Sim(tool, cut, grid, name=f"paper_condition{no}_{nx}x{ny}")
 
 
 CONFIGS = {1: config1, 2: config2, 5: config5}

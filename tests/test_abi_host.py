@@ -66,6 +66,10 @@ def all_sims():
     t = W.paper_case2_tool(eps_r=-0.026, eps_a=0.009)
     sims.append(W.Sim(t, W.Cut(f_z=0.4, a_p=0.4, steps_per_rev=500, a_e=4.0),
                       W.centred_grid(301, 157, 0.01)))
+    sims += [W.paper_mode(no) for no in (1, 5, 9)]
+    sims.append(W.paper_mode(3).replace(cut=dataclasses.replace(W.paper_mode(3).cut, x_end=float("nan"),
+                                                                 x_start=float("nan"), n_passes=0, a_e=1.5,
+                                                                 y_first=float("nan"))))
     sims.append(W.Sim(dataclasses.replace(W.config2().tool, tilt_side=-0.12, rake_radial=0.1,
                                           rake_axial=-0.05, theta=(0, 1.5, 3.2, 4.6)),
                       W.config2().cut, W.centred_grid(50, 60, 0.01)))
@@ -104,6 +108,9 @@ def _plan_rc(tool=None, cut=None, grid=None, precision=0):
     dict(cut=dict(n_passes=-1)), dict(cut=dict(n_steps=-5)), dict(cut=dict(x_start=float("inf"))),
     dict(grid=dict(dd=0.0)), dict(grid=dict(nx=0)), dict(grid=dict(ny=-3)),
     dict(grid=dict(nx=3_000_000_000)), dict(precision=7),
+    dict(cut=dict(time_mode=2)), dict(cut=dict(time_mode=1, v_c=0.0, dt=1e-6)),
+    dict(cut=dict(time_mode=1, v_c=200.0, dt=-1e-6)), dict(cut=dict(time_mode=1, v_c=float("nan"), dt=1e-6)),
+    dict(cut=dict(x_end=float("inf"))),
 ])
 def test_invalid_parameters_rejected(bad):
     base = W.config1()

@@ -1,0 +1,47 @@
+"""GPU parity of the fixed-time-step mode on the paper's own performance conditions (Sec. 4.3):
+the Case-2 tool without runout, one pass along a 10 x 5 mm surface at dt = 0.4 us, so a pass has
+the paper's number of trajectory points.  Double precision equals the oracle bit for bit, single
+precision stays inside the oracle's per-cell intervals."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_28160_amd import workloads as W
+
+import f32_bounds as FB
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=["binned", "scatter"])
+def sctx(request):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28160_amd import Context
+    c = Context(0)
+    c.set_strategy(request.param)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("no", [1, 5, 9])
+def test_paper_condition_f64_exact(sctx, no):
+    s = W.paper_mode(no)
+    print(f"[gpu] paper condition {no} f64 {s.grid.nx}x{s.grid.ny}", flush=True)
+    z, r = sctx.fsm_simulate(s, "f64")
+    zo, cnt = oracle.simulate(s)
+    assert r["n_evals"] == cnt["n_evals"] == s.tool.n_teeth * oracle.plan(s)["n_steps"] * s.tool.n_edge
+    assert r["n_binned"] == cnt["n_binned"]
+    assert np.array_equal(z.cpu().numpy(), zo)
+    ro = oracle.roughness(zo)
+    for k in ("Sa", "Sq", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick"):
+        assert abs(r[k] - ro[k]) <= 1e-4 * abs(ro[k]) + 1e-12, (k, r[k], ro[k])
+
+
+def test_paper_condition_f32_intervals(sctx):
+    s = W.paper_mode(5)
+    print("[gpu] paper condition 5 f32", flush=True)
+    z, _ = sctx.fsm_simulate(s, "f32")
+    low, high, must_hit, must_miss = FB.f32_intervals(s)
+    FB.check_cells(z.cpu().numpy().astype(np.float64), low, high, must_hit, must_miss)

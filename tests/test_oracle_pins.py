@@ -41,6 +41,38 @@ def test_paper_trajectory_point_counts():
         assert got == int(pts), (no, got, pts)
 
 
+def test_fixed_step_plan_reproduces_the_trajectory_counts():
+    # the planner's fixed-time-step mode over a 10 mm travel gives the paper's counts too:
+    # z_n * steps, steps = ceil((L / v_f) / dt)
+    rows = [list(map(float, ln.split())) for ln in open(os.path.join(GOLDEN, "paper_trajectory_points.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    for no, vc, fz, ap, pts in rows:
+        s = W.paper_mode(int(no))
+        p = oracle.plan(s)
+        assert s.tool.n_teeth * p["n_steps"] == int(pts), (no, p["n_steps"], pts)
+
+
+def test_fixed_step_kinematics_match_the_per_revolution_form():
+    # with dt chosen so that a revolution takes exactly S steps, step s of both time modes is
+    # the same instant: every edge point sits at the same place up to rounding
+    S = 720
+    s0 = W.paper_mode(4)
+    n_rpm = 1000.0 * s0.cut.v_c / (math.pi * s0.tool.D)
+    dt = 60.0 / (n_rpm * S)
+    a = s0.replace(cut=dataclasses.replace(s0.cut, dt=dt, n_steps=3 * S, x_end=math.nan))
+    b = s0.replace(cut=dataclasses.replace(s0.cut, time_mode=0, steps_per_rev=S, n_steps=3 * S,
+                                           x_end=math.nan))
+    for step in (0, 1, 359, 720, 1500, 2159):
+        for K in range(2):
+            for p in (0, 17, 39):
+                pa, pb = oracle.point(a, 0, step, K, p), oracle.point(b, 0, step, K, p)
+                assert np.max(np.abs(pa - pb)) < 1e-9, (step, K, p, pa, pb)
+    # and the feed per revolution is z_n f_z
+    x0 = oracle.point(a, 0, 0, 0, 0)[0]
+    x1 = oracle.point(a, 0, S, 0, 0)[0]
+    assert abs((x1 - x0) - s0.tool.n_teeth * s0.cut.f_z) < 1e-9
+
+
 # --- edge discretisation (Eq. (1), (6), chord rule) ------------------------------------------
 
 def test_edge_chord_case2_tool():
