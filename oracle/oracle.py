@@ -6,6 +6,7 @@ is shared with, or imported from, the GPU library.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import math
 import os
@@ -79,32 +80,51 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def _configure(L: C.CDLL) -> C.CDLL:
+    P = C.POINTER
+    L.or_edge_points.argtypes = [P(OrTool), P(OrCut), P(C.c_double), P(C.c_double)]
+    L.or_plan.argtypes = [P(OrTool), P(OrCut), P(OrGrid), P(OrPlan)]
+    L.or_point.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_longlong, C.c_longlong,
+                           C.c_int, C.c_int, P(C.c_double)]
+    L.or_simulate_window.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_longlong,
+                                     C.c_longlong, C.c_longlong, C.c_longlong,
+                                     P(C.c_double), P(C.c_longlong), P(OrCounts)]
+    L.or_cell_bounds.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_double,
+                                 P(C.c_double), P(C.c_double), P(C.c_double)]
+    L.or_cell_bounds_window.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_double,
+                                        C.c_longlong, C.c_longlong, C.c_longlong,
+                                        C.c_longlong, P(C.c_double), P(C.c_double),
+                                        P(C.c_double)]
+    L.or_roughness.argtypes = [P(C.c_double), C.c_longlong, C.c_longlong, P(OrRough)]
+    L.or_paper_trajectory_points.argtypes = [C.c_double, C.c_double, C.c_int,
+                                             C.c_double, C.c_double, C.c_double]
+    L.or_paper_trajectory_points.restype = C.c_longlong
+    return L
+
+
 def lib() -> C.CDLL:
     global _lib
     with _lock:
         if _lib is None:
             build()
-            L = C.CDLL(_LIB)
-            P = C.POINTER
-            L.or_edge_points.argtypes = [P(OrTool), P(OrCut), P(C.c_double), P(C.c_double)]
-            L.or_plan.argtypes = [P(OrTool), P(OrCut), P(OrGrid), P(OrPlan)]
-            L.or_point.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_longlong, C.c_longlong,
-                                   C.c_int, C.c_int, P(C.c_double)]
-            L.or_simulate_window.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_longlong,
-                                             C.c_longlong, C.c_longlong, C.c_longlong,
-                                             P(C.c_double), P(C.c_longlong), P(OrCounts)]
-            L.or_cell_bounds.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_double,
-                                         P(C.c_double), P(C.c_double), P(C.c_double)]
-            L.or_cell_bounds_window.argtypes = [P(OrTool), P(OrCut), P(OrGrid), C.c_double,
-                                                C.c_longlong, C.c_longlong, C.c_longlong,
-                                                C.c_longlong, P(C.c_double), P(C.c_double),
-                                                P(C.c_double)]
-            L.or_roughness.argtypes = [P(C.c_double), C.c_longlong, C.c_longlong, P(OrRough)]
-            L.or_paper_trajectory_points.argtypes = [C.c_double, C.c_double, C.c_int,
-                                                     C.c_double, C.c_double, C.c_double]
-            L.or_paper_trajectory_points.restype = C.c_longlong
-            _lib = L
+            _lib = _configure(C.CDLL(_LIB))
     return _lib
+
+
+@contextlib.contextmanager
+def use_library(path: str):
+    """Run the oracle's functions on another build of its source (a copy with a planted
+    mistake, in the mutation tests) for the duration of the block."""
+    global _lib
+    lib()
+    with _lock:
+        saved = _lib
+        _lib = _configure(C.CDLL(path))
+    try:
+        yield
+    finally:
+        with _lock:
+            _lib = saved
 
 
 def _tool(t) -> OrTool:
