@@ -69,9 +69,11 @@ def stored_traffic(kernel, prec):
     return d.get("hbm_bytes_per_launch")
 
 
-def run_precision(ctx, sim, prec, steps, warmup, profile):
+def run_precision(ctx, sim, prec, steps, warmup, profile, graphs=False):
     import torch
     zmap = ctx.new_zmap(sim.grid, prec)
+    # per-stage events need eager launches; the value steps may replay a captured graph
+    ctx.set_graphs(graphs and not profile)
     ctx.fsm_ctx_set_profiling(profile)
     for _ in range(warmup):
         ctx.fsm_simulate(sim, prec, zmap)
@@ -260,6 +262,13 @@ def main():
     ap.add_argument("--strategy", choices=["binned", "scatter"], default="binned")
     ap.add_argument("--compare-strategies", action="store_true",
                     help="also time the other Z-map strategy (reported, not the value)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the launch sequence from a HIP graph in the timed steps")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let fsm_autotune pick the launch parameters before timing (untimed)")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2603_28160_amd", "tuning_mi355x.json"),
+                    help="saved tuning table to load (the library's autotuner output); "
+                         "'none' to run on the default launch parameters")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batch (configuration 3) and serving (configuration 4) legs")
     ap.add_argument("--batch-sims", type=int, default=256)
@@ -291,6 +300,11 @@ def main():
     n_cells = sim.grid.nx * sim.grid.ny
     res = {}
     with Context(0) as ctx:
+        n_tuned = 0
+        if args.tuning != "none" and os.path.exists(args.tuning):
+            n_tuned = ctx.load_tuning(args.tuning)
+            print(f"[bench] tuning table: {n_tuned} entries from {os.path.basename(args.tuning)}",
+                  file=sys.stderr, flush=True)
         precs = ["f64", "f32"] if args.precision == "both" else [args.precision]
         other = {}
         if args.compare_strategies:
@@ -301,10 +315,15 @@ def main():
                 other[prec] = {"ms_per_step": o["ms_per_step"], "zmap_ms": o["scatter_ms"]}
                 print(f"[bench] {alt} {prec}: {o['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         ctx.set_strategy(args.strategy)
+        tuned = {}
         for prec in precs:
+            if args.autotune:
+                tuned[prec] = ctx.fsm_autotune([sim], prec)
+                print(f"[bench] autotune {prec}: {tuned[prec]}", file=sys.stderr, flush=True)
             print(f"[bench] {sim.name} {prec}: warmup {args.warmup}, steps {args.steps}",
                   file=sys.stderr, flush=True)
-            res[prec] = run_precision(ctx, sim, prec, args.steps, args.warmup, profile=False)
+            res[prec] = run_precision(ctx, sim, prec, args.steps, args.warmup, profile=False,
+                                      graphs=args.graphs)
             res[prec]["prof"] = run_precision(ctx, sim, prec, args.steps, 1, profile=True)
             p = res[prec]["prof"]
             print(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step; z-map {p['scatter_ms']:.3f} ms "
@@ -345,7 +364,8 @@ def main():
                    "passes": plan["n_passes"], "steps_per_pass": plan["n_steps"],
                    "edge_points": sim.tool.n_edge, "evals": plan["n_evals"],
                    "precision": main_prec, "mode": "plain single-simulation launches",
-                   "zmap_strategy": args.strategy},
+                   "zmap_strategy": args.strategy, "graphs": args.graphs,
+                   "tuning_entries": n_tuned, "autotuned": tuned.get(main_prec)},
         "sims_per_s": args.steps / m["elapsed_s"],
         "latency_ms": {"p50": pct(m["lat"], 50), "p99": pct(m["lat"], 99)},
         "evals_per_s": plan["n_evals"] * args.steps / m["elapsed_s"],

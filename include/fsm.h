@@ -265,6 +265,24 @@ typedef struct fsm_tune_result {
 int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tune_result *out,
                  void *stream);
 
+/* One entry of a context's tuning table: the workload class (as fsm_autotune forms it) and
+ * the launch parameters kept for it. */
+typedef struct fsm_tune_entry {
+    char key[64];            /* workload class, NUL-terminated */
+    int32_t strategy;        /* FSM_ZMAP_BINNED or FSM_ZMAP_SCATTER */
+    int32_t tile_shape;      /* FSM_OPT_TILE_SHAPE encoding (0: default) */
+    int32_t target_rows;     /* FSM_OPT_TARGET_ROWS value */
+    int32_t reserved;
+} fsm_tune_entry;
+
+/* Copy the context's tuning table into out[0..cap) (sorted by key); *n receives the number of
+ * entries (which may exceed cap).  Lets a caller save what fsm_autotune measured. */
+int fsm_tune_get(const fsm_ctx *ctx, fsm_tune_entry *out, int cap, int *n);
+
+/* Add (or replace) n entries of the context's tuning table, e.g. from a saved table of the same
+ * device type.  FSM_EINVAL for a bad strategy, tile shape or row count. */
+int fsm_tune_set(fsm_ctx *ctx, const fsm_tune_entry *entries, int n);
+
 /* Roughness of an existing Z-map in device memory (+inf = empty cell), same estimator as
  * fsm_simulate.  n_evals and n_binned of the result are zero. */
 int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_dev,

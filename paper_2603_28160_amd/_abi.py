@@ -86,6 +86,11 @@ class FsmTuneResult(C.Structure):
                 ("n_tried", C.c_int32), ("best_ms", C.c_float), ("default_ms", C.c_float)]
 
 
+class FsmTuneEntry(C.Structure):
+    _fields_ = [("key", C.c_char * 64), ("strategy", C.c_int32), ("tile_shape", C.c_int32),
+                ("target_rows", C.c_int32), ("reserved", C.c_int32)]
+
+
 class FsmRequest(C.Structure):
     _fields_ = [("tool", C.POINTER(FsmTool)), ("cut", C.POINTER(FsmCut)),
                 ("grid", C.POINTER(FsmGrid)), ("arrival_s", C.c_double),
@@ -128,6 +133,8 @@ SIGNATURES = {
                            C.c_int),
     "fsm_autotune": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmTuneResult), C.c_void_p],
                      C.c_int),
+    "fsm_tune_get": ([C.c_void_p, P(FsmTuneEntry), C.c_int, P(C.c_int)], C.c_int),
+    "fsm_tune_set": ([C.c_void_p, P(FsmTuneEntry), C.c_int], C.c_int),
     "fsm_serve_run": ([C.c_void_p, P(FsmServeConfig), C.c_int, P(FsmRequest),
                        P(FsmRequestResult)], C.c_int),
     "fsm_serve_dry_run": ([P(FsmServeConfig), P(FsmServeModel), C.c_int, P(FsmRequest),

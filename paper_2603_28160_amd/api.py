@@ -266,6 +266,34 @@ class Context:
         _check(rc, "fsm_autotune", self._h)
         return {k: getattr(out, k) for k, _ in out._fields_}
 
+    def fsm_tune_get(self) -> list:
+        """The context's tuning table: [{key, strategy, tile_shape, target_rows}, ...]."""
+        n = C.c_int(0)
+        _check(self._lib.fsm_tune_get(self._h, None, 0, C.byref(n)), "fsm_tune_get", self._h)
+        buf = (_abi.FsmTuneEntry * max(1, n.value))()
+        _check(self._lib.fsm_tune_get(self._h, buf, n.value, C.byref(n)), "fsm_tune_get", self._h)
+        return [{"key": e.key.decode(), "strategy": e.strategy, "tile_shape": e.tile_shape,
+                 "target_rows": e.target_rows} for e in buf[:n.value]]
+
+    def fsm_tune_set(self, entries):
+        """Add entries (dicts as fsm_tune_get returns them) to the context's tuning table."""
+        n = len(entries)
+        buf = (_abi.FsmTuneEntry * max(1, n))()
+        for k, e in enumerate(entries):
+            buf[k].key = e["key"].encode()
+            buf[k].strategy = int(e["strategy"])
+            buf[k].tile_shape = int(e["tile_shape"])
+            buf[k].target_rows = int(e["target_rows"])
+        _check(self._lib.fsm_tune_set(self._h, buf, n), "fsm_tune_set", self._h)
+
+    def load_tuning(self, path) -> int:
+        """Load a saved tuning table (JSON written by paper_2603_28160_amd.tune)."""
+        import json
+        with open(path) as f:
+            entries = json.load(f)["entries"]
+        self.fsm_tune_set(entries)
+        return len(entries)
+
     def set_graphs(self, on: bool = True):
         """Capture launch sequences into HIP graphs and replay them per launch shape."""
         self.fsm_ctx_set_option(_abi.OPT_GRAPHS, 1 if on else 0)

@@ -923,6 +923,50 @@ int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tu
     }
 }
 
+int fsm_tune_get(const fsm_ctx *ctx, fsm_tune_entry *out, int cap, int *n)
+{
+    if (!ctx || !n || cap < 0 || (cap > 0 && !out)) return FSM_EINVAL;
+    int k = 0;
+    for (const auto &e : ctx->tuned) {
+        if (k < cap) {
+            fsm_tune_entry &o = out[k];
+            std::memset(&o, 0, sizeof o);
+            std::snprintf(o.key, sizeof o.key, "%s", e.first.c_str());
+            o.strategy = e.second.strategy == fsm::kStrategyScatter ? FSM_ZMAP_SCATTER : FSM_ZMAP_BINNED;
+            o.tile_shape = e.second.tile_shape;
+            o.target_rows = (int32_t)e.second.target_rows;
+        }
+        ++k;
+    }
+    *n = k;
+    return FSM_OK;
+}
+
+int fsm_tune_set(fsm_ctx *ctx, const fsm_tune_entry *entries, int n)
+{
+    if (!ctx) return FSM_EINVAL;
+    if (n < 0 || (n > 0 && !entries)) return set_err(ctx, FSM_EINVAL, "null entries");
+    for (int k = 0; k < n; ++k) {
+        const fsm_tune_entry &e = entries[k];
+        const size_t len = strnlen(e.key, sizeof e.key);
+        const bool shape_ok = e.tile_shape == 0 || valid_tile_shape(ctx, FSM_F64, e.tile_shape) ||
+                              valid_tile_shape(ctx, FSM_F32, e.tile_shape);
+        if (len == 0 || len == sizeof e.key || (e.strategy != FSM_ZMAP_BINNED && e.strategy != FSM_ZMAP_SCATTER) ||
+            !shape_ok || e.target_rows < 256 || e.target_rows > 65536)
+            return set_err(ctx, FSM_EINVAL, "tuning entry " + std::to_string(k) + " is invalid");
+    }
+    for (int k = 0; k < n; ++k) {
+        const fsm_tune_entry &e = entries[k];
+        LaunchParams lp;
+        lp.strategy = e.strategy == FSM_ZMAP_SCATTER ? fsm::kStrategyScatter : fsm::kStrategyBinned;
+        lp.tile_shape = e.tile_shape;
+        lp.target_rows = e.target_rows;
+        lp.bucket_bytes = ctx->bucket_bytes;
+        ctx->tuned[std::string(e.key, strnlen(e.key, sizeof e.key))] = lp;
+    }
+    return FSM_OK;
+}
+
 int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_dev,
                   fsm_rough *out, void *stream)
 {

@@ -40,7 +40,8 @@ def test_struct_layouts_match_header(tmp_path):
                "fsm_timings": _abi.FsmTimings, "fsm_job": _abi.FsmJob,
                "fsm_tune_result": _abi.FsmTuneResult, "fsm_request": _abi.FsmRequest,
                "fsm_request_result": _abi.FsmRequestResult,
-               "fsm_serve_config": _abi.FsmServeConfig, "fsm_serve_model": _abi.FsmServeModel}
+               "fsm_serve_config": _abi.FsmServeConfig, "fsm_serve_model": _abi.FsmServeModel,
+               "fsm_tune_entry": _abi.FsmTuneEntry}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -132,6 +133,8 @@ def test_null_arguments_and_strerror():
     assert lib.fsm_simulate_batch(None, 0, None, 0, None, None) == _abi.EINVAL
     assert lib.fsm_autotune(None, 0, None, 0, None, None) == _abi.EINVAL
     assert lib.fsm_serve_run(None, None, 0, None, None) == _abi.EINVAL
+    assert lib.fsm_tune_get(None, None, 0, None) == _abi.EINVAL
+    assert lib.fsm_tune_set(None, None, 0) == _abi.EINVAL
     assert lib.fsm_serve_dry_run(None, None, 0, None, None, None) == _abi.EINVAL
     assert lib.fsm_last_error(None, None, 0) == _abi.EINVAL
     for code in (0, -1, -2, -3, -4, -5, -99):

@@ -102,3 +102,28 @@ def test_autotune_choice_is_used_and_exact(ctx, prec):
         for k, s in enumerate(sims):
             zo, _ = oracle.simulate(s)
             assert np.array_equal(ref[k], zo), k
+
+
+def test_tuning_table_round_trip(ctx):
+    import json
+    import os
+    entries = [{"key": "0/0/18/22", "strategy": _abi.ZMAP_BINNED, "tile_shape": 0x67, "target_rows": 2048},
+               {"key": "1/0/18/22", "strategy": _abi.ZMAP_SCATTER, "tile_shape": 0, "target_rows": 4096}]
+    ctx.fsm_tune_set(entries)
+    got = {e["key"]: e for e in ctx.fsm_tune_get()}
+    for e in entries:
+        assert got[e["key"]] == e
+    for bad in ({"key": "", "strategy": 0, "tile_shape": 0, "target_rows": 4096},
+                {"key": "x", "strategy": 7, "tile_shape": 0, "target_rows": 4096},
+                {"key": "x", "strategy": 0, "tile_shape": 0x99, "target_rows": 4096},
+                {"key": "x", "strategy": 0, "tile_shape": 0, "target_rows": 10}):
+        with pytest.raises(_abi.FsmError):
+            ctx.fsm_tune_set([bad])
+    # the shipped table loads and keeps the maps of its workload classes
+    path = os.path.join(os.path.dirname(_abi.__file__), "tuning_mi355x.json")
+    if os.path.exists(path):
+        z0, r0 = ctx.fsm_simulate(SIM, "f64")
+        n = ctx.load_tuning(path)
+        assert n == len(json.load(open(path))["entries"])
+        z1, r1 = ctx.fsm_simulate(SIM, "f64")
+        assert np.array_equal(z0.cpu().numpy(), z1.cpu().numpy())
