@@ -226,6 +226,15 @@ int fsm_last_timings(const fsm_ctx *ctx, fsm_timings *out);
 int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid,
                  int precision, void *zmap_dev, fsm_rough *out, void *stream);
 
+/* The trajectory module (Sec. 3.2): for every pass q, time step s and tooth K, the
+ * workpiece-frame position of the lowest point (least z) of the tooth's discretised edge,
+ * the first such point on a tie.  traj_dev: caller-owned device memory of
+ * n_passes * n_steps * n_teeth * 3 doubles (FSM_F64) or floats (FSM_F32), [q][s][K][x, y, z];
+ * index_dev (nullable): as many int32 edge-point indices.  Sizes from fsm_plan.  The work is
+ * queued on `stream`; the call returns after it has finished. */
+int fsm_trajectory(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid,
+                   int precision, void *traj_dev, int32_t *index_dev, void *stream);
+
 /* One simulation of a batch.  Every pointer is borrowed for the duration of the call. */
 typedef struct fsm_job {
     const fsm_tool *tool;

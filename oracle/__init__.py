@@ -5,6 +5,6 @@ reached through ctypes.  It shares no code with the GPU library and is used only
 the smoke check and the benchmark's CPU-baseline leg.
 """
 from .oracle import (  # noqa: F401
-    build, lib, edge_points, plan, point, simulate, cell_bounds, roughness,
+    build, lib, edge_points, plan, point, simulate, trajectory, cell_bounds, roughness,
     paper_trajectory_points,
 )

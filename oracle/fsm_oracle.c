@@ -328,6 +328,44 @@ int or_point(const or_tool *t, const or_cut *c, const or_grid *g,
     return 0;
 }
 
+/* The trajectory module of Sec. 3.2: at every time step, the lowest point (least z) of each
+ * tooth's discretised edge in the workpiece frame; the first such point on a tie. */
+int or_trajectory(const or_tool *t, const or_cut *c, const or_grid *g, double *xyz, int *idx)
+{
+    if (!xyz) return -1;
+    chain ch;
+    int rc = chain_init(t, c, g, &ch);
+    if (rc) return rc;
+    const int Zt = t->n_teeth, N = t->n_edge;
+    for (long long q = 0; q < ch.plan.n_passes; ++q) {
+        for (long long s = 0; s < ch.plan.n_steps; ++s) {
+            m4 W;
+            m_spindle_to_work(c, &ch, q, s, W);
+            for (int K = 0; K < Zt; ++K) {
+                m4 T;
+                m_tool_to_spindle(t, c, &ch, s, K, T);
+                double best[4] = {0.0, 0.0, INFINITY, 1.0};
+                int bp = -1;
+                for (int p = 0; p < N; ++p) {
+                    double w[4];
+                    transform(&ch, T, W, ch.pT + 3 * ((long long)K * N + p), w);
+                    if (w[2] < best[2]) {
+                        best[0] = w[0]; best[1] = w[1]; best[2] = w[2];
+                        bp = p;
+                    }
+                }
+                const long long o = (q * ch.plan.n_steps + s) * Zt + K;
+                xyz[3 * o] = best[0];
+                xyz[3 * o + 1] = best[1];
+                xyz[3 * o + 2] = best[2];
+                if (idx) idx[o] = bp;
+            }
+        }
+    }
+    free(ch.pT);
+    return 0;
+}
+
 /* Eq. (7) with half-open sampling boundaries [x_i - dd/2, x_i + dd/2): the node index is the
  * floor of the offset from the lower boundary in units of dd.  Returns 0 when the point lies
  * outside the grid (such points are dropped, not clamped). */

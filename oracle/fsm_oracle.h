@@ -95,6 +95,11 @@ int or_plan(const or_tool *t, const or_cut *c, const or_grid *g, or_plan_out *ou
 int or_point(const or_tool *t, const or_cut *c, const or_grid *g,
              long long q, long long s, int K, int p, double out[3]);
 
+/* Trajectory module (Sec. 3.2): for every pass q, step s and tooth K, the workpiece-frame
+ * position of the lowest point of the tooth's edge (first on a tie).  xyz: [n_passes][n_steps]
+ * [n_teeth][3] doubles; idx (nullable): the edge point index, same order. */
+int or_trajectory(const or_tool *t, const or_cut *c, const or_grid *g, double *xyz, int *idx);
+
 /* Per-cell minimum Z-map (Sec. 2.3, Eq. (7)) restricted to the cell window
  * [i0,i1) x [j0,j1); Zw is (j1-j0)*(i1-i0) doubles, row-major, filled with +inf for cells no
  * point reached.  win (nullable) receives the flat evaluation index of each cell's winner. */

@@ -95,6 +95,7 @@ def _configure(L: C.CDLL) -> C.CDLL:
                                         C.c_longlong, C.c_longlong, C.c_longlong,
                                         C.c_longlong, P(C.c_double), P(C.c_double),
                                         P(C.c_double)]
+    L.or_trajectory.argtypes = [P(OrTool), P(OrCut), P(OrGrid), P(C.c_double), P(C.c_int)]
     L.or_roughness.argtypes = [P(C.c_double), C.c_longlong, C.c_longlong, P(OrRough)]
     L.or_paper_trajectory_points.argtypes = [C.c_double, C.c_double, C.c_int,
                                              C.c_double, C.c_double, C.c_double]
@@ -214,6 +215,21 @@ def simulate(sim, window=None, winners: bool = False):
     return (Z, counts, W) if winners else (Z, counts)
 
 
+def trajectory(sim):
+    """(xyz [n_passes, n_steps, n_teeth, 3], edge index [n_passes, n_steps, n_teeth]) of the
+    lowest edge point per time step and tooth."""
+    p = plan(sim)
+    shape = (p["n_passes"], p["n_steps"], sim.tool.n_teeth)
+    xyz = np.empty(shape + (3,))
+    idx = np.empty(shape, dtype=np.int32)
+    rc = lib().or_trajectory(C.byref(_tool(sim.tool)), C.byref(_cut(sim.cut)),
+                             C.byref(_grid(sim.grid)), _dp(xyz),
+                             idx.ctypes.data_as(C.POINTER(C.c_int)))
+    if rc:
+        raise ValueError(f"or_trajectory: invalid parameters ({rc})")
+    return xyz, idx
+
+
 def cell_bounds(sim, delta: float, window=None):
     """(lo, hi, top) per cell when every evaluation may move by up to delta in x and y, over
     the whole grid or the cell window (i0, i1, j0, j1)."""
@@ -243,5 +259,5 @@ def paper_trajectory_points(v_c: float, f_z: float, z_n: int, D: float, L: float
     return int(lib().or_paper_trajectory_points(v_c, f_z, z_n, D, L, dt))
 
 
-__all__ = ["build", "lib", "edge_points", "plan", "point", "simulate", "cell_bounds",
+__all__ = ["build", "lib", "edge_points", "plan", "point", "simulate", "trajectory", "cell_bounds",
            "roughness", "paper_trajectory_points"]

@@ -131,6 +131,8 @@ SIGNATURES = {
                       C.c_int),
     "fsm_simulate_batch": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmRough), C.c_void_p],
                            C.c_int),
+    "fsm_trajectory": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, C.c_void_p,
+                        C.c_void_p, C.c_void_p], C.c_int),
     "fsm_autotune": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmTuneResult), C.c_void_p],
                      C.c_int),
     "fsm_tune_get": ([C.c_void_p, P(FsmTuneEntry), C.c_int, P(C.c_int)], C.c_int),

@@ -188,6 +188,23 @@ class Context:
         _check(rc, "fsm_simulate", self._h)
         return zmap, (out.as_dict() if roughness else None)
 
+    def fsm_trajectory(self, sim, precision="f64", stream=None):
+        """Lowest edge point per (pass, step, tooth) in the workpiece frame: returns (xyz
+        tensor [n_passes, n_steps, n_teeth, 3], edge-index tensor [n_passes, n_steps, n_teeth])."""
+        torch = _torch()
+        p = fsm_plan(sim, precision)
+        shape = (int(p["n_passes"]), int(p["n_steps"]), int(sim.tool.n_teeth))
+        dt = torch.float64 if _prec(precision) == _abi.F64 else torch.float32
+        dev = f"cuda:{self.device}"
+        xyz = torch.empty(shape + (3,), dtype=dt, device=dev)
+        idx = torch.empty(shape, dtype=torch.int32, device=dev)
+        rc = self._lib.fsm_trajectory(
+            self._h, C.byref(_abi.tool_struct(sim.tool)), C.byref(_abi.cut_struct(sim.cut)),
+            C.byref(_abi.grid_struct(sim.grid)), _prec(precision), C.c_void_p(xyz.data_ptr()),
+            C.c_void_p(idx.data_ptr()), C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_trajectory", self._h)
+        return xyz, idx
+
     def fsm_roughness(self, grid, zmap, precision="f64", stream=None) -> dict:
         """Roughness of an existing device Z-map (+inf = empty cell)."""
         self._check_zmap(grid, precision, zmap)
@@ -303,4 +320,5 @@ class Context:
     roughness = fsm_roughness
     simulate_batch = fsm_simulate_batch
     serve = fsm_serve_run
+    trajectory = fsm_trajectory
     autotune = fsm_autotune

@@ -781,6 +781,45 @@ int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const f
     }
 }
 
+int fsm_trajectory(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid,
+                   int precision, void *traj_dev, int32_t *index_dev, void *stream)
+{
+    if (!ctx) return FSM_EINVAL;
+    if (!tool || !cut || !grid || !traj_dev || !valid_precision(precision))
+        return set_err(ctx, FSM_EINVAL, "null argument or invalid precision");
+    try {
+        std::vector<Plan> plans(1);
+        std::string err;
+        int rc = fsm::build_plan(*tool, *cut, *grid, plans[0], err, true);
+        if (rc != FSM_OK) return set_err(ctx, rc, err);
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
+        // the image of one simulation (descriptor and tables); no Z-map is touched
+        LaunchParams lp;
+        lp.strategy = fsm::kStrategyScatter;
+        std::vector<DevSim> devs;
+        const SetLayout L = make_layout(ctx, plans, precision, lp, devs);
+        rc = ensure(ctx, ctx->ws, L.total, L.total - L.sims, 1);
+        if (rc != FSM_OK) return rc;
+        char *dev = static_cast<char *>(ctx->ws.d_ws);
+        std::vector<void *> zmaps{nullptr};
+        fill_image(L, plans, devs, zmaps, dev, static_cast<char *>(ctx->ws.h_ws));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        e = hipMemcpyAsync(dev + L.sims, ctx->ws.h_ws, L.total - L.sims, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
+        const int he = fsm::launch_trajectory(reinterpret_cast<const DevSim *>(dev + L.sims),
+                                              devs[0].n_bitems, precision, traj_dev, index_dev, s);
+        if (he) return hip_err(ctx, (hipError_t)he, "trajectory kernel");
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+        return FSM_OK;
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, FSM_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return set_err(ctx, FSM_EINVAL, "unexpected host exception");
+    }
+}
+
 int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_rough *out,
                        void *stream)
 {

@@ -201,6 +201,9 @@ int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_bas
                       int64_t row_end, const BinBuffers &bb, int precision, int sx, int sy,
                       TileStat1 *st1, uint64_t *d_binned, void *stream,
                       const StageEvents *marks = nullptr);
+// Trajectory module: per (pass, step, tooth) the lowest edge point's workpiece position.
+int launch_trajectory(const DevSim *d_sim, int64_t n_items, int precision, void *traj,
+                      int32_t *index, void *stream);
 // Tiled roughness.  with_pass1: run the first pass (decoding scatter keys if `decode`);
 // otherwise its tile partials are already in st1.  out: one record per simulation.
 int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, int64_t n_tiles,

@@ -65,6 +65,7 @@ template <> struct KeyOf<FSM_F32> {
     __device__ static int32_t enc(int32_t k) { return enc32(k); }
     __device__ static double height(int32_t k) { return (double)__int_as_float(k); }
 };
+template <int PREC> __device__ __forceinline__ typename KeyOf<PREC>::T KT_inf() { return KeyOf<PREC>::inf; }
 
 // Block b of a launch runs on XCD (b mod 8).  Give every XCD a contiguous range of items so
 // that the items sharing one XCD's L2 are neighbours along the tool path.
@@ -459,6 +460,59 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
         }
         const uint32_t w = wave_sum(cnt);
         if ((tid & 63) == 0 && w) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)w);
+    }
+}
+
+// ---- trajectory module ---------------------------------------------------------------------------
+
+// One item per (pass, block of kBlock steps, tooth), lanes over the steps: every lane walks the
+// tooth's edge points and keeps the first one of least height (keys order like heights).
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void trajectory(const DevSim *__restrict__ sims, int64_t n_items,
+                                                     void *__restrict__ traj, int32_t *__restrict__ index)
+{
+    using Key = typename KeyOf<PREC>::T;
+    using Real = decltype(Edge<PREC>::x);
+    const DevSim d = sims[0];
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        int64_t local = item;
+        const int K = (int)(local % d.z_n);
+        local /= d.z_n;
+        const int sb = (int)(local % d.n_sblocks);
+        const int q = (int)(local / d.n_sblocks);
+        const int s = sb * kBlock + (int)threadIdx.x;
+        if (s >= d.n_steps) continue;
+        const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
+        Key best = KT_inf<PREC>();
+        Real bx = 0, by = 0;
+        int bp = -1;
+        for (int p = 0; p < d.N; ++p) {
+            Real xs, ys;
+            Key key;
+            turn_point(d, a, edge_point<PREC>(d, K, p), xs, ys, key);
+            if (key < best) {
+                best = key;
+                bx = xs;
+                by = ys;
+                bp = p;
+            }
+        }
+        const double xcs = gptr(d.xc)[s];
+        const double yq = d.y_first + (double)q * d.a_e;
+        const int64_t o = ((int64_t)q * d.n_steps + s) * d.z_n + K;
+        const double z = KeyOf<PREC>::height(KeyOf<PREC>::enc(best));
+        if (PREC == FSM_F64) {
+            FSM_GLOBAL double *t = gptr(static_cast<double *>(traj)) + 3 * o;
+            t[0] = xcs + (double)bx;
+            t[1] = yq + (double)by;
+            t[2] = z;
+        } else {
+            FSM_GLOBAL float *t = gptr(static_cast<float *>(traj)) + 3 * o;
+            t[0] = (float)(xcs + (double)bx);
+            t[1] = (float)(yq + (double)by);
+            t[2] = (float)z;
+        }
+        if (index) gptr(index)[o] = bp;
     }
 }
 
@@ -1272,6 +1326,20 @@ int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_bas
     return (int)hipGetLastError();
 }
 
+
+int launch_trajectory(const DevSim *d_sim, int64_t n_items, int precision, void *traj,
+                      int32_t *index, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int ib = (int)(n_items < kMaxGrid ? n_items : kMaxGrid);
+    if (ib > 0) {
+        if (precision == FSM_F64)
+            hipLaunchKernelGGL(trajectory<FSM_F64>, dim3(ib), dim3(kBlock), 0, s, d_sim, n_items, traj, index);
+        else
+            hipLaunchKernelGGL(trajectory<FSM_F32>, dim3(ib), dim3(kBlock), 0, s, d_sim, n_items, traj, index);
+    }
+    return (int)hipGetLastError();
+}
 
 int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, int64_t n_tiles,
                  int precision, int, int, bool with_pass1, bool decode, TileStat1 *st1,

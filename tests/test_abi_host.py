@@ -134,6 +134,7 @@ def test_null_arguments_and_strerror():
     assert lib.fsm_autotune(None, 0, None, 0, None, None) == _abi.EINVAL
     assert lib.fsm_serve_run(None, None, 0, None, None) == _abi.EINVAL
     assert lib.fsm_tune_get(None, None, 0, None) == _abi.EINVAL
+    assert lib.fsm_trajectory(None, None, None, None, 0, None, None, None) == _abi.EINVAL
     assert lib.fsm_tune_set(None, None, 0) == _abi.EINVAL
     assert lib.fsm_serve_dry_run(None, None, 0, None, None, None) == _abi.EINVAL
     assert lib.fsm_last_error(None, None, 0) == _abi.EINVAL

@@ -520,3 +520,50 @@ def test_roughness_skew_sign():
     assert r["Ssk"] > 5 and r["Sku"] > 30
     r2 = oracle.roughness(-Z)     # one pit: negative skew
     assert r2["Ssk"] == pytest.approx(-r["Ssk"], rel=1e-13)
+
+
+# --- trajectory module (Sec. 3.2) ------------------------------------------------------------
+
+def test_trajectory_of_a_plain_insert_is_the_trochoid():
+    # no rake, helix, runout or tilt: the lowest point of a round insert is its middle point at
+    # radius D/2, so the trajectory is the trochoid x = x_c + (D/2) cos a, y = y_q - (D/2) sin a
+    # with a = phi + theta_K - 2 pi s / S (the Eq. (3) layout)
+    t = W.Tool(kind=W.ROUND, n_teeth=3, n_edge=21, D=10.0, R_edge=5.0)
+    c = W.Cut(f_z=0.2, a_p=0.5, phi0=0.3, steps_per_rev=90, n_passes=2, a_e=0.7, n_steps=200,
+              x_start=-1.0, y_first=0.25)
+    s = W.Sim(t, c, W.centred_grid(10, 10, 0.1))
+    xyz, idx = oracle.trajectory(s)
+    assert np.all(idx == 10)
+    q, st, K = np.meshgrid(np.arange(2), np.arange(200), np.arange(3), indexing="ij")
+    a = 0.3 + 2 * np.pi * K / 3 - 2 * np.pi * (st % 90) / 90
+    xc = -1.0 + st * (3 * 0.2) / 90
+    assert np.allclose(xyz[..., 0], xc + 5.0 * np.cos(a), atol=1e-12)
+    assert np.allclose(xyz[..., 1], 0.25 + q * 0.7 - 5.0 * np.sin(a), atol=1e-12)
+    assert np.allclose(xyz[..., 2], 0.0, atol=1e-12)
+
+
+def test_trajectory_of_an_upright_ball_is_the_centre_path():
+    # an untilted ball end's lowest point is its tip on the axis: the trajectory is the
+    # tool-centre path itself, at z = 0, from the first edge point
+    t = W.Tool(kind=W.BALL, n_teeth=2, n_edge=16, D=6.0, helix=0.4)
+    c = W.Cut(f_z=0.1, a_p=0.5, steps_per_rev=60, n_passes=3, a_e=0.3, n_steps=90,
+              x_start=0.5, y_first=-0.2)
+    s = W.Sim(t, c, W.centred_grid(8, 8, 0.1))
+    xyz, idx = oracle.trajectory(s)
+    assert np.all(idx == 0)
+    q, st, _ = np.meshgrid(np.arange(3), np.arange(90), np.arange(2), indexing="ij")
+    assert np.allclose(xyz[..., 0], 0.5 + st * (2 * 0.1) / 60, atol=1e-12)
+    assert np.allclose(xyz[..., 1], -0.2 + q * 0.3, atol=1e-12)
+    assert np.all(np.abs(xyz[..., 2]) <= 1e-15)
+
+
+def test_trajectory_tilted_ball_bottom():
+    # a ball tilted by tau touches lowest R (1 - cos tau) below the tip height, a point of the
+    # sphere off the axis: the trajectory's z is that constant (to the meridian sampling)
+    tau = math.radians(15.0)
+    t = W.Tool(kind=W.BALL, n_teeth=1, n_edge=401, D=6.0, tilt_lead=tau)
+    c = W.Cut(f_z=0.0, a_p=1.0, steps_per_rev=36, n_passes=1, n_steps=36, x_start=0.0, y_first=0.0)
+    s = W.Sim(t, c, W.centred_grid(4, 4, 0.1))
+    xyz, _ = oracle.trajectory(s)
+    assert np.all(xyz[..., 2] >= -3.0 * (1 - math.cos(tau)) - 1e-12)
+    assert np.min(xyz[..., 2]) == pytest.approx(-3.0 * (1 - math.cos(tau)), abs=2e-5)
