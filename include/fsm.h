@@ -178,6 +178,18 @@ int fsm_plan(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, int
  * doubles, [tooth][point][x,y,z]. */
 int fsm_edge_points(const fsm_tool *tool, const fsm_cut *cut, double *out);
 
+/* Host only.  Coverage-complete planning: the smallest edge-point count and time step at
+ * which consecutive samples of the swept edge lie at most `spacing` apart -- neighbouring edge
+ * points in space, and each edge point between consecutive time steps (its turn about the axis
+ * plus the feed) -- so that with spacing <= half the grid interval no cell the edge sweeps is
+ * left without a point (the paper refines the time step for the same reason, Sec. 2.2-2.3).
+ * Writes copies of the tool and cut with n_edge raised, and steps_per_rev raised (per-
+ * revolution mode) or dt lowered (fixed-step mode); never coarser than the input; n_steps is
+ * cleared so the path is planned again.  FSM_EINVAL for bad parameters, a spacing <= 0, or a
+ * refinement beyond 4096 edge points or 2^24 steps per revolution. */
+int fsm_refine(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, double spacing,
+               fsm_tool *tool_out, fsm_cut *cut_out);
+
 /* Create a context on HIP device `device`.  The context owns the device workspace (edge,
  * angle and path tables, reduction partials, counters) and pinned host staging; they grow on
  * demand and are freed by fsm_ctx_destroy.  FSM_EDEVICE if the device cannot be used. */

@@ -10,5 +10,6 @@ is its thin Python binding; torch provides device memory and streams.
         zmap, rough = ctx.fsm_simulate(workloads.config2(), precision="f32")
 """
 from ._abi import F32, F64, FsmError, TOOL_BALL, TOOL_ROUND  # noqa: F401
-from .api import Context, fsm_edge_points, fsm_plan, fsm_serve_dry_run, fsm_version  # noqa: F401
+from .api import (Context, fsm_edge_points, fsm_plan, fsm_refine, fsm_serve_dry_run,  # noqa: F401
+                  fsm_version)
 from . import workloads  # noqa: F401

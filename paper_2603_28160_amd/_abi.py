@@ -119,6 +119,7 @@ SIGNATURES = {
     "fsm_strerror": ([C.c_int], C.c_char_p),
     "fsm_plan": ([P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, P(FsmPlanInfo)], C.c_int),
     "fsm_edge_points": ([P(FsmTool), P(FsmCut), P(C.c_double)], C.c_int),
+    "fsm_refine": ([P(FsmTool), P(FsmCut), P(FsmGrid), C.c_double, P(FsmTool), P(FsmCut)], C.c_int),
     "fsm_ctx_create": ([P(C.c_void_p), C.c_int], C.c_int),
     "fsm_ctx_destroy": ([C.c_void_p], None),
     "fsm_last_error": ([C.c_void_p, C.c_char_p, C.c_size_t], C.c_int),

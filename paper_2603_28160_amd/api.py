@@ -58,6 +58,21 @@ def fsm_edge_points(sim) -> np.ndarray:
     return out
 
 
+def fsm_refine(sim, spacing: float):
+    """Coverage-complete planning: a copy of `sim` whose edge-point count and time step keep
+    every pair of consecutive samples of the swept edge at most `spacing` apart."""
+    import dataclasses
+    t_in, c_in = _abi.tool_struct(sim.tool), _abi.cut_struct(sim.cut)
+    t_out, c_out = _abi.FsmTool(), _abi.FsmCut()
+    rc = _abi.load().fsm_refine(C.byref(t_in), C.byref(c_in), C.byref(_abi.grid_struct(sim.grid)),
+                                float(spacing), C.byref(t_out), C.byref(c_out))
+    _check(rc, "fsm_refine")
+    tool = dataclasses.replace(sim.tool, n_edge=int(t_out.n_edge))
+    cut = dataclasses.replace(sim.cut, steps_per_rev=int(c_out.steps_per_rev), dt=c_out.dt,
+                              n_steps=int(c_out.n_steps))
+    return sim.replace(tool=tool, cut=cut, name=(sim.name + "_refined") if sim.name else "")
+
+
 def _torch():
     import torch
     return torch

@@ -665,6 +665,66 @@ int fsm_edge_points(const fsm_tool *tool, const fsm_cut *cut, double *out)
     }
 }
 
+int fsm_refine(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, double spacing,
+               fsm_tool *tool_out, fsm_cut *cut_out)
+{
+    if (!tool || !cut || !grid || !tool_out || !cut_out || !(spacing > 0.0) || !std::isfinite(spacing))
+        return FSM_EINVAL;
+    try {
+        fsm_tool t = *tool;
+        fsm_cut c = *cut;
+        std::string err;
+        Plan P;
+        int rc = fsm::build_plan(t, c, *grid, P, err, false);
+        if (rc != FSM_OK) return rc;
+        // largest distance between neighbouring edge points of any tooth (tool frame)
+        auto edge_gap = [](const Plan &Q) {
+            double gap = 0.0;
+            for (int K = 0; K < Q.z_n; ++K)
+                for (int p = 0; p + 1 < Q.N; ++p) {
+                    const double *a = &Q.pT[((size_t)K * Q.N + p) * 3], *b = a + 3;
+                    const double dx = b[0] - a[0], dy = b[1] - a[1], dz = b[2] - a[2];
+                    gap = std::max(gap, std::sqrt(dx * dx + dy * dy + dz * dz));
+                }
+            return gap;
+        };
+        // the edge is sampled uniformly in its parameter, so the gap shrinks like 1/(N - 1)
+        for (int it = 0; it < 16 && edge_gap(P) > spacing; ++it) {
+            const double need = std::ceil((double)(t.n_edge - 1) * edge_gap(P) / spacing) + 1.0;
+            if (!(need <= (double)FSM_MAX_EDGE)) return FSM_EINVAL;
+            t.n_edge = std::max(t.n_edge + 1, (int)need);
+            rc = fsm::build_plan(t, c, *grid, P, err, false);
+            if (rc != FSM_OK) return rc;
+        }
+        if (edge_gap(P) > spacing) return FSM_EINVAL;
+        // in one time step a point at distance r from the axis turns through a chord of at most
+        // r times the step angle, and the tool centre advances by the feed per step
+        double r_max = 0.0;
+        for (size_t k = 0; k < P.pT.size() / 3; ++k)
+            r_max = std::max(r_max, std::sqrt(P.pT[3 * k] * P.pT[3 * k] + P.pT[3 * k + 1] * P.pT[3 * k + 1]));
+        if (c.time_mode == FSM_TIME_FIXED_DT) {
+            const double n_rpm = (1000.0 * c.v_c) / (M_PI * t.D);
+            const double omega = ((2.0 * M_PI) * n_rpm) / 60.0;
+            const double v_f = (c.f_z * (double)t.n_teeth * n_rpm) / 60.0;
+            c.dt = std::min(c.dt, spacing / (omega * r_max + v_f));
+        } else {
+            const double need = std::ceil((2.0 * M_PI * r_max + (double)t.n_teeth * c.f_z) / spacing);
+            if (!(need <= (double)(1 << 24))) return FSM_EINVAL;
+            c.steps_per_rev = std::max(c.steps_per_rev, (int)need);
+        }
+        c.n_steps = 0;
+        rc = fsm::build_plan(t, c, *grid, P, err, false);
+        if (rc != FSM_OK) return rc;
+        *tool_out = t;
+        *cut_out = c;
+        return FSM_OK;
+    } catch (const std::bad_alloc &) {
+        return FSM_ENOMEM;
+    } catch (...) {
+        return FSM_EINVAL;
+    }
+}
+
 int fsm_ctx_create(fsm_ctx **out, int device)
 {
     if (!out) return FSM_EINVAL;
