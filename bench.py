@@ -158,6 +158,36 @@ def large_leg(ctx, steps=3):
             "coverage": r["n_hit"] / cells, "steps": steps}
 
 
+def coverage_leg(ctx, steps=3):
+    """Coverage-complete mode: the 200 x 200 single pass at 5 um refined by fsm_refine to a
+    sample spacing of half a cell, both precisions; coverage before and after, time per
+    simulation and evaluations/s."""
+    import torch
+    from paper_2603_28160_amd import fsm_plan, fsm_refine, workloads
+    coarse = workloads.config1()
+    sim = fsm_refine(coarse, coarse.grid.dd / 2)
+    plan = fsm_plan(sim)
+    cells = sim.grid.nx * sim.grid.ny
+    out = {"workload": "config1_refined_to_half_cell", "n_edge": sim.tool.n_edge,
+           "steps_per_rev": sim.cut.steps_per_rev, "evals": plan["n_evals"]}
+    for prec in ("f64", "f32"):
+        z = ctx.new_zmap(sim.grid, prec)
+        _, r0 = ctx.fsm_simulate(coarse, prec, z)
+        ctx.fsm_simulate(sim, prec, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, r = ctx.fsm_simulate(sim, prec, z)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        out[prec] = {"ms_per_sim": el * 1e3, "evals_per_s": plan["n_evals"] / el,
+                     "coverage_coarse": r0["n_hit"] / cells, "coverage": r["n_hit"] / cells}
+    print(f"[bench] refined config1: f64 {out['f64']['ms_per_sim']:.2f} ms, coverage "
+          f"{out['f64']['coverage_coarse']:.3f} -> {out['f64']['coverage']:.3f}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 # EFSM wall times (s) of the paper's nine performance conditions on its laptop CPU, from the
 # computation-time table of Sec. 4.3: context for the paper-mode leg, not a target
 PAPER_EFSM_S = {1: 0.81, 2: 0.68, 3: 0.55, 4: 0.65, 5: 0.52, 6: 0.45, 7: 0.59, 8: 0.46, 9: 0.43}
@@ -336,6 +366,7 @@ def main():
             extras["serving"] = serve_leg(ctx, args.serve_requests, args.serve_rate)
             extras["large_field"] = large_leg(ctx)
             extras["paper_mode"] = paper_leg(ctx)
+            extras["coverage_complete"] = coverage_leg(ctx)
 
     main_prec = "f64" if "f64" in res else precs[0]
     m = res[main_prec]
