@@ -6,5 +6,5 @@ the smoke check and the benchmark's CPU-baseline leg.
 """
 from .oracle import (  # noqa: F401
     build, lib, edge_points, plan, point, simulate, trajectory, cell_bounds, roughness,
-    paper_trajectory_points,
+    paper_trajectory_points, level, gauss_filter,
 )

@@ -573,3 +573,140 @@ long long or_paper_trajectory_points(double v_c, double f_z, int z_n, double D,
     const long long steps = (long long)ceil(T / dt);
     return (long long)z_n * steps;                        /* one trajectory point per tooth per step */
 }
+
+/* ---- surface-texture operators (measurement practice of Sec. 4.1.1) ----------------------- */
+
+/* Least-squares plane: the normal equations (A^T A) c = A^T z of the design rows (1, x, y),
+ * solved by Gaussian elimination with partial pivoting. */
+int or_level(const double *Z, const or_grid *g, double *out, double *plane)
+{
+    if (!Z || !g || !out || g->nx < 1 || g->ny < 1 || !(g->dd > 0.0)) return -1;
+    double M[3][4] = {{0.0}};
+    for (long long j = 0; j < g->ny; ++j) {
+        for (long long i = 0; i < g->nx; ++i) {
+            const double z = Z[j * g->nx + i];
+            if (!(z < INFINITY)) continue;
+            const double r[3] = {1.0, g->x0 + (double)i * g->dd, g->y0 + (double)j * g->dd};
+            for (int a = 0; a < 3; ++a) {
+                for (int b = 0; b < 3; ++b) M[a][b] += r[a] * r[b];
+                M[a][3] += r[a] * z;
+            }
+        }
+    }
+    if (M[0][0] < 3.0) return -2;
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+        if (!(fabs(M[piv][col]) > 1e-12 * M[0][0])) return -2;
+        if (piv != col)
+            for (int k = 0; k < 4; ++k) {
+                const double tmp = M[col][k];
+                M[col][k] = M[piv][k];
+                M[piv][k] = tmp;
+            }
+        for (int r = col + 1; r < 3; ++r) {
+            const double f = M[r][col] / M[col][col];
+            for (int k = col; k < 4; ++k) M[r][k] -= f * M[col][k];
+        }
+    }
+    double c[3];
+    for (int r = 2; r >= 0; --r) {
+        double v = M[r][3];
+        for (int k = r + 1; k < 3; ++k) v -= M[r][k] * c[k];
+        c[r] = v / M[r][r];
+    }
+    for (long long j = 0; j < g->ny; ++j) {
+        for (long long i = 0; i < g->nx; ++i) {
+            const long long k = j * g->nx + i;
+            const double z = Z[k];
+            out[k] = z < INFINITY
+                ? z - (c[0] + c[1] * (g->x0 + (double)i * g->dd) + c[2] * (g->y0 + (double)j * g->dd))
+                : INFINITY;
+        }
+    }
+    if (plane) {
+        plane[0] = c[0];
+        plane[1] = c[1];
+        plane[2] = c[2];
+    }
+    return 0;
+}
+
+static long long gauss_radius(const or_grid *g, double lambda, double trunc)
+{
+    return (long long)floor(trunc * lambda / g->dd + 1e-9);
+}
+
+/* weights w[a] = exp(-pi (a dd / (alpha lambda))^2), a = 0..R */
+static double *gauss_weights(const or_grid *g, double lambda, long long R)
+{
+    double *w = (double *)malloc(sizeof(double) * (size_t)(R + 1));
+    if (!w) return NULL;
+    const double alpha = sqrt(log(2.0) / M_PI);
+    for (long long a = 0; a <= R; ++a) {
+        const double u = ((double)a * g->dd) / (alpha * lambda);
+        w[a] = exp(-M_PI * (u * u));
+    }
+    return w;
+}
+
+static double gauss_cell(const double *Z, const or_grid *g, const double *w, long long R,
+                         int mode, long long i, long long j)
+{
+    const double z = Z[j * g->nx + i];
+    if (!(z < INFINITY)) return INFINITY;
+    double num = 0.0, den = 0.0;
+    for (long long b = -R; b <= R; ++b) {
+        const long long jj = j + b;
+        if (jj < 0 || jj >= g->ny) continue;
+        for (long long a = -R; a <= R; ++a) {
+            const long long ii = i + a;
+            if (ii < 0 || ii >= g->nx) continue;
+            const double v = Z[jj * g->nx + ii];
+            if (!(v < INFINITY)) continue;
+            const double wt = w[a < 0 ? -a : a] * w[b < 0 ? -b : b];
+            num += wt * v;
+            den += wt;
+        }
+    }
+    const double mean = num / den;
+    return mode == 0 ? mean : z - mean;
+}
+
+static int gauss_check(const double *Z, const or_grid *g, double lambda, double trunc, int mode)
+{
+    if (!Z || !g || g->nx < 1 || g->ny < 1 || !(g->dd > 0.0) || !(lambda > 0.0) ||
+        !(trunc > 0.0) || !(trunc <= 4.0) || (mode != 0 && mode != 1))
+        return -1;
+    return 0;
+}
+
+int or_gauss_filter(const double *Z, const or_grid *g, double lambda, double trunc, int mode,
+                    double *out)
+{
+    if (gauss_check(Z, g, lambda, trunc, mode) || !out || out == Z) return -1;
+    const long long R = gauss_radius(g, lambda, trunc);
+    double *w = gauss_weights(g, lambda, R);
+    if (!w) return -3;
+    for (long long j = 0; j < g->ny; ++j)
+        for (long long i = 0; i < g->nx; ++i)
+            out[j * g->nx + i] = gauss_cell(Z, g, w, R, mode, i, j);
+    free(w);
+    return 0;
+}
+
+int or_gauss_filter_cells(const double *Z, const or_grid *g, double lambda, double trunc,
+                          int mode, const long long *cells, long long n, double *out)
+{
+    if (gauss_check(Z, g, lambda, trunc, mode) || !cells || !out || n < 0) return -1;
+    for (long long k = 0; k < n; ++k)
+        if (cells[k] < 0 || cells[k] >= g->nx * g->ny) return -1;
+    const long long R = gauss_radius(g, lambda, trunc);
+    double *w = gauss_weights(g, lambda, R);
+    if (!w) return -3;
+    for (long long k = 0; k < n; ++k)
+        out[k] = gauss_cell(Z, g, w, R, mode, cells[k] % g->nx, cells[k] / g->nx);
+    free(w);
+    return 0;
+}

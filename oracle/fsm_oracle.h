@@ -127,6 +127,27 @@ int or_roughness(const double *Z, long long nx, long long ny, or_rough *out);
 long long or_paper_trajectory_points(double v_c, double f_z, int z_n, double D,
                                      double L, double dt);
 
+/* ---- surface-texture operators on a Z-map (the measurement practice of Sec. 4.1.1) ------ */
+
+/* F-operator: the least-squares plane z = c0 + c1 x + c2 y over the hit cells, with (x, y) =
+ * (x0 + i dd, y0 + j dd) the cell's node.  out = Z - plane on hit cells, +inf elsewhere (out
+ * may be Z).  plane (nullable) receives c0, c1, c2.  Fewer than three hit cells, or hit cells
+ * on one line: -2. */
+int or_level(const double *Z, const or_grid *g, double *out, double *plane);
+
+/* Areal Gaussian filter of cut-off wavelength lambda: weights exp(-pi (r / (alpha lambda))^2),
+ * alpha = sqrt(ln 2 / pi), over the square |i' - i|, |j' - j| <= R with
+ * R = floor(trunc lambda / dd + 1e-9), normalised over the hit cells of that square.
+ * mode 0: out = the weighted mean (smooth part: the S-filter output);
+ * mode 1: out = Z - the weighted mean (roughness part: the L-filter output).
+ * Empty cells stay +inf.  out must not alias Z. */
+int or_gauss_filter(const double *Z, const or_grid *g, double lambda, double trunc, int mode,
+                    double *out);
+
+/* The same for the n flat cell indices cells[] only: out[k] is the value of cell cells[k]. */
+int or_gauss_filter_cells(const double *Z, const or_grid *g, double lambda, double trunc,
+                          int mode, const long long *cells, long long n, double *out);
+
 #ifdef __cplusplus
 }
 #endif

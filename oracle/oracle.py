@@ -100,6 +100,11 @@ def _configure(L: C.CDLL) -> C.CDLL:
     L.or_paper_trajectory_points.argtypes = [C.c_double, C.c_double, C.c_int,
                                              C.c_double, C.c_double, C.c_double]
     L.or_paper_trajectory_points.restype = C.c_longlong
+    L.or_level.argtypes = [P(C.c_double), P(OrGrid), P(C.c_double), P(C.c_double)]
+    L.or_gauss_filter.argtypes = [P(C.c_double), P(OrGrid), C.c_double, C.c_double, C.c_int,
+                                  P(C.c_double)]
+    L.or_gauss_filter_cells.argtypes = [P(C.c_double), P(OrGrid), C.c_double, C.c_double,
+                                        C.c_int, P(C.c_longlong), C.c_longlong, P(C.c_double)]
     return L
 
 
@@ -259,5 +264,38 @@ def paper_trajectory_points(v_c: float, f_z: float, z_n: int, D: float, L: float
     return int(lib().or_paper_trajectory_points(v_c, f_z, z_n, D, L, dt))
 
 
+def level(Z: np.ndarray, grid):
+    """(Z minus its least-squares plane over the hit cells, (c0, c1, c2)) with the plane
+    c0 + c1 x + c2 y in the grid's node coordinates."""
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    out = np.empty_like(Z)
+    c = np.empty(3)
+    rc = lib().or_level(_dp(Z), C.byref(_grid(grid)), _dp(out), _dp(c))
+    if rc:
+        raise ValueError(f"or_level: {'degenerate hit set' if rc == -2 else 'bad input'}")
+    return out, tuple(float(v) for v in c)
+
+
+def gauss_filter(Z: np.ndarray, grid, cutoff: float, trunc: float = 1.0, highpass: bool = False,
+                 cells=None):
+    """Areal Gaussian filter of the Z-map (+inf = empty): the weighted mean (S-filter) or, with
+    highpass, Z minus it (L-filter).  cells: flat indices to evaluate (default: every cell)."""
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    mode = 1 if highpass else 0
+    if cells is None:
+        out = np.empty_like(Z)
+        rc = lib().or_gauss_filter(_dp(Z), C.byref(_grid(grid)), cutoff, trunc, mode, _dp(out))
+    else:
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty(cells.shape[0])
+        rc = lib().or_gauss_filter_cells(_dp(Z), C.byref(_grid(grid)), cutoff, trunc, mode,
+                                         cells.ctypes.data_as(C.POINTER(C.c_longlong)),
+                                         cells.shape[0], _dp(out))
+    if rc:
+        raise ValueError("or_gauss_filter: bad input")
+    return out
+
+
 __all__ = ["build", "lib", "edge_points", "plan", "point", "simulate", "trajectory", "cell_bounds",
-           "roughness", "paper_trajectory_points"]
+           "roughness", "paper_trajectory_points",
+           "level", "gauss_filter"]

@@ -210,4 +210,44 @@ def paper_mode(no: int, dd: float = 0.005, n_edge: int = 40, travel: float = 10.
     return Sim(tool, cut, grid, name=f"paper_condition{no}_{nx}x{ny}")
 
 
+# --- dataset generation (Sec. 4.3: many simulations over parameter ranges by LHS) ------------
+
+DATASET_RANGES = {
+    "D": (4.0, 16.0), "n_teeth": (2.0, 5.0), "helix": (math.radians(20.0), math.radians(45.0)),
+    "f_z": (0.02, 0.2), "a_e": (0.1, 1.0), "runout_ecc": (0.0, 0.010),
+    "runout_phase": (0.0, 2.0 * math.pi), "tilt_lead": (0.0, math.radians(30.0)),
+}
+
+
+def lhs(n: int, ranges, seed: int = 0) -> List[dict]:
+    """Latin hypercube sample of n points in the box `ranges` (name -> (lo, hi)): every
+    parameter's range is cut into n equal strata, each stratum holds exactly one point at a
+    uniform position inside it, and the strata are paired across parameters by independent
+    random permutations."""
+    r = _rng(6, seed)
+    out = [dict() for _ in range(n)]
+    for name, (lo, hi) in ranges.items():
+        u = (r.permutation(n) + r.random(n)) / n
+        for k in range(n):
+            out[k][name] = lo + (hi - lo) * float(u[k])
+    return out
+
+
+def dataset_sims(n: int, kind: int = BALL, side: int = 1024, dd: float = 0.002,
+                 seed: int = 0, ranges=None) -> List[Sim]:
+    """n simulations of one tool type over the parameter box (DATASET_RANGES by default) drawn
+    by Latin hypercube sampling, all on the same side x side grid at dd, so that the Z-maps
+    stack into one dataset tensor.  The flute count takes the integer part of its stratum."""
+    sims = []
+    for k, p in enumerate(lhs(n, ranges or DATASET_RANGES, seed)):
+        D = p["D"]
+        tool = Tool(kind=kind, n_teeth=min(4, int(p["n_teeth"])), n_edge=64, D=D,
+                    R_edge=0.5 * D if kind == ROUND else 0.0, helix=p["helix"],
+                    runout_ecc=p["runout_ecc"], runout_phase=p["runout_phase"],
+                    tilt_lead=p["tilt_lead"])
+        cut = Cut(f_z=p["f_z"], a_p=0.5, a_e=p["a_e"], steps_per_rev=720)
+        sims.append(Sim(tool, cut, centred_grid(side, side, dd), name=f"lhs{seed}_{k}"))
+    return sims
+
+
 CONFIGS = {1: config1, 2: config2, 5: config5}

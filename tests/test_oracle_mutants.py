@@ -1,8 +1,8 @@
 """Mutation tests of the oracle's pins.  Each case plants one plausible mistake in a copy of
 the oracle's C source (a flipped sign, a dropped term, a wrong index or boundary), builds it
-with the oracle's own flags, runs the pin battery (tests/test_oracle_pins.py and the oracle
-checks of tests/test_f32_bounds.py) on it and requires at least one pin to fail.  Every
-planted mistake stays memory-safe.  CPU only."""
+with the oracle's own flags, runs the pin battery (tests/test_oracle_pins.py, the oracle
+checks of tests/test_f32_bounds.py and the texture pins of tests/test_texture_pins.py) on it
+and requires at least one pin to fail.  Every planted mistake stays memory-safe.  CPU only."""
 import inspect
 import os
 import subprocess
@@ -13,6 +13,7 @@ import oracle
 
 import test_f32_bounds as bounds_pins
 import test_oracle_pins as pins
+import test_texture_pins as texture_pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "fsm_oracle.c")
 
@@ -80,13 +81,26 @@ MUTANTS = [
      [("const int sure = ia == ib && ja == jb;", "const int sure = 1;")]),
     ("interval: certain points not counted as reachable",
      [("if (w[2] < lo[k]) lo[k] = w[2];", "if (!sure && w[2] < lo[k]) lo[k] = w[2];")]),
+    ("Gaussian width without the square root",
+     [("const double alpha = sqrt(log(2.0) / M_PI);", "const double alpha = log(2.0) / M_PI;")]),
+    ("Gaussian y weight indexed by x",
+     [("w[a < 0 ? -a : a] * w[b < 0 ? -b : b]", "w[a < 0 ? -a : a] * w[a < 0 ? -a : a]")]),
+    ("empty cells weighted in the filter",
+     [("            if (!(v < INFINITY)) continue;\n", "")]),
+    ("high-pass sign",
+     [("return mode == 0 ? mean : z - mean;", "return mode == 0 ? mean : mean - z;")]),
+    ("plane y term evaluated at the column",
+     [("c[2] * (g->y0 + (double)j * g->dd))", "c[2] * (g->y0 + (double)i * g->dd))")]),
+    ("normal equations without the cross term",
+     [("for (int b = 0; b < 3; ++b) M[a][b] += r[a] * r[b];",
+       "for (int b = 0; b < 3; ++b) M[a][b] += a == b ? r[a] * r[b] : 0.0;")]),
 ]
 
 
 def battery():
     """Every pin as a zero-argument call, cheapest first (parametrised pins expanded)."""
     calls = []
-    for mod in (pins, bounds_pins):
+    for mod in (pins, bounds_pins, texture_pins):
         for name, f in inspect.getmembers(mod, inspect.isfunction):
             if not name.startswith("test_") or f.__module__ != mod.__name__:
                 continue
