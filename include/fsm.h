@@ -309,6 +309,50 @@ int fsm_tune_set(fsm_ctx *ctx, const fsm_tune_entry *entries, int n);
 int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_dev,
                   fsm_rough *out, void *stream);
 
+/* ---- surface texture of a Z-map ---------------------------------------------------------------
+ *
+ * The paper's measured topographies pass an S-filter (10 um) and an L-filter (0.8 mm) before
+ * their roughness is taken (Sec. 4.1.1).  These calls apply the same operators to a predicted
+ * Z-map in device memory, so that predictions and measurements are evaluated alike and a
+ * dataset of maps (Sec. 4.3) carries measurement-like roughness.  Empty cells (+inf) take no
+ * part and stay empty.  zmap_in and zmap_out may be the same map.  Each call waits for its
+ * work on `stream` before it returns.  Scratch: 16 bytes per cell (filter) from the context's
+ * workspace, which grows on demand. */
+
+/* F-operator: subtract the least-squares plane z = plane[0] + plane[1] x + plane[2] y (x, y
+ * the cells' node coordinates, mm) fitted over the hit cells.  plane may be NULL.
+ * FSM_EINVAL for a bad grid, pointer or precision, and when fewer than three cells are hit or
+ * all hit cells lie on one line (zmap_out then holds the input values). */
+int fsm_level(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_in,
+              void *zmap_out, double plane[3], void *stream);
+
+#define FSM_FILTER_SMOOTH 0   /* the weighted mean: the S-filter's output */
+#define FSM_FILTER_ROUGH 1    /* the input minus the weighted mean: the L-filter's output */
+
+/* Areal Gaussian filter of cut-off wavelength `cutoff` (mm): weights
+ * exp(-pi (r / (alpha cutoff))^2), alpha = sqrt(ln 2 / pi), whose transmission is 50 % at the
+ * cut-off wavelength, over the square window of half-width R = floor(trunc cutoff / dd + 1e-9)
+ * cells, normalised over the hit cells inside it (so the map's border and holes need no
+ * padding).  mode FSM_FILTER_SMOOTH or FSM_FILTER_ROUGH.  FSM_EINVAL for cutoff <= 0, trunc
+ * outside (0, 4], a half-width above 3072 cells, or a bad grid, pointer, precision or mode. */
+int fsm_filter(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_in,
+               void *zmap_out, double cutoff, double trunc, int mode, void *stream);
+
+typedef struct fsm_texture_spec {
+    double lambda_s;   /* S-filter cut-off (mm), 0: none (the paper's instrument: 0.010) */
+    double lambda_c;   /* L-filter cut-off (mm), 0: none (the paper's instrument: 0.8) */
+    double trunc;      /* window half-width in cut-offs, both filters (0 < trunc <= 4) */
+    int32_t level;     /* nonzero: remove the least-squares plane between the two filters */
+    int32_t reserved;
+} fsm_texture_spec;
+
+/* The chain S-filter -> F-operator -> L-filter, then the roughness of the result (as
+ * fsm_roughness).  plane (nullable) receives the removed plane (zeros without levelling).
+ * Errors as the single operators. */
+int fsm_texture(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_in,
+                void *zmap_out, const fsm_texture_spec *spec, fsm_rough *out, double plane[3],
+                void *stream);
+
 /* ---- serving loop --------------------------------------------------------------------------
  *
  * Simulations of different sizes and parameters arriving over time, the way a surrogate-model

@@ -23,6 +23,7 @@ TOOL_ROUND, TOOL_BALL = 0, 1
 FLAG_SQ_ZERO, FLAG_NO_HIT, FLAG_LOW_COVERAGE = 1, 2, 4
 OPT_ZMAP_STRATEGY, OPT_BUCKET_BYTES, OPT_GRAPHS = 1, 2, 3
 OPT_TILE_SHAPE, OPT_TARGET_ROWS, OPT_AUTOTUNED = 4, 5, 6
+FILTER_SMOOTH, FILTER_ROUGH = 0, 1
 ZMAP_BINNED, ZMAP_SCATTER = 0, 1
 
 
@@ -91,6 +92,11 @@ class FsmTuneEntry(C.Structure):
                 ("target_rows", C.c_int32), ("reserved", C.c_int32)]
 
 
+class FsmTextureSpec(C.Structure):
+    _fields_ = [("lambda_s", C.c_double), ("lambda_c", C.c_double), ("trunc", C.c_double),
+                ("level", C.c_int32), ("reserved", C.c_int32)]
+
+
 class FsmRequest(C.Structure):
     _fields_ = [("tool", C.POINTER(FsmTool)), ("cut", C.POINTER(FsmCut)),
                 ("grid", C.POINTER(FsmGrid)), ("arrival_s", C.c_double),
@@ -130,6 +136,12 @@ SIGNATURES = {
                       P(FsmRough), C.c_void_p], C.c_int),
     "fsm_roughness": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, P(FsmRough), C.c_void_p],
                       C.c_int),
+    "fsm_level": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, C.c_void_p, P(C.c_double),
+                   C.c_void_p], C.c_int),
+    "fsm_filter": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                    C.c_double, C.c_int, C.c_void_p], C.c_int),
+    "fsm_texture": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, C.c_void_p, P(FsmTextureSpec),
+                     P(FsmRough), P(C.c_double), C.c_void_p], C.c_int),
     "fsm_simulate_batch": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmRough), C.c_void_p],
                            C.c_int),
     "fsm_trajectory": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, C.c_void_p,

@@ -230,6 +230,54 @@ class Context:
         _check(rc, "fsm_roughness", self._h)
         return out.as_dict()
 
+    def _out_map(self, grid, precision, zmap, out):
+        if out is None:
+            out = self.new_zmap(grid, precision)
+        self._check_zmap(grid, precision, zmap)
+        self._check_zmap(grid, precision, out)
+        return out
+
+    def fsm_level(self, grid, zmap, precision="f64", out=None, stream=None):
+        """Subtract the least-squares plane of the hit cells (F-operator); returns (levelled
+        map, (c0, c1, c2)) with the plane c0 + c1 x + c2 y.  out may be zmap (in place)."""
+        out = self._out_map(grid, precision, zmap, out)
+        plane = (C.c_double * 3)()
+        rc = self._lib.fsm_level(self._h, C.byref(_abi.grid_struct(grid)), _prec(precision),
+                                 C.c_void_p(zmap.data_ptr()), C.c_void_p(out.data_ptr()), plane,
+                                 C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_level", self._h)
+        return out, tuple(plane)
+
+    def fsm_filter(self, grid, zmap, cutoff: float, precision="f64", highpass: bool = False,
+                   trunc: float = 1.0, out=None, stream=None):
+        """Areal Gaussian filter of cut-off `cutoff` mm: the weighted mean (S-filter) or, with
+        highpass, the map minus it (L-filter).  out may be zmap (in place)."""
+        out = self._out_map(grid, precision, zmap, out)
+        rc = self._lib.fsm_filter(self._h, C.byref(_abi.grid_struct(grid)), _prec(precision),
+                                  C.c_void_p(zmap.data_ptr()), C.c_void_p(out.data_ptr()),
+                                  float(cutoff), float(trunc),
+                                  _abi.FILTER_ROUGH if highpass else _abi.FILTER_SMOOTH,
+                                  C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_filter", self._h)
+        return out
+
+    def fsm_texture(self, grid, zmap, precision="f64", lambda_s: float = 0.01,
+                    lambda_c: float = 0.8, level: bool = True, trunc: float = 1.0, out=None,
+                    stream=None):
+        """S-filter -> F-operator -> L-filter, then the roughness of the result (defaults: the
+        paper's instrument, 10 um and 0.8 mm).  Returns (map, roughness dict, plane)."""
+        out = self._out_map(grid, precision, zmap, out)
+        spec = _abi.FsmTextureSpec(lambda_s=float(lambda_s), lambda_c=float(lambda_c),
+                                   trunc=float(trunc), level=1 if level else 0)
+        r = _abi.FsmRough()
+        plane = (C.c_double * 3)()
+        rc = self._lib.fsm_texture(self._h, C.byref(_abi.grid_struct(grid)), _prec(precision),
+                                   C.c_void_p(zmap.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   C.byref(spec), C.byref(r), plane,
+                                   C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_texture", self._h)
+        return out, r.as_dict(), tuple(plane)
+
     def fsm_simulate_batch(self, sims, precision="f64", zmaps=None, stream=None):
         """Run many simulations in one launch sequence; returns (Z-map tensors, roughness
         dicts), both in the order of `sims`."""

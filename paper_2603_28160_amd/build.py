@@ -45,14 +45,15 @@ def build(verbose: bool = False) -> str:
     o = os.path.join(BUILD, "fsm_sched.o")
     _run(["g++", *COMMON, "-c", os.path.join(CSRC, "fsm_sched.cpp"), "-o", o])
     objs.append(o)
-    for name in ("fsm_api", "fsm_serve"):
+    for name in ("fsm_api", "fsm_serve", "fsm_texture_api"):
         o = os.path.join(BUILD, name + ".o")
         _run([HIPCC, *COMMON, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
               os.path.join(CSRC, name + ".cpp"), "-o", o])
         objs.append(o)
-    o = os.path.join(BUILD, "fsm_kernels.o")
-    _run([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, "fsm_kernels.hip"), "-o", o])
-    objs.append(o)
+    for name in ("fsm_kernels", "fsm_texture"):
+        o = os.path.join(BUILD, name + ".o")
+        _run([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, name + ".hip"), "-o", o])
+        objs.append(o)
     tmp = LIB + f".tmp{os.getpid()}"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)

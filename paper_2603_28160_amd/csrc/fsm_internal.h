@@ -211,4 +211,18 @@ int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, i
                  TileStat2 *st2, RoughState *state, const uint64_t *d_binned,
                  const int64_t *d_evals, fsm_rough *d_out, void *stream);
 
+// Surface-texture operators (fsm_texture.hip).  zin and zout may be the same map.
+// Least-squares plane over the hit cells, subtracted into zout.  part: kPlanePartials doubles
+// of scratch; coef: 4 doubles receiving (c0, cu, cv, status) in centred cell units.
+constexpr int kPlanePartials = 1024 * 9;
+int launch_plane(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, double *part,
+                 double *coef, void *stream);
+// Separable normalised Gaussian of half-width R cells: g_row holds K8 (2R + 1 rounded up to a
+// multiple of 8) row weights, g_col 2R + 33 column weights (16 zeros on either side), nd
+// 16 * nx * ny bytes of scratch.  mode 0: weighted mean; 1: input minus weighted mean.
+int launch_gauss(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, int R, int K8,
+                 const double *g_row, const double *g_col, void *nd, int mode, void *stream);
+// Dynamic LDS of the row pass for K8 row weights.
+size_t gauss_lds_bytes(int K8);
+
 }  // namespace fsm

@@ -1,0 +1,319 @@
+// fsm_texture.hip -- gfx950 kernels of the surface-texture operators applied to a Z-map: the
+// S-filter, F-operator and L-filter under which the paper's measured topographies were taken
+// (Sec. 4.1.1), so that a predicted map can be evaluated the same way.
+//
+//   plane  : least-squares plane over the hit cells.  Per block, FP64 moments of the design
+//            rows (1, u, v) and of z, with (u, v) the cell's column and row measured from the
+//            grid's centre (exact integers, so the normal matrix is exact for maps up to ~1e8
+//            cells); one block combines the block partials in a fixed order and solves the
+//            3 x 3 normal equations; a third kernel subtracts the plane.
+//   gauss  : separable normalised Gaussian, out = sum(w z h) / sum(w h) over the square window
+//            (h = 1 on hit cells), every product of the 2-D weight being w(dx) w(dy):
+//            rows - one block per (row, 1024-column tile); the tile and its halo in LDS
+//                   (skewed by one slot per eight against bank conflicts); each lane owns
+//                   eight consecutive outputs and slides a register window over the taps,
+//                   so each LDS value feeds sixteen fused multiply-adds; weights are wave-
+//                   uniform scalar loads.  Writes (numerator, denominator) pairs.
+//            cols - lanes along the row (coalesced 16-byte pair loads from L2), each lane owns
+//                   sixteen consecutive rows of one column and accumulates every input row
+//                   into all sixteen outputs with a scalar weight each; then the quotient,
+//                   or the input minus it, is stored, empty cells stay +inf.
+//
+// All arithmetic is FP64 (both map precisions: single-precision maps are widened on load and
+// rounded once on store).  Without packed FP32 the FP64 and FP32 FMA rates are equal here, so
+// the wider type costs only LDS and L2 bytes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "fsm_internal.h"
+
+namespace fsm {
+
+namespace {
+
+constexpr int kRowThreads = 128;
+constexpr int kRowOut = 8;
+constexpr int kRowTile = kRowThreads * kRowOut;   // outputs per row block
+constexpr int kColOut = 16;                       // rows per lane in the column pass
+constexpr int kColWaves = 4;
+constexpr int kColRows = kColWaves * kColOut;     // rows per column block
+constexpr int kPlaneBlocks = kPlanePartials / 9;
+constexpr int64_t kMaxItems = 1 << 20;
+
+__device__ __forceinline__ bool is_hit(double v) { return v < INFINITY; }
+
+__device__ __forceinline__ int skew(int p) { return p + (p >> 3); }
+
+template <typename T> __device__ __forceinline__ T inf_of();
+template <> __device__ __forceinline__ double inf_of<double>() { return INFINITY; }
+template <> __device__ __forceinline__ float inf_of<float>() { return INFINITY; }
+
+// Sum of v over the 256 threads of a block; every thread gets the result.  Fixed order.
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// ---- F-operator ------------------------------------------------------------------------------
+
+// Block partials of (n, su, sv, suu, suv, svv, sz, suz, svz) over rows blockIdx.x, +gridDim.x...
+template <typename T>
+__global__ void __launch_bounds__(256) plane_moments(const T *__restrict__ z, int64_t nx, int64_t ny,
+                                                     double ci, double cj, double *__restrict__ part)
+{
+    __shared__ double sh[4];
+    double a[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = blockIdx.x; j < ny; j += gridDim.x) {
+        const double v = (double)j - cj;
+        for (int64_t i = threadIdx.x; i < nx; i += blockDim.x) {
+            const double h = (double)z[j * nx + i];
+            if (!is_hit(h)) continue;
+            const double u = (double)i - ci;
+            a[0] += 1.0;
+            a[1] += u;
+            a[2] += v;
+            a[3] += u * u;
+            a[4] += u * v;
+            a[5] += v * v;
+            a[6] += h;
+            a[7] += u * h;
+            a[8] += v * h;
+        }
+    }
+    for (int q = 0; q < 9; ++q) {
+        const double s = block_sum(a[q], sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 9 + q] = s;
+    }
+}
+
+// Combine the partials in block order and solve the normal equations by Gaussian elimination
+// with partial pivoting.  coef = (c0, cu, cv, status): z ~ c0 + cu u + cv v; status 1, or 0
+// for fewer than three hit cells or hit cells on one line (a pivot that vanishes relative to
+// its column's diagonal).
+__global__ void __launch_bounds__(256) plane_solve(const double *__restrict__ part, int nb,
+                                                   double *__restrict__ coef)
+{
+    __shared__ double sh[4];
+    __shared__ double m[9];
+    for (int q = 0; q < 9; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(int64_t)b * 9 + q];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) m[q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double M[3][4] = {{m[0], m[1], m[2], m[6]}, {m[1], m[3], m[4], m[7]}, {m[2], m[4], m[5], m[8]}};
+    const double diag[3] = {m[0], m[3], m[5]};
+    bool ok = m[0] >= 3.0;
+    for (int col = 0; col < 3 && ok; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+        if (!(fabs(M[piv][col]) > 1e-10 * diag[col])) { ok = false; break; }
+        if (piv != col)
+            for (int k = 0; k < 4; ++k) {
+                const double t = M[col][k];
+                M[col][k] = M[piv][k];
+                M[piv][k] = t;
+            }
+        for (int r = col + 1; r < 3; ++r) {
+            const double f = M[r][col] / M[col][col];
+            for (int k = col; k < 4; ++k) M[r][k] -= f * M[col][k];
+        }
+    }
+    double c[3] = {0.0, 0.0, 0.0};
+    if (ok)
+        for (int r = 2; r >= 0; --r) {
+            double v = M[r][3];
+            for (int k = r + 1; k < 3; ++k) v -= M[r][k] * c[k];
+            c[r] = v / M[r][r];
+        }
+    coef[0] = c[0];
+    coef[1] = c[1];
+    coef[2] = c[2];
+    coef[3] = ok ? 1.0 : 0.0;
+}
+
+// out = z - plane on hit cells (+inf elsewhere); a degenerate fit leaves the values as they are.
+template <typename T>
+__global__ void __launch_bounds__(256) plane_apply(const T *z, T *out, int64_t nx, int64_t ny,
+                                                   double ci, double cj, const double *__restrict__ coef)
+{
+    const double c0 = coef[0], cu = coef[1], cv = coef[2];
+    const bool ok = coef[3] != 0.0;
+    for (int64_t j = blockIdx.x; j < ny; j += gridDim.x) {
+        const double v = (double)j - cj;
+        for (int64_t i = threadIdx.x; i < nx; i += blockDim.x) {
+            const int64_t k = j * nx + i;
+            const double h = (double)z[k];
+            double r = h;
+            if (ok && is_hit(h)) r = h - ((c0 + cu * ((double)i - ci)) + cv * v);
+            out[k] = is_hit(h) ? (T)r : inf_of<T>();
+        }
+    }
+}
+
+// ---- Gaussian filter -------------------------------------------------------------------------
+
+// Row pass.  g[k] = w(|k - R|) for k <= 2R, zero up to K8 (a multiple of eight).  nd[j][i] =
+// (sum_k g[k] zh(i - R + k), sum_k g[k] h(i - R + k)) over the grid's columns.
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *__restrict__ z, int64_t nx, int64_t ny,
+                                                          int R, int K8, const double *__restrict__ g,
+                                                          double2 *__restrict__ nd)
+{
+    extern __shared__ double lds[];
+    const int64_t tiles = (nx + kRowTile - 1) / kRowTile;
+    const int L = kRowTile + K8 + 8;
+    const int b = threadIdx.x * kRowOut;
+    for (int64_t item = blockIdx.x; item < tiles * ny; item += gridDim.x) {
+        const int64_t j = item / tiles, tx = item - j * tiles;
+        const int64_t x0 = tx * kRowTile - R;        // grid column of LDS position 0
+        const T *row = z + j * nx;
+        __syncthreads();
+        for (int p = threadIdx.x; p < L; p += kRowThreads) {
+            const int64_t c = x0 + p;
+            lds[skew(p)] = (c >= 0 && c < nx) ? (double)row[c] : INFINITY;
+        }
+        __syncthreads();
+        double an[kRowOut], ad[kRowOut], cz[2 * kRowOut], ch[2 * kRowOut];
+#pragma unroll
+        for (int o = 0; o < kRowOut; ++o) {
+            an[o] = 0.0;
+            ad[o] = 0.0;
+            const double v = lds[skew(b + o)];
+            ch[o] = is_hit(v) ? 1.0 : 0.0;
+            cz[o] = is_hit(v) ? v : 0.0;
+        }
+        for (int k0 = 0; k0 < K8; k0 += kRowOut) {
+#pragma unroll
+            for (int o = 0; o < kRowOut; ++o) {
+                const double v = lds[skew(b + k0 + kRowOut + o)];
+                ch[kRowOut + o] = is_hit(v) ? 1.0 : 0.0;
+                cz[kRowOut + o] = is_hit(v) ? v : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kRowOut; ++u) {
+                const double w = g[k0 + u];
+#pragma unroll
+                for (int o = 0; o < kRowOut; ++o) {
+                    an[o] = fma(w, cz[u + o], an[o]);
+                    ad[o] = fma(w, ch[u + o], ad[o]);
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < kRowOut; ++o) {
+                cz[o] = cz[kRowOut + o];
+                ch[o] = ch[kRowOut + o];
+            }
+        }
+        const int64_t c0 = tx * kRowTile + b;
+#pragma unroll
+        for (int o = 0; o < kRowOut; ++o)
+            if (c0 + o < nx) nd[j * nx + c0 + o] = make_double2(an[o], ad[o]);
+    }
+}
+
+// Column pass.  gc[16 + k] = w(|k - R|) for k in [0, 2R], zero in the 16 slots on either
+// side.  Lane i of wave w in block (tx, ty) owns rows j0 .. j0 + 15 of column tx*64 + lane,
+// j0 = ty*64 + 16 w (kColRows = 64 rows per block).
+template <typename T>
+__global__ void __launch_bounds__(64 * kColWaves) gauss_cols(const T *z, T *out, int64_t nx, int64_t ny,
+                                                             int R, const double *__restrict__ gc,
+                                                             const double2 *__restrict__ nd, int mode)
+{
+    const int64_t tiles_x = (nx + 63) / 64, tiles_y = (ny + kColRows - 1) / kColRows;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t item = blockIdx.x; item < tiles_x * tiles_y; item += gridDim.x) {
+        const int64_t ty = item / tiles_x, tx = item - ty * tiles_x;
+        const int64_t i = tx * 64 + lane;
+        const int64_t j0 = ty * kColRows + (int64_t)wave * kColOut;
+        if (j0 >= ny) continue;
+        double an[kColOut], ad[kColOut];
+#pragma unroll
+        for (int o = 0; o < kColOut; ++o) {
+            an[o] = 0.0;
+            ad[o] = 0.0;
+        }
+        if (i < nx) {
+            const int64_t m_lo = j0 - R > 0 ? j0 - R : 0;
+            const int64_t m_hi = j0 + kColOut - 1 + R < ny - 1 ? j0 + kColOut - 1 + R : ny - 1;
+            for (int64_t m = m_lo; m <= m_hi; ++m) {
+                const double2 v = nd[m * nx + i];
+                const double *w = gc + (m - j0 + R + 16);
+#pragma unroll
+                for (int o = 0; o < kColOut; ++o) {
+                    an[o] = fma(w[-o], v.x, an[o]);
+                    ad[o] = fma(w[-o], v.y, ad[o]);
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < kColOut; ++o) {
+                const int64_t j = j0 + o;
+                if (j < ny) {
+                    const int64_t k = j * nx + i;
+                    const double h = (double)z[k];
+                    const double lp = an[o] / ad[o];
+                    out[k] = is_hit(h) ? (T)(mode == 0 ? lp : h - lp) : inf_of<T>();
+                }
+            }
+        }
+    }
+}
+
+int64_t grid_for(int64_t items) { return items < kMaxItems ? items : kMaxItems; }
+
+}  // namespace
+
+int launch_plane(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, double *part,
+                 double *coef, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double ci = 0.5 * (double)(nx - 1), cj = 0.5 * (double)(ny - 1);
+    const int nb = (int)(ny < kPlaneBlocks ? ny : kPlaneBlocks);
+    if (precision == FSM_F64) {
+        hipLaunchKernelGGL(plane_moments<double>, dim3(nb), dim3(256), 0, s, (const double *)zin, nx, ny, ci, cj, part);
+        hipLaunchKernelGGL(plane_solve, dim3(1), dim3(256), 0, s, (const double *)part, nb, coef);
+        hipLaunchKernelGGL(plane_apply<double>, dim3(nb), dim3(256), 0, s, (const double *)zin, (double *)zout, nx, ny, ci, cj, (const double *)coef);
+    } else {
+        hipLaunchKernelGGL(plane_moments<float>, dim3(nb), dim3(256), 0, s, (const float *)zin, nx, ny, ci, cj, part);
+        hipLaunchKernelGGL(plane_solve, dim3(1), dim3(256), 0, s, (const double *)part, nb, coef);
+        hipLaunchKernelGGL(plane_apply<float>, dim3(nb), dim3(256), 0, s, (const float *)zin, (float *)zout, nx, ny, ci, cj, (const double *)coef);
+    }
+    return (int)hipGetLastError();
+}
+
+size_t gauss_lds_bytes(int K8)
+{
+    const int L = kRowTile + K8 + 8;
+    return sizeof(double) * (size_t)(L + (L >> 3) + 1);
+}
+
+int launch_gauss(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, int R, int K8,
+                 const double *g_row, const double *g_col, void *nd, int mode, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t row_items = ((nx + kRowTile - 1) / kRowTile) * ny;
+    const int64_t col_items = ((nx + 63) / 64) * ((ny + kColRows - 1) / kColRows);
+    const size_t lds = gauss_lds_bytes(K8);
+    const dim3 gr((unsigned)grid_for(row_items)), gcol((unsigned)grid_for(col_items));
+    if (precision == FSM_F64) {
+        hipLaunchKernelGGL(gauss_rows<double>, gr, dim3(kRowThreads), lds, s, (const double *)zin, nx, ny, R, K8, g_row, (double2 *)nd);
+        hipLaunchKernelGGL(gauss_cols<double>, gcol, dim3(64 * kColWaves), 0, s, (const double *)zin, (double *)zout, nx, ny, R, g_col, (const double2 *)nd, mode);
+    } else {
+        hipLaunchKernelGGL(gauss_rows<float>, gr, dim3(kRowThreads), lds, s, (const float *)zin, nx, ny, R, K8, g_row, (double2 *)nd);
+        hipLaunchKernelGGL(gauss_cols<float>, gcol, dim3(64 * kColWaves), 0, s, (const float *)zin, (float *)zout, nx, ny, R, g_col, (const double2 *)nd, mode);
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace fsm

@@ -250,4 +250,24 @@ def dataset_sims(n: int, kind: int = BALL, side: int = 1024, dd: float = 0.002,
     return sims
 
 
+def synthetic_surface(nx: int, ny: int, dd: float, seed: int = 0, hole_frac: float = 0.0,
+                      feed: float = 0.1, depth: float = 0.002) -> np.ndarray:
+    """Seeded stand-in for a milled Z-map, [ny, nx] float64 in mm: feed marks along x (a
+    cosine of wavelength `feed` and amplitude `depth`), waviness along y (wavelength 1.3 mm),
+    a tilted plane, white noise of depth/20, and holes (+inf) at a fraction hole_frac of the
+    cells.  Input for the surface-texture operators; it holds none of the method."""
+    r = _rng(7, seed)
+    x = np.arange(nx) * dd
+    y = np.arange(ny) * dd
+    X, Y = np.meshgrid(x, y)
+    ph = r.uniform(0.0, 2.0 * math.pi, 2)
+    Z = (-0.5 + depth * np.cos(2.0 * math.pi * X / feed + ph[0])
+         + 0.25 * depth * np.cos(2.0 * math.pi * Y / 1.3 + ph[1])
+         + float(r.uniform(-0.01, 0.01)) * X + float(r.uniform(-0.01, 0.01)) * Y
+         + r.normal(0.0, depth / 20.0, (ny, nx)))
+    if hole_frac > 0.0:
+        Z[r.random((ny, nx)) < hole_frac] = np.inf
+    return Z
+
+
 CONFIGS = {1: config1, 2: config2, 5: config5}

@@ -1,0 +1,205 @@
+"""GPU parity of the surface-texture operators (F-operator plane, areal Gaussian S- and
+L-filters and their chain with the roughness) against the FP64 oracle, on seeded synthetic
+maps with holes, at sizes that span several row tiles and column blocks with ragged ends, and
+on sampled cells of a 5000 x 5000 map with the paper's 0.8 mm L-filter at 1 um (a 1601-cell
+window).
+
+Tolerances.  Double precision, filter: the oracle sums the n = (2R + 1)^2 positive-weight
+terms of a cell directly, the kernels 2R + 1 per separable pass.  Such sums carry a rounding
+error that grows like sqrt(n) u in practice (n u at worst, u = eps / 2); the test allows
+4 (2R + 1) eps = 8 sqrt(n) u times the largest |z|.  Plane: the oracle solves the normal
+equations in mm, the kernel in centred cell units, each with a relative error of about
+cond(normal matrix) eps; the test allows 32 cond eps times the largest |z|.  Single
+precision: the kernels widen the float map, compute in double and round once, so they may
+differ from the oracle (run on the same float values) by one float ulp of the result plus
+the double bound."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_28160_amd import _abi, workloads as W
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_28160_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def to_dev(Z, prec):
+    import torch
+    dt = torch.float64 if prec == "f64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(Z)).to(dtype=dt, device="cuda:0")
+
+
+def host_input(Z, prec):
+    """The values the device sees, as float64 for the oracle."""
+    return Z if prec == "f64" else Z.astype(np.float32).astype(np.float64)
+
+
+def assert_close(got, want, R, scale, prec):
+    got = got.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.isinf(got), np.isinf(want))
+    m = np.isfinite(want)
+    tol = 4 * (2 * R + 1) * EPS * scale
+    if prec == "f32":
+        tol = tol + np.spacing(np.abs(want[m]).astype(np.float32)).astype(np.float64)
+    err = np.abs(got[m] - want[m])
+    assert np.all(err <= tol), float(np.max(err - tol))
+
+
+def grid(nx, ny, dd):
+    return W.centred_grid(nx, ny, dd)
+
+
+# --- F-operator ------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_level_matches_oracle(ctx, prec):
+    g = grid(1100, 333, 0.002)
+    Z = host_input(W.synthetic_surface(g.nx, g.ny, g.dd, seed=1, hole_frac=0.2), prec)
+    print(f"[gpu] level {prec} {g.nx}x{g.ny}", flush=True)
+    out, plane = ctx.fsm_level(g, to_dev(Z, prec), prec)
+    want, pw = oracle.level(Z, g)
+    scale = np.abs(Z[np.isfinite(Z)]).max()
+    assert np.allclose(plane, pw, rtol=1e-9, atol=1e-12)
+    # the oracle solves the normal equations in mm, the kernel in centred cell units: each
+    # side's plane carries a relative error of about cond(normal matrix) eps
+    X, Y = np.meshgrid(g.x0 + np.arange(g.nx) * g.dd, g.y0 + np.arange(g.ny) * g.dd)
+    hit = np.isfinite(Z)
+    A = np.stack([np.ones(hit.sum()), X[hit], Y[hit]], axis=1)
+    tol = 32 * np.linalg.cond(A.T @ A) * EPS * scale
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.isinf(got), np.isinf(want))
+    err = np.abs(got[hit] - want[hit])
+    if prec == "f32":
+        tol = tol + np.spacing(np.abs(want[hit]).astype(np.float32)).astype(np.float64)
+    assert np.all(err <= tol), float(np.max(err - tol))
+
+
+def test_level_in_place_and_degenerate(ctx):
+    g = grid(200, 150, 0.005)
+    Z = W.synthetic_surface(g.nx, g.ny, g.dd, seed=2, hole_frac=0.1)
+    z = to_dev(Z, "f64")
+    ref, _ = ctx.fsm_level(g, z, "f64")
+    ctx.fsm_level(g, z, "f64", out=z)
+    assert np.array_equal(z.cpu().numpy(), ref.cpu().numpy())
+    one_row = np.full((g.ny, g.nx), np.inf)
+    one_row[7, :] = 0.25
+    with pytest.raises(_abi.FsmError):
+        ctx.fsm_level(g, to_dev(one_row, "f64"), "f64")
+
+
+# --- Gaussian filter --------------------------------------------------------------------------
+
+CASES = [  # (nx, ny, dd, cutoff): several 1024-column row tiles; several 64-row column blocks
+    (2100, 40, 0.001, 0.024),
+    (150, 700, 0.002, 0.06),
+    (77, 61, 0.005, 0.0049),     # window below one cell: the identity
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("highpass", [False, True])
+@pytest.mark.parametrize("case", CASES, ids=["wide", "tall", "identity"])
+def test_filter_matches_oracle(ctx, prec, highpass, case):
+    nx, ny, dd, cutoff = case
+    g = grid(nx, ny, dd)
+    Z = host_input(W.synthetic_surface(nx, ny, dd, seed=3, hole_frac=0.15), prec)
+    R = int(math.floor(cutoff / dd + 1e-9))
+    print(f"[gpu] filter {prec} highpass={highpass} {nx}x{ny} R={R}", flush=True)
+    out = ctx.fsm_filter(g, to_dev(Z, prec), cutoff, prec, highpass=highpass)
+    want = oracle.gauss_filter(Z, g, cutoff, highpass=highpass)
+    assert_close(out, want, R, np.abs(Z[np.isfinite(Z)]).max(), prec)
+
+
+def test_filter_in_place_and_truncation(ctx):
+    g = grid(300, 260, 0.002)
+    Z = W.synthetic_surface(g.nx, g.ny, g.dd, seed=4, hole_frac=0.05)
+    z = to_dev(Z, "f64")
+    ref = ctx.fsm_filter(g, z, 0.03, "f64", highpass=True, trunc=0.5)
+    ctx.fsm_filter(g, z, 0.03, "f64", highpass=True, trunc=0.5, out=z)
+    assert np.array_equal(z.cpu().numpy(), ref.cpu().numpy())
+    want = oracle.gauss_filter(Z, g, 0.03, trunc=0.5, highpass=True)
+    assert_close(ref, want, 7, np.abs(Z[np.isfinite(Z)]).max(), "f64")
+
+
+def test_filter_rejects_bad_requests(ctx):
+    g = grid(100, 100, 0.001)
+    z = to_dev(W.synthetic_surface(100, 100, 0.001), "f64")
+    for cutoff, trunc in ((0.0, 1.0), (-1.0, 1.0), (0.1, 0.0), (0.1, 4.5), (3.1, 1.0)):
+        with pytest.raises(_abi.FsmError):
+            ctx.fsm_filter(g, z, cutoff, "f64", trunc=trunc)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_l_filter_full_size_sampled(ctx, prec):
+    # 5000 x 5000 at 1 um with the paper's 0.8 mm L-filter: R = 800 (1601 x 1601 window);
+    # corners, edges and interior cells, and the cells next to the row-tile boundaries
+    n, dd, lc = 5000, 0.001, 0.8
+    g = grid(n, n, dd)
+    Z = host_input(W.synthetic_surface(n, n, dd, seed=5, hole_frac=0.02), prec)
+    print(f"[gpu] L-filter 5000x5000 {prec}", flush=True)
+    out = ctx.fsm_filter(g, to_dev(Z, prec), lc, prec, highpass=True).cpu().numpy()
+    rng = np.random.default_rng(11)
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (1023, 17), (1024, 17), (2048, 4999),
+           (4095, 2500), (4096, 255), (2500, 256), (799, 800), (4200, 4199)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(20)]
+    cells = np.array([j * n + i for i, j in pts], dtype=np.int64)
+    want = oracle.gauss_filter(Z, g, lc, highpass=True, cells=cells)
+    got = out.ravel()[cells].astype(np.float64)
+    scale = np.abs(Z[np.isfinite(Z)]).max()
+    for k in range(len(cells)):
+        if np.isinf(want[k]):
+            assert np.isinf(got[k])
+            continue
+        tol = 4 * 1601 * EPS * scale
+        if prec == "f32":
+            tol += float(np.spacing(np.float32(abs(want[k]))))
+        assert abs(got[k] - want[k]) <= tol, (pts[k], got[k], want[k])
+
+
+# --- the chain --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_texture_chain_matches_oracle(ctx, prec):
+    g = grid(640, 300, 0.002)
+    Z = host_input(W.synthetic_surface(g.nx, g.ny, g.dd, seed=6, hole_frac=0.1), prec)
+    ls, lc = 0.01, 0.08
+    print(f"[gpu] texture chain {prec}", flush=True)
+    out, r, plane = ctx.fsm_texture(g, to_dev(Z, prec), prec, lambda_s=ls, lambda_c=lc)
+    s_out = oracle.gauss_filter(Z, g, ls)
+    if prec == "f32":
+        s_out = np.where(np.isfinite(s_out), s_out.astype(np.float32).astype(np.float64), np.inf)
+    f_out, pw = oracle.level(s_out, g)
+    if prec == "f32":
+        f_out = np.where(np.isfinite(f_out), f_out.astype(np.float32).astype(np.float64), np.inf)
+    want = oracle.gauss_filter(f_out, g, lc, highpass=True)
+    R = int(math.floor(lc / g.dd + 1e-9))
+    scale = np.abs(Z[np.isfinite(Z)]).max()
+    # in single precision each stage rounds its map to float: the later stages see those values
+    # (the oracle chain above does the same), so the bound of the last stage applies, with the
+    # rounding differences of the earlier stages carried through the (linear, weight-sum-one)
+    # filters: a few float ulps of the largest |z|
+    if prec == "f64":
+        assert_close(out, want, R, scale, prec)
+    else:
+        got = out.cpu().numpy().astype(np.float64)
+        m = np.isfinite(want)
+        assert np.array_equal(np.isfinite(got), m)
+        assert np.abs(got[m] - want[m]).max() <= 4 * float(np.spacing(np.float32(scale)))
+    assert np.allclose(plane, pw, rtol=1e-6 if prec == "f32" else 1e-9, atol=1e-12)
+    ro = oracle.roughness(want)
+    for k in ("Sa", "Sq", "Sz", "Ssk", "Sku"):
+        assert r[k] == pytest.approx(ro[k], rel=1e-9 if prec == "f64" else 1e-3), k
+    assert r["n_hit"] == ro["n_hit"]
