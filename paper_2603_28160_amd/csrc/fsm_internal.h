@@ -217,11 +217,16 @@ int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, i
 constexpr int kPlanePartials = 1024 * 9;
 int launch_plane(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, double *part,
                  double *coef, void *stream);
+// flag (device int) = 1 if any of the n cells is empty, else 0.
+int launch_scan_holes(const void *zin, int64_t n, int precision, int *flag, void *stream);
 // Separable normalised Gaussian of half-width R cells: g_row holds K8 (2R + 1 rounded up to a
 // multiple of 8) row weights, g_col 2R + 33 column weights (16 zeros on either side), nd
-// 16 * nx * ny bytes of scratch.  mode 0: weighted mean; 1: input minus weighted mean.
+// 16 * nx * ny bytes of scratch.  holes = false asserts that every cell is hit: the
+// denominators are then cx[i] cy[j] (nx and ny sums of the in-grid weights) and nd needs only
+// 8 * nx * ny bytes.  mode 0: weighted mean; 1: input minus weighted mean.
 int launch_gauss(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, int R, int K8,
-                 const double *g_row, const double *g_col, void *nd, int mode, void *stream);
+                 const double *g_row, const double *g_col, const double *cx, const double *cy,
+                 bool holes, void *nd, int mode, void *stream);
 // Dynamic LDS of the row pass for K8 row weights.
 size_t gauss_lds_bytes(int K8);
 

@@ -163,17 +163,33 @@ __global__ void __launch_bounds__(256) plane_apply(const T *z, T *out, int64_t n
 
 // ---- Gaussian filter -------------------------------------------------------------------------
 
-// Row pass.  g[k] = w(|k - R|) for k <= 2R, zero up to K8 (a multiple of eight).  nd[j][i] =
-// (sum_k g[k] zh(i - R + k), sum_k g[k] h(i - R + k)) over the grid's columns.
+// flag = 1 if any cell of the map is empty (flag zeroed by the first kernel of the pair).
+__global__ void clear_flag(int *flag) { *flag = 0; }
+
 template <typename T>
+__global__ void __launch_bounds__(256) scan_holes(const T *__restrict__ z, int64_t n, int *flag)
+{
+    int any = 0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+        any |= is_hit((double)z[k]) ? 0 : 1;
+    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+// Row pass.  g[k] = w(|k - R|) for k <= 2R, zero up to K8 (a multiple of eight).
+// HOLES: nd[j][i] = (sum_k g[k] zh(i - R + k), sum_k g[k] h(i - R + k)) as double2 pairs.
+// Without holes (every cell hit) the denominator is separable and known (the caller's
+// per-column and per-row weight sums), so only the numerator is summed and stored (double).
+template <typename T, bool HOLES>
 __global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *__restrict__ z, int64_t nx, int64_t ny,
                                                           int R, int K8, const double *__restrict__ g,
-                                                          double2 *__restrict__ nd)
+                                                          double *__restrict__ nd)
 {
     extern __shared__ double lds[];
     const int64_t tiles = (nx + kRowTile - 1) / kRowTile;
     const int L = kRowTile + K8 + 8;
     const int b = threadIdx.x * kRowOut;
+    // outside the grid: empty with holes; a zero that adds nothing without
+    const double outside = HOLES ? INFINITY : 0.0;
     for (int64_t item = blockIdx.x; item < tiles * ny; item += gridDim.x) {
         const int64_t j = item / tiles, tx = item - j * tiles;
         const int64_t x0 = tx * kRowTile - R;        // grid column of LDS position 0
@@ -181,7 +197,7 @@ __global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *__restrict__ 
         __syncthreads();
         for (int p = threadIdx.x; p < L; p += kRowThreads) {
             const int64_t c = x0 + p;
-            lds[skew(p)] = (c >= 0 && c < nx) ? (double)row[c] : INFINITY;
+            lds[skew(p)] = (c >= 0 && c < nx) ? (double)row[c] : outside;
         }
         __syncthreads();
         double an[kRowOut], ad[kRowOut], cz[2 * kRowOut], ch[2 * kRowOut];
@@ -190,15 +206,23 @@ __global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *__restrict__ 
             an[o] = 0.0;
             ad[o] = 0.0;
             const double v = lds[skew(b + o)];
-            ch[o] = is_hit(v) ? 1.0 : 0.0;
-            cz[o] = is_hit(v) ? v : 0.0;
+            if (HOLES) {
+                ch[o] = is_hit(v) ? 1.0 : 0.0;
+                cz[o] = is_hit(v) ? v : 0.0;
+            } else {
+                cz[o] = v;
+            }
         }
         for (int k0 = 0; k0 < K8; k0 += kRowOut) {
 #pragma unroll
             for (int o = 0; o < kRowOut; ++o) {
                 const double v = lds[skew(b + k0 + kRowOut + o)];
-                ch[kRowOut + o] = is_hit(v) ? 1.0 : 0.0;
-                cz[kRowOut + o] = is_hit(v) ? v : 0.0;
+                if (HOLES) {
+                    ch[kRowOut + o] = is_hit(v) ? 1.0 : 0.0;
+                    cz[kRowOut + o] = is_hit(v) ? v : 0.0;
+                } else {
+                    cz[kRowOut + o] = v;
+                }
             }
 #pragma unroll
             for (int u = 0; u < kRowOut; ++u) {
@@ -206,29 +230,37 @@ __global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *__restrict__ 
 #pragma unroll
                 for (int o = 0; o < kRowOut; ++o) {
                     an[o] = fma(w, cz[u + o], an[o]);
-                    ad[o] = fma(w, ch[u + o], ad[o]);
+                    if (HOLES) ad[o] = fma(w, ch[u + o], ad[o]);
                 }
             }
 #pragma unroll
             for (int o = 0; o < kRowOut; ++o) {
                 cz[o] = cz[kRowOut + o];
-                ch[o] = ch[kRowOut + o];
+                if (HOLES) ch[o] = ch[kRowOut + o];
             }
         }
         const int64_t c0 = tx * kRowTile + b;
 #pragma unroll
-        for (int o = 0; o < kRowOut; ++o)
-            if (c0 + o < nx) nd[j * nx + c0 + o] = make_double2(an[o], ad[o]);
+        for (int o = 0; o < kRowOut; ++o) {
+            if (c0 + o >= nx) continue;
+            if (HOLES)
+                reinterpret_cast<double2 *>(nd)[j * nx + c0 + o] = make_double2(an[o], ad[o]);
+            else
+                nd[j * nx + c0 + o] = an[o];
+        }
     }
 }
 
 // Column pass.  gc[16 + k] = w(|k - R|) for k in [0, 2R], zero in the 16 slots on either
 // side.  Lane i of wave w in block (tx, ty) owns rows j0 .. j0 + 15 of column tx*64 + lane,
-// j0 = ty*64 + 16 w (kColRows = 64 rows per block).
-template <typename T>
+// j0 = ty*64 + 16 w (kColRows = 64 rows per block).  Without holes the denominator of cell
+// (i, j) is cx[i] cy[j], the sums of the weights whose cells lie inside the grid.
+template <typename T, bool HOLES>
 __global__ void __launch_bounds__(64 * kColWaves) gauss_cols(const T *z, T *out, int64_t nx, int64_t ny,
                                                              int R, const double *__restrict__ gc,
-                                                             const double2 *__restrict__ nd, int mode)
+                                                             const double *__restrict__ cx,
+                                                             const double *__restrict__ cy,
+                                                             const double *__restrict__ nd, int mode)
 {
     const int64_t tiles_x = (nx + 63) / 64, tiles_y = (ny + kColRows - 1) / kColRows;
     const int lane = threadIdx.x & 63;
@@ -248,12 +280,18 @@ __global__ void __launch_bounds__(64 * kColWaves) gauss_cols(const T *z, T *out,
             const int64_t m_lo = j0 - R > 0 ? j0 - R : 0;
             const int64_t m_hi = j0 + kColOut - 1 + R < ny - 1 ? j0 + kColOut - 1 + R : ny - 1;
             for (int64_t m = m_lo; m <= m_hi; ++m) {
-                const double2 v = nd[m * nx + i];
                 const double *w = gc + (m - j0 + R + 16);
+                if (HOLES) {
+                    const double2 v = reinterpret_cast<const double2 *>(nd)[m * nx + i];
 #pragma unroll
-                for (int o = 0; o < kColOut; ++o) {
-                    an[o] = fma(w[-o], v.x, an[o]);
-                    ad[o] = fma(w[-o], v.y, ad[o]);
+                    for (int o = 0; o < kColOut; ++o) {
+                        an[o] = fma(w[-o], v.x, an[o]);
+                        ad[o] = fma(w[-o], v.y, ad[o]);
+                    }
+                } else {
+                    const double v = nd[m * nx + i];
+#pragma unroll
+                    for (int o = 0; o < kColOut; ++o) an[o] = fma(w[-o], v, an[o]);
                 }
             }
 #pragma unroll
@@ -262,7 +300,7 @@ __global__ void __launch_bounds__(64 * kColWaves) gauss_cols(const T *z, T *out,
                 if (j < ny) {
                     const int64_t k = j * nx + i;
                     const double h = (double)z[k];
-                    const double lp = an[o] / ad[o];
+                    const double lp = an[o] / (HOLES ? ad[o] : cx[i] * cy[j]);
                     out[k] = is_hit(h) ? (T)(mode == 0 ? lp : h - lp) : inf_of<T>();
                 }
             }
@@ -298,20 +336,47 @@ size_t gauss_lds_bytes(int K8)
     return sizeof(double) * (size_t)(L + (L >> 3) + 1);
 }
 
-int launch_gauss(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, int R, int K8,
-                 const double *g_row, const double *g_col, void *nd, int mode, void *stream)
+int launch_scan_holes(const void *zin, int64_t n, int precision, int *flag, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t blocks = (n + 255) / 256;
+    const dim3 gr((unsigned)(blocks < 4096 ? blocks : 4096));
+    hipLaunchKernelGGL(clear_flag, dim3(1), dim3(1), 0, s, flag);
+    if (precision == FSM_F64)
+        hipLaunchKernelGGL(scan_holes<double>, gr, dim3(256), 0, s, (const double *)zin, n, flag);
+    else
+        hipLaunchKernelGGL(scan_holes<float>, gr, dim3(256), 0, s, (const float *)zin, n, flag);
+    return (int)hipGetLastError();
+}
+
+namespace {
+
+template <typename T, bool HOLES>
+void gauss_pair(const void *zin, void *zout, int64_t nx, int64_t ny, int R, int K8, const double *g_row,
+                const double *g_col, const double *cx, const double *cy, void *nd, int mode, hipStream_t s)
+{
     const int64_t row_items = ((nx + kRowTile - 1) / kRowTile) * ny;
     const int64_t col_items = ((nx + 63) / 64) * ((ny + kColRows - 1) / kColRows);
-    const size_t lds = gauss_lds_bytes(K8);
     const dim3 gr((unsigned)grid_for(row_items)), gcol((unsigned)grid_for(col_items));
+    hipLaunchKernelGGL((gauss_rows<T, HOLES>), gr, dim3(kRowThreads), gauss_lds_bytes(K8), s,
+                       (const T *)zin, nx, ny, R, K8, g_row, (double *)nd);
+    hipLaunchKernelGGL((gauss_cols<T, HOLES>), gcol, dim3(64 * kColWaves), 0, s, (const T *)zin, (T *)zout,
+                       nx, ny, R, g_col, cx, cy, (const double *)nd, mode);
+}
+
+}  // namespace
+
+int launch_gauss(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, int R, int K8,
+                 const double *g_row, const double *g_col, const double *cx, const double *cy,
+                 bool holes, void *nd, int mode, void *stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64) {
-        hipLaunchKernelGGL(gauss_rows<double>, gr, dim3(kRowThreads), lds, s, (const double *)zin, nx, ny, R, K8, g_row, (double2 *)nd);
-        hipLaunchKernelGGL(gauss_cols<double>, gcol, dim3(64 * kColWaves), 0, s, (const double *)zin, (double *)zout, nx, ny, R, g_col, (const double2 *)nd, mode);
+        if (holes) gauss_pair<double, true>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
+        else gauss_pair<double, false>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
     } else {
-        hipLaunchKernelGGL(gauss_rows<float>, gr, dim3(kRowThreads), lds, s, (const float *)zin, nx, ny, R, K8, g_row, (double2 *)nd);
-        hipLaunchKernelGGL(gauss_cols<float>, gcol, dim3(64 * kColWaves), 0, s, (const float *)zin, (float *)zout, nx, ny, R, g_col, (const double2 *)nd, mode);
+        if (holes) gauss_pair<float, true>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
+        else gauss_pair<float, false>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
     }
     return (int)hipGetLastError();
 }

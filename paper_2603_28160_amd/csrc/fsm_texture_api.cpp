@@ -7,9 +7,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "fsm_runtime.h"
 
@@ -75,62 +77,66 @@ int do_level(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zin,
     return FSM_OK;
 }
 
-int do_filter(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zin, void *zout,
-              int R, int mode, hipStream_t s)
-{
-    const int K8 = (2 * R + 1 + 7) / 8 * 8;
-    const int n_col = 2 * R + 33;
-    if (fsm::gauss_lds_bytes(K8) > ctx->max_lds)
-        return set_err(ctx, FSM_EINVAL, "filter window too wide for the device's LDS");
-    const size_t w_bytes = sizeof(double) * (size_t)(K8 + n_col);
-    const size_t nd_at = align256(w_bytes);
-    const size_t nd_bytes = (size_t)16 * (size_t)grid->nx * (size_t)grid->ny;
-    int rc = ensure(ctx, ctx->ws, nd_at + nd_bytes, w_bytes, 1);
-    if (rc != FSM_OK) return rc;
-    // the weight tables sit at the start of the workspace (stage_weights)
-    char *dev = static_cast<char *>(ctx->ws.d_ws);
-    const double *g_row = reinterpret_cast<const double *>(dev);
-    const double *g_col = g_row + K8;
-    int he = fsm::launch_gauss(zin, zout, grid->nx, grid->ny, precision, R, K8, g_row, g_col,
-                               dev + nd_at, mode, s);
-    if (he) return hip_err(ctx, (hipError_t)he, "filter kernels");
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
-    return FSM_OK;
-}
-
-// Stage the row and column weight tables of half-width R for `cutoff` into the workspace.
-int stage_weights(fsm_ctx *ctx, const fsm_grid *grid, double cutoff, int R, hipStream_t s)
-{
-    const int K8 = (2 * R + 1 + 7) / 8 * 8;
-    const int n_col = 2 * R + 33;
-    const size_t w_bytes = sizeof(double) * (size_t)(K8 + n_col);
-    const size_t nd_bytes = (size_t)16 * (size_t)grid->nx * (size_t)grid->ny;
-    int rc = ensure(ctx, ctx->ws, align256(w_bytes) + nd_bytes, w_bytes, 1);
-    if (rc != FSM_OK) return rc;
-    // no earlier copy from the staging is in flight: every call here waits for its stream
-    double *h = static_cast<double *>(ctx->ws.h_ws);
-    const double alpha = std::sqrt(std::log(2.0) / M_PI);
-    std::memset(h, 0, w_bytes);
-    for (int k = 0; k <= 2 * R; ++k) {
-        const double u = ((double)(k - R) * grid->dd) / (alpha * cutoff);
-        const double w = std::exp(-M_PI * (u * u));
-        h[k] = w;               // row table
-        h[K8 + 16 + k] = w;     // column table
-    }
-    hipError_t e = hipMemcpyAsync(ctx->ws.d_ws, h, w_bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(weights)");
-    return FSM_OK;
-}
-
+// One Gaussian filter pass: stage the weight tables, find out whether the map has empty cells
+// (the hole-free kernels sum only numerators), then the row and column passes.
 int filter_once(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zin, void *zout,
                 double cutoff, double trunc, int mode, hipStream_t s)
 {
     const int R = half_width(grid, cutoff, trunc);
     if (R < 0) return set_err(ctx, FSM_EINVAL, "cut-off must be > 0, trunc in (0, 4], half-width <= 3072 cells");
-    int rc = stage_weights(ctx, grid, cutoff, R, s);
+    const int K8 = (2 * R + 1 + 7) / 8 * 8;
+    const int n_col = 2 * R + 33;
+    if (fsm::gauss_lds_bytes(K8) > ctx->max_lds)
+        return set_err(ctx, FSM_EINVAL, "filter window too wide for the device's LDS");
+    const int64_t nx = grid->nx, ny = grid->ny;
+    // staging: row weights, column weights, per-column and per-row in-grid weight sums
+    const size_t n_w = (size_t)K8 + (size_t)n_col + (size_t)nx + (size_t)ny;
+    const size_t w_bytes = sizeof(double) * n_w;
+    const size_t flag_at = align256(w_bytes);
+    const size_t nd_at = flag_at + 256;
+    const size_t nd_bytes = (size_t)16 * (size_t)nx * (size_t)ny;
+    int rc = ensure(ctx, ctx->ws, nd_at + nd_bytes, w_bytes + 64, 1);
     if (rc != FSM_OK) return rc;
-    return do_filter(ctx, grid, precision, zin, zout, R, mode, s);
+    // no earlier copy from the staging is in flight: every call here waits for its stream
+    double *h = static_cast<double *>(ctx->ws.h_ws);
+    std::memset(h, 0, w_bytes);
+    // w(a) = exp(-pi (a dd / (alpha cutoff))^2), a = k - R
+    const double alpha = std::sqrt(std::log(2.0) / M_PI);
+    std::vector<double> prefix((size_t)2 * R + 2, 0.0);
+    for (int k = 0; k <= 2 * R; ++k) {
+        const double u = ((double)(k - R) * grid->dd) / (alpha * cutoff);
+        const double w = std::exp(-M_PI * (u * u));
+        h[k] = w;                         // row table
+        h[K8 + 16 + k] = w;               // column table
+        prefix[(size_t)k + 1] = prefix[(size_t)k] + w;
+    }
+    // sum of the weights whose offset keeps index t + a inside [0, n)
+    auto in_grid_sum = [&](int64_t t, int64_t n) {
+        const int64_t lo = std::max<int64_t>(0, R - t), hi = std::min<int64_t>(2 * R, R + (n - 1 - t));
+        return prefix[(size_t)hi + 1] - prefix[(size_t)lo];
+    };
+    double *cx = h + K8 + n_col, *cy = cx + nx;
+    for (int64_t i = 0; i < nx; ++i) cx[i] = in_grid_sum(i, nx);
+    for (int64_t j = 0; j < ny; ++j) cy[j] = in_grid_sum(j, ny);
+    char *dev = static_cast<char *>(ctx->ws.d_ws);
+    hipError_t e = hipMemcpyAsync(dev, h, w_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(weights)");
+    int *d_flag = reinterpret_cast<int *>(dev + flag_at);
+    int he = fsm::launch_scan_holes(zin, nx * ny, precision, d_flag, s);
+    if (he) return hip_err(ctx, (hipError_t)he, "hole scan");
+    int *h_flag = reinterpret_cast<int *>(h + n_w);
+    e = hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(flag)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+    const double *g_row = reinterpret_cast<const double *>(dev);
+    const double *g_col = g_row + K8;
+    he = fsm::launch_gauss(zin, zout, nx, ny, precision, R, K8, g_row, g_col, g_col + n_col,
+                           g_col + n_col + nx, *h_flag != 0, dev + nd_at, mode, s);
+    if (he) return hip_err(ctx, (hipError_t)he, "filter kernels");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+    return FSM_OK;
 }
 
 }  // namespace

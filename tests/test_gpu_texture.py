@@ -111,13 +111,15 @@ CASES = [  # (nx, ny, dd, cutoff): several 1024-column row tiles; several 64-row
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("highpass", [False, True])
+@pytest.mark.parametrize("holes", [0.15, 0.0], ids=["holes", "full"])
 @pytest.mark.parametrize("case", CASES, ids=["wide", "tall", "identity"])
-def test_filter_matches_oracle(ctx, prec, highpass, case):
+def test_filter_matches_oracle(ctx, prec, highpass, holes, case):
+    # a map with empty cells sums numerators and denominators; a full one only numerators
     nx, ny, dd, cutoff = case
     g = grid(nx, ny, dd)
-    Z = host_input(W.synthetic_surface(nx, ny, dd, seed=3, hole_frac=0.15), prec)
+    Z = host_input(W.synthetic_surface(nx, ny, dd, seed=3, hole_frac=holes), prec)
     R = int(math.floor(cutoff / dd + 1e-9))
-    print(f"[gpu] filter {prec} highpass={highpass} {nx}x{ny} R={R}", flush=True)
+    print(f"[gpu] filter {prec} highpass={highpass} holes={holes} {nx}x{ny} R={R}", flush=True)
     out = ctx.fsm_filter(g, to_dev(Z, prec), cutoff, prec, highpass=highpass)
     want = oracle.gauss_filter(Z, g, cutoff, highpass=highpass)
     assert_close(out, want, R, np.abs(Z[np.isfinite(Z)]).max(), prec)
@@ -143,13 +145,14 @@ def test_filter_rejects_bad_requests(ctx):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_l_filter_full_size_sampled(ctx, prec):
+@pytest.mark.parametrize("holes", [0.02, 0.0], ids=["holes", "full"])
+def test_l_filter_full_size_sampled(ctx, prec, holes):
     # 5000 x 5000 at 1 um with the paper's 0.8 mm L-filter: R = 800 (1601 x 1601 window);
     # corners, edges and interior cells, and the cells next to the row-tile boundaries
     n, dd, lc = 5000, 0.001, 0.8
     g = grid(n, n, dd)
-    Z = host_input(W.synthetic_surface(n, n, dd, seed=5, hole_frac=0.02), prec)
-    print(f"[gpu] L-filter 5000x5000 {prec}", flush=True)
+    Z = host_input(W.synthetic_surface(n, n, dd, seed=5, hole_frac=holes), prec)
+    print(f"[gpu] L-filter 5000x5000 {prec} holes={holes}", flush=True)
     out = ctx.fsm_filter(g, to_dev(Z, prec), lc, prec, highpass=True).cpu().numpy()
     rng = np.random.default_rng(11)
     pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (1023, 17), (1024, 17), (2048, 4999),
