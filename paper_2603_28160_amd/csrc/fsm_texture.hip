@@ -279,7 +279,37 @@ __global__ void __launch_bounds__(64 * kColWaves) gauss_cols(const T *z, T *out,
         if (i < nx) {
             const int64_t m_lo = j0 - R > 0 ? j0 - R : 0;
             const int64_t m_hi = j0 + kColOut - 1 + R < ny - 1 ? j0 + kColOut - 1 + R : ny - 1;
-            for (int64_t m = m_lo; m <= m_hi; ++m) {
+            int64_t m = m_lo;
+            // chunks of CH input rows: CH independent loads in flight and the 2 CH - 1 weights
+            // they need in scalar registers, then CH x 16 fused multiply-adds
+            constexpr int CH = HOLES ? 4 : 8;
+            for (; m + CH - 1 <= m_hi; m += CH) {
+                const double *w = gc + (m - j0 + R + 16);
+                double wr[CH + kColOut - 1];
+#pragma unroll
+                for (int t = 0; t < CH + kColOut - 1; ++t) wr[t] = w[t - (kColOut - 1)];
+                if (HOLES) {
+                    double2 v[CH];
+#pragma unroll
+                    for (int q = 0; q < CH; ++q) v[q] = reinterpret_cast<const double2 *>(nd)[(m + q) * nx + i];
+#pragma unroll
+                    for (int q = 0; q < CH; ++q)
+#pragma unroll
+                        for (int o = 0; o < kColOut; ++o) {
+                            an[o] = fma(wr[q - o + kColOut - 1], v[q].x, an[o]);
+                            ad[o] = fma(wr[q - o + kColOut - 1], v[q].y, ad[o]);
+                        }
+                } else {
+                    double v[CH];
+#pragma unroll
+                    for (int q = 0; q < CH; ++q) v[q] = nd[(m + q) * nx + i];
+#pragma unroll
+                    for (int q = 0; q < CH; ++q)
+#pragma unroll
+                        for (int o = 0; o < kColOut; ++o) an[o] = fma(wr[q - o + kColOut - 1], v[q], an[o]);
+                }
+            }
+            for (; m <= m_hi; ++m) {
                 const double *w = gc + (m - j0 + R + 16);
                 if (HOLES) {
                     const double2 v = reinterpret_cast<const double2 *>(nd)[m * nx + i];
