@@ -13,10 +13,13 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -188,6 +191,64 @@ def coverage_leg(ctx, steps=3):
     return out
 
 
+def dataset_leg(ctx, n=64, side=1024, dd=0.002):
+    """Dataset generation (Sec. 4.3): n ball-end simulations drawn by Latin hypercube sampling
+    on one side x side grid at dd, simulated in one batch, then every map through the
+    measurement chain of Sec. 4.1.1 (S-filter 10 um, least-squares plane, L-filter 0.8 mm) and
+    its roughness, in single precision: samples/s end to end.  Then the 0.8 mm L-filter alone
+    on a full 5000 x 5000 map at 1 um (synthetic, with and without empty cells), both
+    precisions: time and FP64 fused multiply-add rate (2 passes x (2R + 1) taps per cell; with
+    empty cells numerator and denominator)."""
+    import torch
+    from paper_2603_28160_amd import workloads
+    sims = workloads.dataset_sims(n, side=side, dd=dd)
+    prec = "f32"
+    zmaps = [ctx.new_zmap(s.grid, prec) for s in sims]
+    tex = ctx.new_zmap(sims[0].grid, prec)
+    out = {"workload": f"lhs_ball_{n}x{side}x{side}", "precision": prec}
+
+    def run():
+        t0 = time.perf_counter()
+        ctx.fsm_simulate_batch(sims, prec, zmaps=zmaps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rough = [ctx.fsm_texture(s.grid, z, prec, out=tex)[1] for s, z in zip(sims, zmaps)]
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1, rough
+
+    run()
+    ts, tt, rough = run()
+    out.update({"simulate_s": ts, "texture_s": tt, "samples_per_s": n / (ts + tt),
+                "mean_coverage": float(np.mean([r["n_hit"] for r in rough])) / (side * side),
+                "Sa_range_um": [1e3 * min(r["Sa"] for r in rough), 1e3 * max(r["Sa"] for r in rough)]})
+    del zmaps, tex
+    big = workloads.centred_grid(5000, 5000, 0.001)
+    R = int(math.floor(0.8 / big.dd + 1e-9))
+    out["l_filter_5000x5000"] = {}
+    for holes in (0.0, 0.02):
+        Z = workloads.synthetic_surface(5000, 5000, 0.001, seed=5, hole_frac=holes)
+        for p in ("f64", "f32"):
+            z = torch.from_numpy(Z).to(dtype=torch.float64 if p == "f64" else torch.float32,
+                                       device="cuda:0")
+            o = ctx.new_zmap(big, p)
+            ctx.fsm_filter(big, z, 0.8, p, highpass=True, out=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                ctx.fsm_filter(big, z, 0.8, p, highpass=True, out=o)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / 3
+            fma = 2 * (2 * R + 1) * 25e6 * (2 if holes else 1)
+            out["l_filter_5000x5000"][f"{p}_{'holes' if holes else 'full'}"] = {
+                "ms": el * 1e3, "fp64_tflops": 2 * fma / el / 1e12,
+                "frac_of_fp64_peak": 2 * fma / el / 78.6e12}
+            del z, o
+        torch.cuda.empty_cache()
+    print(f"[bench] dataset: {out['samples_per_s']:.1f} samples/s; L-filter 5000^2 f64 "
+          f"{out['l_filter_5000x5000']['f64_full']['ms']:.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 # EFSM wall times (s) of the paper's nine performance conditions on its laptop CPU, from the
 # computation-time table of Sec. 4.3: context for the paper-mode leg, not a target
 PAPER_EFSM_S = {1: 0.81, 2: 0.68, 3: 0.55, 4: 0.65, 5: 0.52, 6: 0.45, 7: 0.59, 8: 0.46, 9: 0.43}
@@ -301,6 +362,9 @@ def main():
                          "'none' to run on the default launch parameters")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batch (configuration 3) and serving (configuration 4) legs")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated extra legs to run (default all): batch, serving, "
+                         "large_field, paper_mode, coverage_complete, dataset")
     ap.add_argument("--batch-sims", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-rate", type=float, default=500.0)
@@ -361,12 +425,17 @@ def main():
                   f"reduce {p['reduce_ms']:.3f}), roughness {p['rough_ms']:.3f} ms",
                   file=sys.stderr, flush=True)
         extras = {}
-        if not args.no_extras:
-            extras["batch"] = batch_leg(ctx, args.batch_sims)
-            extras["serving"] = serve_leg(ctx, args.serve_requests, args.serve_rate)
-            extras["large_field"] = large_leg(ctx)
-            extras["paper_mode"] = paper_leg(ctx)
-            extras["coverage_complete"] = coverage_leg(ctx)
+        legs = {"batch": lambda: batch_leg(ctx, args.batch_sims),
+                "serving": lambda: serve_leg(ctx, args.serve_requests, args.serve_rate),
+                "large_field": lambda: large_leg(ctx),
+                "paper_mode": lambda: paper_leg(ctx),
+                "coverage_complete": lambda: coverage_leg(ctx),
+                "dataset": lambda: dataset_leg(ctx)}
+        wanted = list(legs) if args.extras == "all" else [x for x in args.extras.split(",") if x]
+        for name in ([] if args.no_extras else wanted):
+            if name not in legs:
+                raise SystemExit(f"unknown leg {name!r}; legs: {', '.join(legs)}")
+            extras[name] = legs[name]()
 
     main_prec = "f64" if "f64" in res else precs[0]
     m = res[main_prec]
