@@ -980,16 +980,17 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
         const uint32_t e0 = (int64_t)offsets[tl] < cap ? offsets[tl] : (uint32_t)cap;
         const uint32_t e1 = (int64_t)offsets[tl + 1] < cap ? offsets[tl + 1] : (uint32_t)cap;
         uint32_t e = e0 + tid;
-        for (; e + 3 * kBlock < e1; e += 4 * kBlock) {
-            Key k4[4];
-            uint16_t c4[4];
+        constexpr int kDepth = 8;   // bucket entries in flight per thread
+        for (; e + (kDepth - 1) * kBlock < e1; e += kDepth * kBlock) {
+            Key k4[kDepth];
+            uint16_t c4[kDepth];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
+            for (int v = 0; v < kDepth; ++v) {
                 k4[v] = bkey[e + v * kBlock];
                 c4[v] = bix[e + v * kBlock];
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int v = 0; v < kDepth; ++v)
                 __hip_atomic_fetch_min(&lds[c4[v]], k4[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         for (; e < e1; e += kBlock)
