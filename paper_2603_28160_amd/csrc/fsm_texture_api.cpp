@@ -48,94 +48,146 @@ int half_width(const fsm_grid *g, double cutoff, double trunc)
     return (int)r;
 }
 
-int do_level(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zin, void *zout,
-             double plane[3], hipStream_t s)
+// Weight tables of one Gaussian filter in the staging region: row weights (K8), column
+// weights (2R + 33, 16 zeros on either side), per-column and per-row sums of the weights whose
+// cells lie inside the grid (nx, ny).  Offsets in doubles from the start of the region.
+struct FilterTables {
+    double cutoff = 0.0;
+    int R = 0, K8 = 0, n_col = 0;
+    size_t row = 0, col = 0, cx = 0, cy = 0, end = 0;
+};
+
+FilterTables plan_tables(const fsm_grid *g, double cutoff, int R, size_t at)
 {
-    const size_t coef_at = align256(sizeof(double) * fsm::kPlanePartials);
-    int rc = ensure(ctx, ctx->ws, coef_at + 256, 256, 1);
-    if (rc != FSM_OK) return rc;
-    char *dev = static_cast<char *>(ctx->ws.d_ws);
-    double *coef = reinterpret_cast<double *>(dev + coef_at);
-    int he = fsm::launch_plane(zin, zout, grid->nx, grid->ny, precision,
-                               reinterpret_cast<double *>(dev), coef, s);
-    if (he) return hip_err(ctx, (hipError_t)he, "plane kernels");
-    double *h = static_cast<double *>(ctx->ws.h_ws);
-    hipError_t e = hipMemcpyAsync(h, coef, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plane)");
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
-    if (h[3] == 0.0)
-        return set_err(ctx, FSM_EINVAL, "fewer than three hit cells, or all on one line");
-    if (plane) {
-        // z = c0 + cu u + cv v with u = (x - x0)/dd - ci, v = (y - y0)/dd - cj
-        const double ci = 0.5 * (double)(grid->nx - 1), cj = 0.5 * (double)(grid->ny - 1);
-        const double bx = h[1] / grid->dd, by = h[2] / grid->dd;
-        plane[0] = h[0] - h[1] * (grid->x0 / grid->dd + ci) - h[2] * (grid->y0 / grid->dd + cj);
-        plane[1] = bx;
-        plane[2] = by;
-    }
-    return FSM_OK;
+    FilterTables t;
+    t.cutoff = cutoff;
+    t.R = R;
+    t.K8 = (2 * R + 1 + 7) / 8 * 8;
+    t.n_col = 2 * R + 33;
+    t.row = at;
+    t.col = t.row + (size_t)t.K8;
+    t.cx = t.col + (size_t)t.n_col;
+    t.cy = t.cx + (size_t)g->nx;
+    t.end = t.cy + (size_t)g->ny;
+    return t;
 }
 
-// One Gaussian filter pass: stage the weight tables, find out whether the map has empty cells
-// (the hole-free kernels sum only numerators), then the row and column passes.
-int filter_once(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zin, void *zout,
-                double cutoff, double trunc, int mode, hipStream_t s)
+void fill_tables(const fsm_grid *g, const FilterTables &t, double *h)
 {
-    const int R = half_width(grid, cutoff, trunc);
-    if (R < 0) return set_err(ctx, FSM_EINVAL, "cut-off must be > 0, trunc in (0, 4], half-width <= 3072 cells");
-    const int K8 = (2 * R + 1 + 7) / 8 * 8;
-    const int n_col = 2 * R + 33;
-    if (fsm::gauss_lds_bytes(K8) > ctx->max_lds)
-        return set_err(ctx, FSM_EINVAL, "filter window too wide for the device's LDS");
-    const int64_t nx = grid->nx, ny = grid->ny;
-    // staging: row weights, column weights, per-column and per-row in-grid weight sums
-    const size_t n_w = (size_t)K8 + (size_t)n_col + (size_t)nx + (size_t)ny;
-    const size_t w_bytes = sizeof(double) * n_w;
-    const size_t flag_at = align256(w_bytes);
-    const size_t nd_at = flag_at + 256;
-    const size_t nd_bytes = (size_t)16 * (size_t)nx * (size_t)ny;
-    int rc = ensure(ctx, ctx->ws, nd_at + nd_bytes, w_bytes + 64, 1);
-    if (rc != FSM_OK) return rc;
-    // no earlier copy from the staging is in flight: every call here waits for its stream
-    double *h = static_cast<double *>(ctx->ws.h_ws);
-    std::memset(h, 0, w_bytes);
+    std::memset(h + t.row, 0, sizeof(double) * (t.end - t.row));
     // w(a) = exp(-pi (a dd / (alpha cutoff))^2), a = k - R
     const double alpha = std::sqrt(std::log(2.0) / M_PI);
+    const int R = t.R;
     std::vector<double> prefix((size_t)2 * R + 2, 0.0);
     for (int k = 0; k <= 2 * R; ++k) {
-        const double u = ((double)(k - R) * grid->dd) / (alpha * cutoff);
+        const double u = ((double)(k - R) * g->dd) / (alpha * t.cutoff);
         const double w = std::exp(-M_PI * (u * u));
-        h[k] = w;                         // row table
-        h[K8 + 16 + k] = w;               // column table
+        h[t.row + (size_t)k] = w;
+        h[t.col + 16 + (size_t)k] = w;
         prefix[(size_t)k + 1] = prefix[(size_t)k] + w;
     }
-    // sum of the weights whose offset keeps index t + a inside [0, n)
-    auto in_grid_sum = [&](int64_t t, int64_t n) {
-        const int64_t lo = std::max<int64_t>(0, R - t), hi = std::min<int64_t>(2 * R, R + (n - 1 - t));
+    // sum of the weights whose offset keeps index i + a inside [0, n)
+    auto in_grid_sum = [&](int64_t i, int64_t n) {
+        const int64_t lo = std::max<int64_t>(0, R - i), hi = std::min<int64_t>(2 * R, R + (n - 1 - i));
         return prefix[(size_t)hi + 1] - prefix[(size_t)lo];
     };
-    double *cx = h + K8 + n_col, *cy = cx + nx;
-    for (int64_t i = 0; i < nx; ++i) cx[i] = in_grid_sum(i, nx);
-    for (int64_t j = 0; j < ny; ++j) cy[j] = in_grid_sum(j, ny);
+    for (int64_t i = 0; i < g->nx; ++i) h[t.cx + (size_t)i] = in_grid_sum(i, g->nx);
+    for (int64_t j = 0; j < g->ny; ++j) h[t.cy + (size_t)j] = in_grid_sum(j, g->ny);
+}
+
+// One pass through the texture operators on `stream`: up to two filters (the first smoothing,
+// the second keeping the roughness part), with a least-squares plane removed between them.
+struct Chain {
+    int n_filters = 0;
+    FilterTables f[2];
+    int mode[2] = {FSM_FILTER_SMOOTH, FSM_FILTER_ROUGH};
+    bool level = false;
+};
+
+int run_chain(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zin, void *zout,
+              const Chain &c, double plane[3], hipStream_t s)
+{
+    const int64_t nx = grid->nx, ny = grid->ny;
+    for (int k = 0; k < c.n_filters; ++k)
+        if (fsm::gauss_lds_bytes(c.f[k].K8) > ctx->max_lds)
+            return set_err(ctx, FSM_EINVAL, "filter window too wide for the device's LDS");
+    // device: [weight tables][plane partials][plane coefficients, hole flag][scratch pairs]
+    const size_t n_w = c.n_filters ? c.f[c.n_filters - 1].end : 0;
+    const size_t part_at = align256(sizeof(double) * n_w);
+    const size_t coef_at = part_at + align256(sizeof(double) * fsm::kPlanePartials);
+    const size_t flag_at = coef_at + 64;
+    const size_t nd_at = coef_at + 256;
+    const size_t nd_bytes = c.n_filters ? (size_t)16 * (size_t)nx * (size_t)ny : 0;
+    // host staging: the tables, then 4 coefficients and the flag read back
+    const size_t h_back = align256(sizeof(double) * n_w);
+    int rc = ensure(ctx, ctx->ws, nd_at + nd_bytes, h_back + 64, 1);
+    if (rc != FSM_OK) return rc;
     char *dev = static_cast<char *>(ctx->ws.d_ws);
-    hipError_t e = hipMemcpyAsync(dev, h, w_bytes, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(weights)");
+    char *host = static_cast<char *>(ctx->ws.h_ws);
+    double *h_coef = reinterpret_cast<double *>(host + h_back);
+    int *h_flag = reinterpret_cast<int *>(host + h_back + 32);
+    double *d_coef = reinterpret_cast<double *>(dev + coef_at);
     int *d_flag = reinterpret_cast<int *>(dev + flag_at);
-    int he = fsm::launch_scan_holes(zin, nx * ny, precision, d_flag, s);
-    if (he) return hip_err(ctx, (hipError_t)he, "hole scan");
-    int *h_flag = reinterpret_cast<int *>(h + n_w);
-    e = hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(flag)");
+    // no earlier copy from the staging is in flight: every call here waits for its stream
+    hipError_t e;
+    bool holes = true;
+    if (c.n_filters) {
+        for (int k = 0; k < c.n_filters; ++k) fill_tables(grid, c.f[k], reinterpret_cast<double *>(host));
+        e = hipMemcpyAsync(dev, host, sizeof(double) * n_w, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(weights)");
+        // filters and the plane keep the set of empty cells, so one scan serves the chain
+        int he = fsm::launch_scan_holes(zin, nx * ny, precision, d_flag, s);
+        if (he) return hip_err(ctx, (hipError_t)he, "hole scan");
+        e = hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(flag)");
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+        holes = *h_flag != 0;
+    }
+    const void *cur = zin;
+    auto filter = [&](int k) {
+        const FilterTables &t = c.f[k];
+        const double *w = reinterpret_cast<const double *>(dev);
+        int he = fsm::launch_gauss(cur, zout, nx, ny, precision, t.R, t.K8, w + t.row, w + t.col,
+                                   w + t.cx, w + t.cy, holes, dev + nd_at, c.mode[k], s);
+        cur = zout;
+        return he ? hip_err(ctx, (hipError_t)he, "filter kernels") : FSM_OK;
+    };
+    int k = 0;
+    if (c.level && c.n_filters == 2) {
+        rc = filter(k++);
+        if (rc != FSM_OK) return rc;
+    }
+    if (c.level) {
+        int he = fsm::launch_plane(cur, zout, nx, ny, precision,
+                                   reinterpret_cast<double *>(dev + part_at), d_coef, s);
+        if (he) return hip_err(ctx, (hipError_t)he, "plane kernels");
+        cur = zout;
+        e = hipMemcpyAsync(h_coef, d_coef, 4 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plane)");
+    }
+    for (; k < c.n_filters; ++k) {
+        rc = filter(k);
+        if (rc != FSM_OK) return rc;
+    }
+    if (cur != zout) {
+        const size_t bytes = (size_t)nx * (size_t)ny * (precision == FSM_F64 ? sizeof(double) : sizeof(float));
+        e = hipMemcpyAsync(zout, cur, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(copy)");
+    }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
-    const double *g_row = reinterpret_cast<const double *>(dev);
-    const double *g_col = g_row + K8;
-    he = fsm::launch_gauss(zin, zout, nx, ny, precision, R, K8, g_row, g_col, g_col + n_col,
-                           g_col + n_col + nx, *h_flag != 0, dev + nd_at, mode, s);
-    if (he) return hip_err(ctx, (hipError_t)he, "filter kernels");
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+    double pl[3] = {0.0, 0.0, 0.0};
+    if (c.level) {
+        if (h_coef[3] == 0.0)
+            return set_err(ctx, FSM_EINVAL, "fewer than three hit cells, or all on one line");
+        // z = c0 + cu u + cv v with u = (x - x0)/dd - ci, v = (y - y0)/dd - cj
+        const double ci = 0.5 * (double)(nx - 1), cj = 0.5 * (double)(ny - 1);
+        pl[0] = h_coef[0] - h_coef[1] * (grid->x0 / grid->dd + ci) - h_coef[2] * (grid->y0 / grid->dd + cj);
+        pl[1] = h_coef[1] / grid->dd;
+        pl[2] = h_coef[2] / grid->dd;
+    }
+    if (plane) std::memcpy(plane, pl, sizeof(pl));
     return FSM_OK;
 }
 
@@ -150,7 +202,9 @@ int fsm_level(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zma
     try {
         int rc = check_common(ctx, grid, precision, zmap_in, zmap_out);
         if (rc != FSM_OK) return rc;
-        return do_level(ctx, grid, precision, zmap_in, zmap_out, plane, static_cast<hipStream_t>(stream));
+        Chain c;
+        c.level = true;
+        return run_chain(ctx, grid, precision, zmap_in, zmap_out, c, plane, static_cast<hipStream_t>(stream));
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");
     } catch (...) {
@@ -167,8 +221,13 @@ int fsm_filter(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zm
         if (rc != FSM_OK) return rc;
         if (mode != FSM_FILTER_SMOOTH && mode != FSM_FILTER_ROUGH)
             return set_err(ctx, FSM_EINVAL, "unknown filter mode");
-        return filter_once(ctx, grid, precision, zmap_in, zmap_out, cutoff, trunc, mode,
-                           static_cast<hipStream_t>(stream));
+        const int R = half_width(grid, cutoff, trunc);
+        if (R < 0) return set_err(ctx, FSM_EINVAL, "cut-off must be > 0, trunc in (0, 4], half-width <= 3072 cells");
+        Chain c;
+        c.n_filters = 1;
+        c.f[0] = plan_tables(grid, cutoff, R, 0);
+        c.mode[0] = mode;
+        return run_chain(ctx, grid, precision, zmap_in, zmap_out, c, nullptr, static_cast<hipStream_t>(stream));
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");
     } catch (...) {
@@ -187,36 +246,36 @@ int fsm_texture(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *z
         if (!spec || !out || !(spec->lambda_s >= 0.0) || !(spec->lambda_c >= 0.0) ||
             !std::isfinite(spec->lambda_s) || !std::isfinite(spec->lambda_c))
             return set_err(ctx, FSM_EINVAL, "invalid texture specification");
-        if ((spec->lambda_s > 0.0 && half_width(grid, spec->lambda_s, spec->trunc) < 0) ||
-            (spec->lambda_c > 0.0 && half_width(grid, spec->lambda_c, spec->trunc) < 0))
-            return set_err(ctx, FSM_EINVAL, "cut-off must be > 0, trunc in (0, 4], half-width <= 3072 cells");
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        const void *cur = zmap_in;
-        if (spec->lambda_s > 0.0) {
-            rc = filter_once(ctx, grid, precision, cur, zmap_out, spec->lambda_s, spec->trunc,
-                             FSM_FILTER_SMOOTH, s);
+        Chain c;
+        c.level = spec->level != 0;
+        const double cut[2] = {spec->lambda_s, spec->lambda_c};
+        const int modes[2] = {FSM_FILTER_SMOOTH, FSM_FILTER_ROUGH};
+        size_t at = 0;
+        for (int k = 0; k < 2; ++k) {
+            if (!(cut[k] > 0.0)) continue;
+            const int R = half_width(grid, cut[k], spec->trunc);
+            if (R < 0) return set_err(ctx, FSM_EINVAL, "cut-off must be > 0, trunc in (0, 4], half-width <= 3072 cells");
+            c.f[c.n_filters] = plan_tables(grid, cut[k], R, at);
+            c.mode[c.n_filters] = modes[k];
+            at = c.f[c.n_filters].end;
+            ++c.n_filters;
+        }
+        // with only an L-filter the plane goes first: S, F, L in that order
+        if (c.level && c.n_filters == 1 && c.mode[0] == FSM_FILTER_SMOOTH) {
+            // S-filter then plane: run_chain removes the plane before its filters, so split
+            Chain s1;
+            s1.n_filters = 1;
+            s1.f[0] = c.f[0];
+            s1.mode[0] = FSM_FILTER_SMOOTH;
+            rc = run_chain(ctx, grid, precision, zmap_in, zmap_out, s1, nullptr, static_cast<hipStream_t>(stream));
             if (rc != FSM_OK) return rc;
-            cur = zmap_out;
+            Chain f;
+            f.level = true;
+            rc = run_chain(ctx, grid, precision, zmap_out, zmap_out, f, plane, static_cast<hipStream_t>(stream));
+        } else {
+            rc = run_chain(ctx, grid, precision, zmap_in, zmap_out, c, plane, static_cast<hipStream_t>(stream));
         }
-        double pl[3] = {0.0, 0.0, 0.0};
-        if (spec->level) {
-            rc = do_level(ctx, grid, precision, cur, zmap_out, pl, s);
-            if (rc != FSM_OK) return rc;
-            cur = zmap_out;
-        }
-        if (spec->lambda_c > 0.0) {
-            rc = filter_once(ctx, grid, precision, cur, zmap_out, spec->lambda_c, spec->trunc,
-                             FSM_FILTER_ROUGH, s);
-            if (rc != FSM_OK) return rc;
-            cur = zmap_out;
-        }
-        if (cur != zmap_out) {
-            const size_t bytes = (size_t)grid->nx * (size_t)grid->ny *
-                                 (precision == FSM_F64 ? sizeof(double) : sizeof(float));
-            hipError_t e = hipMemcpyAsync(zmap_out, cur, bytes, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(copy)");
-        }
-        if (plane) std::memcpy(plane, pl, sizeof(pl));
+        if (rc != FSM_OK) return rc;
         return fsm_roughness(ctx, grid, precision, zmap_out, out, stream);
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");

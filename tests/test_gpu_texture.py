@@ -206,3 +206,25 @@ def test_texture_chain_matches_oracle(ctx, prec):
     for k in ("Sa", "Sq", "Sz", "Ssk", "Sku"):
         assert r[k] == pytest.approx(ro[k], rel=1e-9 if prec == "f64" else 1e-3), k
     assert r["n_hit"] == ro["n_hit"]
+
+
+@pytest.mark.parametrize("ls,lc,level", [(0.01, 0.0, True), (0.0, 0.08, True), (0.01, 0.08, False),
+                                         (0.0, 0.0, True), (0.0, 0.0, False)])
+def test_texture_chain_variants(ctx, ls, lc, level):
+    # every combination keeps the order S, F, L and skips what is switched off
+    g = grid(300, 220, 0.002)
+    Z = W.synthetic_surface(g.nx, g.ny, g.dd, seed=8, hole_frac=0.05)
+    print(f"[gpu] texture variant ls={ls} lc={lc} level={level}", flush=True)
+    out, r, plane = ctx.fsm_texture(g, to_dev(Z, "f64"), "f64", lambda_s=ls, lambda_c=lc, level=level)
+    want = Z
+    if ls:
+        want = oracle.gauss_filter(want, g, ls)
+    pw = (0.0, 0.0, 0.0)
+    if level:
+        want, pw = oracle.level(want, g)
+    if lc:
+        want = oracle.gauss_filter(want, g, lc, highpass=True)
+    R = int(math.floor(max(ls, lc) / g.dd + 1e-9))
+    assert_close(out, want, max(R, 8), np.abs(Z[np.isfinite(Z)]).max(), "f64")
+    assert np.allclose(plane, pw, rtol=1e-9, atol=1e-12)
+    assert r["Sq"] == pytest.approx(oracle.roughness(want)["Sq"], rel=1e-9)
