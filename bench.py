@@ -193,9 +193,9 @@ def coverage_leg(ctx, steps=3):
 
 def dataset_leg(ctx, n=64, side=1024, dd=0.002):
     """Dataset generation (Sec. 4.3): n ball-end simulations drawn by Latin hypercube sampling
-    on one side x side grid at dd, simulated in one batch, then every map through the
+    on one side x side grid at dd, simulated in one batch, then all maps through the
     measurement chain of Sec. 4.1.1 (S-filter 10 um, least-squares plane, L-filter 0.8 mm) and
-    its roughness, in single precision: samples/s end to end.  Then the 0.8 mm L-filter alone
+    their roughness in one texture batch, in single precision: samples/s end to end.  Then the 0.8 mm L-filter alone
     on a full 5000 x 5000 map at 1 um (synthetic, with and without empty cells), both
     precisions: time and FP64 fused multiply-add rate (2 passes x (2R + 1) taps per cell; with
     empty cells numerator and denominator)."""
@@ -204,7 +204,7 @@ def dataset_leg(ctx, n=64, side=1024, dd=0.002):
     sims = workloads.dataset_sims(n, side=side, dd=dd)
     prec = "f32"
     zmaps = [ctx.new_zmap(s.grid, prec) for s in sims]
-    tex = ctx.new_zmap(sims[0].grid, prec)
+    texs = [ctx.new_zmap(sims[0].grid, prec) for _ in sims]
     out = {"workload": f"lhs_ball_{n}x{side}x{side}", "precision": prec}
 
     def run():
@@ -212,7 +212,7 @@ def dataset_leg(ctx, n=64, side=1024, dd=0.002):
         ctx.fsm_simulate_batch(sims, prec, zmaps=zmaps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        rough = [ctx.fsm_texture(s.grid, z, prec, out=tex)[1] for s, z in zip(sims, zmaps)]
+        rough = ctx.fsm_texture_batch(sims[0].grid, zmaps, prec, outs=texs)[1]
         torch.cuda.synchronize()
         return t1 - t0, time.perf_counter() - t1, rough
 
@@ -221,7 +221,7 @@ def dataset_leg(ctx, n=64, side=1024, dd=0.002):
     out.update({"simulate_s": ts, "texture_s": tt, "samples_per_s": n / (ts + tt),
                 "mean_coverage": float(np.mean([r["n_hit"] for r in rough])) / (side * side),
                 "Sa_range_um": [1e3 * min(r["Sa"] for r in rough), 1e3 * max(r["Sa"] for r in rough)]})
-    del zmaps, tex
+    del zmaps, texs
     big = workloads.centred_grid(5000, 5000, 0.001)
     R = int(math.floor(0.8 / big.dd + 1e-9))
     out["l_filter_5000x5000"] = {}

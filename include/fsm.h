@@ -353,6 +353,15 @@ int fsm_texture(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *z
                 void *zmap_out, const fsm_texture_spec *spec, fsm_rough *out, double plane[3],
                 void *stream);
 
+/* fsm_texture over n maps of one grid in one launch sequence (a dataset of predicted maps,
+ * Sec. 4.3): zmaps_in[m] -> zmaps_out[m] (device pointers; a map may be its own output),
+ * out[m] its roughness, planes[3m .. 3m + 2] its removed plane (planes nullable).  The maps
+ * are processed in groups whose filter scratch (16 bytes per cell and map) stays within
+ * 4 GiB.  Errors as fsm_texture; a degenerate map is named in the message. */
+int fsm_texture_batch(fsm_ctx *ctx, int n, const fsm_grid *grid, int precision,
+                      const void *const *zmaps_in, void *const *zmaps_out,
+                      const fsm_texture_spec *spec, fsm_rough *out, double *planes, void *stream);
+
 /* ---- serving loop --------------------------------------------------------------------------
  *
  * Simulations of different sizes and parameters arriving over time, the way a surrogate-model

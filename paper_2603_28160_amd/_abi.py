@@ -142,6 +142,8 @@ SIGNATURES = {
                     C.c_double, C.c_int, C.c_void_p], C.c_int),
     "fsm_texture": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, C.c_void_p, P(FsmTextureSpec),
                      P(FsmRough), P(C.c_double), C.c_void_p], C.c_int),
+    "fsm_texture_batch": ([C.c_void_p, C.c_int, P(FsmGrid), C.c_int, P(C.c_void_p), P(C.c_void_p),
+                           P(FsmTextureSpec), P(FsmRough), P(C.c_double), C.c_void_p], C.c_int),
     "fsm_simulate_batch": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmRough), C.c_void_p],
                            C.c_int),
     "fsm_trajectory": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, C.c_void_p,

@@ -278,6 +278,33 @@ class Context:
         _check(rc, "fsm_texture", self._h)
         return out, r.as_dict(), tuple(plane)
 
+    def fsm_texture_batch(self, grid, zmaps, precision="f64", lambda_s: float = 0.01,
+                          lambda_c: float = 0.8, level: bool = True, trunc: float = 1.0,
+                          outs=None, stream=None):
+        """fsm_texture over many maps of one grid in one launch sequence; returns (maps,
+        roughness dicts, planes), in the order of `zmaps`.  outs may be zmaps (in place)."""
+        n = len(zmaps)
+        if n == 0:
+            return [], [], []
+        if outs is None:
+            outs = [self.new_zmap(grid, precision) for _ in range(n)]
+        if len(outs) != n:
+            raise ValueError("outs must hold one map per input map")
+        for z, o in zip(zmaps, outs):
+            self._check_zmap(grid, precision, z)
+            self._check_zmap(grid, precision, o)
+        spec = _abi.FsmTextureSpec(lambda_s=float(lambda_s), lambda_c=float(lambda_c),
+                                   trunc=float(trunc), level=1 if level else 0)
+        zin = (C.c_void_p * n)(*[z.data_ptr() for z in zmaps])
+        zout = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        res = (_abi.FsmRough * n)()
+        planes = (C.c_double * (3 * n))()
+        rc = self._lib.fsm_texture_batch(self._h, n, C.byref(_abi.grid_struct(grid)), _prec(precision),
+                                         zin, zout, C.byref(spec), res, planes,
+                                         C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_texture_batch", self._h)
+        return outs, [r.as_dict() for r in res], [tuple(planes[3 * k:3 * k + 3]) for k in range(n)]
+
     def fsm_simulate_batch(self, sims, precision="f64", zmaps=None, stream=None):
         """Run many simulations in one launch sequence; returns (Z-map tensors, roughness
         dicts), both in the order of `sims`."""

@@ -593,6 +593,55 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
 
 bool valid_precision(int p) { return p == FSM_F64 || p == FSM_F32; }
 
+int roughness_maps(fsm_ctx *ctx, const fsm_grid *grid, int precision, const std::vector<void *> &zmaps,
+                   fsm_rough *out, hipStream_t s)
+{
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
+    const int n = (int)zmaps.size();
+    // a set of pseudo-simulations carrying only the grid: the tiled roughness passes
+    std::vector<Plan> plans((size_t)n);
+    for (Plan &p : plans) {
+        p.nx = grid->nx;
+        p.ny = grid->ny;
+        p.N = 1;
+    }
+    std::vector<DevSim> devs;
+    LaunchParams lp;
+    lp.strategy = fsm::kStrategyScatter;
+    lp.tile_shape = ctx->tile_shape;
+    const SetLayout L = make_layout(ctx, plans, precision, lp, devs);
+    int rc = ensure(ctx, ctx->ws, L.total, L.total - L.sims, (size_t)n);
+    if (rc != FSM_OK) return rc;
+    char *dev = static_cast<char *>(ctx->ws.d_ws);
+    char *host = static_cast<char *>(ctx->ws.h_ws);
+    fill_image(L, plans, devs, zmaps, dev, host);
+    ctx->timings.valid = 0;
+    ctx->stages_used = 0;
+    mark(ctx, 0, s, false);
+    e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
+    mark(ctx, 1, s, false);
+    mark(ctx, 2, s, false);
+    mark(ctx, 3, s, false);
+    int he = fsm::launch_rough(reinterpret_cast<const DevSim *>(dev + L.sims), n,
+                               reinterpret_cast<const int64_t *>(dev + L.tbase), L.total_tiles,
+                               precision, L.sx, L.sy, true, false,
+                               reinterpret_cast<fsm::TileStat1 *>(dev + L.st1),
+                               reinterpret_cast<fsm::TileStat2 *>(dev + L.st2),
+                               reinterpret_cast<fsm::RoughState *>(dev + L.state), nullptr, nullptr,
+                               reinterpret_cast<fsm_rough *>(dev + L.out), s);
+    if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
+    e = hipMemcpyAsync(ctx->ws.h_out, dev + L.out, sizeof(fsm_rough) * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
+    mark(ctx, 4, s, false);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
+    collect(ctx, true);
+    std::memcpy(out, ctx->ws.h_out, sizeof(fsm_rough) * (size_t)n);
+    return FSM_OK;
+}
+
 }  // namespace rt
 }  // namespace fsm
 
@@ -1074,49 +1123,8 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
         grid->nx > INT32_MAX || grid->ny > INT32_MAX || grid->nx > INT64_MAX / grid->ny)
         return set_err(ctx, FSM_EINVAL, "invalid grid, pointer or precision");
     try {
-        hipError_t e = hipSetDevice(ctx->device);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
-        // a set of one pseudo-simulation carrying only the grid: the tiled roughness passes
-        std::vector<Plan> plans(1);
-        plans[0].nx = grid->nx;
-        plans[0].ny = grid->ny;
-        plans[0].N = 1;
-        std::vector<DevSim> devs;
-        LaunchParams lp;
-        lp.strategy = fsm::kStrategyScatter;
-        lp.tile_shape = ctx->tile_shape;
-        const SetLayout L = make_layout(ctx, plans, precision, lp, devs);
-        int rc = ensure(ctx, ctx->ws, L.total, L.total - L.sims, 1);
-        if (rc != FSM_OK) return rc;
-        char *dev = static_cast<char *>(ctx->ws.d_ws);
-        char *host = static_cast<char *>(ctx->ws.h_ws);
         std::vector<void *> zmaps{const_cast<void *>(zmap_dev)};
-        fill_image(L, plans, devs, zmaps, dev, host);
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        ctx->timings.valid = 0;
-        ctx->stages_used = 0;
-        mark(ctx, 0, s, false);
-        e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
-        mark(ctx, 1, s, false);
-        mark(ctx, 2, s, false);
-        mark(ctx, 3, s, false);
-        int he = fsm::launch_rough(reinterpret_cast<const DevSim *>(dev + L.sims), 1,
-                                   reinterpret_cast<const int64_t *>(dev + L.tbase), L.total_tiles,
-                                   precision, L.sx, L.sy, true, false,
-                                   reinterpret_cast<fsm::TileStat1 *>(dev + L.st1),
-                                   reinterpret_cast<fsm::TileStat2 *>(dev + L.st2),
-                                   reinterpret_cast<fsm::RoughState *>(dev + L.state), nullptr, nullptr,
-                                   reinterpret_cast<fsm_rough *>(dev + L.out), s);
-        if (he) return hip_err(ctx, (hipError_t)he, "roughness kernels");
-        e = hipMemcpyAsync(ctx->ws.h_out, dev + L.out, sizeof(fsm_rough), hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(result)");
-        mark(ctx, 4, s, false);
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_err(ctx, e, "hipStreamSynchronize");
-        collect(ctx, true);
-        *out = *ctx->ws.h_out;
-        return FSM_OK;
+        return fsm::rt::roughness_maps(ctx, grid, precision, zmaps, out, static_cast<hipStream_t>(stream));
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");
     } catch (...) {

@@ -211,21 +211,24 @@ int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, i
                  TileStat2 *st2, RoughState *state, const uint64_t *d_binned,
                  const int64_t *d_evals, fsm_rough *d_out, void *stream);
 
-// Surface-texture operators (fsm_texture.hip).  zin and zout may be the same map.
-// Least-squares plane over the hit cells, subtracted into zout.  part: kPlanePartials doubles
-// of scratch; coef: 4 doubles receiving (c0, cu, cv, status) in centred cell units.
+// Surface-texture operators (fsm_texture.hip), over n_maps maps of one grid at once: zin and
+// zout are device arrays of n_maps map pointers (a map may be its own output).
+// Least-squares plane over each map's hit cells, subtracted into its output.  part:
+// n_maps * plane_blocks(ny) * 9 doubles of scratch; coef: 4 doubles per map receiving (c0, cu,
+// cv, status) in centred cell units.
 constexpr int kPlanePartials = 1024 * 9;
-int launch_plane(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, double *part,
-                 double *coef, void *stream);
-// flag (device int) = 1 if any of the n cells is empty, else 0.
-int launch_scan_holes(const void *zin, int64_t n, int precision, int *flag, void *stream);
+int plane_blocks(int64_t ny);
+int launch_plane(const void *const *zin, void *const *zout, int n_maps, int64_t nx, int64_t ny,
+                 int precision, double *part, double *coef, void *stream);
+// flag (device int) = 1 if any of the n cells of any map is empty, else 0.
+int launch_scan_holes(const void *const *zin, int n_maps, int64_t n, int precision, int *flag, void *stream);
 // Separable normalised Gaussian of half-width R cells: g_row holds K8 (2R + 1 rounded up to a
 // multiple of 8) row weights, g_col 2R + 33 column weights (16 zeros on either side), nd
-// 16 * nx * ny bytes of scratch.  holes = false asserts that every cell is hit: the
+// 16 * nx * ny bytes of scratch per map.  holes = false asserts that every cell is hit: the
 // denominators are then cx[i] cy[j] (nx and ny sums of the in-grid weights) and nd needs only
-// 8 * nx * ny bytes.  mode 0: weighted mean; 1: input minus weighted mean.
-int launch_gauss(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, int R, int K8,
-                 const double *g_row, const double *g_col, const double *cx, const double *cy,
+// 8 * nx * ny bytes per map.  mode 0: weighted mean; 1: input minus weighted mean.
+int launch_gauss(const void *const *zin, void *const *zout, int n_maps, int64_t nx, int64_t ny, int precision,
+                 int R, int K8, const double *g_row, const double *g_col, const double *cx, const double *cy,
                  bool holes, void *nd, int mode, void *stream);
 // Dynamic LDS of the row pass for K8 row weights.
 size_t gauss_lds_bytes(int K8);

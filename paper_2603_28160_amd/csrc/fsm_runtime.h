@@ -101,6 +101,10 @@ bool valid_tile_shape(const fsm_ctx *ctx, int precision, int code);
 // Grow w to at least the given sizes (device workspace, host staging, result records).
 int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size_t n_out);
 void release(Workspace &w);
+// Roughness of existing Z-maps (device pointers) of one grid, one launch sequence; waits for
+// stream s and writes zmaps.size() records to out.
+int roughness_maps(fsm_ctx *ctx, const fsm_grid *grid, int precision, const std::vector<void *> &zmaps,
+                   fsm_rough *out, hipStream_t s);
 // Upload the image of L from w's staging, launch every kernel and queue the copy of the
 // result records into w.h_out, all on stream s; returns without waiting.  profile: record the
 // context's timing events (synchronous calls only).

@@ -63,12 +63,15 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 
 // ---- F-operator ------------------------------------------------------------------------------
 
-// Block partials of (n, su, sv, suu, suv, svv, sz, suz, svz) over rows blockIdx.x, +gridDim.x...
+// Block partials of (n, su, sv, suu, suv, svv, sz, suz, svz) of map blockIdx.y over rows
+// blockIdx.x, +gridDim.x, ...
 template <typename T>
-__global__ void __launch_bounds__(256) plane_moments(const T *__restrict__ z, int64_t nx, int64_t ny,
+__global__ void __launch_bounds__(256) plane_moments(const T *const *__restrict__ zs, int64_t nx, int64_t ny,
                                                      double ci, double cj, double *__restrict__ part)
 {
     __shared__ double sh[4];
+    const T *__restrict__ z = zs[blockIdx.y];
+    part += (int64_t)blockIdx.y * gridDim.x * 9;
     double a[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t j = blockIdx.x; j < ny; j += gridDim.x) {
         const double v = (double)j - cj;
@@ -93,15 +96,17 @@ __global__ void __launch_bounds__(256) plane_moments(const T *__restrict__ z, in
     }
 }
 
-// Combine the partials in block order and solve the normal equations by Gaussian elimination
-// with partial pivoting.  coef = (c0, cu, cv, status): z ~ c0 + cu u + cv v; status 1, or 0
-// for fewer than three hit cells or hit cells on one line (a pivot that vanishes relative to
-// its column's diagonal).
+// One block per map: combine its nb partials in block order and solve the normal equations by
+// Gaussian elimination with partial pivoting.  coef[4 map ..] = (c0, cu, cv, status): z ~ c0 +
+// cu u + cv v; status 1, or 0 for fewer than three hit cells or hit cells on one line (a pivot
+// that vanishes relative to its column's diagonal).
 __global__ void __launch_bounds__(256) plane_solve(const double *__restrict__ part, int nb,
                                                    double *__restrict__ coef)
 {
     __shared__ double sh[4];
     __shared__ double m[9];
+    part += (int64_t)blockIdx.x * nb * 9;
+    coef += (int64_t)blockIdx.x * 4;
     for (int q = 0; q < 9; ++q) {
         double s = 0.0;
         for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[(int64_t)b * 9 + q];
@@ -142,11 +147,15 @@ __global__ void __launch_bounds__(256) plane_solve(const double *__restrict__ pa
     coef[3] = ok ? 1.0 : 0.0;
 }
 
-// out = z - plane on hit cells (+inf elsewhere); a degenerate fit leaves the values as they are.
+// out = z - plane on hit cells (+inf elsewhere) of map blockIdx.y; a degenerate fit leaves the
+// values as they are.
 template <typename T>
-__global__ void __launch_bounds__(256) plane_apply(const T *z, T *out, int64_t nx, int64_t ny,
+__global__ void __launch_bounds__(256) plane_apply(const T *const *zs, T *const *outs, int64_t nx, int64_t ny,
                                                    double ci, double cj, const double *__restrict__ coef)
 {
+    const T *z = zs[blockIdx.y];
+    T *out = outs[blockIdx.y];
+    coef += (int64_t)blockIdx.y * 4;
     const double c0 = coef[0], cu = coef[1], cv = coef[2];
     const bool ok = coef[3] != 0.0;
     for (int64_t j = blockIdx.x; j < ny; j += gridDim.x) {
@@ -167,8 +176,9 @@ __global__ void __launch_bounds__(256) plane_apply(const T *z, T *out, int64_t n
 __global__ void clear_flag(int *flag) { *flag = 0; }
 
 template <typename T>
-__global__ void __launch_bounds__(256) scan_holes(const T *__restrict__ z, int64_t n, int *flag)
+__global__ void __launch_bounds__(256) scan_holes(const T *const *__restrict__ zs, int64_t n, int *flag)
 {
+    const T *__restrict__ z = zs[blockIdx.y];
     int any = 0;
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
         any |= is_hit((double)z[k]) ? 0 : 1;
@@ -180,11 +190,13 @@ __global__ void __launch_bounds__(256) scan_holes(const T *__restrict__ z, int64
 // Without holes (every cell hit) the denominator is separable and known (the caller's
 // per-column and per-row weight sums), so only the numerator is summed and stored (double).
 template <typename T, bool HOLES>
-__global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *__restrict__ z, int64_t nx, int64_t ny,
+__global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *const *__restrict__ zs, int64_t nx, int64_t ny,
                                                           int R, int K8, const double *__restrict__ g,
                                                           double *__restrict__ nd)
 {
     extern __shared__ double lds[];
+    const T *__restrict__ z = zs[blockIdx.y];
+    nd += (int64_t)blockIdx.y * nx * ny * (HOLES ? 2 : 1);
     const int64_t tiles = (nx + kRowTile - 1) / kRowTile;
     const int L = kRowTile + K8 + 8;
     const int b = threadIdx.x * kRowOut;
@@ -256,12 +268,15 @@ __global__ void __launch_bounds__(kRowThreads) gauss_rows(const T *__restrict__ 
 // j0 = ty*64 + 16 w (kColRows = 64 rows per block).  Without holes the denominator of cell
 // (i, j) is cx[i] cy[j], the sums of the weights whose cells lie inside the grid.
 template <typename T, bool HOLES>
-__global__ void __launch_bounds__(64 * kColWaves) gauss_cols(const T *z, T *out, int64_t nx, int64_t ny,
+__global__ void __launch_bounds__(64 * kColWaves) gauss_cols(const T *const *zs, T *const *outs, int64_t nx, int64_t ny,
                                                              int R, const double *__restrict__ gc,
                                                              const double *__restrict__ cx,
                                                              const double *__restrict__ cy,
                                                              const double *__restrict__ nd, int mode)
 {
+    const T *z = zs[blockIdx.y];
+    T *out = outs[blockIdx.y];
+    nd += (int64_t)blockIdx.y * nx * ny * (HOLES ? 2 : 1);
     const int64_t tiles_x = (nx + 63) / 64, tiles_y = (ny + kColRows - 1) / kColRows;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -342,23 +357,26 @@ int64_t grid_for(int64_t items) { return items < kMaxItems ? items : kMaxItems; 
 
 }  // namespace
 
-int launch_plane(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, double *part,
-                 double *coef, void *stream)
+int launch_plane(const void *const *zin, void *const *zout, int n_maps, int64_t nx, int64_t ny,
+                 int precision, double *part, double *coef, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double ci = 0.5 * (double)(nx - 1), cj = 0.5 * (double)(ny - 1);
-    const int nb = (int)(ny < kPlaneBlocks ? ny : kPlaneBlocks);
+    const int nb = plane_blocks(ny);
+    const dim3 g2((unsigned)nb, (unsigned)n_maps);
     if (precision == FSM_F64) {
-        hipLaunchKernelGGL(plane_moments<double>, dim3(nb), dim3(256), 0, s, (const double *)zin, nx, ny, ci, cj, part);
-        hipLaunchKernelGGL(plane_solve, dim3(1), dim3(256), 0, s, (const double *)part, nb, coef);
-        hipLaunchKernelGGL(plane_apply<double>, dim3(nb), dim3(256), 0, s, (const double *)zin, (double *)zout, nx, ny, ci, cj, (const double *)coef);
+        hipLaunchKernelGGL(plane_moments<double>, g2, dim3(256), 0, s, (const double *const *)zin, nx, ny, ci, cj, part);
+        hipLaunchKernelGGL(plane_solve, dim3((unsigned)n_maps), dim3(256), 0, s, (const double *)part, nb, coef);
+        hipLaunchKernelGGL(plane_apply<double>, g2, dim3(256), 0, s, (const double *const *)zin, (double *const *)zout, nx, ny, ci, cj, (const double *)coef);
     } else {
-        hipLaunchKernelGGL(plane_moments<float>, dim3(nb), dim3(256), 0, s, (const float *)zin, nx, ny, ci, cj, part);
-        hipLaunchKernelGGL(plane_solve, dim3(1), dim3(256), 0, s, (const double *)part, nb, coef);
-        hipLaunchKernelGGL(plane_apply<float>, dim3(nb), dim3(256), 0, s, (const float *)zin, (float *)zout, nx, ny, ci, cj, (const double *)coef);
+        hipLaunchKernelGGL(plane_moments<float>, g2, dim3(256), 0, s, (const float *const *)zin, nx, ny, ci, cj, part);
+        hipLaunchKernelGGL(plane_solve, dim3((unsigned)n_maps), dim3(256), 0, s, (const double *)part, nb, coef);
+        hipLaunchKernelGGL(plane_apply<float>, g2, dim3(256), 0, s, (const float *const *)zin, (float *const *)zout, nx, ny, ci, cj, (const double *)coef);
     }
     return (int)hipGetLastError();
 }
+
+int plane_blocks(int64_t ny) { return (int)(ny < kPlaneBlocks ? ny : kPlaneBlocks); }
 
 size_t gauss_lds_bytes(int K8)
 {
@@ -366,47 +384,49 @@ size_t gauss_lds_bytes(int K8)
     return sizeof(double) * (size_t)(L + (L >> 3) + 1);
 }
 
-int launch_scan_holes(const void *zin, int64_t n, int precision, int *flag, void *stream)
+int launch_scan_holes(const void *const *zin, int n_maps, int64_t n, int precision, int *flag, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t blocks = (n + 255) / 256;
-    const dim3 gr((unsigned)(blocks < 4096 ? blocks : 4096));
+    const dim3 gr((unsigned)(blocks < 4096 ? blocks : 4096), (unsigned)n_maps);
     hipLaunchKernelGGL(clear_flag, dim3(1), dim3(1), 0, s, flag);
     if (precision == FSM_F64)
-        hipLaunchKernelGGL(scan_holes<double>, gr, dim3(256), 0, s, (const double *)zin, n, flag);
+        hipLaunchKernelGGL(scan_holes<double>, gr, dim3(256), 0, s, (const double *const *)zin, n, flag);
     else
-        hipLaunchKernelGGL(scan_holes<float>, gr, dim3(256), 0, s, (const float *)zin, n, flag);
+        hipLaunchKernelGGL(scan_holes<float>, gr, dim3(256), 0, s, (const float *const *)zin, n, flag);
     return (int)hipGetLastError();
 }
 
 namespace {
 
 template <typename T, bool HOLES>
-void gauss_pair(const void *zin, void *zout, int64_t nx, int64_t ny, int R, int K8, const double *g_row,
-                const double *g_col, const double *cx, const double *cy, void *nd, int mode, hipStream_t s)
+void gauss_pair(const void *const *zin, void *const *zout, int n_maps, int64_t nx, int64_t ny, int R, int K8,
+                const double *g_row, const double *g_col, const double *cx, const double *cy, void *nd, int mode,
+                hipStream_t s)
 {
     const int64_t row_items = ((nx + kRowTile - 1) / kRowTile) * ny;
     const int64_t col_items = ((nx + 63) / 64) * ((ny + kColRows - 1) / kColRows);
-    const dim3 gr((unsigned)grid_for(row_items)), gcol((unsigned)grid_for(col_items));
+    const dim3 gr((unsigned)grid_for(row_items), (unsigned)n_maps);
+    const dim3 gcol((unsigned)grid_for(col_items), (unsigned)n_maps);
     hipLaunchKernelGGL((gauss_rows<T, HOLES>), gr, dim3(kRowThreads), gauss_lds_bytes(K8), s,
-                       (const T *)zin, nx, ny, R, K8, g_row, (double *)nd);
-    hipLaunchKernelGGL((gauss_cols<T, HOLES>), gcol, dim3(64 * kColWaves), 0, s, (const T *)zin, (T *)zout,
-                       nx, ny, R, g_col, cx, cy, (const double *)nd, mode);
+                       (const T *const *)zin, nx, ny, R, K8, g_row, (double *)nd);
+    hipLaunchKernelGGL((gauss_cols<T, HOLES>), gcol, dim3(64 * kColWaves), 0, s, (const T *const *)zin,
+                       (T *const *)zout, nx, ny, R, g_col, cx, cy, (const double *)nd, mode);
 }
 
 }  // namespace
 
-int launch_gauss(const void *zin, void *zout, int64_t nx, int64_t ny, int precision, int R, int K8,
-                 const double *g_row, const double *g_col, const double *cx, const double *cy,
+int launch_gauss(const void *const *zin, void *const *zout, int n_maps, int64_t nx, int64_t ny, int precision,
+                 int R, int K8, const double *g_row, const double *g_col, const double *cx, const double *cy,
                  bool holes, void *nd, int mode, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64) {
-        if (holes) gauss_pair<double, true>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
-        else gauss_pair<double, false>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
+        if (holes) gauss_pair<double, true>(zin, zout, n_maps, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
+        else gauss_pair<double, false>(zin, zout, n_maps, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
     } else {
-        if (holes) gauss_pair<float, true>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
-        else gauss_pair<float, false>(zin, zout, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
+        if (holes) gauss_pair<float, true>(zin, zout, n_maps, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
+        else gauss_pair<float, false>(zin, zout, n_maps, nx, ny, R, K8, g_row, g_col, cx, cy, nd, mode, s);
     }
     return (int)hipGetLastError();
 }

@@ -228,3 +228,50 @@ def test_texture_chain_variants(ctx, ls, lc, level):
     assert_close(out, want, max(R, 8), np.abs(Z[np.isfinite(Z)]).max(), "f64")
     assert np.allclose(plane, pw, rtol=1e-9, atol=1e-12)
     assert r["Sq"] == pytest.approx(oracle.roughness(want)["Sq"], rel=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_texture_batch_matches_oracle_per_map(ctx, prec):
+    # maps with and without empty cells in one batch (the batch then sums denominators for all)
+    g = grid(260, 190, 0.002)
+    Zs = [host_input(W.synthetic_surface(g.nx, g.ny, g.dd, seed=20 + k, hole_frac=h), prec)
+          for k, h in enumerate((0.0, 0.1, 0.02, 0.0, 0.3))]
+    ls, lc = 0.01, 0.06
+    print(f"[gpu] texture batch of {len(Zs)} {prec}", flush=True)
+    outs, rs, planes = ctx.fsm_texture_batch(g, [to_dev(Z, prec) for Z in Zs], prec,
+                                             lambda_s=ls, lambda_c=lc)
+    R = int(math.floor(lc / g.dd + 1e-9))
+    for k, Z in enumerate(Zs):
+        s_out = oracle.gauss_filter(Z, g, ls)
+        if prec == "f32":
+            s_out = np.where(np.isfinite(s_out), s_out.astype(np.float32).astype(np.float64), np.inf)
+        f_out, pw = oracle.level(s_out, g)
+        if prec == "f32":
+            f_out = np.where(np.isfinite(f_out), f_out.astype(np.float32).astype(np.float64), np.inf)
+        want = oracle.gauss_filter(f_out, g, lc, highpass=True)
+        scale = np.abs(Z[np.isfinite(Z)]).max()
+        if prec == "f64":
+            assert_close(outs[k], want, R, scale, prec)
+        else:
+            got = outs[k].cpu().numpy().astype(np.float64)
+            m = np.isfinite(want)
+            assert np.array_equal(np.isfinite(got), m)
+            assert np.abs(got[m] - want[m]).max() <= 4 * float(np.spacing(np.float32(scale)))
+        assert np.allclose(planes[k], pw, rtol=1e-6 if prec == "f32" else 1e-9, atol=1e-12)
+        assert rs[k]["n_hit"] == int(np.isfinite(Z).sum())
+        assert rs[k]["Sq"] == pytest.approx(oracle.roughness(want)["Sq"], rel=1e-9 if prec == "f64" else 1e-3)
+
+
+def test_texture_batch_in_place_and_errors(ctx):
+    g = grid(120, 100, 0.002)
+    Zs = [W.synthetic_surface(g.nx, g.ny, g.dd, seed=30 + k, hole_frac=0.05) for k in range(3)]
+    zs = [to_dev(Z, "f64") for Z in Zs]
+    ref, r_ref, _ = ctx.fsm_texture_batch(g, zs, "f64", lambda_c=0.05)
+    ctx.fsm_texture_batch(g, zs, "f64", lambda_c=0.05, outs=zs)
+    for a, b in zip(zs, ref):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    bad = np.full((g.ny, g.nx), np.inf)
+    bad[3, :] = 1.0                                  # one row: no plane
+    with pytest.raises(_abi.FsmError, match="map 1"):
+        ctx.fsm_texture_batch(g, [to_dev(Zs[0], "f64"), to_dev(bad, "f64")], "f64", lambda_c=0.05)
+    assert ctx.fsm_texture_batch(g, [], "f64") == ([], [], [])
