@@ -979,6 +979,8 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
         const int64_t cap = bb.cap;
         const uint32_t e0 = (int64_t)offsets[tl] < cap ? offsets[tl] : (uint32_t)cap;
         const uint32_t e1 = (int64_t)offsets[tl + 1] < cap ? offsets[tl + 1] : (uint32_t)cap;
+        // bucket entries are read once: non-temporal loads keep them from displacing the
+        // Z-map, which the roughness passes read next
         uint32_t e = e0 + tid;
         constexpr int kDepth = 8;   // bucket entries in flight per thread
         for (; e + (kDepth - 1) * kBlock < e1; e += kDepth * kBlock) {
@@ -986,15 +988,16 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
             uint16_t c4[kDepth];
 #pragma unroll
             for (int v = 0; v < kDepth; ++v) {
-                k4[v] = bkey[e + v * kBlock];
-                c4[v] = bix[e + v * kBlock];
+                k4[v] = __builtin_nontemporal_load(&bkey[e + v * kBlock]);
+                c4[v] = __builtin_nontemporal_load(&bix[e + v * kBlock]);
             }
 #pragma unroll
             for (int v = 0; v < kDepth; ++v)
                 __hip_atomic_fetch_min(&lds[c4[v]], k4[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         for (; e < e1; e += kBlock)
-            __hip_atomic_fetch_min(&lds[bix[e]], bkey[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_min(&lds[__builtin_nontemporal_load(&bix[e])], __builtin_nontemporal_load(&bkey[e]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (tid == 0 && e1 > e0) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)(e1 - e0));
         __syncthreads();
         Stat1Acc acc;

@@ -115,7 +115,9 @@ int run_chain(fsm_ctx *ctx, const fsm_grid *grid, int precision, int n, const vo
         if (fsm::gauss_lds_bytes(c.f[k].K8) > ctx->max_lds)
             return set_err(ctx, FSM_EINVAL, "filter window too wide for the device's LDS");
     const size_t per_map = c.n_filters ? (size_t)16 * (size_t)nx * (size_t)ny : 0;
-    const int group = per_map ? (int)std::max<size_t>(1, std::min<size_t>((size_t)n, kScratchBudget / per_map)) : n;
+    // maps of a group share the launches (one grid row per map: at most 65535)
+    int group = per_map ? (int)std::max<size_t>(1, std::min<size_t>((size_t)n, kScratchBudget / per_map)) : n;
+    group = std::min(group, 65535);
     const int nb = fsm::plane_blocks(ny);
     // device: [weight tables][input and output pointer arrays][plane partials][plane
     // coefficients, 4 per map][hole flag][filter scratch of one group]
