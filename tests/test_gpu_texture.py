@@ -275,3 +275,17 @@ def test_texture_batch_in_place_and_errors(ctx):
     with pytest.raises(_abi.FsmError, match="map 1"):
         ctx.fsm_texture_batch(g, [to_dev(Zs[0], "f64"), to_dev(bad, "f64")], "f64", lambda_c=0.05)
     assert ctx.fsm_texture_batch(g, [], "f64") == ([], [], [])
+
+
+@pytest.mark.parametrize("holes", [0.0, 0.3])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (5, 3), (1100, 2), (2, 700)])
+def test_filter_degenerate_shapes(ctx, shape, holes):
+    # single rows and columns, maps smaller than the window, one row tile or column block
+    nx, ny = shape
+    g = grid(nx, ny, 0.002)
+    Z = W.synthetic_surface(nx, ny, g.dd, seed=40, hole_frac=holes)
+    Z.ravel()[0] = -0.5                               # at least one reached cell
+    for highpass in (False, True):
+        out = ctx.fsm_filter(g, to_dev(Z, "f64"), 0.03, "f64", highpass=highpass)
+        want = oracle.gauss_filter(Z, g, 0.03, highpass=highpass)
+        assert_close(out, want, 15, np.abs(Z[np.isfinite(Z)]).max(), "f64")
