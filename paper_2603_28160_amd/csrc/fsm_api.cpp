@@ -129,6 +129,10 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         std::memset(&d, 0, sizeof d);
         d.y_first = P.y_first;
         d.a_e = P.a_e;
+        d.x_start = P.x_start;
+        d.feed = P.feed;
+        d.dt = P.dt;
+        d.fixed_dt = P.fixed_dt ? 1 : 0;
         d.x_lo = P.x_lo;
         d.y_lo = P.y_lo;
         d.inv_dd = P.inv_dd;
@@ -253,7 +257,6 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         // only the precision's own angle table travels (it is per step in the fixed-step mode)
         L.cs.push_back(take(precision == FSM_F64 ? sizeof(double) * 2 * angles : 0));
         L.csf.push_back(take(precision == FSM_F32 ? sizeof(float) * 2 * angles : 0));
-        L.xc.push_back(take(sizeof(double) * (size_t)P.n_steps));
         L.gm.push_back(take(sizeof(double) * (size_t)P.z_n * P.n_groups));
     }
     L.total = o;
@@ -319,7 +322,6 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         d.pTf = reinterpret_cast<const float *>(dev + L.pTf[k]);
         d.cs = reinterpret_cast<const double *>(dev + L.cs[k]);
         d.csf = reinterpret_cast<const float *>(dev + L.csf[k]);
-        d.xc = reinterpret_cast<const double *>(dev + L.xc[k]);
         d.gm = reinterpret_cast<const double *>(dev + L.gm[k]);
         d.zmap = zmaps[k];
         ib[k] = d.item_base;
@@ -341,7 +343,6 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
             float *csf = reinterpret_cast<float *>(H(L.csf[k]));
             for (size_t q = 0; q < P.cs.size(); ++q) csf[q] = (float)P.cs[q];
         }
-        if (!P.xc.empty()) std::memcpy(H(L.xc[k]), P.xc.data(), sizeof(double) * P.xc.size());
         if (!P.gm.empty()) std::memcpy(H(L.gm[k]), P.gm.data(), sizeof(double) * P.gm.size());
     });
     std::memcpy(H(L.sims), devs.data(), sizeof(DevSim) * L.n);

@@ -17,7 +17,8 @@ namespace fsm {
 
 // Host-side plan of one simulation: the resolved path, the discretised edge and the tables
 // the kernels read.  All values are computed in double precision with libm on the host, in a
-// fixed operation order, so that the device only ever adds, subtracts and multiplies them.
+// fixed operation order, so that the device only ever adds, subtracts, multiplies and (for the
+// tool-centre position) divides them, each correctly rounded.
 struct Plan {
     int kind = 0, z_n = 0, N = 0, S = 0;
     int64_t n_passes = 0, n_steps = 0, n_evals = 0;
@@ -28,7 +29,10 @@ struct Plan {
     bool tilt_lead = false, tilt_side = false;
     std::vector<double> pT;   // [z_n][N][3] tool-frame edge points
     std::vector<double> cs;   // [z_n][S][2] cos, sin of the spindle angle alpha
-    std::vector<double> xc;   // [n_steps] tool-centre x per step
+    // tool-centre x of step s (Eq. (4), feed along X): x_start + (s fpr) / S per revolution,
+    // x_start + v_f (s dt) at a fixed time step; formed on the device in that order
+    bool fixed_dt = false;
+    double feed = 0, dt = 0;  // fpr (per revolution) or v_f (fixed step); dt
     // swept-box culling: per tooth and group of kGroup consecutive edge points, a margin that
     // bounds every point of the group over one wave of steps around its reference point's arc
     int n_groups = 0;
@@ -98,7 +102,8 @@ struct DevSim {
     const float *pTf;        // [z_n][N][4] (x, y, z, pad) single-precision copy
     const double *cs;        // [z_n][S][2]
     const float *csf;        // [z_n][S][2]
-    const double *xc;        // [n_steps]
+    double x_start, feed, dt; // tool-centre x of step s: see centre_x
+    int32_t fixed_dt, pad_c;
     void *zmap;              // the caller's Z-map
     double y_first, a_e;
     double x_lo, y_lo, inv_dd;

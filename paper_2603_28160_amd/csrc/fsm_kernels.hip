@@ -44,6 +44,15 @@ namespace {
 template <typename T>
 __device__ __forceinline__ FSM_GLOBAL T *gptr(T *p) { return (FSM_GLOBAL T *)p; }
 
+// Tool-centre x of step s (Eq. (4), feed along X) in the planner's operation order: the
+// step's share of the feed per revolution, or the feed speed times the step's time.  Double
+// division is correctly rounded on the device, so the position equals the plain definition's.
+__device__ __forceinline__ double centre_x(const DevSim &d, int64_t s)
+{
+    return d.fixed_dt ? d.x_start + d.feed * ((double)s * d.dt)
+                      : d.x_start + ((double)s * d.feed) / (double)d.S;
+}
+
 constexpr int64_t kInf64 = 0x7FF0000000000000LL;   // bits of +inf (double)
 constexpr int32_t kInf32 = 0x7F800000;             // bits of +inf (float)
 
@@ -376,8 +385,8 @@ __device__ __forceinline__ bool wave_steps(const DevSim &d, int sb, WaveSteps &w
     const int rem = d.n_steps - 1 - s0;
     w.s0 = s0;
     w.last = rem < 63 ? rem : 63;
-    w.xc0 = gptr(d.xc)[s0];
-    w.xc1 = gptr(d.xc)[s0 + w.last];
+    w.xc0 = centre_x(d, s0);
+    w.xc1 = centre_x(d, s0 + w.last);
     return true;
 }
 
@@ -442,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
                 int m = s % S;
                 for (; s < s1; s += spi) {
                     const Turn<PREC> a = spindle_turn<PREC>(d, K, m);
-                    const double xcs = gptr(d.xc)[s];
+                    const double xcs = centre_x(d, s);
                     Centre32 c32 = {};
                     if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
                     Key key;
@@ -497,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void trajectory(const DevSim *__restrict__ 
                 bp = p;
             }
         }
-        const double xcs = gptr(d.xc)[s];
+        const double xcs = centre_x(d, s);
         const double yq = d.y_first + (double)q * d.a_e;
         const int64_t o = ((int64_t)q * d.n_steps + s) * d.z_n + K;
         const double z = KeyOf<PREC>::height(KeyOf<PREC>::enc(best));
@@ -575,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
         const bool vs = lane <= w.last;
         const int s = w.s0 + (vs ? lane : w.last);
         const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
-        const double xcs = gptr(d.xc)[s];
+        const double xcs = centre_x(d, s);
         Centre32 c32 = {};
         if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
         const int sx = d.sx, sy = d.sy;
@@ -666,7 +675,7 @@ __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t 
         const bool act = lane <= w.last;
         const int s = w.s0 + (act ? lane : w.last);
         const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
-        const double xcs = gptr(d.xc)[s];
+        const double xcs = centre_x(d, s);
         Centre32 c32 = {};
         if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
         for (int g = 0; g < d.n_groups; ++g) {

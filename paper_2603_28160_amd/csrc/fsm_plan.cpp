@@ -235,15 +235,10 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
         }
     });
     // --- tool-centre x per step (Eq. (4) with the feed along X): z_n f_z per revolution, or
-    // v_f (s dt) in the fixed-step mode
-    P.xc.resize((size_t)P.n_steps);
-    const int x_chunks = (int)((P.n_steps + kChunk - 1) / kChunk);
-    parallel_for(x_chunks, [&](int job) {
-        const int64_t s0 = (int64_t)job * kChunk, s1 = std::min<int64_t>(P.n_steps, s0 + kChunk);
-        for (int64_t s = s0; s < s1; ++s)
-            P.xc[(size_t)s] = fixed_dt ? P.x_start + v_f * ((double)s * c.dt)
-                                       : P.x_start + ((double)s * fpr) / (double)S;
-    });
+    // v_f (s dt) in the fixed-step mode; the kernels form it per step
+    P.fixed_dt = fixed_dt;
+    P.feed = fixed_dt ? v_f : fpr;
+    P.dt = fixed_dt ? c.dt : 0.0;
 
     // --- culling margins.  Over the 64 consecutive steps of one wave the reference point of a
     // group turns by at most 63 steps about the tool axis (a circular arc of radius r_m, tilted

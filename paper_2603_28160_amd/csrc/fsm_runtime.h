@@ -52,7 +52,7 @@ struct SetLayout {
     size_t scratch_end = 0;
     // uploaded region
     size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0;
-    std::vector<size_t> pT, pTf, cs, csf, xc, gm;
+    std::vector<size_t> pT, pTf, cs, csf, gm;
     size_t total = 0;
 };
 
