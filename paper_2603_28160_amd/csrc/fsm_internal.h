@@ -9,6 +9,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fsm.h"
@@ -52,33 +53,40 @@ constexpr int group_ref(int g, int N)
 int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &out,
                std::string &err, bool tables = true);
 
-// f(k) for k in [0, n) on up to 16 host threads (the caller's included); the first exception
+// Persistent host threads (up to 16 with the caller's, fsm_plan.cpp).  pool_run calls
+// f(ctx, k) for k in [0, n) on them and on the calling thread and returns true; it returns
+// false, having run nothing, when the pool is busy with another caller, when the caller is
+// already inside a pool job (nested loops run inline), or in a process forked after the pool
+// started.
+bool pool_run(int n, void (*f)(void *, int), void *ctx);
+
+// f(k) for k in [0, n) on the host pool (inline when it is unavailable); the first exception
 // thrown by any f is rethrown here.
 template <typename F>
 void parallel_for(int n, F &&f)
 {
-    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-    const int T = std::min({n, hw, 16});
-    if (T <= 1 || n < 4) {
-        for (int k = 0; k < n; ++k) f(k);
-        return;
-    }
-    std::atomic<int> next{0};
-    std::exception_ptr err;
-    std::mutex m;
-    auto work = [&]() {
-        try {
-            for (int k; (k = next.fetch_add(1)) < n;) f(k);
-        } catch (...) {
-            std::lock_guard<std::mutex> g(m);
-            if (!err) err = std::current_exception();
+    using Fn = std::remove_reference_t<F>;
+    if (n >= 2) {
+        struct Job {
+            Fn *f;
+            std::exception_ptr err;
+            std::mutex m;
+        } job{&f, nullptr, {}};
+        auto call = [](void *p, int k) {
+            Job &jb = *static_cast<Job *>(p);
+            try {
+                (*jb.f)(k);
+            } catch (...) {
+                std::lock_guard<std::mutex> g(jb.m);
+                if (!jb.err) jb.err = std::current_exception();
+            }
+        };
+        if (pool_run(n, call, &job)) {
+            if (job.err) std::rethrow_exception(job.err);
+            return;
         }
-    };
-    std::vector<std::thread> pool;
-    for (int t = 1; t < T; ++t) pool.emplace_back(work);
-    work();
-    for (auto &t : pool) t.join();
-    if (err) std::rethrow_exception(err);
+    }
+    for (int k = 0; k < n; ++k) f(k);
 }
 
 constexpr int kBlock = 256;            // threads per block of every kernel

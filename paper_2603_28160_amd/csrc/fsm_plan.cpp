@@ -1,20 +1,90 @@
 // fsm_plan.cpp -- host planner of libfsm: parameter validation, edge discretisation, the
 // resolved tool path and the per-simulation tables the kernels read.
 //
-// Every quantity that needs a division, a square root or a trigonometric function is
-// computed here, once, in double precision with the C library, so the device kernels only
-// add, subtract and multiply.  The operation order of each expression is fixed (the build
-// turns off contraction into fused multiply-adds), which makes the double-precision path
-// reproduce the plain definition of the method bit for bit.
+// Every quantity that needs a square root or a trigonometric function is computed here,
+// once, in double precision with the C library, so the device kernels only add, subtract,
+// multiply and divide.  The operation order of each expression is fixed (the build turns off
+// contraction into fused multiply-adds), which makes the double-precision path reproduce the
+// plain definition of the method bit for bit.
+//
+// The file also holds the host thread pool that builds large tables (and many plans) in
+// parallel.
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <limits>
+#include <unistd.h>
 
 #include "fsm_internal.h"
 
 namespace fsm {
 namespace {
+
+// Worker threads that wait for jobs, so that a call does not pay for creating threads.
+class HostPool {
+public:
+    HostPool() : pid_(getpid())
+    {
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        const int w = std::min(hw, 16) - 1;
+        for (int i = 0; i < w; ++i) workers_.emplace_back([this] { loop(); });
+    }
+    bool run(int n, void (*f)(void *, int), void *ctx)
+    {
+        if (depth_ > 0 || workers_.empty() || getpid() != pid_) return false;
+        std::unique_lock<std::mutex> busy(busy_, std::try_to_lock);
+        if (!busy.owns_lock()) return false;
+        {
+            std::lock_guard<std::mutex> g(m_);
+            f_ = f;
+            ctx_ = ctx;
+            n_ = n;
+            next_.store(0);
+            running_ = (int)workers_.size();
+            ++gen_;
+        }
+        cv_.notify_all();
+        ++depth_;
+        work();
+        --depth_;
+        std::unique_lock<std::mutex> g(m_);
+        done_.wait(g, [this] { return running_ == 0; });
+        return true;
+    }
+
+private:
+    static thread_local int depth_;   // > 0 inside a pool job (workers always)
+    void work()
+    {
+        for (int k; (k = next_.fetch_add(1)) < n_;) f_(ctx_, k);
+    }
+    void loop()
+    {
+        depth_ = 1;
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> g(m_);
+                cv_.wait(g, [&] { return gen_ != seen; });
+                seen = gen_;
+            }
+            work();
+            std::lock_guard<std::mutex> g(m_);
+            if (--running_ == 0) done_.notify_one();
+        }
+    }
+    const pid_t pid_;
+    std::vector<std::thread> workers_;
+    std::mutex m_, busy_;
+    std::condition_variable cv_, done_;
+    void (*f_)(void *, int) = nullptr;
+    void *ctx_ = nullptr;
+    int n_ = 0, running_ = 0;
+    std::atomic<int> next_{0};
+    uint64_t gen_ = 0;
+};
+thread_local int HostPool::depth_ = 0;
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -98,6 +168,14 @@ int validate(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, std::string
 }
 
 }  // namespace
+
+bool pool_run(int n, void (*f)(void *, int), void *ctx)
+{
+    // never destroyed: its threads wait until the process ends, also in a forked child that
+    // does not own them
+    static HostPool *pool = new HostPool;
+    return pool->run(n, f, ctx);
+}
 
 int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
                std::string &err, bool tables)
@@ -220,12 +298,15 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     // m = step mod S: one (cos, sin) pair per tooth and step of a revolution.  Fixed-step
     // mode: omega t = omega (s dt) for every step s of a pass.
     // (large tables, as in the fixed-step mode, are filled in chunks on several threads)
-    constexpr int kChunk = 16384;
+    // a few thousand angles are cheaper on the calling thread than waking the pool
+    constexpr int kChunk = 4096;          // angles per pool job
+    constexpr int64_t kPoolAngles = 32768;
     P.cs.assign((size_t)Z * S * 2, 0.0);
-    const int n_chunks = (S + kChunk - 1) / kChunk;
-    parallel_for(Z * n_chunks, [&](int job) {
-        const int K = job / n_chunks, m0 = (job % n_chunks) * kChunk;
-        const int m1 = std::min(S, m0 + kChunk);
+    const int n_chunks = (int64_t)Z * S < kPoolAngles ? 1 : (S + kChunk - 1) / kChunk;
+    const int chunk = (S + n_chunks - 1) / n_chunks;
+    auto angles = [&](int job) {
+        const int K = job / n_chunks, m0 = (job % n_chunks) * chunk;
+        const int m1 = std::min(S, m0 + chunk);
         const double a = c.phi0 + tooth_angle(t, K);
         for (int m = m0; m < m1; ++m) {
             const double alpha = fixed_dt ? a - omega * ((double)m * c.dt)
@@ -233,7 +314,12 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
             P.cs[((size_t)K * S + m) * 2] = std::cos(alpha);
             P.cs[((size_t)K * S + m) * 2 + 1] = std::sin(alpha);
         }
-    });
+    };
+    if ((int64_t)Z * S < kPoolAngles) {
+        for (int K = 0; K < Z; ++K) angles(K);
+    } else {
+        parallel_for(Z * n_chunks, angles);
+    }
     // --- tool-centre x per step (Eq. (4) with the feed along X): z_n f_z per revolution, or
     // v_f (s dt) in the fixed-step mode; the kernels form it per step
     P.fixed_dt = fixed_dt;
