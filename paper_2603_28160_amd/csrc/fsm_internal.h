@@ -226,13 +226,14 @@ int launch_rough(const DevSim *d_sims, int n_sims, const int64_t *d_tile_base, i
 
 // Surface-texture operators (fsm_texture.hip), over n_maps maps of one grid at once: zin and
 // zout are device arrays of n_maps map pointers (a map may be its own output).
-// Least-squares plane over each map's hit cells, subtracted into its output.  part:
-// n_maps * plane_blocks(ny) * 9 doubles of scratch; coef: 4 doubles per map receiving (c0, cu,
-// cv, status) in centred cell units.
+// Least-squares plane over each map's hit cells, subtracted into its output, with nb blocks
+// per map (plane_blocks gives a count for a batch size; any nb in [1, ny] works).  part:
+// n_maps * nb * 9 doubles of scratch; coef: 4 doubles per map receiving (c0, cu, cv, status)
+// in centred cell units.
 constexpr int kPlanePartials = 1024 * 9;
-int plane_blocks(int64_t ny);
+int plane_blocks(int64_t ny, int n_maps);
 int launch_plane(const void *const *zin, void *const *zout, int n_maps, int64_t nx, int64_t ny,
-                 int precision, double *part, double *coef, void *stream);
+                 int precision, int nb, double *part, double *coef, void *stream);
 // flag (device int) = 1 if any of the n cells of any map is empty, else 0.
 int launch_scan_holes(const void *const *zin, int n_maps, int64_t n, int precision, int *flag, void *stream);
 // Separable normalised Gaussian of half-width R cells: g_row holds K8 (2R + 1 rounded up to a

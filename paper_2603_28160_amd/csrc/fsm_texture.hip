@@ -24,6 +24,7 @@
 // the wider type costs only LDS and L2 bytes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -179,10 +180,16 @@ template <typename T>
 __global__ void __launch_bounds__(256) scan_holes(const T *const *__restrict__ zs, int64_t n, int *flag)
 {
     const T *__restrict__ z = zs[blockIdx.y];
+    // the flag only ever goes from 0 to 1: once it is set, nothing is left to find (one
+    // thread reads it and the whole block follows, so every thread reaches the barriers)
+    if (__syncthreads_or(threadIdx.x == 0 && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0))
+        return;
     int any = 0;
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
         any |= is_hit((double)z[k]) ? 0 : 1;
-    if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(flag, 1);
+    if (__syncthreads_or(any) && threadIdx.x == 0 &&
+        __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(flag, 1);
 }
 
 // Row pass.  g[k] = w(|k - R|) for k <= 2R, zero up to K8 (a multiple of eight).
@@ -358,11 +365,10 @@ int64_t grid_for(int64_t items) { return items < kMaxItems ? items : kMaxItems; 
 }  // namespace
 
 int launch_plane(const void *const *zin, void *const *zout, int n_maps, int64_t nx, int64_t ny,
-                 int precision, double *part, double *coef, void *stream)
+                 int precision, int nb, double *part, double *coef, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double ci = 0.5 * (double)(nx - 1), cj = 0.5 * (double)(ny - 1);
-    const int nb = plane_blocks(ny);
     const dim3 g2((unsigned)nb, (unsigned)n_maps);
     if (precision == FSM_F64) {
         hipLaunchKernelGGL(plane_moments<double>, g2, dim3(256), 0, s, (const double *const *)zin, nx, ny, ci, cj, part);
@@ -376,7 +382,12 @@ int launch_plane(const void *const *zin, void *const *zout, int n_maps, int64_t 
     return (int)hipGetLastError();
 }
 
-int plane_blocks(int64_t ny) { return (int)(ny < kPlaneBlocks ? ny : kPlaneBlocks); }
+int plane_blocks(int64_t ny, int n_maps)
+{
+    // about 2048 blocks over all maps, each at least a few rows when maps are many
+    const int64_t want = std::max<int64_t>(8, std::min<int64_t>(kPlaneBlocks, 2048 / std::max(1, n_maps)));
+    return (int)(ny < want ? ny : want);
+}
 
 size_t gauss_lds_bytes(int K8)
 {
@@ -387,8 +398,9 @@ size_t gauss_lds_bytes(int K8)
 int launch_scan_holes(const void *const *zin, int n_maps, int64_t n, int precision, int *flag, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t blocks = (n + 255) / 256;
-    const dim3 gr((unsigned)(blocks < 4096 ? blocks : 4096), (unsigned)n_maps);
+    // about 8192 blocks over all maps, each striding over its map
+    const int64_t blocks = (n + 255) / 256, per_map = std::max<int64_t>(1, 8192 / n_maps);
+    const dim3 gr((unsigned)(blocks < per_map ? blocks : per_map), (unsigned)n_maps);
     hipLaunchKernelGGL(clear_flag, dim3(1), dim3(1), 0, s, flag);
     if (precision == FSM_F64)
         hipLaunchKernelGGL(scan_holes<double>, gr, dim3(256), 0, s, (const double *const *)zin, n, flag);

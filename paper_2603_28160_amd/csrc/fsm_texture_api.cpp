@@ -118,7 +118,7 @@ int run_chain(fsm_ctx *ctx, const fsm_grid *grid, int precision, int n, const vo
     // maps of a group share the launches (one grid row per map: at most 65535)
     int group = per_map ? (int)std::max<size_t>(1, std::min<size_t>((size_t)n, kScratchBudget / per_map)) : n;
     group = std::min(group, 65535);
-    const int nb = fsm::plane_blocks(ny);
+    const int nb = fsm::plane_blocks(ny, group);
     // device: [weight tables][input and output pointer arrays][plane partials][plane
     // coefficients, 4 per map][hole flag][filter scratch of one group]
     const size_t n_w = c.n_filters ? c.f[c.n_filters - 1].end : 0;
@@ -182,7 +182,7 @@ int run_chain(fsm_ctx *ctx, const fsm_grid *grid, int precision, int n, const vo
             if (rc != FSM_OK) return rc;
         }
         if (c.level) {
-            int he = fsm::launch_plane(cur, dst, cnt, nx, ny, precision,
+            int he = fsm::launch_plane(cur, dst, cnt, nx, ny, precision, nb,
                                        reinterpret_cast<double *>(dev + part_at), d_coef + 4 * (size_t)m0, s);
             if (he) return hip_err(ctx, (hipError_t)he, "plane kernels");
             cur = dst;
