@@ -357,7 +357,8 @@ int fsm_texture(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *z
  * Sec. 4.3): zmaps_in[m] -> zmaps_out[m] (device pointers; a map may be its own output),
  * out[m] its roughness, planes[3m .. 3m + 2] its removed plane (planes nullable).  The maps
  * are processed in groups whose filter scratch (16 bytes per cell and map) stays within
- * 4 GiB.  Errors as fsm_texture; a degenerate map is named in the message. */
+ * 4 GiB (a larger map forms a group of its own).  Errors as fsm_texture; a degenerate map is
+ * named in the message. */
 int fsm_texture_batch(fsm_ctx *ctx, int n, const fsm_grid *grid, int precision,
                       const void *const *zmaps_in, void *const *zmaps_out,
                       const fsm_texture_spec *spec, fsm_rough *out, double *planes, void *stream);

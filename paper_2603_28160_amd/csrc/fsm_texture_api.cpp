@@ -2,12 +2,13 @@
 // plane), areal Gaussian S- and L-filters and their chain with the roughness, applied to a
 // Z-map in device memory (the measurement practice of Sec. 4.1.1).
 //
-// The host only validates, computes the Gaussian weight tables and stages them in the
-// context's workspace; every operation on the map runs in fsm_texture.hip.
+// The host validates, computes the Gaussian weight tables, stages them with the map pointers
+// in the context's workspace and turns the solved plane into mm units; every operation on the
+// maps runs in fsm_texture.hip.
 #include <hip/hip_runtime.h>
 
-#include <cmath>
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
