@@ -41,7 +41,7 @@ def test_struct_layouts_match_header(tmp_path):
                "fsm_tune_result": _abi.FsmTuneResult, "fsm_request": _abi.FsmRequest,
                "fsm_request_result": _abi.FsmRequestResult,
                "fsm_serve_config": _abi.FsmServeConfig, "fsm_serve_model": _abi.FsmServeModel,
-               "fsm_tune_entry": _abi.FsmTuneEntry}
+               "fsm_tune_entry": _abi.FsmTuneEntry, "fsm_texture_spec": _abi.FsmTextureSpec}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
