@@ -218,6 +218,10 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
 #define FSM_OPT_AUTOTUNED 6       /* nonzero (default): a call whose workload class fsm_autotune
                                        has measured uses the parameters it kept; zero: the
                                        context's own options */
+#define FSM_OPT_ASYNC_SLOTS 7      /* asynchronous batches in flight at once, 1..16 (default 2);
+                                       FSM_EAGAIN while any is in flight */
+#define FSM_OPT_HBM_BUDGET 8       /* device bytes the workspaces of the asynchronous slots may
+                                       hold together; 0 (default): no limit */
 #define FSM_ZMAP_BINNED 0
 #define FSM_ZMAP_SCATTER 1
 
@@ -263,6 +267,26 @@ typedef struct fsm_job {
  * same shape comes again.  Returns after the work has finished. */
 int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision,
                        fsm_rough *out, void *stream);
+
+/* Asynchronous batches.  fsm_batch_submit plans the jobs (on the host, before it returns),
+ * takes a free slot of the context (its own stream and workspace), and queues the batch's
+ * upload, kernels and result copy on the slot's stream behind the work already queued on
+ * `stream`; later work on `stream` is ordered after the batch.  The host returns at once with
+ * *batch_id, so the next batch can be planned while this one runs.  The Z-maps stay borrowed
+ * until fsm_batch_wait returns; the tool, cut and grid records only for the call.
+ * FSM_EAGAIN (nothing queued) when every slot holds a batch not yet waited for, or when the
+ * slot's workspace would take the slots' workspaces beyond FSM_OPT_HBM_BUDGET; FSM_EINVAL for
+ * bad jobs as fsm_simulate_batch. */
+int fsm_batch_submit(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, void *stream,
+                     uint64_t *batch_id);
+
+/* *done = 1 if the batch has finished on the device, else 0.  FSM_EINVAL for an unknown (or
+ * already waited for) batch. */
+int fsm_batch_poll(fsm_ctx *ctx, uint64_t batch_id, int *done);
+
+/* Wait for the batch, write its n result records to out (host memory, nullable) and free its
+ * slot; the id is then no longer valid.  FSM_EINVAL for an unknown batch. */
+int fsm_batch_wait(fsm_ctx *ctx, uint64_t batch_id, fsm_rough *out);
 
 /* Launch parameters chosen by fsm_autotune. */
 typedef struct fsm_tune_result {

@@ -24,6 +24,8 @@ FLAG_SQ_ZERO, FLAG_NO_HIT, FLAG_LOW_COVERAGE = 1, 2, 4
 OPT_ZMAP_STRATEGY, OPT_BUCKET_BYTES, OPT_GRAPHS = 1, 2, 3
 OPT_TILE_SHAPE, OPT_TARGET_ROWS, OPT_AUTOTUNED = 4, 5, 6
 FILTER_SMOOTH, FILTER_ROUGH = 0, 1
+OPT_ASYNC_SLOTS, OPT_HBM_BUDGET = 7, 8
+FSM_EAGAIN = -4
 ZMAP_BINNED, ZMAP_SCATTER = 0, 1
 
 
@@ -144,6 +146,10 @@ SIGNATURES = {
                      P(FsmRough), P(C.c_double), C.c_void_p], C.c_int),
     "fsm_texture_batch": ([C.c_void_p, C.c_int, P(FsmGrid), C.c_int, P(C.c_void_p), P(C.c_void_p),
                            P(FsmTextureSpec), P(FsmRough), P(C.c_double), C.c_void_p], C.c_int),
+    "fsm_batch_submit": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, C.c_void_p, P(C.c_uint64)],
+                         C.c_int),
+    "fsm_batch_poll": ([C.c_void_p, C.c_uint64, P(C.c_int)], C.c_int),
+    "fsm_batch_wait": ([C.c_void_p, C.c_uint64, P(FsmRough)], C.c_int),
     "fsm_simulate_batch": ([C.c_void_p, C.c_int, P(FsmJob), C.c_int, P(FsmRough), C.c_void_p],
                            C.c_int),
     "fsm_trajectory": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, C.c_void_p,

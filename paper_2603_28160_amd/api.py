@@ -133,6 +133,7 @@ class Context:
     def __init__(self, device: int = 0):
         self.device = int(device)
         self._lib = _abi.load()
+        self._batches = {}   # asynchronous batch id -> number of simulations
         h = C.c_void_p()
         rc = self._lib.fsm_ctx_create(C.byref(h), self.device)
         _check(rc, "fsm_ctx_create")
@@ -328,6 +329,48 @@ class Context:
                                           C.c_void_p(_stream_handle(stream, self.device)))
         _check(rc, "fsm_simulate_batch", self._h)
         return list(zmaps), [o.as_dict() for o in out]
+
+    def fsm_batch_submit(self, sims, precision="f64", zmaps=None, stream=None):
+        """Queue many simulations as one asynchronous batch on a slot of the context; returns
+        (batch id, Z-map tensors).  The tensors must stay alive until fsm_batch_wait.  Raises
+        FsmError with code FSM_EAGAIN when no slot (or HBM budget) is free."""
+        n = len(sims)
+        if n == 0:
+            raise ValueError("an asynchronous batch needs at least one simulation")
+        if zmaps is None:
+            zmaps = [self.new_zmap(s.grid, precision) for s in sims]
+        keep = []
+        jobs = (_abi.FsmJob * n)()
+        for k, (s, z) in enumerate(zip(sims, zmaps)):
+            self._check_zmap(s.grid, precision, z)
+            t, c, g = _abi.tool_struct(s.tool), _abi.cut_struct(s.cut), _abi.grid_struct(s.grid)
+            keep += [t, c, g]
+            jobs[k].tool = C.pointer(t)
+            jobs[k].cut = C.pointer(c)
+            jobs[k].grid = C.pointer(g)
+            jobs[k].zmap_dev = z.data_ptr()
+        bid = C.c_uint64(0)
+        rc = self._lib.fsm_batch_submit(self._h, n, jobs, _prec(precision),
+                                        C.c_void_p(_stream_handle(stream, self.device)), C.byref(bid))
+        _check(rc, "fsm_batch_submit", self._h)
+        self._batches[bid.value] = n
+        return bid.value, list(zmaps)
+
+    def fsm_batch_poll(self, batch_id: int) -> bool:
+        """Whether the batch has finished on the device."""
+        done = C.c_int(0)
+        _check(self._lib.fsm_batch_poll(self._h, C.c_uint64(batch_id), C.byref(done)),
+               "fsm_batch_poll", self._h)
+        return bool(done.value)
+
+    def fsm_batch_wait(self, batch_id: int):
+        """Wait for the batch and free its slot; returns its roughness dicts in job order."""
+        n = self._batches.get(batch_id, 0)
+        out = (_abi.FsmRough * n)() if n else None   # a batch not submitted here gets no records
+        rc = self._lib.fsm_batch_wait(self._h, C.c_uint64(batch_id), out)
+        _check(rc, "fsm_batch_wait", self._h)
+        self._batches.pop(batch_id, None)
+        return [out[k].as_dict() for k in range(n)]
 
     def fsm_serve_run(self, requests, precision="f32", n_slots=2, max_batch=16, realtime=True,
                       arena_bytes=None, slot_bytes=1 << 30):

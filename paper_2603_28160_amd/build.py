@@ -45,7 +45,7 @@ def build(verbose: bool = False) -> str:
     o = os.path.join(BUILD, "fsm_sched.o")
     _run(["g++", *COMMON, "-c", os.path.join(CSRC, "fsm_sched.cpp"), "-o", o])
     objs.append(o)
-    for name in ("fsm_api", "fsm_serve", "fsm_texture_api"):
+    for name in ("fsm_api", "fsm_serve", "fsm_texture_api", "fsm_async"):
         o = os.path.join(BUILD, name + ".o")
         _run([HIPCC, *COMMON, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
               os.path.join(CSRC, name + ".cpp"), "-o", o])

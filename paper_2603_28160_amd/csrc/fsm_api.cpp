@@ -804,6 +804,7 @@ void fsm_ctx_destroy(fsm_ctx *ctx)
             if (e) hipEventDestroy(static_cast<hipEvent_t>(e));
     if (ctx->join) hipEventDestroy(ctx->join);
     if (ctx->own) hipStreamDestroy(ctx->own);
+    release_async(ctx);
     release(ctx->ws);
     delete ctx;
 }
@@ -843,6 +844,17 @@ int fsm_ctx_set_option(fsm_ctx *ctx, int option, int64_t value)
         return FSM_OK;
     case FSM_OPT_AUTOTUNED:
         ctx->use_tuned = value != 0;
+        return FSM_OK;
+    case FSM_OPT_ASYNC_SLOTS:
+        if (value < 1 || value > 16) return set_err(ctx, FSM_EINVAL, "asynchronous slots out of range 1..16");
+        for (const auto &sl : ctx->async)
+            if (sl.id) return set_err(ctx, FSM_EAGAIN, "asynchronous batches in flight");
+        release_async(ctx);
+        ctx->async_slots = (int)value;
+        return FSM_OK;
+    case FSM_OPT_HBM_BUDGET:
+        if (value < 0) return set_err(ctx, FSM_EINVAL, "negative HBM budget");
+        ctx->hbm_budget = value;
         return FSM_OK;
     default:
         return set_err(ctx, FSM_EINVAL, "unknown option");

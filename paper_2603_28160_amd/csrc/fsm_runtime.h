@@ -56,6 +56,18 @@ struct SetLayout {
     size_t total = 0;
 };
 
+// One slot of asynchronous batches (fsm_batch_submit): its own stream, workspace and events,
+// and the host plans of the batch in flight (read by its uploads until it is waited for).
+struct AsyncSlot {
+    hipStream_t stream = nullptr;
+    hipEvent_t start = nullptr, done = nullptr;
+    Workspace ws;
+    uint64_t id = 0;          // batch in flight, 0: free
+    int n = 0;
+    std::vector<Plan> plans;
+    std::vector<DevSim> devs;
+};
+
 }  // namespace rt
 }  // namespace fsm
 
@@ -79,6 +91,11 @@ struct fsm_ctx {
     hipEvent_t join = nullptr;
     std::map<std::string, hipGraphExec_t> graph_cache;
     size_t max_lds = 65536;
+    // asynchronous batches
+    std::vector<fsm::rt::AsyncSlot> async;   // created on demand, at most async_slots
+    int async_slots = 2;                     // FSM_OPT_ASYNC_SLOTS
+    int64_t hbm_budget = 0;                  // FSM_OPT_HBM_BUDGET: slot workspaces, 0: no limit
+    uint64_t next_batch = 1;
 };
 
 
@@ -101,6 +118,8 @@ bool valid_tile_shape(const fsm_ctx *ctx, int precision, int code);
 // Grow w to at least the given sizes (device workspace, host staging, result records).
 int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size_t n_out);
 void release(Workspace &w);
+// Wait for and free every asynchronous slot of the context (fsm_async.cpp).
+void release_async(fsm_ctx *ctx);
 // Roughness of existing Z-maps (device pointers) of one grid, one launch sequence; waits for
 // stream s and writes zmaps.size() records to out.
 int roughness_maps(fsm_ctx *ctx, const fsm_grid *grid, int precision, const std::vector<void *> &zmaps,
