@@ -230,7 +230,20 @@ def test_roughness_sinusoid_closed_form(ctx):
 
 # --- full-size workloads ------------------------------------------------------------------------------
 
-def test_config2_full_f64_exact(ctx):
-    # the 5000 x 5000 ball-end raster exactly as the benchmark runs it (default strategy)
-    zo = check_f64(ctx, W.config2())
-    check_f32(ctx, W.config2(), zo=zo)
+@pytest.mark.parametrize("params", ["default", "tuned"])
+def test_config2_full_f64_exact(ctx, params):
+    # the 5000 x 5000 ball-end raster with the default launch parameters, and exactly as the
+    # benchmark runs it (the shipped tuning table loaded)
+    import os
+    from paper_2603_28160_amd import _abi
+    if params == "tuned":
+        path = os.path.join(os.path.dirname(_abi.__file__), "tuning_mi355x.json")
+        assert ctx.load_tuning(path) > 0
+    else:
+        ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 0)
+    try:
+        print(f"[gpu] config2 full size, {params} launch parameters", flush=True)
+        zo = check_f64(ctx, W.config2())
+        check_f32(ctx, W.config2(), zo=zo)
+    finally:
+        ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 1)
