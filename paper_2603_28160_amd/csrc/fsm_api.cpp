@@ -26,7 +26,6 @@ namespace fsm {
 namespace rt {
 
 constexpr int kItersPerItem = 16;   // steps each thread walks per scatter item and edge point
-constexpr int kRowChunk = 32;              // rows per column-scan chunk
 constexpr int64_t kMinSliceRows = 2048;    // rows (blocks) a slice of the histogram mode keeps
 constexpr int64_t kHistBudget = (int64_t)1 << 30;   // bytes of the row matrix
 

@@ -89,6 +89,7 @@ void parallel_for(int n, F &&f)
     for (int k = 0; k < n; ++k) f(k);
 }
 
+constexpr int kRowChunk = 32;          // histogram rows per column-scan chunk
 constexpr int kBlock = 256;            // threads per block of every kernel
 constexpr int kWaves = kBlock / 64;    // waves per block
 

@@ -755,7 +755,19 @@ __global__ __launch_bounds__(kBlock) void hist_chunkscan(int64_t n_tiles, int64_
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n_tiles; t += stride) {
         uint32_t run = 0;
-        for (int64_t c = 0; c < n_chunks; ++c) {
+        int64_t c = 0;
+        // sixteen chunk sums in flight before their offsets are stored over them
+        for (; c + 16 <= n_chunks; c += 16) {
+            uint32_t v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = bb.chunk[(c + u) * n_tiles + t];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                bb.chunk[(c + u) * n_tiles + t] = run;
+                run += v[u];
+            }
+        }
+        for (; c < n_chunks; ++c) {
             const uint32_t v = bb.chunk[c * n_tiles + t];
             bb.chunk[c * n_tiles + t] = run;
             run += v;
@@ -779,11 +791,24 @@ __global__ __launch_bounds__(kBlock) void hist_apply(const DevSim *__restrict__ 
         sim_rows(d, r0 + c * bb.row_chunk, r0 + (c + 1) * bb.row_chunk < r1 ? r0 + (c + 1) * bb.row_chunk : r1, a, b);
         const int64_t lt = t - d.tile_base;
         uint32_t run = bb.chunk[x];
-        for (int64_t r = a; r < b; ++r) {
-            uint32_t *e = bb.hist + d.hbase + (r - d.row_base) * d.n_tiles + lt;
-            const uint32_t v = *e;
-            *e = run;
-            run += v;
+        uint32_t *e = bb.hist + d.hbase + (a - d.row_base) * d.n_tiles + lt;
+        const int64_t nr = b - a;
+        if (nr == kRowChunk) {
+            // the chunk's counts in flight before their offsets are stored over them
+            uint32_t v[kRowChunk];
+#pragma unroll
+            for (int u = 0; u < kRowChunk; ++u) v[u] = e[(int64_t)u * d.n_tiles];
+#pragma unroll
+            for (int u = 0; u < kRowChunk; ++u) {
+                e[(int64_t)u * d.n_tiles] = run;
+                run += v[u];
+            }
+        } else {
+            for (int64_t r = 0; r < nr; ++r) {
+                const uint32_t v = e[r * d.n_tiles];
+                e[r * d.n_tiles] = run;
+                run += v;
+            }
         }
     }
 }
