@@ -921,6 +921,32 @@ __global__ __launch_bounds__(kBlock) void scan_apply(const uint32_t *counts, int
     }
 }
 
+// The same for at most kScanSeg tiles in one block: offsets, cursors and the total.
+__global__ __launch_bounds__(kBlock) void scan_single(const uint32_t *counts, int64_t n, uint32_t *offsets,
+                                                     uint32_t *cursor)
+{
+    __shared__ uint32_t sh[4];
+    const int64_t a = (int64_t)threadIdx.x * kScanPer;
+    uint32_t c[kScanPer];
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        c[k] = a + k < n ? counts[a + k] : 0u;
+        v += c[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(v, sh, tot);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (a + k < n) {
+            offsets[a + k] = run;
+            cursor[a + k] = run;
+        }
+        run += c[k];
+    }
+    if (threadIdx.x == 0) offsets[n] = tot;
+}
+
 // Accumulator of the first roughness pass over one tile.
 struct Stat1Acc {
     double sum = 0.0, mn = INFINITY, mx = -INFINITY, row_sum = 0.0, col_sum = 0.0;
@@ -1272,6 +1298,11 @@ void stage(const StageEvents *marks, int k, hipStream_t s)
 // Exclusive scan of counts[0, n) into offsets and cursors.
 void launch_scan(int64_t n_tiles, const BinBuffers &bb, hipStream_t s)
 {
+    if (n_tiles <= kScanSeg) {
+        // one segment: one launch
+        hipLaunchKernelGGL(scan_single, dim3(1), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bb.offsets, bb.cursor);
+        return;
+    }
     const int nb = (int)((n_tiles + kScanSeg - 1) / kScanSeg);
     hipLaunchKernelGGL(scan_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t *)bb.counts, n_tiles, bb.bsum);
     hipLaunchKernelGGL(scan_top, dim3(1), dim3(kBlock), 0, s, bb.bsum, nb, bb.offsets, n_tiles);
