@@ -191,7 +191,7 @@ int fsm_refine(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, d
                fsm_tool *tool_out, fsm_cut *cut_out);
 
 /* Create a context on HIP device `device`.  The context owns the device workspace (edge,
- * angle and path tables, reduction partials, counters) and pinned host staging; they grow on
+ * angle tables, reduction partials, counters) and pinned host staging; they grow on
  * demand and are freed by fsm_ctx_destroy.  FSM_EDEVICE if the device cannot be used. */
 int fsm_ctx_create(fsm_ctx **out, int device);
 void fsm_ctx_destroy(fsm_ctx *ctx);
@@ -201,9 +201,10 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
 
 /* context options (fsm_ctx_set_option) */
 #define FSM_OPT_ZMAP_STRATEGY 1   /* how points reach the Z-map:
-                                       FSM_ZMAP_BINNED (default): bucket the points by 64 x 64
-                                       cell tile, then min-reduce each tile in LDS and store it
-                                       once; FSM_ZMAP_SCATTER: one global atomic min per point */
+                                       FSM_ZMAP_BINNED (default): bucket the points by cell
+                                       tile (FSM_OPT_TILE_SHAPE), then min-reduce each tile in
+                                       LDS and store it once; FSM_ZMAP_SCATTER: one global
+                                       atomic min per point */
 #define FSM_OPT_BUCKET_BYTES 2    /* device bytes the binned strategy may use for its point
                                        buckets (default 4 GiB); larger simulations run in
                                        slices of the evaluation range */
