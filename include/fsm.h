@@ -190,9 +190,10 @@ int fsm_edge_points(const fsm_tool *tool, const fsm_cut *cut, double *out);
 int fsm_refine(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, double spacing,
                fsm_tool *tool_out, fsm_cut *cut_out);
 
-/* Create a context on HIP device `device`.  The context owns the device workspace (edge,
- * angle tables, reduction partials, counters) and pinned host staging; they grow on
- * demand and are freed by fsm_ctx_destroy.  FSM_EDEVICE if the device cannot be used. */
+/* Create a context on HIP device `device`.  The context owns the device workspace (edge and
+ * angle tables, reduction partials, counters), the slots of asynchronous batches and pinned
+ * host staging; they grow on demand and are freed by fsm_ctx_destroy (which first waits for
+ * batches still in flight).  FSM_EDEVICE if the device cannot be used. */
 int fsm_ctx_create(fsm_ctx **out, int device);
 void fsm_ctx_destroy(fsm_ctx *ctx);
 
