@@ -1,0 +1,20 @@
+"""The C ABI from C: a C11 program built against include/fsm.h and linked to libfsm.so calls
+the host-only entry points (tests/host/abi_from_c.c).  CPU only: nothing touches a device."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2603_28160_amd")
+
+
+def test_host_calls_from_c(tmp_path):
+    if not os.path.exists(os.path.join(PKG, "libfsm.so")):
+        pytest.skip("libfsm.so not built")
+    exe = tmp_path / "abi_from_c"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "host", "abi_from_c.c"), "-L", PKG, "-lfsm",
+                    f"-Wl,-rpath,{PKG}", "-lm", "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and "OK" in r.stdout, r.stdout + r.stderr
