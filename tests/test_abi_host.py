@@ -138,6 +138,25 @@ def test_null_arguments_and_strerror():
     assert lib.fsm_tune_set(None, None, 0) == _abi.EINVAL
     assert lib.fsm_serve_dry_run(None, None, 0, None, None, None) == _abi.EINVAL
     assert lib.fsm_last_error(None, None, 0) == _abi.EINVAL
+    assert lib.fsm_level(None, None, 0, None, None, None, None) == _abi.EINVAL
+    assert lib.fsm_filter(None, None, 0, None, None, 0.8, 0.0, 0, None) == _abi.EINVAL
+    assert lib.fsm_texture(None, None, 0, None, None, None, None, None, None) == _abi.EINVAL
+    assert lib.fsm_texture_batch(None, 0, None, 0, None, None, None, None, None, None) == _abi.EINVAL
+    bid, done = C.c_uint64(0), C.c_int(0)
+    assert lib.fsm_batch_submit(None, 0, None, 0, None, C.byref(bid)) == _abi.EINVAL
+    assert lib.fsm_batch_poll(None, 1, C.byref(done)) == _abi.EINVAL
+    assert lib.fsm_batch_wait(None, 1, None) == _abi.EINVAL
+    assert lib.fsm_ctx_set_option(None, 0, 0) == _abi.EINVAL
+    assert lib.fsm_ctx_set_profiling(None, 1) == _abi.EINVAL
+    assert lib.fsm_last_timings(None, None) == _abi.EINVAL
+    assert lib.fsm_ctx_create(None, 0) == _abi.EINVAL
+    base = W.config1()
+    t, c, g = _abi.tool_struct(base.tool), _abi.cut_struct(base.cut), _abi.grid_struct(base.grid)
+    t2, c2 = _abi.FsmTool(), _abi.FsmCut()
+    assert lib.fsm_refine(None, C.byref(c), C.byref(g), 0.01, C.byref(t2), C.byref(c2)) == _abi.EINVAL
+    assert lib.fsm_refine(C.byref(t), C.byref(c), C.byref(g), 0.01, None, C.byref(c2)) == _abi.EINVAL
+    for bad in (0.0, -0.01, float("nan"), float("inf")):
+        assert lib.fsm_refine(C.byref(t), C.byref(c), C.byref(g), bad, C.byref(t2), C.byref(c2)) == _abi.EINVAL
     for code in (0, -1, -2, -3, -4, -5, -99):
         assert lib.fsm_strerror(code)
     lib.fsm_ctx_destroy(None)
