@@ -266,7 +266,8 @@ typedef struct fsm_job {
  * at once, so small and large simulations share the device (the batched form of the method,
  * used for dataset generation).  out: n host records.  With FSM_OPT_GRAPHS on, the launch
  * sequence is captured into a HIP graph keyed by its shape and replayed when a batch of the
- * same shape comes again.  Returns after the work has finished. */
+ * same shape comes again.  Returns after the work has finished.  FSM_EINVAL, naming two jobs,
+ * when their Z-maps share a byte (checked before anything is queued). */
 int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision,
                        fsm_rough *out, void *stream);
 
@@ -278,7 +279,8 @@ int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision,
  * until fsm_batch_wait returns; the tool, cut and grid records only for the call.
  * FSM_EAGAIN (nothing queued) when every slot holds a batch not yet waited for, or when the
  * slot's workspace would take the slots' workspaces beyond FSM_OPT_HBM_BUDGET; FSM_EINVAL for
- * bad jobs as fsm_simulate_batch. */
+ * bad jobs and overlapping Z-maps as fsm_simulate_batch.  Batches in flight at the same time
+ * must not share Z-maps either (not checked). */
 int fsm_batch_submit(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, void *stream,
                      uint64_t *batch_id);
 
@@ -341,9 +343,10 @@ int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void 
  * their roughness is taken (Sec. 4.1.1).  These calls apply the same operators to a predicted
  * Z-map in device memory, so that predictions and measurements are evaluated alike and a
  * dataset of maps (Sec. 4.3) carries measurement-like roughness.  Empty cells (+inf) take no
- * part and stay empty.  zmap_in and zmap_out may be the same map.  Each call waits for its
- * work on `stream` before it returns.  Scratch: 16 bytes per cell (filter) from the context's
- * workspace, which grows on demand. */
+ * part and stay empty.  zmap_in and zmap_out may be the same map; otherwise an output shares
+ * no byte with any map of the call (inputs may share bytes), else FSM_EINVAL before anything
+ * is queued.  Each call waits for its work on `stream` before it returns.  Scratch: 16 bytes
+ * per cell (filter) from the context's workspace, which grows on demand. */
 
 /* F-operator: subtract the least-squares plane z = plane[0] + plane[1] x + plane[2] y (x, y
  * the cells' node coordinates, mm) fitted over the hit cells.  plane may be NULL.

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "fsm_runtime.h"
+#include "fsm_spans.h"
 
 namespace fsm {
 namespace rt {
@@ -593,6 +594,21 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
 
 bool valid_precision(int p) { return p == FSM_F64 || p == FSM_F32; }
 
+int check_job_maps(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void *> &zmaps,
+                   int precision)
+{
+    const uintptr_t key = precision == FSM_F64 ? sizeof(double) : sizeof(float);
+    std::vector<fsm::Span> spans(zmaps.size());
+    for (size_t k = 0; k < zmaps.size(); ++k) {
+        const uintptr_t b = reinterpret_cast<uintptr_t>(zmaps[k]);
+        spans[k] = {b, b + (uintptr_t)plans[k].nx * (uintptr_t)plans[k].ny * key, (int)k, false};
+    }
+    const std::pair<int, int> o = fsm::first_conflict(std::move(spans));
+    if (o.first < 0) return FSM_OK;
+    return set_err(ctx, FSM_EINVAL, "jobs " + std::to_string(std::min(o.first, o.second)) + " and " +
+                                        std::to_string(std::max(o.first, o.second)) + ": Z-maps overlap");
+}
+
 int roughness_maps(fsm_ctx *ctx, const fsm_grid *grid, int precision, const std::vector<void *> &zmaps,
                    fsm_rough *out, hipStream_t s)
 {
@@ -964,6 +980,8 @@ int fsm_simulate_batch(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, 
         });
         for (int k = 0; k < n; ++k)
             if (rcs[k] != FSM_OK) return set_err(ctx, rcs[k], "job " + std::to_string(k) + ": " + errs[k]);
+        int rc = check_job_maps(ctx, plans, zmaps, precision);
+        if (rc != FSM_OK) return rc;
         return run_set(ctx, plans, zmaps, precision, out, static_cast<hipStream_t>(stream));
     } catch (const std::bad_alloc &) {
         return set_err(ctx, FSM_ENOMEM, "host allocation failed");
@@ -993,6 +1011,8 @@ int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tu
         });
         for (int k = 0; k < n; ++k)
             if (rcs[k] != FSM_OK) return set_err(ctx, rcs[k], "job " + std::to_string(k) + ": " + errs[k]);
+        int jrc = check_job_maps(ctx, plans, zmaps, precision);
+        if (jrc != FSM_OK) return jrc;
         hipStream_t s = static_cast<hipStream_t>(stream);
 
         // the candidates run eagerly through the tuned-table slot of this class; the guard

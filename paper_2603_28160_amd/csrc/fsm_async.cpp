@@ -103,9 +103,11 @@ int fsm_batch_submit(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, vo
         });
         for (int k = 0; k < n; ++k)
             if (rcs[k] != FSM_OK) return set_err(ctx, rcs[k], "job " + std::to_string(k) + ": " + errs[k]);
+        int rc = check_job_maps(ctx, plans, zmaps, precision);
+        if (rc != FSM_OK) return rc;
 
         AsyncSlot *slot = nullptr;
-        int rc = free_slot(ctx, slot);
+        rc = free_slot(ctx, slot);
         if (rc != FSM_OK) return rc;
         if (!slot) return set_err(ctx, FSM_EAGAIN, "every asynchronous slot holds a batch not yet waited for");
         std::vector<DevSim> devs;

@@ -120,6 +120,10 @@ int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size
 void release(Workspace &w);
 // Wait for and free every asynchronous slot of the context (fsm_async.cpp).
 void release_async(fsm_ctx *ctx);
+// FSM_EINVAL, naming two jobs, when Z-maps of one set share a byte (the set's launches write
+// them all); plans[k] gives the size of zmaps[k].
+int check_job_maps(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void *> &zmaps,
+                   int precision);
 // Roughness of existing Z-maps (device pointers) of one grid, one launch sequence; waits for
 // stream s and writes zmaps.size() records to out.
 int roughness_maps(fsm_ctx *ctx, const fsm_grid *grid, int precision, const std::vector<void *> &zmaps,

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "fsm_runtime.h"
+#include "fsm_spans.h"
 
 using namespace fsm::rt;
 
@@ -38,6 +39,30 @@ int check_common(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
     return FSM_OK;
+}
+
+// The maps of a call: an output shares no byte with another map's input or output, nor with
+// its own input unless it is that input (in place); inputs may share bytes.
+int check_maps(fsm_ctx *ctx, const fsm_grid *grid, int precision, int n, const void *const *zin,
+               void *const *zout)
+{
+    const uintptr_t bytes = (uintptr_t)grid->nx * (uintptr_t)grid->ny *
+                            (precision == FSM_F64 ? sizeof(double) : sizeof(float));
+    std::vector<fsm::Span> spans;
+    spans.reserve(2 * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(zin[m]), b = reinterpret_cast<uintptr_t>(zout[m]);
+        spans.push_back({b, b + bytes, m, false});
+        if (a != b) spans.push_back({a, a + bytes, m, true});
+    }
+    const std::pair<int, int> o = fsm::first_conflict(std::move(spans));
+    if (o.first < 0) return FSM_OK;
+    if (o.first == o.second)
+        return set_err(ctx, FSM_EINVAL, "map " + std::to_string(o.first) +
+                                            ": output overlaps its input without being the same map");
+    return set_err(ctx, FSM_EINVAL, "maps " + std::to_string(std::min(o.first, o.second)) + " and " +
+                                        std::to_string(std::max(o.first, o.second)) +
+                                        ": an output overlaps another map");
 }
 
 // Half-width in cells of the Gaussian window, or -1 when the request is invalid.
@@ -287,6 +312,7 @@ int fsm_level(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zma
     if (!ctx) return FSM_EINVAL;
     try {
         int rc = check_common(ctx, grid, precision, zmap_in, zmap_out);
+        if (rc == FSM_OK) rc = check_maps(ctx, grid, precision, 1, &zmap_in, &zmap_out);
         if (rc != FSM_OK) return rc;
         Chain c;
         c.level = true;
@@ -304,6 +330,7 @@ int fsm_filter(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zm
     if (!ctx) return FSM_EINVAL;
     try {
         int rc = check_common(ctx, grid, precision, zmap_in, zmap_out);
+        if (rc == FSM_OK) rc = check_maps(ctx, grid, precision, 1, &zmap_in, &zmap_out);
         if (rc != FSM_OK) return rc;
         if (mode != FSM_FILTER_SMOOTH && mode != FSM_FILTER_ROUGH)
             return set_err(ctx, FSM_EINVAL, "unknown filter mode");
@@ -328,6 +355,7 @@ int fsm_texture(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *z
     if (!ctx) return FSM_EINVAL;
     try {
         int rc = check_common(ctx, grid, precision, zmap_in, zmap_out);
+        if (rc == FSM_OK) rc = check_maps(ctx, grid, precision, 1, &zmap_in, &zmap_out);
         if (rc != FSM_OK) return rc;
         if (!out) return set_err(ctx, FSM_EINVAL, "no result record");
         return texture_maps(ctx, grid, precision, 1, &zmap_in, &zmap_out, spec, out, plane,
@@ -352,6 +380,8 @@ int fsm_texture_batch(fsm_ctx *ctx, int n, const fsm_grid *grid, int precision,
             int rc = check_common(ctx, grid, precision, zmaps_in[m], zmaps_out[m]);
             if (rc != FSM_OK) return rc;
         }
+        int rc = check_maps(ctx, grid, precision, n, zmaps_in, zmaps_out);
+        if (rc != FSM_OK) return rc;
         return texture_maps(ctx, grid, precision, n, zmaps_in, zmaps_out, spec, out, planes,
                             static_cast<hipStream_t>(stream));
     } catch (const std::bad_alloc &) {

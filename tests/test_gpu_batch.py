@@ -130,3 +130,27 @@ def test_batch_with_empty_and_tiny_members(Ctx):
     for k in (0, 2, 3):
         zo, _ = oracle.simulate(sims[k])
         assert np.array_equal(mb[k], zo), k
+
+
+def test_overlapping_maps_rejected(Ctx):
+    # the jobs' Z-maps of one call are written by the same launches: a shared byte is an
+    # error found on the host before anything is queued; disjoint views of one buffer are fine
+    torch = pytest.importorskip("torch")
+    sims = small_mix(2)
+    sims = [sims[0], sims[0].replace(name="copy")]
+    g = sims[0].grid
+    cells = g.nx * g.ny
+    with Ctx(0) as ctx:
+        buf = torch.empty(2 * cells + 1, dtype=torch.float64, device="cuda:0")
+        a = buf[:cells].view(g.ny, g.nx)
+        b = buf[cells - 1:2 * cells - 1].view(g.ny, g.nx)      # shares a's last cell
+        for call in (ctx.fsm_simulate_batch, ctx.fsm_batch_submit):
+            with pytest.raises(_abi.FsmError, match="jobs 0 and 1: Z-maps overlap") as e:
+                call(sims, "f64", zmaps=[a, b])
+            assert e.value.code == _abi.EINVAL
+        with pytest.raises(_abi.FsmError, match="overlap"):
+            ctx.fsm_simulate_batch(sims, "f64", zmaps=[a, a])
+        c = buf[cells:2 * cells].view(g.ny, g.nx)
+        zs, rs = ctx.fsm_simulate_batch(sims, "f64", zmaps=[a, c])
+        assert np.array_equal(zs[0].cpu().numpy(), zs[1].cpu().numpy())
+        same_rough(rs[0], rs[1])

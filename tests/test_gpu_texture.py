@@ -277,6 +277,28 @@ def test_texture_batch_in_place_and_errors(ctx):
     assert ctx.fsm_texture_batch(g, [], "f64") == ([], [], [])
 
 
+def test_texture_overlapping_maps_rejected(ctx):
+    # an output may be its own input, and inputs may be shared; an output on any other map's
+    # bytes is an error found on the host before anything is queued
+    torch = pytest.importorskip("torch")
+    g = grid(60, 50, 0.002)
+    n = g.nx * g.ny
+    Z = W.synthetic_surface(g.nx, g.ny, g.dd, seed=41, hole_frac=0.0)
+    buf = torch.empty(3 * n, dtype=torch.float64, device="cuda:0")
+    a, b, c = (buf[k * n:(k + 1) * n].view(g.ny, g.nx) for k in range(3))
+    a.copy_(torch.from_numpy(Z))
+    shifted = buf[1:n + 1].view(g.ny, g.nx)
+    with pytest.raises(_abi.FsmError, match="map 0: output overlaps its input"):
+        ctx.fsm_level(g, a, "f64", out=shifted)
+    with pytest.raises(_abi.FsmError, match="maps 0 and 1"):
+        ctx.fsm_texture_batch(g, [a, b], "f64", lambda_c=0.05, outs=[c, a])
+    with pytest.raises(_abi.FsmError, match="maps 0 and 1"):
+        ctx.fsm_texture_batch(g, [a, a], "f64", lambda_c=0.05, outs=[b, b])
+    outs, rs, _ = ctx.fsm_texture_batch(g, [a, a], "f64", lambda_c=0.05, outs=[b, c])
+    assert np.array_equal(outs[0].cpu().numpy(), outs[1].cpu().numpy())
+    assert rs[0]["Sq"] == rs[1]["Sq"]
+
+
 @pytest.mark.parametrize("holes", [0.0, 0.3])
 @pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (5, 3), (1100, 2), (2, 700)])
 def test_filter_degenerate_shapes(ctx, shape, holes):
