@@ -410,7 +410,8 @@ typedef struct fsm_request {
     double arrival_s;        /* arrival time, seconds after the start of the run */
     void *zmap_dev;          /* caller-owned device Z-map (kept), or NULL: the server holds the
                                 map in its arena while the request is in flight and returns
-                                only the roughness */
+                                only the roughness.  The caller-owned maps of one run share no
+                                byte (FSM_EINVAL from fsm_serve_run otherwise) */
 } fsm_request;
 
 typedef struct fsm_request_result {
@@ -438,8 +439,9 @@ typedef struct fsm_serve_config {
 /* Serve n requests to completion on ctx's device.  out: n records, written for every request
  * (a rejected request carries its status; the call still returns FSM_OK).  The call allocates
  * the arena and the slot workspaces once at the start and frees them at the end; nothing is
- * allocated while requests are served.  Returns FSM_EINVAL for a bad configuration, FSM_ENOMEM
- * if the arena or workspaces cannot be allocated, FSM_EDEVICE on a HIP error. */
+ * allocated while requests are served.  Returns FSM_EINVAL for a bad configuration or
+ * overlapping caller-owned Z-maps (before anything runs), FSM_ENOMEM if the arena or
+ * workspaces cannot be allocated, FSM_EDEVICE on a HIP error. */
 int fsm_serve_run(fsm_ctx *ctx, const fsm_serve_config *cfg, int n, const fsm_request *req,
                   fsm_request_result *out);
 

@@ -16,6 +16,7 @@
 
 #include "fsm_runtime.h"
 #include "fsm_sched.h"
+#include "fsm_spans.h"
 
 using namespace fsm::rt;
 using fsm::parallel_for;
@@ -305,6 +306,18 @@ int fsm_serve_run(fsm_ctx *ctx, const fsm_serve_config *cfg, int n, const fsm_re
         hipError_t e = hipSetDevice(ctx->device);
         if (e != hipSuccess) return hip_err(ctx, e, "hipSetDevice");
         Book book = book_requests(*cfg, n, req, out);
+        // requests of one run may share a batch, whose launches write all its maps
+        const uintptr_t key = cfg->precision == FSM_F64 ? sizeof(double) : sizeof(float);
+        std::vector<fsm::Span> spans;
+        for (size_t v = 0; v < book.index.size(); ++v) {
+            const uintptr_t b = reinterpret_cast<uintptr_t>(req[book.index[v]].zmap_dev);
+            if (b) spans.push_back({b, b + (uintptr_t)book.shape[v].nx * (uintptr_t)book.shape[v].ny * key,
+                                    book.index[v], false});
+        }
+        const std::pair<int, int> o = fsm::first_conflict(std::move(spans));
+        if (o.first >= 0)
+            return set_err(ctx, FSM_EINVAL, "requests " + std::to_string(std::min(o.first, o.second)) + " and " +
+                                                std::to_string(std::max(o.first, o.second)) + ": Z-maps overlap");
         DeviceExecutor ex(ctx, *cfg, req, book, out);
         int rc = ex.setup();
         if (rc != FSM_OK) return rc;

@@ -82,3 +82,21 @@ def test_rejected_request_does_not_stall_others(ctx):
         assert res[k]["status"] == 0
         _, r1 = ctx.fsm_simulate(s, "f32")
         same_rough(res[k]["rough"], r1)
+
+
+def test_overlapping_request_maps_rejected(ctx):
+    # requests of one run may share a batch: caller-owned maps that share a byte are an error
+    # found before anything runs; a map-less request beside them is unaffected by the check
+    torch = pytest.importorskip("torch")
+    reqs = mix(3, burst=3)
+    g = reqs[0][0].grid
+    cells = g.nx * g.ny
+    buf = torch.empty(cells + g.nx, dtype=torch.float32, device="cuda:0")
+    a = buf[:cells].view(g.ny, g.nx)
+    b = buf[g.nx:g.nx + cells].view(g.ny, g.nx)
+    s0, t0 = reqs[0]
+    print("[gpu] serve with overlapping maps (rejected on the host)", flush=True)
+    with pytest.raises(_abi.FsmError, match="requests 0 and 2: Z-maps overlap") as e:
+        ctx.fsm_serve_run([(s0, t0, a), (reqs[1][0], reqs[1][1], None), (s0, t0, b)], "f32",
+                          n_slots=2, max_batch=3)
+    assert e.value.code == _abi.EINVAL
