@@ -430,7 +430,8 @@ typedef struct fsm_serve_config {
     int32_t precision;       /* FSM_F64 or FSM_F32, for every request */
     int32_t n_slots;         /* batches in flight at once, 1..16 */
     int32_t max_batch;       /* simulations per batch, >= 1 */
-    int32_t realtime;        /* 1: requests arrive at arrival_s on the wall clock; 0: all at 0 */
+    int32_t realtime;        /* 1: requests arrive at arrival_s on the wall clock; 0: all at 0,
+                                queued in the order of arrival_s (ties: request order) */
     int64_t arena_bytes;     /* device bytes for server-held Z-maps (allocated once per run) */
     int64_t slot_bytes;      /* device workspace per slot (allocated once per run); batches are
                                 sized, and their buckets sliced, to fit it */
