@@ -439,8 +439,9 @@ typedef struct fsm_serve_config {
 
 /* Serve n requests to completion on ctx's device.  out: n records, written for every request
  * (a rejected request carries its status; the call still returns FSM_OK).  The call allocates
- * the arena and the slot workspaces once at the start and frees them at the end; nothing is
- * allocated while requests are served.  Returns FSM_EINVAL for a bad configuration or
+ * the arena and the slot workspaces once at the start and frees them at the end; no device
+ * memory is allocated while requests are served (each slot's pinned host staging grows to the
+ * largest batch image it has carried).  Returns FSM_EINVAL for a bad configuration or
  * overlapping caller-owned Z-maps (before anything runs), FSM_ENOMEM if the arena or
  * workspaces cannot be allocated, FSM_EDEVICE on a HIP error. */
 int fsm_serve_run(fsm_ctx *ctx, const fsm_serve_config *cfg, int n, const fsm_request *req,
