@@ -267,10 +267,10 @@ int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size
 {
     if (w.d_bytes < dev_bytes) {
         if (w.d_ws) {
-            hipFree(w.d_ws);
+            (void)hipFree(w.d_ws);
             if (&w == &ctx->ws) {
                 // captured graphs point into the old workspace
-                for (auto &g : ctx->graph_cache) hipGraphExecDestroy(g.second);
+                for (auto &g : ctx->graph_cache) (void)hipGraphExecDestroy(g.second);
                 ctx->graph_cache.clear();
             }
         }
@@ -281,7 +281,7 @@ int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size
         w.d_bytes = dev_bytes;
     }
     if (w.h_bytes < host_bytes) {
-        if (w.h_ws) hipHostFree(w.h_ws);
+        if (w.h_ws) (void)hipHostFree(w.h_ws);
         w.h_ws = nullptr;
         w.h_bytes = 0;
         hipError_t e = hipHostMalloc(&w.h_ws, host_bytes, hipHostMallocDefault);
@@ -289,7 +289,7 @@ int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size
         w.h_bytes = host_bytes;
     }
     if (w.h_out_n < n_out) {
-        if (w.h_out) hipHostFree(w.h_out);
+        if (w.h_out) (void)hipHostFree(w.h_out);
         w.h_out = nullptr;
         w.h_out_n = 0;
         hipError_t e = hipHostMalloc((void **)&w.h_out, sizeof(fsm_rough) * n_out, hipHostMallocDefault);
@@ -301,9 +301,9 @@ int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size
 
 void release(Workspace &w)
 {
-    if (w.d_ws) hipFree(w.d_ws);
-    if (w.h_ws) hipHostFree(w.h_ws);
-    if (w.h_out) hipHostFree(w.h_out);
+    if (w.d_ws) (void)hipFree(w.d_ws);
+    if (w.h_ws) (void)hipHostFree(w.h_ws);
+    if (w.h_out) (void)hipHostFree(w.h_out);
     w = Workspace();
 }
 
@@ -355,7 +355,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
 
 void mark(fsm_ctx *ctx, int k, hipStream_t s, bool capturing)
 {
-    if (ctx->profiling && !capturing) hipEventRecord(ctx->ev[k], s);
+    if (ctx->profiling && !capturing) (void)hipEventRecord(ctx->ev[k], s);
 }
 
 // Stage events of binned slice k of a profiled eager call (nullptr otherwise).
@@ -565,11 +565,11 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
             rc = launch_set(ctx, L, devs, plans, dev, s, true);
             hipGraph_t g = nullptr;
             hipError_t e2 = hipStreamEndCapture(s, &g);
-            if (rc != FSM_OK) { if (g) hipGraphDestroy(g); return rc; }
+            if (rc != FSM_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
             if (e2 != hipSuccess) return hip_err(ctx, e2, "hipStreamEndCapture");
             hipGraphExec_t x = nullptr;
             e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             if (e != hipSuccess) return hip_err(ctx, e, "hipGraphInstantiate");
             it = ctx->graph_cache.emplace(k, x).first;
         }
@@ -810,15 +810,15 @@ int fsm_ctx_create(fsm_ctx **out, int device)
 void fsm_ctx_destroy(fsm_ctx *ctx)
 {
     if (!ctx) return;
-    hipSetDevice(ctx->device);
-    for (auto &g : ctx->graph_cache) hipGraphExecDestroy(g.second);
+    (void)hipSetDevice(ctx->device);
+    for (auto &g : ctx->graph_cache) (void)hipGraphExecDestroy(g.second);
     for (auto &ev : ctx->ev)
-        if (ev) hipEventDestroy(ev);
+        if (ev) (void)hipEventDestroy(ev);
     for (auto &m : ctx->stage_ev)
         for (void *e : m.ev)
-            if (e) hipEventDestroy(static_cast<hipEvent_t>(e));
-    if (ctx->join) hipEventDestroy(ctx->join);
-    if (ctx->own) hipStreamDestroy(ctx->own);
+            if (e) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->own) (void)hipStreamDestroy(ctx->own);
     release_async(ctx);
     release(ctx->ws);
     delete ctx;

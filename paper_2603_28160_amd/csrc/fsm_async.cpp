@@ -26,10 +26,10 @@ namespace rt {
 void release_async(fsm_ctx *ctx)
 {
     for (AsyncSlot &s : ctx->async) {
-        if (s.id && s.done) hipEventSynchronize(s.done);
-        if (s.start) hipEventDestroy(s.start);
-        if (s.done) hipEventDestroy(s.done);
-        if (s.stream) hipStreamDestroy(s.stream);
+        if (s.id && s.done) (void)hipEventSynchronize(s.done);
+        if (s.start) (void)hipEventDestroy(s.start);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
         release(s.ws);
     }
     ctx->async.clear();
@@ -66,8 +66,8 @@ int free_slot(fsm_ctx *ctx, AsyncSlot *&out)
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.start, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
     if (e != hipSuccess) {
-        if (s.start) hipEventDestroy(s.start);
-        if (s.stream) hipStreamDestroy(s.stream);
+        if (s.start) (void)hipEventDestroy(s.start);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
         ctx->async.pop_back();
         return hip_err(ctx, e, "slot stream or events");
     }
@@ -134,7 +134,7 @@ int fsm_batch_submit(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, vo
         }
         if (rc != FSM_OK) {
             // whatever was queued finishes before the slot is reused
-            hipStreamSynchronize(slot->stream);
+            (void)hipStreamSynchronize(slot->stream);
             slot->plans.clear();
             slot->devs.clear();
             return rc;

@@ -149,13 +149,13 @@ public:
     void teardown()
     {
         for (Slot &s : slots_) {
-            if (s.stream) hipStreamSynchronize(s.stream);
-            if (s.done) hipEventDestroy(s.done);
-            if (s.stream) hipStreamDestroy(s.stream);
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
+            if (s.done) (void)hipEventDestroy(s.done);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
             release(s.ws);
             s = Slot();
         }
-        if (arena_) hipFree(arena_);
+        if (arena_) (void)hipFree(arena_);
         arena_ = nullptr;
     }
 
