@@ -8,7 +8,6 @@ from __future__ import annotations
 
 import contextlib
 import ctypes as C
-import math
 import os
 import subprocess
 import threading

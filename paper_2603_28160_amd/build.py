@@ -11,7 +11,6 @@ calls in the planner.  Packed FP32 instructions are disabled for device code.
 from __future__ import annotations
 
 import os
-import shutil
 import subprocess
 import sys
 

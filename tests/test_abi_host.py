@@ -3,7 +3,6 @@ declares, the ctypes mirror matches the C struct layouts, the host planner repro
 oracle's edge points and path bit for bit, and bad arguments come back as status codes."""
 import ctypes as C
 import dataclasses
-import math
 import os
 import re
 import subprocess

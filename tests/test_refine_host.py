@@ -2,14 +2,13 @@
 kinematics: after refinement, neighbouring edge points and consecutive time steps of every edge
 point lie within the requested spacing, and the swept band of a small face-milling pass is
 covered completely where the unrefined plan leaves holes."""
-import dataclasses
 import math
 
 import numpy as np
 import pytest
 
 import oracle
-from paper_2603_28160_amd import _abi, fsm_plan, fsm_refine, workloads as W
+from paper_2603_28160_amd import _abi, fsm_refine, workloads as W
 
 
 def small_face_mill():
