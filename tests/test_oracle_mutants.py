@@ -22,6 +22,12 @@ MUTANTS = [
     ("rotation sense of Eq. (3)",
      [("M[0][0] = ca;  M[0][1] = sa;\n    M[1][0] = -sa; M[1][1] = ca;",
        "M[0][0] = ca;  M[0][1] = -sa;\n    M[1][0] = sa; M[1][1] = ca;")]),
+    ("per-insert radial offset inward",
+     [("M[0][3] = off + t->eps_r[K];", "M[0][3] = off - t->eps_r[K];")]),
+    ("per-insert axial offset upward",
+     [("M[2][3] = t->eps_a[K];", "M[2][3] = -t->eps_a[K];")]),
+    ("variable pitch ignored",
+     [("if (t->uniform_pitch) return", "if (1) return")]),
     ("tooth phase sign",
      [("return ((2.0 * M_PI) * (double)K) / (double)t->n_teeth;",
        "return -((2.0 * M_PI) * (double)K) / (double)t->n_teeth;")]),
