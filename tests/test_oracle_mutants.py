@@ -28,6 +28,13 @@ MUTANTS = [
      [("M[2][3] = t->eps_a[K];", "M[2][3] = -t->eps_a[K];")]),
     ("variable pitch ignored",
      [("if (t->uniform_pitch) return", "if (1) return")]),
+    ("peak height from zero, not from the mean",
+     [("r->Sp = mx - mu;", "r->Sp = mx;")]),
+    ("arithmetic mean deviation without the absolute value",
+     [("s1 += fabs(d);", "s1 += d;")]),
+    ("feed-direction profile taken along a column",
+     [("profile_ra(Z, (ny / 2) * nx, 1, nx, &r->Ra_feed, &r->n_feed);",
+       "profile_ra(Z, nx / 2, nx, ny, &r->Ra_feed, &r->n_feed);")]),
     ("tooth phase sign",
      [("return ((2.0 * M_PI) * (double)K) / (double)t->n_teeth;",
        "return -((2.0 * M_PI) * (double)K) / (double)t->n_teeth;")]),
