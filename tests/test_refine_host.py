@@ -67,3 +67,34 @@ def test_refine_rejects_bad_requests():
             fsm_refine(s, spacing)
     with pytest.raises(_abi.FsmError):          # would need more than 4096 edge points
         fsm_refine(W.config2(), 0.0005)
+
+
+hyp = pytest.importorskip("hypothesis")
+from hypothesis import HealthCheck, given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(st.integers(0, 10_000), st.floats(0.002, 0.05), st.booleans())
+def test_spacing_bound_holds_on_drawn_tools(index, spacing, fixed_step):
+    # the bound of the refined plan for any drawn tool of the batch mix (round or ball, helix,
+    # eccentric runout, lead tilt) or of the paper's fixed-step conditions, with the oracle's
+    # own kinematics: neighbouring edge points, and one step of the outermost and end points
+    s = W.paper_mode(1 + index % 9, dd=0.05) if fixed_step else W.random_sim(3, index)
+    try:
+        r = fsm_refine(s, spacing)
+    except _abi.FsmError as e:
+        assert e.code == _abi.EINVAL                # beyond 4096 edge points or 2^24 steps
+        hyp.event("refused")
+        return
+    hyp.event("refined")
+    _, pT = oracle.edge_points(r)
+    assert np.linalg.norm(np.diff(pT, axis=1), axis=2).max() <= spacing
+    radius = np.hypot(pT[..., 0], pT[..., 1])
+    S = r.cut.steps_per_rev
+    for K in range(r.tool.n_teeth):
+        for p in {int(np.argmax(radius[K])), 0, r.tool.n_edge - 1}:
+            for st_ in (0, 1, S // 3, S + 7):
+                a = oracle.point(r, 0, st_, K, p)
+                b = oracle.point(r, 0, st_ + 1, K, p)
+                assert math.hypot(*(b - a)[:2]) <= spacing, (K, p, st_)
