@@ -364,12 +364,15 @@ def roofline(sim, plan, prec, prof):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["f64", "f32", "both"], default="both")
-    ap.add_argument("--strategy", choices=["binned", "scatter"], default="binned")
+    ap.add_argument("--gpus", type=int, default=1, help="GPUs to use; only 1 is supported")
+    ap.add_argument("--steps", type=int, default=10, help="timed steps (one simulation each)")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed steps before the timed ones")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip timing the CPU oracle on a sample of the workload")
+    ap.add_argument("--precision", choices=["f64", "f32", "both"], default="both",
+                    help="precision of the value (f64) and of the reported FP32 line")
+    ap.add_argument("--strategy", choices=["binned", "scatter"], default="binned",
+                    help="Z-map strategy of the timed steps")
     ap.add_argument("--compare-strategies", action="store_true",
                     help="also time the other Z-map strategy (reported, not the value)")
     ap.add_argument("--graphs", action="store_true",
@@ -384,16 +387,17 @@ def main():
     ap.add_argument("--extras", default="all",
                     help="comma-separated extra legs to run (default all): batch, serving, "
                          "large_field, paper_mode, coverage_complete, dataset")
-    ap.add_argument("--batch-sims", type=int, default=256)
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-rate", type=float, default=500.0)
+    ap.add_argument("--batch-sims", type=int, default=256, help="simulations in the batch leg")
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests in the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=500.0,
+                    help="Poisson arrival rate of the serving leg, requests/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reads 1 GiB, writes "
                          "1 GiB) five times, to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(simulations shard across GPUs without communication; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (independent "
+              "simulations would shard across GPUs, one process each, without communication)",
               file=sys.stderr)
         sys.exit(2)
 
