@@ -100,6 +100,11 @@ MUTANTS = [
      [("w[a < 0 ? -a : a] * w[b < 0 ? -b : b]", "w[a < 0 ? -a : a] * w[a < 0 ? -a : a]")]),
     ("empty cells weighted in the filter",
      [("            if (!(v < INFINITY)) continue;\n", "")]),
+    ("Gaussian window one cell short on the right",
+     [("for (long long a = -R; a <= R; ++a) {", "for (long long a = -R; a < R; ++a) {")]),
+    ("Gaussian border renormalised as if columns beyond the right edge were hit",
+     [("if (ii < 0 || ii >= g->nx) continue;",
+       "if (ii < 0) continue;\n            if (ii >= g->nx) { den += w[a < 0 ? -a : a] * w[b < 0 ? -b : b]; continue; }")]),
     ("high-pass sign",
      [("return mode == 0 ? mean : z - mean;", "return mode == 0 ? mean : mean - z;")]),
     ("plane y term evaluated at the column",

@@ -2,8 +2,8 @@
 S-/L-filter of the measurement practice in Sec. 4.1.1), checked against what mathematics fixes:
 exact planes and moment-free patterns, orthogonality of least-squares residuals, the Gaussian
 filter's defining 50 % transmission at the cut-off wavelength, its transmission at other
-wavelengths, invariance of constants and planes, holes, and scipy's Gaussian filter on the
-interior.  CPU only."""
+wavelengths, invariance of constants and planes, holes, symmetry under mirroring and
+transposition, linearity, and scipy's Gaussian filter on the interior.  CPU only."""
 import math
 
 import numpy as np
@@ -164,6 +164,54 @@ def test_gaussian_interior_equals_scipy():
     ref = ndimage.gaussian_filter(Z, sigma, truncate=R / sigma, mode="constant")
     inner = (slice(R, g.ny - R), slice(R, g.nx - R))
     assert np.abs(out[inner] - ref[inner]).max() < 1e-13
+
+
+def test_gaussian_commutes_with_flips_and_transposition():
+    # symmetric weights, renormalised over the hit cells of a square window: mirroring the map
+    # (holes included) mirrors the result, and so does swapping the axes
+    rng = np.random.default_rng(12)
+    g = grid(37, 23, 0.01)
+    Z = rng.normal(size=(g.ny, g.nx))
+    Z[rng.random(Z.shape) < 0.15] = np.inf
+    for hp in (False, True):
+        out = oracle.gauss_filter(Z, g, 0.06, highpass=hp)
+        pairs = ((oracle.gauss_filter(Z[:, ::-1], g, 0.06, highpass=hp), out[:, ::-1]),
+                 (oracle.gauss_filter(Z[::-1, :], g, 0.06, highpass=hp), out[::-1, :]),
+                 (oracle.gauss_filter(Z.T, grid(g.ny, g.nx, g.dd), 0.06, highpass=hp), out.T))
+        for a, b in pairs:
+            assert np.array_equal(np.isinf(a), np.isinf(b))
+            m = np.isfinite(b)
+            assert np.abs(a[m] - b[m]).max() < 1e-13
+
+
+def test_gaussian_is_linear_for_one_hole_set():
+    rng = np.random.default_rng(13)
+    g = grid(31, 26, 0.01)
+    holes = rng.random((g.ny, g.nx)) < 0.1
+    Z1, Z2 = rng.normal(size=(2, g.ny, g.nx))
+    mix = 2.5 * Z1 - 0.75 * Z2
+    for Z in (Z1, Z2, mix):
+        Z[holes] = np.inf
+    for hp in (False, True):
+        lhs = oracle.gauss_filter(mix, g, 0.05, highpass=hp)
+        f1, f2 = (oracle.gauss_filter(Z, g, 0.05, highpass=hp)[~holes] for Z in (Z1, Z2))
+        assert np.array_equal(np.isinf(lhs), holes)
+        assert np.abs(lhs[~holes] - (2.5 * f1 - 0.75 * f2)).max() < 1e-13
+
+
+def test_level_residual_ignores_an_added_plane():
+    # the least-squares residual of Z + plane is that of Z, and the fitted plane moves by it
+    rng = np.random.default_rng(14)
+    g = grid(25, 19, 0.02, x0=-0.3, y0=0.1)
+    X, Y = nodes(g)
+    Z = rng.normal(0.0, 0.01, (g.ny, g.nx))
+    Z[rng.random(Z.shape) < 0.2] = np.inf
+    r0, c0 = oracle.level(Z, g)
+    r1, c1 = oracle.level(Z + (0.4 - 0.7 * X + 0.2 * Y), g)
+    m = np.isfinite(Z)
+    assert np.array_equal(np.isfinite(r1), m)
+    assert np.abs(r1[m] - r0[m]).max() < 1e-13
+    np.testing.assert_allclose(np.subtract(c1, c0), [0.4, -0.7, 0.2], atol=1e-12)
 
 
 def test_gaussian_cells_variant_and_zero_radius():
