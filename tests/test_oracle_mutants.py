@@ -35,6 +35,11 @@ MUTANTS = [
     ("feed-direction profile taken along a column",
      [("profile_ra(Z, (ny / 2) * nx, 1, nx, &r->Ra_feed, &r->n_feed);",
        "profile_ra(Z, nx / 2, nx, ny, &r->Ra_feed, &r->n_feed);")]),
+    ("eccentric runout phased by the uniform pitch for variable-pitch teeth",
+     [("const double ph = t->ecc_phase + tooth_angle(t, K);",
+       "const double ph = t->ecc_phase + ((2.0 * M_PI) * (double)K) / (double)t->n_teeth;")]),
+    ("per-insert offsets taken by position, not by insert",
+     [("M[0][3] = off + t->eps_r[K];", "M[0][3] = off + (double)K * t->eps_r[1];")]),
     ("tooth phase sign",
      [("return ((2.0 * M_PI) * (double)K) / (double)t->n_teeth;",
        "return -((2.0 * M_PI) * (double)K) / (double)t->n_teeth;")]),

@@ -161,6 +161,30 @@ def test_variable_pitch():
         assert ang == pytest.approx((-a) % 360.0, abs=1e-9)
 
 
+def test_teeth_are_interchangeable():
+    # the Z-map is a minimum over all teeth: listing variable-pitch teeth (each with its own
+    # per-insert offsets) in another order changes nothing, bit for bit, and a tool whose teeth
+    # repeat cuts exactly like the tool without the repeats at the same feed per revolution
+    th, er, ea = (0.0, 1.7, 3.3, 4.9), (0.0, 0.004, -0.002, 0.003), (0.0, 0.001, 0.002, -0.001)
+    cut = W.Cut(f_z=0.0625, a_p=0.5, steps_per_rev=720, n_passes=1, n_steps=1440, x_start=-0.25,
+                y_first=-5.0)
+    grid = W.centred_grid(24, 24, 0.1)
+
+    def zmap(theta, eps_r, eps_a, f_z):
+        t = simple_round(n_teeth=len(theta), n_edge=41, helix=0.3, runout_ecc=0.003,
+                         runout_phase=0.8, theta=theta, eps_r=eps_r, eps_a=eps_a)
+        return oracle.simulate(W.Sim(t, dataclasses.replace(cut, f_z=f_z), grid))[0]
+
+    z0 = zmap(th, er, ea, 0.0625)
+    assert np.isfinite(z0).mean() > 0.3
+    perm = (2, 0, 3, 1)
+    pick = lambda v: tuple(v[k] for k in perm)  # noqa: E731
+    assert np.array_equal(zmap(pick(th), pick(er), pick(ea), 0.0625), z0)
+    two = zmap(th[:2], er[:2], ea[:2], 0.125)
+    assert np.array_equal(zmap(th[:2] * 2, er[:2] * 2, ea[:2] * 2, 0.0625), two)
+    assert not np.array_equal(two, z0)
+
+
 def test_feed_and_pass_offsets():
     t = simple_round(n_teeth=3, n_edge=5)
     S = 200
