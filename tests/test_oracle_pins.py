@@ -485,6 +485,22 @@ def test_adding_pass_never_raises():
     assert np.all(Zb <= Za)
 
 
+def test_passes_combine_by_the_cell_minimum():
+    # a raster of passes is the cell-wise minimum of its passes run one at a time, bit for bit:
+    # pass q sits at y_first + q a_e, the same double either way
+    s = W.config2(nx=40, ny=30, dd=0.05)
+    pl = oracle.plan(s)
+    q0 = pl["n_passes"] // 2 - 2
+    y0 = pl["y_first"] + float(q0) * s.cut.a_e
+    base = dataclasses.replace(s.cut, x_start=pl["x_start"], n_steps=pl["n_steps"], y_first=y0)
+    Z4, _ = oracle.simulate(s.replace(cut=dataclasses.replace(base, n_passes=4)))
+    singles = [oracle.simulate(s.replace(cut=dataclasses.replace(
+        base, n_passes=1, y_first=y0 + float(q) * s.cut.a_e)))[0] for q in range(4)]
+    assert np.array_equal(Z4, np.minimum.reduce(singles))
+    assert np.isfinite(Z4).mean() > 0.2
+    assert all(not np.array_equal(Z4, Zq) for Zq in singles)
+
+
 # --- roughness (closed forms) -----------------------------------------------------------------------
 
 def test_roughness_sinusoid():
