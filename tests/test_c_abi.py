@@ -1,5 +1,6 @@
-"""The C ABI from C: a C11 program built against include/fsm.h and linked to libfsm.so calls
-the host-only entry points (tests/host/abi_from_c.c).  CPU only: nothing touches a device."""
+"""The C ABI from C and C++: a C11 program built against include/fsm.h and linked to
+libfsm.so calls the host-only entry points (tests/host/abi_from_c.c), a C++ caller links with
+C linkage, and the header is plain C99.  CPU only: nothing touches a device."""
 import os
 import subprocess
 
