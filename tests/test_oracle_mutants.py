@@ -93,6 +93,8 @@ MUTANTS = [
        "return (c->f_z * spindle_rpm(t, c)) / 60.0;")]),
     ("trajectory counts per step, not per tooth and step",
      [("return (long long)z_n * steps;", "return steps;")]),
+    ("trajectory ties won by the last point",
+     [("if (w[2] < best[2]) {", "if (w[2] <= best[2]) {")]),
     ("trajectory keeps the highest point",
      [("                    if (w[2] < best[2]) {", "                    if (!(w[2] <= best[2]) || bp < 0) {")]),
     ("interval: every candidate counted as certain",

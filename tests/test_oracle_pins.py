@@ -597,6 +597,36 @@ def test_trajectory_of_an_upright_ball_is_the_centre_path():
     assert np.all(np.abs(xyz[..., 2]) <= 1e-15)
 
 
+def test_trajectory_ties_take_the_first_point():
+    # a two-point round edge without rake, helix, runout or tilt has its points at l = -dL and
+    # +dL, mirror images at the same height: every step and tooth is a tie, won by point 0
+    t = W.Tool(kind=W.ROUND, n_teeth=2, n_edge=2, D=10.0, R_edge=5.0)
+    c = W.Cut(f_z=0.1, a_p=0.5, steps_per_rev=40, n_passes=1, n_steps=80, x_start=0.0,
+              y_first=0.0)
+    s = W.Sim(t, c, W.centred_grid(6, 6, 0.1))
+    _, pT = oracle.edge_points(s)
+    assert pT[0, 0, 2] == pT[0, 1, 2]
+    _, idx = oracle.trajectory(s)
+    assert np.all(idx == 0)
+
+
+def test_trajectory_is_the_lowest_of_the_placed_points():
+    # with every extension on, each entry is the lowest of the tooth's points placed one by one
+    t = W.Tool(kind=W.ROUND, n_teeth=3, n_edge=15, D=8.0, R_edge=2.0, helix=0.5,
+               rake_radial=0.1, rake_axial=-0.05, runout_ecc=0.004, runout_phase=1.1,
+               tilt_lead=0.2, tilt_side=-0.1)
+    c = W.Cut(f_z=0.15, a_p=0.6, steps_per_rev=50, n_passes=2, a_e=0.4, n_steps=60,
+              x_start=-0.5, y_first=0.1)
+    s = W.Sim(t, c, W.centred_grid(6, 6, 0.1))
+    xyz, idx = oracle.trajectory(s)
+    for q, st, K in ((0, 0, 0), (0, 17, 2), (1, 33, 1), (1, 59, 0)):
+        pts = np.array([oracle.point(s, q, st, K, p) for p in range(t.n_edge)])
+        p = int(np.argmin(pts[:, 2]))
+        assert idx[q, st, K] == p
+        assert np.array_equal(xyz[q, st, K], pts[p])
+    assert len(np.unique(idx)) > 1
+
+
 def test_trajectory_tilted_ball_bottom():
     # a ball tilted by tau touches lowest R (1 - cos tau) below the tip height, a point of the
     # sphere off the axis: the trajectory's z is that constant (to the meridian sampling)
