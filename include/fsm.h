@@ -90,7 +90,9 @@ typedef struct fsm_tool {
 
 typedef struct fsm_cut {
     double f_z;              /* feed per tooth, >= 0 */
-    double a_p;              /* axial depth of cut, > 0 (sets the engaged edge length) */
+    double a_p;              /* axial depth of cut, > 0 (sets the engaged edge length; a round
+                                edge's chord is capped at R_edge, so a_p >= R_edge engages
+                                the whole half profile) */
     double a_e;              /* stepover between parallel passes; <= 0: one pass */
     double phi0;             /* initial phase angle phi of Eq. (3) */
     int32_t steps_per_rev;   /* S, time steps per spindle revolution, >= 1 (FSM_TIME_PER_REV) */
