@@ -47,7 +47,9 @@ extern "C" {
 #define FSM_ENOMEM (-2)   /* host or device allocation failed */
 #define FSM_EDEVICE (-3)  /* HIP runtime error (message kept in the context) */
 #define FSM_EAGAIN (-4)   /* batch admission refused: memory budget or slots exhausted */
-#define FSM_ENOTSUP (-5)  /* valid request the library does not support */
+#define FSM_ENOTSUP (-5)  /* reserved for valid requests the library cannot serve; ABI
+                             version 1 reports its limits (edge points, window width) as
+                             FSM_EINVAL */
 
 /* precision of the Z-map and of the edge-point arithmetic */
 #define FSM_F64 0  /* every operation in double precision; binning bit-exact with the plain
