@@ -83,8 +83,10 @@ typedef struct fsm_tool {
     double runout_ecc;       /* eccentric runout: offset e of the cutter body from the
                                 spindle axis */
     double runout_phase;     /* its direction lambda in the cutter body */
-    double eps_r[FSM_MAX_TEETH];   /* per-insert radial offset ((K-1)*eps_r of Eq. (2)) */
-    double eps_a[FSM_MAX_TEETH];   /* per-insert axial offset ((K-1)*eps_a of Eq. (2)) */
+    double eps_r[FSM_MAX_TEETH];   /* radial offset of each insert, added to D/2 in Eq. (2)
+                                      (the paper's (K-1)*eps_r, given per tooth) */
+    double eps_a[FSM_MAX_TEETH];   /* axial offset of each insert in Eq. (2) (the paper's
+                                      (K-1)*eps_a, given per tooth) */
     double tilt_lead;        /* tool tilt about the workpiece Y axis; positive lowers the
                                 leading (+X) side */
     double tilt_side;        /* tool tilt about the workpiece X axis; positive raises +Y */
@@ -147,8 +149,10 @@ typedef struct fsm_rough {
     uint32_t reserved;
 } fsm_rough;
 
-/* Per-kernel device times of the last fsm_simulate / fsm_roughness call on a context with
- * profiling on, measured with HIP events on the caller's stream (milliseconds). */
+/* Per-kernel device times of the last fsm_simulate / fsm_simulate_batch / fsm_roughness call
+ * on a context with profiling on, measured with HIP events on the stream the library launches
+ * on (milliseconds).  Per-stage times need eager launches: with FSM_OPT_GRAPHS on, only
+ * total_ms is reported (the other fields are zero). */
 typedef struct fsm_timings {
     float upload_ms;         /* plan tables host -> device */
     float fill_ms;           /* Z-map initialisation */
@@ -213,8 +217,10 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
 #define FSM_OPT_BUCKET_BYTES 2    /* device bytes the binned strategy may use for its point
                                        buckets (default 4 GiB); larger simulations run in
                                        slices of the evaluation range */
-#define FSM_OPT_GRAPHS 3           /* nonzero: capture batch launch sequences into HIP graphs
-                                       and replay them for batches of the same shape */
+#define FSM_OPT_GRAPHS 3           /* nonzero: capture the launch sequences of fsm_simulate and
+                                       fsm_simulate_batch into HIP graphs (on a stream of the
+                                       context, ordered after the caller's) and replay them for
+                                       later calls of the same shape */
 #define FSM_OPT_TILE_SHAPE 4      /* cell tile of the binned Z-map and of the roughness partials:
                                        16 * log2(width) + log2(height), both 16..256 cells and the
                                        tile's keys at most 64 KiB; 0 (default): 64 x 64 cells in
@@ -314,7 +320,8 @@ typedef struct fsm_tune_result {
  * evaluations).  Later fsm_simulate / fsm_simulate_batch / fsm_serve_run calls of the same
  * class use them while FSM_OPT_AUTOTUNED is on.  Parameters change only the launch, not the
  * Z-maps; roughness sums may differ in the last bits with the tile shape.  The jobs' Z-maps
- * are overwritten.  out: the kept parameters and timings. */
+ * are overwritten (FSM_EINVAL when two of them overlap, as fsm_simulate_batch).  out: the kept
+ * parameters and timings. */
 int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tune_result *out,
                  void *stream);
 
