@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define FSM_ABI_VERSION 1
+#define FSM_ABI_VERSION 2
 #define FSM_MAX_TEETH 8
 #define FSM_MAX_EDGE 4096
 
@@ -141,10 +141,20 @@ typedef struct fsm_rough {
     double Ra_feed;          /* profile Ra along row ny/2 (feed direction) */
     double Ra_pick;          /* profile Ra along column nx/2 (pick-feed direction) */
     double mean;             /* mean height of the reached cells (reference plane) */
+    double pos_err;          /* FSM_F32: bound on the single-precision error of every evaluated
+                                position along x and y (mm), 2^-20 times the largest distance of
+                                an edge point from the tool origin (at most 13 roundings per
+                                coordinate, each below 2^-24 times that distance); heights err
+                                by no more.  0 in FSM_F64 */
     int64_t n_hit;           /* reached cells */
     int64_t n_evals;         /* edge-point evaluations */
     int64_t n_binned;        /* evaluations that fell inside the grid */
     int64_t n_feed, n_pick;  /* reached cells on the two profiles */
+    int64_t n_near;          /* FSM_F32: in-grid evaluations that lay within pos_err of a cell
+                                boundary: the only binning decisions that may differ from
+                                double precision (a cell's height differs from the double-
+                                precision map by more than pos_err only where one of them
+                                decided its minimum).  0 in FSM_F64 */
     uint32_t flags;          /* FSM_FLAG_* */
     uint32_t reserved;
 } fsm_rough;

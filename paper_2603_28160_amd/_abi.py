@@ -13,7 +13,7 @@ import threading
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libfsm.so")
 
-FSM_ABI_VERSION = 1
+FSM_ABI_VERSION = 2
 MAXT = 8
 MAX_EDGE = 4096
 
@@ -59,8 +59,9 @@ class FsmPlanInfo(C.Structure):
                 ("workspace_bytes", C.c_int64)]
 
 
-ROUGH_DOUBLES = ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean")
-ROUGH_COUNTS = ("n_hit", "n_evals", "n_binned", "n_feed", "n_pick")
+ROUGH_DOUBLES = ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean",
+                 "pos_err")
+ROUGH_COUNTS = ("n_hit", "n_evals", "n_binned", "n_feed", "n_pick", "n_near")
 
 
 class FsmRough(C.Structure):

@@ -174,6 +174,13 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         d.tile_base = tiles;
         tiles += d.n_tiles;
         d.sim = k;
+        if (precision == FSM_F32) {
+            d.pos_err = fsm::kF32PosErr * P.pos_r;
+            d.near_w = d.pos_err * P.inv_dd * (1.0 + 0x1p-20) + 0x1p-30;
+        } else {
+            d.pos_err = 0.0;
+            d.near_w = -1.0;
+        }
         L.max_n = std::max(L.max_n, P.N);
     }
     L.total_tiles = tiles;
@@ -248,6 +255,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     L.tbase = take(sizeof(int64_t) * L.n);
     L.binned = take(sizeof(uint64_t) * L.n);
     L.evals = take(sizeof(int64_t) * L.n);
+    L.near = take(sizeof(uint64_t) * L.n);
     // table sizes follow from the plan's shape, so a plan built without its tables lays out
     // the same image
     for (const Plan &P : plans) {
@@ -324,6 +332,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         d.csf = reinterpret_cast<const float *>(dev + L.csf[k]);
         d.gm = reinterpret_cast<const double *>(dev + L.gm[k]);
         d.zmap = zmaps[k];
+        d.near = reinterpret_cast<uint64_t *>(dev + L.near) + k;
         ib[k] = d.item_base;
         bb[k] = d.bitem_base;
         tb[k] = d.tile_base;
@@ -351,6 +360,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
     std::memcpy(H(L.tbase), tb.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.binned), zero.data(), sizeof(uint64_t) * L.n);
     std::memcpy(H(L.evals), ev.data(), sizeof(int64_t) * L.n);
+    std::memcpy(H(L.near), zero.data(), sizeof(uint64_t) * L.n);
 }
 
 void mark(fsm_ctx *ctx, int k, hipStream_t s, bool capturing)
@@ -424,10 +434,10 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
     int he = 0;
     mark(ctx, 1, s, capturing);
     if (!binned) {
-        for (int k = 0; k < L.n; ++k) {
-            he = fsm::launch_fill(devs[k].zmap, plans[k].nx * plans[k].ny, L.precision, s);
-            if (he) return hip_err(ctx, (hipError_t)he, "fill kernel");
-        }
+        int64_t max_cells = 0;
+        for (const Plan &P : plans) max_cells = std::max<int64_t>(max_cells, P.nx * P.ny);
+        he = fsm::launch_fill(d_sims, L.n, max_cells, L.precision, s);
+        if (he) return hip_err(ctx, (hipError_t)he, "fill kernel");
     }
     mark(ctx, 2, s, capturing);
     if (binned) {
@@ -556,8 +566,14 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
                       L.strategy, L.n, (long long)L.total_tiles, (long long)L.total_items,
                       (long long)L.per_slice, (long long)L.cap, L.sx, L.sy, (int)L.hist,
                       (long long)L.total_rows, (long long)L.rows_per_slice, w.d_ws);
+        // every host value a captured launch bakes in follows from these: the grids (tiles,
+        // fill sizes) and each simulation's item and row counts (the tile range of every
+        // slice); map pointers and tables travel in the uploaded descriptors
         std::string k(key);
-        for (int i = 0; i < L.n; ++i) k += "/" + std::to_string(plans[i].nx) + "x" + std::to_string(plans[i].ny);
+        for (int i = 0; i < L.n; ++i)
+            k += "/" + std::to_string(plans[i].nx) + "x" + std::to_string(plans[i].ny) + ":" +
+                 std::to_string(devs[i].n_items) + ":" + std::to_string(devs[i].n_bitems) + ":" +
+                 std::to_string(devs[i].n_rows);
         auto it = ctx->graph_cache.find(k);
         if (it == ctx->graph_cache.end()) {
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);

@@ -39,7 +39,15 @@ struct Plan {
     int n_groups = 0;
     double x_hi = 0, y_hi = 0, cull_reach = 0;
     std::vector<double> gm;   // [z_n][n_groups]
+    double pos_r = 0;         // largest distance of a tool-frame edge point from the origin
 };
+
+// Single-precision position error bound, in units of pos_r: the rotation, lead tilt and side
+// tilt of a point in float with fused multiply-adds round at most 13 times per coordinate
+// (inputs included), each error at most 2^-24 times a value no larger than pos_r in magnitude
+// (every intermediate is a coordinate of a rotated edge point); 16 covers the second-order
+// terms and the double-precision reference's own rounding.
+constexpr double kF32PosErr = 16.0 / 16777216.0;
 
 // Edge points per culling group, and the group's reference point (its middle point).
 constexpr int kGroup = 16;
@@ -150,6 +158,11 @@ struct DevSim {
     int32_t pad1;
     double x_hi, y_hi;       // upper grid boundaries
     double cull_reach;       // bound on any point's horizontal distance from the tool centre
+    // single-precision error statement: the position error bound (mm, 0 in double precision),
+    // the same in cell units widened for the binning arithmetic (< 0: none), and the counter
+    // of in-grid evaluations that lay that close to a cell boundary
+    double pos_err, near_w;
+    uint64_t *near;
 };
 
 // Per-tile partial sums of the roughness passes (device memory).  Row ny/2 and column nx/2
@@ -194,7 +207,8 @@ struct StageEvents {
 
 // Launch wrappers (fsm_kernels.hip).  All return a hipError_t as int.  `sims`/`d_*base`
 // describe n_sims simulations whose items and tiles are numbered consecutively.
-int launch_fill(void *zmap, int64_t n, int precision, void *stream);
+// Every Z-map of the uploaded descriptors to +inf; max_cells: the largest map of the set.
+int launch_fill(const DevSim *d_sims, int n_sims, int64_t max_cells, int precision, void *stream);
 int launch_scatter(const DevSim *d_sims, int n_sims, const int64_t *d_item_base,
                    int64_t n_items, int precision, uint64_t *d_binned, void *stream);
 // One slice [item_begin, item_begin + n_items) of binning items: count -> scan -> write ->

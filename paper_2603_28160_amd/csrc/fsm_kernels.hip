@@ -24,9 +24,8 @@
 // Double precision: only +, -, * run on the device (no contraction: -ffp-contract=off), in
 // the order the host planner documents, so binning decisions equal those of the plain
 // definition bit for bit.  Single precision: rotation and tilt in float with explicit fused
-// multiply-adds on tool-local coordinates; the tool-centre position is formed in double and
-// split into an integer cell plus a fraction once per step, and each point bins from its
-// float offset.
+// multiply-adds on tool-local coordinates; the tool-centre position, the workpiece position
+// (centre plus the widened float offset) and the binning stay in double.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -172,24 +171,18 @@ constexpr int64_t kMaxGrid = (int64_t)1 << 20;
 
 // ---- fill ------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void fill64(int64_t *z, int64_t n)
+// Every Z-map of a set starts at +inf (the scatter strategy min-reduces into it).  The map
+// pointers come from the uploaded descriptors, so a captured launch fills the maps of the call
+// that replays it.
+template <typename K>
+__global__ __launch_bounds__(kBlock) void fill_maps(const DevSim *__restrict__ sims, int n_sims, K inf)
 {
-    const int64_t n2 = n >> 1;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    longlong2 v = {kInf64, kInf64};
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n2; k += stride)
-        reinterpret_cast<longlong2 *>(z)[k] = v;
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) z[n - 1] = kInf64;
-}
-
-__global__ __launch_bounds__(kBlock) void fill32(int32_t *z, int64_t n)
-{
-    const int64_t n4 = n >> 2;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    int4 v = {kInf32, kInf32, kInf32, kInf32};
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n4; k += stride)
-        reinterpret_cast<int4 *>(z)[k] = v;
-    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) z[(n4 << 2) + threadIdx.x] = kInf32;
+    for (int k = 0; k < n_sims; ++k) {
+        FSM_GLOBAL K *z = gptr(static_cast<K *>(sims[k].zmap));
+        const int64_t n = sims[k].nx * sims[k].ny;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) z[i] = inf;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void zero_u32(uint32_t *p, int64_t n)
@@ -293,12 +286,12 @@ __device__ __forceinline__ void turn_point(const DevSim &d, const Turn<FSM_F32> 
 }
 
 // Eq. (4) tool-centre offset and Eq. (7) half-open sampling boundaries: the cell (i, j), or
-// false outside the grid.
+// false outside the grid.  fx, fy: the position in cell units.
 __device__ __forceinline__ bool bin_cell(const DevSim &d, double xcs, double yq, double xs,
-                                         double ys, int32_t &i, int32_t &j)
+                                         double ys, int32_t &i, int32_t &j, double &fx, double &fy)
 {
-    const double fx = ((xcs + xs) - d.x_lo) * d.inv_dd;
-    const double fy = ((yq + ys) - d.y_lo) * d.inv_dd;
+    fx = ((xcs + xs) - d.x_lo) * d.inv_dd;
+    fy = ((yq + ys) - d.y_lo) * d.inv_dd;
     if (fx >= 0.0 && fx < d.nx_d && fy >= 0.0 && fy < d.ny_d) {
         i = (int32_t)fx;
         j = (int32_t)fy;
@@ -307,52 +300,31 @@ __device__ __forceinline__ bool bin_cell(const DevSim &d, double xcs, double yq,
     return false;
 }
 
-// Single precision: the tool centre's cell coordinates are formed in double precision once per
-// step and split into an integer cell and a fraction; every point then bins from its float
-// tool-local offset with one fused multiply-add per axis.
-struct Centre32 {
-    int32_t ix, iy;
-    float fx, fy;
-    bool near;               // false: the centre is too far from the grid for any point to land
-};
-__device__ __forceinline__ Centre32 centre32(const DevSim &d, double xcs, double yq)
-{
-    Centre32 c;
-    const double gx = (xcs - d.x_lo) * d.inv_dd, gy = (yq - d.y_lo) * d.inv_dd;
-    c.near = gx > -1073741824.0 && gx < 1073741824.0 && gy > -1073741824.0 && gy < 1073741824.0;
-    const double fx = floor(gx), fy = floor(gy);
-    c.ix = c.near ? (int32_t)fx : 0;
-    c.iy = c.near ? (int32_t)fy : 0;
-    c.fx = (float)(gx - fx);
-    c.fy = (float)(gy - fy);
-    return c;
-}
-__device__ __forceinline__ bool bin_cell32(const DevSim &d, const Centre32 &c, float xs, float ys,
-                                           int32_t &i, int32_t &j)
-{
-    const float inv = (float)d.inv_dd;
-    i = c.ix + __float2int_rd(fmaf(xs, inv, c.fx));
-    j = c.iy + __float2int_rd(fmaf(ys, inv, c.fy));
-    return c.near && (uint32_t)i < (uint32_t)d.nx && (uint32_t)j < (uint32_t)d.ny;
-}
-
-// One point of either precision: its cell (i, j) and key; false outside the grid.
+// One point of either precision: its cell (i, j) and key; false outside the grid.  Single
+// precision turns the point in float on tool-local coordinates and widens the offsets to
+// double: the workpiece position x_c + (double)x_S and its cell follow in double precision,
+// exactly as for a double-precision point.  near (single precision): the position lies within
+// the error bound of a cell boundary, so double precision might bin it into a neighbour.
 __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F64> &a,
                                             const Edge<FSM_F64> &e, double xcs, double yq,
-                                            const Centre32 &, int32_t &i, int32_t &j, int64_t &key)
+                                            int32_t &i, int32_t &j, int64_t &key, bool &near)
 {
-    double xs, ys;
+    double xs, ys, fx, fy;
     turn_point(d, a, e, xs, ys, key);
-    return bin_cell(d, xcs, yq, xs, ys, i, j);
+    near = false;
+    return bin_cell(d, xcs, yq, xs, ys, i, j, fx, fy);
 }
 __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F32> &a,
-                                            const Edge<FSM_F32> &e, double, double,
-                                            const Centre32 &c32, int32_t &i, int32_t &j,
-                                            int32_t &key)
+                                            const Edge<FSM_F32> &e, double xcs, double yq,
+                                            int32_t &i, int32_t &j, int32_t &key, bool &near)
 {
     float xs, ys;
+    double fx, fy;
     turn_point(d, a, e, xs, ys, key);
-    return bin_cell32(d, c32, xs, ys, i, j);
+    const bool in = bin_cell(d, xcs, yq, (double)xs, (double)ys, i, j, fx, fy);
+    const double rx = fx - (double)i, ry = fy - (double)j, w = d.near_w;
+    near = in && (rx < w || rx > 1.0 - w || ry < w || ry > 1.0 - w);
+    return in;
 }
 
 // ---- swept-box culling -------------------------------------------------------------------------
@@ -417,6 +389,13 @@ __device__ __forceinline__ bool group_near(const DevSim &d, const Turn<PREC> &a,
            yq + fmax(ay0, ay1) + m >= d.y_lo && yq + fmin(ay0, ay1) - m < d.y_hi;
 }
 
+// Add a wave's near-boundary counts to the simulation's counter (single precision).
+__device__ __forceinline__ void add_near(const DevSim &d, uint32_t n)
+{
+    const uint32_t w = wave_sum(n);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd((unsigned long long *)d.near, (unsigned long long)w);
+}
+
 // ---- scatter strategy ------------------------------------------------------------------------
 
 template <int PREC>
@@ -438,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
         const int q = (int)(local / d.n_chunks);
         const int ppi = d.ppi, spi = d.spi;
         const int lane_p = tid % ppi, lane_s = tid / ppi;
-        uint32_t cnt = 0;
+        uint32_t cnt = 0, n_near = 0;
         if (lane_s < spi) {
             const int s0 = chunk * d.chunk;
             const int s1 = s0 + d.chunk < d.n_steps ? s0 + d.chunk : d.n_steps;
@@ -452,15 +431,15 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
                 for (; s < s1; s += spi) {
                     const Turn<PREC> a = spindle_turn<PREC>(d, K, m);
                     const double xcs = centre_x(d, s);
-                    Centre32 c32 = {};
-                    if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
                     Key key;
                     int32_t i, j;
-                    if (place_point(d, a, e, xcs, yq, c32, i, j, key)) {
+                    bool near;
+                    if (place_point(d, a, e, xcs, yq, i, j, key, near)) {
                         const int64_t idx = (int64_t)j * d.nx + i;
                         if (key < __hip_atomic_load(zk + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                             __hip_atomic_fetch_min(zk + idx, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ++cnt;
+                        n_near += near;
                     }
                     m += spi;
                     while (m >= S) m -= S;
@@ -469,6 +448,7 @@ __global__ __launch_bounds__(kBlock) void scatter(const DevSim *__restrict__ sim
         }
         const uint32_t w = wave_sum(cnt);
         if ((tid & 63) == 0 && w) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)w);
+        if (PREC == FSM_F32) add_near(d, n_near);
     }
 }
 
@@ -585,10 +565,9 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
         const int s = w.s0 + (vs ? lane : w.last);
         const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
         const double xcs = centre_x(d, s);
-        Centre32 c32 = {};
-        if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
         const int sx = d.sx, sy = d.sy;
         const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
+        uint32_t n_near = 0;
         for (int g = 0; g < d.n_groups; ++g) {
             if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
             const int pg = g * kGroup;
@@ -607,9 +586,11 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
                     key[u] = 0;
                     if (vs && pg + h + u < d.N) {
                         int32_t i, j;
-                        if (place_point(d, a, ep[h + u], xcs, yq, c32, i, j, key[u])) {
+                        bool near;
+                        if (place_point(d, a, ep[h + u], xcs, yq, i, j, key[u], near)) {
                             tile[u] = (int32_t)d.tile_base + (j >> sy) * d.tiles_x + (i >> sx);
                             cell[u] = (uint16_t)(((j & my) << sx) | (i & mx));
+                            n_near += near;
                         }
                     }
                 }
@@ -640,6 +621,7 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
                 }
             }
         }
+        if (!WRITE && PREC == FSM_F32) add_near(d, n_near);
     }
 }
 
@@ -651,8 +633,8 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
 // matrix into the offset of every (row, tile) inside the tile's bucket, and the write pass
 // recomputes the points, claiming slots with LDS atomics on the row's cursors.
 
-// Visit every in-grid point of binning items [i0, i1) of simulation d: f(tile, cell, key) with
-// the tile numbered inside the simulation.  Lanes hold consecutive time steps; the edge points
+// Visit every in-grid point of binning items [i0, i1) of simulation d: f(tile, cell, key, near)
+// with the tile numbered inside the simulation.  Lanes hold consecutive time steps; the edge points
 // are walked one at a time (the compiler overlaps consecutive iterations).
 template <int PREC, typename F>
 __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t i1, F &&f)
@@ -676,8 +658,6 @@ __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t 
         const int s = w.s0 + (act ? lane : w.last);
         const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
         const double xcs = centre_x(d, s);
-        Centre32 c32 = {};
-        if (PREC == FSM_F32) c32 = centre32(d, xcs, yq);
         for (int g = 0; g < d.n_groups; ++g) {
             if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
             const int pg = g * kGroup;
@@ -685,8 +665,9 @@ __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t 
             for (int p = pg; p < pe; ++p) {
                 Key key;
                 int32_t i, j;
-                if (act && place_point(d, a, edge_point<PREC>(d, K, p), xcs, yq, c32, i, j, key))
-                    f((j >> sy) * d.tiles_x + (i >> sx), (uint16_t)(((j & my) << sx) | (i & mx)), key);
+                bool near;
+                if (act && place_point(d, a, edge_point<PREC>(d, K, p), xcs, yq, i, j, key, near))
+                    f((j >> sy) * d.tiles_x + (i >> sx), (uint16_t)(((j & my) << sx) | (i & mx)), key, near);
             }
         }
     }
@@ -710,9 +691,12 @@ __global__ __launch_bounds__(kBlock) void hist_count(const DevSim *__restrict__ 
         const int T = (int)d.n_tiles;
         for (int t = tid; t < T; t += kBlock) hist[t] = 0u;
         __syncthreads();
-        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t, Key) {
+        uint32_t n_near = 0;
+        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t, Key, bool near) {
             __hip_atomic_fetch_add(&hist[lt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            n_near += near;
         });
+        if (PREC == FSM_F32) add_near(d, n_near);
         __syncthreads();
         FSM_GLOBAL uint32_t *row = gptr(bb.hist) + d.hbase + lr * T;
         for (int t = tid; t < T; t += kBlock) row[t] = hist[t];
@@ -836,7 +820,7 @@ __global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ 
         for (int t = tid; t < T; t += kBlock) cur[t] = off[t] + row[t];
         __syncthreads();
         const int64_t cap = bb.cap;
-        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t cell, Key key) {
+        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t cell, Key key, bool) {
             const uint32_t pos = __hip_atomic_fetch_add(&cur[lt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if ((int64_t)pos < cap) {
                 bkey[pos] = key;
@@ -1236,6 +1220,8 @@ __global__ __launch_bounds__(kBlock) void rough_final2(const DevSim *__restrict_
         o.flags = 0;
         o.reserved = 0;
         o.mean = st.mean;
+        o.pos_err = d.pos_err;
+        o.n_near = d.near ? (int64_t)*d.near : 0;
         if (n == 0) {
             o.Sa = o.Sq = o.Sp = o.Sv = o.Sz = o.Ssk = o.Sku = NAN;
             o.flags |= FSM_FLAG_NO_HIT;
@@ -1264,14 +1250,14 @@ __global__ __launch_bounds__(kBlock) void rough_final2(const DevSim *__restrict_
 
 // ---- launch wrappers ---------------------------------------------------------------------------
 
-int launch_fill(void *zmap, int64_t n, int precision, void *stream)
+int launch_fill(const DevSim *d_sims, int n_sims, int64_t max_cells, int precision, void *stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int blocks = stream_blocks(n, (int64_t)kBlock * 8, 8192);
+    const int blocks = stream_blocks(max_cells, (int64_t)kBlock * 8, 8192);
     if (precision == FSM_F64)
-        hipLaunchKernelGGL(fill64, dim3(blocks), dim3(kBlock), 0, s, static_cast<int64_t *>(zmap), n);
+        hipLaunchKernelGGL(fill_maps<int64_t>, dim3(blocks), dim3(kBlock), 0, s, d_sims, n_sims, (int64_t)kInf64);
     else
-        hipLaunchKernelGGL(fill32, dim3(blocks), dim3(kBlock), 0, s, static_cast<int32_t *>(zmap), n);
+        hipLaunchKernelGGL(fill_maps<int32_t>, dim3(blocks), dim3(kBlock), 0, s, d_sims, n_sims, (int32_t)kInf32);
     return (int)hipGetLastError();
 }
 

@@ -221,12 +221,14 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
 
     // --- reach and the automatic path (feed along +X, passes along +Y)
     const double sl = std::fabs(std::sin(t.tilt_lead)), ss = std::fabs(std::sin(t.tilt_side));
-    double reach = 0.0;
+    double reach = 0.0, pos_r = 0.0;
     for (size_t k = 0; k < (size_t)Z * N; ++k) {
         const double x = P.pT[3 * k], y = P.pT[3 * k + 1], z = P.pT[3 * k + 2];
         const double r = std::sqrt(x * x + y * y) + std::fabs(z) * (sl + ss);
         if (r > reach) reach = r;
+        pos_r = std::max(pos_r, std::sqrt(x * x + y * y + z * z));
     }
+    P.pos_r = pos_r;
     const double x_lo = g.x0 - 0.5 * g.dd, y_lo = g.y0 - 0.5 * g.dd;
     const double x_hi = x_lo + (double)g.nx * g.dd, y_hi = y_lo + (double)g.ny * g.dd;
     const double fpr = (double)Z * c.f_z;

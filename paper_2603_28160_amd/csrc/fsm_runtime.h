@@ -51,7 +51,7 @@ struct SetLayout {
            bkey = 0, bidx = 0, hist_m = 0, chunk = 0;
     size_t scratch_end = 0;
     // uploaded region
-    size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0;
+    size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0, near = 0;
     std::vector<size_t> pT, pTf, cs, csf, gm;
     size_t total = 0;
 };

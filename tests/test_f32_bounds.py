@@ -100,3 +100,96 @@ def test_window_equals_full_grid_slice():
     win = oracle.cell_bounds(s, delta, window=(7, 40, 5, 31))
     for a, b in zip(full, win):
         assert np.array_equal(a[5:31, 7:40], b)
+
+
+ROUGH_KEYS = ("mean", "Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick")
+
+
+def random_intervals(rng, ny, nx, p_slack):
+    """An oracle-like map with per-cell intervals, some cells forced hit, some forced empty
+    and a fraction p_slack whose hit state is open (empty in the oracle or not)."""
+    Z = rng.normal(-0.2, 0.05, (ny, nx)) + 0.01 * np.sin(np.arange(nx) / 4.0)[None, :]
+    empty = rng.random((ny, nx)) < 0.15
+    Z[empty] = np.inf
+    slack = rng.random((ny, nx)) < p_slack
+    w = rng.uniform(0.0, 2e-3, (ny, nx)) * (rng.random((ny, nx)) < 0.3)
+    centre = np.where(empty, rng.normal(-0.2, 0.05, (ny, nx)), Z)
+    low = centre - w - rng.uniform(0, 1e-4, (ny, nx))
+    high = centre + w + rng.uniform(0, 1e-4, (ny, nx))
+    must_hit = ~empty & ~slack
+    must_miss = empty & ~slack
+    return Z, low, high, must_hit, must_miss
+
+
+def allowed_map(rng, Z, low, high, must_hit, must_miss):
+    """A map the intervals allow: forced cells as forced, slack cells hit or empty at random,
+    every hit cell at a random height of its interval (often at an end)."""
+    slack = ~must_hit & ~must_miss
+    hit = must_hit | (slack & (rng.random(Z.shape) < 0.5))
+    t = rng.uniform(0, 1, Z.shape)
+    t = np.where(rng.random(Z.shape) < 0.5, np.round(t), t)
+    return np.where(hit, low + t * (high - low), np.inf)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_rough_bounds_hold_with_hit_state_changes(seed):
+    rng = np.random.default_rng([28160, 79, seed])
+    Z, low, high, mh, mm = random_intervals(rng, 41, 57, p_slack=[0.0, 0.01, 0.05][seed % 3])
+    r = oracle.roughness(Z)
+    b = FB.rough_bounds(Z, low, high, mh, mm, r)
+    for trial in range(30):
+        Zp = allowed_map(rng, Z, low, high, mh, mm)
+        rp = oracle.roughness(Zp)
+        for k in ROUGH_KEYS:
+            assert abs(rp[k] - r[k]) <= b[k] * (1 + 1e-12) + 1e-15, (k, rp[k], r[k], b[k])
+
+
+def test_rough_bounds_cover_a_dropped_extreme_cell():
+    # dropping the highest cell (a slack cell) moves Sp by the gap to the next one: the bound
+    # must reach that far, which a bound over fixed hit sets does not
+    Z = np.full((5, 6), -0.3)
+    Z[2, 3] = -0.1
+    low, high = Z - 1e-6, Z + 1e-6
+    mh = np.isfinite(Z)
+    mh[2, 3] = False
+    mm = np.zeros_like(mh)
+    r = oracle.roughness(Z)
+    b = FB.rough_bounds(Z, low, high, mh, mm, r)
+    Zp = Z.copy()
+    Zp[2, 3] = np.inf
+    rp = oracle.roughness(Zp)
+    for k in ("mean", "Sa", "Sq", "Sp", "Sz"):
+        assert abs(rp[k] - r[k]) <= b[k], k
+    assert abs(rp["Sp"] - r["Sp"]) > 0.1
+    mb = FB.moment_bounds(Z, FB.interval_widths(Z, low, high), r)
+    assert abs(rp["Sa"] - r["Sa"]) > mb["Sa"]
+
+
+@pytest.mark.parametrize("shift", [(0.9, 0.0), (-0.7, -0.7)])
+def test_shifted_grid_roughness_inside_rough_bounds(shift):
+    # a grid moved by less than the position error is an allowed result, hit-state changes
+    # included: its roughness must lie inside the bounds of the unmoved grid's intervals
+    s = small_sim()
+    s = s.replace(grid=dataclasses.replace(s.grid, dd=0.003))   # 79 % coverage
+    delta = 0.3 * s.grid.dd
+    low, high, mh, mm = FB.f32_intervals(s, delta=delta, tol=0.0)
+    g = s.grid
+    moved = s.replace(grid=dataclasses.replace(g, x0=g.x0 + shift[0] * delta,
+                                               y0=g.y0 + shift[1] * delta))
+    zs, _ = oracle.simulate(moved)
+    zo, _ = oracle.simulate(s)
+    assert not np.array_equal(np.isfinite(zs), np.isfinite(zo))   # hit states do change
+    r = oracle.roughness(zo)
+    b = FB.rough_bounds(zo, low, high, mh, mm, r)
+    rs = oracle.roughness(zs)
+    for k in ROUGH_KEYS:
+        assert abs(rs[k] - r[k]) <= b[k] * (1 + 1e-12) + 1e-15, (k, rs[k], r[k], b[k])
+
+
+def test_f32_delta_from_operation_count():
+    # 16 single-precision rounding units of the farthest edge point from the tool origin
+    s = W.config2()
+    _, pts = oracle.edge_points(s)
+    R = float(np.max(np.linalg.norm(pts, axis=-1)))
+    assert FB.f32_delta(s) == 16.0 * 2.0 ** -24 * R
+    assert 2.0 < R < 3.1                      # ball R3: points on the engaged meridian

@@ -118,6 +118,45 @@ def test_graph_replays_match_eager(Ctx, prec):
             assert np.array_equal(one.cpu().numpy().astype(np.float64), me[rep % len(sims)])
 
 
+@pytest.mark.parametrize("strategy", ["binned", "scatter"])
+def test_graph_replay_fresh_maps_and_parameters(Ctx, strategy):
+    # A captured launch sequence is reused only for a set that lays out the same way: fresh
+    # Z-maps on every call and members whose parameters (so item and row counts) change while
+    # every grid stays the same must each give the eager result.  The small bucket budget
+    # splits the histogram work into several slices whose tile ranges depend on the members'
+    # row counts; swapping the members keeps every total but moves those ranges.
+    import torch
+    mix = small_mix(3)
+    g = mix[0].grid
+    a, b, c = [s.replace(grid=g) for s in mix]
+    sets = [[a, b, c], [c, b, a], [b, a, c]]
+    with Ctx(0) as eager:
+        eager.set_strategy(strategy)
+        eager.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 1 << 20)
+        eager.fsm_ctx_set_profiling(True)
+        want = []
+        for s in sets:
+            z, r = eager.fsm_simulate_batch(s, "f64")
+            want.append([np_maps(z), r])
+            if strategy == "binned":
+                assert eager.fsm_last_timings()["n_slices"] > 1
+    with Ctx(0) as ctx:
+        ctx.set_strategy(strategy)
+        ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 1 << 20)
+        ctx.set_graphs(True)
+        for rep in range(2):
+            for k, s in enumerate(sets):
+                print(f"[gpu] graph {strategy} set {k} replay {rep}", flush=True)
+                zg, rg = ctx.fsm_simulate_batch(s, "f64")
+                torch.cuda.synchronize()
+                for m, (zm, r) in enumerate(zip(np_maps(zg), rg)):
+                    assert np.array_equal(zm, want[k][0][m]), (rep, k, m)
+                    same_rough(r, want[k][1][m])
+    for s, zm in zip(sets[0], want[0][0]):
+        zo, _ = oracle.simulate(s)
+        assert np.array_equal(zm, zo)
+
+
 def test_batch_with_empty_and_tiny_members(Ctx):
     base = W.config2(nx=90, ny=70, dd=0.02)
     far = base.replace(cut=dataclasses.replace(base.cut, n_passes=1, y_first=80.0, a_e=0.0))

@@ -77,7 +77,11 @@ def check_f64(ctx, sim):
     return zo
 
 
-def check_f32(ctx, sim, zo=None, max_open=0.05):
+def check_f32(ctx, sim, zo=None, max_open=0.05, areal_bar=False):
+    """Single precision against the oracle: every cell inside its interval, the library's own
+    error statement (pos_err, n_near) consistent with the oracle's map, and every roughness
+    parameter within 1e-4 relative plus the largest change the intervals allow (hit-state
+    changes of the slack cells included).  Returns the map and the measured errors."""
     zg, rg = run_gpu(ctx, sim, "f32")
     if zo is None:
         zo, _ = oracle.simulate(sim)
@@ -86,16 +90,37 @@ def check_f32(ctx, sim, zo=None, max_open=0.05):
     open_ = high - low > 2 * FB.F32_TOL + 1e-15
     assert open_.mean() <= max_open, open_.mean()
     FB.check_cells(zg, low, high, must_hit, must_miss)
+    # the library's statement: its position bound is the operation-count bound, and a cell
+    # differs from double precision by more than that only where a near-boundary evaluation
+    # changed its cell (each such evaluation touches two cells)
+    assert rg["pos_err"] == pytest.approx(FB.f32_delta(sim), rel=1e-12)
+    hg, ho = np.isfinite(zg), np.isfinite(zo)
+    with np.errstate(invalid="ignore"):
+        moved = (hg != ho) | (hg & ho & (np.abs(zg - zo) > rg["pos_err"]))
+    assert int(moved.sum()) <= 2 * rg["n_near"], (int(moved.sum()), rg["n_near"])
+    assert rg["n_near"] <= rg["n_binned"]
     ro = oracle.roughness(zo)
-    slack = np.sum(np.isfinite(zo) & ~must_hit) + np.sum(~np.isfinite(zo) & ~must_miss)
+    slack = np.sum(ho & ~must_hit) + np.sum(~ho & ~must_miss)
     assert abs(rg["n_hit"] - ro["n_hit"]) <= slack
-    if np.array_equal(np.isfinite(zg), np.isfinite(zo)) and ro["n_hit"] > 0:
-        mb = FB.moment_bounds(zo, FB.interval_widths(zo, low, high), ro)
-        for k in ("Sa", "Sq", "Ssk", "Sku", "mean"):
+    err = {"cells_moved": int(moved.sum()), "n_near": rg["n_near"], "open": float(open_.mean())}
+    if ro["n_hit"] > 0:
+        rb = FB.rough_bounds(zo, low, high, must_hit, must_miss, ro)
+        for k in ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean"):
             if math.isnan(ro[k]):
                 continue
-            assert abs(rg[k] - ro[k]) <= ROUGH_RTOL * abs(ro[k]) + mb[k] + 1e-9, (k, rg[k], ro[k], mb[k])
-    return zg
+            e = abs(rg[k] - ro[k])
+            err[k] = e / abs(ro[k]) if ro[k] else e
+            assert e <= ROUGH_RTOL * abs(ro[k]) + rb[k] + 1e-12, (k, rg[k], ro[k], rb[k])
+    if areal_bar:
+        # the areal parameters average over every hit cell: the few cells a near-boundary
+        # evaluation moves leave them inside the stated bar itself (a profile line has too
+        # few cells for that and keeps the interval bound above)
+        for k in ("Sa", "Sq", "Ssk", "Sku", "Sp", "Sv", "Sz", "mean"):
+            assert abs(rg[k] - ro[k]) <= ROUGH_RTOL * abs(ro[k]), (k, rg[k], ro[k])
+    print(f"[f32 vs oracle] {sim.name or 'sim'}: " +
+          ", ".join(f"{k}={v:.3g}" if isinstance(v, float) else f"{k}={v}" for k, v in err.items()),
+          flush=True)
+    return zg, err
 
 
 # --- double precision: bit-exact against the oracle ----------------------------------------
@@ -244,6 +269,6 @@ def test_config2_full_f64_exact(ctx, params):
     try:
         print(f"[gpu] config2 full size, {params} launch parameters", flush=True)
         zo = check_f64(ctx, W.config2())
-        check_f32(ctx, W.config2(), zo=zo)
+        check_f32(ctx, W.config2(), zo=zo, areal_bar=True)
     finally:
         ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 1)

@@ -1,10 +1,16 @@
 """GPU tests of the serving loop (fsm_serve_run): requests of different sizes arriving over time
 are batched and overlapped on several streams, and each result must equal the same simulation
 run alone, bit for bit in both precisions (every kernel treats a simulation of a batch exactly
-as it treats it alone)."""
+as it treats it alone), and the double-precision results must equal the CPU oracle.  Requests
+that arrive while a long one runs must start, and finish, on another slot before it ends."""
+import dataclasses
+import math
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
+import oracle
 from paper_2603_28160_amd import _abi, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -100,3 +106,77 @@ def test_overlapping_request_maps_rejected(ctx):
         ctx.fsm_serve_run([(s0, t0, a), (reqs[1][0], reqs[1][1], None), (s0, t0, b)], "f32",
                           n_slots=2, max_batch=3)
     assert e.value.code == _abi.EINVAL
+
+
+def lite_mix(n, spread=0.01):
+    """Serving requests drawn like the mix with coarser cells and fewer edge points and steps, so
+    that the oracle finishes each in seconds."""
+    rng = np.random.default_rng([28160, 45, n])
+    arrivals = np.sort(rng.uniform(0.0, spread, n))
+    out = []
+    for i, a in enumerate(arrivals):
+        sm = W.random_sim(4, 600 + i, side_max=256)
+        sm = sm.replace(tool=dataclasses.replace(sm.tool, n_edge=16),
+                        cut=dataclasses.replace(sm.cut, steps_per_rev=180),
+                        grid=dataclasses.replace(sm.grid, dd=sm.grid.dd * 4))
+        out.append((sm, float(a)))
+    return out
+
+
+def test_served_f64_maps_equal_the_oracle(ctx):
+    reqs = lite_mix(10)
+    zmaps = [ctx.new_zmap(s.grid, "f64") for s, _ in reqs]
+    print(f"[gpu] serve {len(reqs)} requests f64 against the oracle", flush=True)
+    res = ctx.fsm_serve_run([(s, a, z) for (s, a), z in zip(reqs, zmaps)], "f64",
+                            n_slots=2, max_batch=4)
+    got = [z.cpu().numpy() for z in zmaps]
+    with ThreadPoolExecutor(8) as pool:
+        want = list(pool.map(lambda r: oracle.simulate(r[0]), reqs))
+    for k, (zg, (zo, cnt)) in enumerate(zip(got, want)):
+        assert res[k]["status"] == 0
+        r = res[k]["rough"]
+        assert np.array_equal(zg, zo), k
+        assert r["n_binned"] == cnt["n_binned"] and r["n_evals"] == cnt["n_evals"]
+        ro = oracle.roughness(zo)
+        for key in ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick"):
+            if math.isnan(ro[key]):
+                assert math.isnan(r[key]), (k, key)
+            else:
+                assert abs(r[key] - ro[key]) <= 1e-4 * abs(ro[key]) + 1e-12, (k, key)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_requests_arriving_during_a_long_one_overlap_it(ctx, prec):
+    # one long simulation (the 5000 x 5000 raster at 20 times the time resolution) arrives
+    # first; short ones arrive one by one while it runs.  With one request per batch the long
+    # one holds a slot, and each short one must be admitted to the other slot and finish there
+    # before the long one is done: their work shares the device.
+    big = W.config2()
+    big = big.replace(cut=dataclasses.replace(big.cut, steps_per_rev=720 * 20), name="long")
+    shorts = [(W.config1().replace(name=f"short{k}"), 0.002 * (k + 1)) for k in range(4)]
+    items = [(big, 0.0, ctx.new_zmap(big.grid, prec))] + \
+            [(s, a, ctx.new_zmap(s.grid, prec)) for s, a in shorts]
+    print(f"[gpu] serve a long request and {len(shorts)} short ones, {prec}", flush=True)
+    res = ctx.fsm_serve_run(items, prec, n_slots=2, max_batch=1, slot_bytes=2 << 30)
+    assert all(r["status"] == 0 for r in res)
+    lg = res[0]
+    print(f"[gpu] long: start {lg['start_s'] * 1e3:.2f} ms done {lg['done_s'] * 1e3:.2f} ms; shorts: " +
+          ", ".join(f"{r['start_s'] * 1e3:.2f}-{r['done_s'] * 1e3:.2f} ms (slot {r['slot']})"
+                    for r in res[1:]), flush=True)
+    assert lg["start_s"] < shorts[0][1]
+    for r in res[1:]:
+        assert r["slot"] != lg["slot"]
+        assert r["start_s"] < lg["done_s"]
+    # the slots' busy intervals overlap, and short work completed while the long one ran
+    assert any(r["done_s"] < lg["done_s"] for r in res[1:])
+    # each result is the same as alone; the short ones are also the oracle's (double precision)
+    zl, rl = ctx.fsm_simulate(big, prec)
+    assert np.array_equal(items[0][2].cpu().numpy(), zl.cpu().numpy())
+    same_rough(lg["rough"], rl)
+    zo, _ = oracle.simulate(shorts[0][0])
+    for (s, _, z), r in zip(items[1:], res[1:]):
+        z1, r1 = ctx.fsm_simulate(s, prec)
+        assert np.array_equal(z.cpu().numpy(), z1.cpu().numpy())
+        same_rough(r["rough"], r1)
+        if prec == "f64":
+            assert np.array_equal(z.cpu().numpy(), zo)
