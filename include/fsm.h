@@ -264,6 +264,23 @@ int fsm_last_timings(const fsm_ctx *ctx, fsm_timings *out);
 int fsm_simulate(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid,
                  int precision, void *zmap_dev, fsm_rough *out, void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): fsm_simulate without any device or pinned-host
+ * allocation.  The scratch it needs (reduction partials, counters, the binned Z-map's row
+ * matrix and buckets, the plan image) is a fixed device array of FSM_NOALLOC_SCRATCH_BYTES
+ * inside the library, one per GPU, held until the process ends; the binned Z-map runs in as
+ * many slices as that size requires (the row matrix gets at most a quarter of it).  The caller
+ * passes the Z-map and the result record as for fsm_simulate, and gets the same Z-map and
+ * roughness.  The plan is built in ordinary host memory.  FSM_EINVAL, with a message, when
+ * the simulation cannot run within the array (its tile partials, row matrix and one slice of
+ * buckets exceed it), besides fsm_simulate's errors.  Every call on a GPU uses that GPU's one
+ * array: calls that overlap in time on one GPU (from any context or thread) race and must be
+ * serialised by the caller. */
+#define FSM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fsm_simulate_noalloc(fsm_ctx *ctx, const fsm_tool *tool, const fsm_cut *cut,
+                         const fsm_grid *grid, int precision, void *zmap_dev, fsm_rough *out,
+                         void *stream);
+
 /* The trajectory module (Sec. 3.2): for every pass q, time step s and tooth K, the
  * workpiece-frame position of the lowest point (least z) of the tooth's discretised edge,
  * the first such point on a tie.  traj_dev: caller-owned device memory of

@@ -62,6 +62,7 @@ class FsmPlanInfo(C.Structure):
 ROUGH_DOUBLES = ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean",
                  "pos_err")
 ROUGH_COUNTS = ("n_hit", "n_evals", "n_binned", "n_feed", "n_pick", "n_near")
+NOALLOC_SCRATCH_BYTES = 64 << 20        # FSM_NOALLOC_SCRATCH_BYTES
 
 
 class FsmRough(C.Structure):
@@ -137,6 +138,8 @@ SIGNATURES = {
     "fsm_last_timings": ([C.c_void_p, P(FsmTimings)], C.c_int),
     "fsm_simulate": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int, C.c_void_p,
                       P(FsmRough), C.c_void_p], C.c_int),
+    "fsm_simulate_noalloc": ([C.c_void_p, P(FsmTool), P(FsmCut), P(FsmGrid), C.c_int,
+                              C.c_void_p, P(FsmRough), C.c_void_p], C.c_int),
     "fsm_roughness": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, P(FsmRough), C.c_void_p],
                       C.c_int),
     "fsm_level": ([C.c_void_p, P(FsmGrid), C.c_int, C.c_void_p, C.c_void_p, P(C.c_double),

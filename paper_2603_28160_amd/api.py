@@ -204,6 +204,19 @@ class Context:
         _check(rc, "fsm_simulate", self._h)
         return zmap, (out.as_dict() if roughness else None)
 
+    def fsm_simulate_noalloc(self, sim, zmap, precision="f64", stream=None) -> dict:
+        """fsm_simulate into the caller's Z-map tensor without any device or pinned-host
+        allocation by the library (its scratch is a fixed per-GPU array); returns the
+        roughness dict."""
+        self._check_zmap(sim.grid, precision, zmap)
+        out = _abi.FsmRough()
+        rc = self._lib.fsm_simulate_noalloc(
+            self._h, C.byref(_abi.tool_struct(sim.tool)), C.byref(_abi.cut_struct(sim.cut)),
+            C.byref(_abi.grid_struct(sim.grid)), _prec(precision), C.c_void_p(zmap.data_ptr()),
+            C.byref(out), C.c_void_p(_stream_handle(stream, self.device)))
+        _check(rc, "fsm_simulate_noalloc", self._h)
+        return out.as_dict()
+
     def fsm_trajectory(self, sim, precision="f64", stream=None):
         """Lowest edge point per (pass, step, tooth) in the workpiece frame: returns (xyz
         tensor [n_passes, n_steps, n_teeth, 3], edge-index tensor [n_passes, n_steps, n_teeth])."""

@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
         _run([HIPCC, *COMMON, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-c",
               os.path.join(CSRC, name + ".cpp"), "-o", o])
         objs.append(o)
-    for name in ("fsm_kernels", "fsm_texture"):
+    for name in ("fsm_kernels", "fsm_texture", "fsm_noalloc"):
         o = os.path.join(BUILD, name + ".o")
         _run([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, name + ".hip"), "-o", o])
         objs.append(o)

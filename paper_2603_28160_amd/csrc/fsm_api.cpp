@@ -28,7 +28,6 @@ namespace rt {
 
 constexpr int kItersPerItem = 16;   // steps each thread walks per scatter item and edge point
 constexpr int64_t kMinSliceRows = 2048;    // rows (blocks) a slice of the histogram mode keeps
-constexpr int64_t kHistBudget = (int64_t)1 << 30;   // bytes of the row matrix
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -208,12 +207,12 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
                 rows += d.n_rows;
                 hsize += d.n_rows * d.n_tiles;
             }
-            if (hsize * 4 <= kHistBudget || ipr >= slice_items) break;
+            if (hsize * 4 <= lp.hist_bytes || ipr >= slice_items) break;
             ipr = std::min(slice_items, ipr * 2);
         }
         L.items_per_row = ipr;
         L.total_rows = rows;
-        L.hist = L.max_tiles <= fsm::kMaxHistTiles && hsize * 4 <= kHistBudget;
+        L.hist = L.max_tiles <= fsm::kMaxHistTiles && hsize * 4 <= lp.hist_bytes;
         if (!L.hist) L.max_tiles = 0;
     }
 
@@ -269,6 +268,23 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     }
     L.total = o;
     return L;
+}
+
+bool fit_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
+                int64_t bytes, LaunchParams lp, SetLayout &L, std::vector<DevSim> &devs)
+{
+    const int64_t entry = precision == FSM_F64 ? 10 : 6;
+    for (int it = 0; it < 8; ++it) {
+        devs.clear();
+        L = make_layout(ctx, plans, precision, lp, devs);
+        if ((int64_t)L.total <= bytes) return true;
+        const int64_t floor_bytes = (int64_t)fsm::kBlock * L.max_n * entry;
+        const int64_t used = L.cap * entry;
+        const int64_t next = used - ((int64_t)L.total - bytes) - (1 << 20);
+        if (used <= floor_bytes) return false;
+        lp.bucket_bytes = std::max(next, floor_bytes);
+    }
+    return false;
 }
 
 int ensure(fsm_ctx *ctx, Workspace &w, size_t dev_bytes, size_t host_bytes, size_t n_out)
@@ -816,6 +832,9 @@ int fsm_ctx_create(fsm_ctx **out, int device)
     fsm_ctx *c = new (std::nothrow) fsm_ctx;
     if (!c) return FSM_ENOMEM;
     c->device = device;
+    // the fixed scratch of fsm_simulate_noalloc: its address on this device, once per device
+    // (a failure is reported by that call, not here)
+    (void)noalloc_setup(device);
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = (size_t)lds;

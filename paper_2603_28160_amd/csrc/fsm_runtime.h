@@ -36,6 +36,7 @@ struct LaunchParams {
     int tile_shape = 0;
     int64_t target_rows = 4096;
     int64_t bucket_bytes = (int64_t)4 << 30;
+    int64_t hist_bytes = (int64_t)1 << 30;   // row matrix of the histogram mode, at most
 };
 
 // Shape and layout of one launch over a set of simulations.
@@ -113,6 +114,13 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
 // uses: the context's options, or what fsm_autotune kept for the class.
 std::string tune_key(const std::vector<Plan> &plans, int precision);
 LaunchParams params_for(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision);
+// Layout of a set whose whole workspace fits `bytes`: starting from lp, the bucket budget
+// shrinks (more slices) until it does; false if even the smallest bucket does not fit.
+bool fit_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
+                int64_t bytes, LaunchParams lp, SetLayout &L, std::vector<DevSim> &devs);
+// The fixed device scratch of fsm_simulate_noalloc on `device` (fsm_noalloc.hip): its
+// address is looked up once per device, with the device current (fsm_ctx_create does it).
+int noalloc_setup(int device);
 // Whether a tile shape code is valid for the precision (and the context's LDS).
 bool valid_tile_shape(const fsm_ctx *ctx, int precision, int code);
 // Grow w to at least the given sizes (device workspace, host staging, result records).

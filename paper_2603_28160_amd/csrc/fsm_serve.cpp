@@ -76,24 +76,10 @@ Book book_requests(const fsm_serve_config &cfg, int n, const fsm_request *req,
 
 // Layout of a batch fitted to a slot: the bucket budget shrinks (more slices) until the whole
 // image fits slot_bytes; false if even the smallest bucket does not.
-bool fit_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
-                int64_t slot_bytes, SetLayout &L, std::vector<DevSim> &devs, int64_t &bucket)
+bool fit_slot(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
+              int64_t slot_bytes, SetLayout &L, std::vector<DevSim> &devs)
 {
-    LaunchParams lp = params_for(ctx, plans, precision);
-    bucket = lp.bucket_bytes;
-    const int64_t entry = precision == FSM_F64 ? 10 : 6;
-    for (int it = 0; it < 8; ++it) {
-        devs.clear();
-        lp.bucket_bytes = bucket;
-        L = make_layout(ctx, plans, precision, lp, devs);
-        if ((int64_t)L.total <= slot_bytes) return true;
-        const int64_t floor_bytes = (int64_t)fsm::kBlock * L.max_n * entry;
-        const int64_t used = L.cap * entry;
-        const int64_t next = used - ((int64_t)L.total - slot_bytes) - (1 << 20);
-        if (used <= floor_bytes) return false;
-        bucket = std::max(next, floor_bytes);
-    }
-    return false;
+    return fit_layout(ctx, plans, precision, slot_bytes, params_for(ctx, plans, precision), L, devs);
 }
 
 void fill_result(fsm_request_result &o, const fsm::SchedResult &s)
@@ -170,9 +156,8 @@ public:
         for (int v : batch) plans.push_back(book_.shape[v]);
         SetLayout L;
         std::vector<DevSim> devs;
-        int64_t bucket = 0;
         status = FSM_ENOMEM;
-        return fit_layout(ctx_, plans, cfg_.precision, cfg_.slot_bytes, L, devs, bucket);
+        return fit_slot(ctx_, plans, cfg_.precision, cfg_.slot_bytes, L, devs);
     }
 
     int submit(int slot, const std::vector<int> &batch, const std::vector<fsm::SchedResult> &res) override
@@ -195,8 +180,7 @@ public:
         }
         SetLayout L;
         std::vector<DevSim> devs;
-        int64_t bucket = 0;
-        if (!fit_layout(ctx_, plans, cfg_.precision, cfg_.slot_bytes, L, devs, bucket))
+        if (!fit_slot(ctx_, plans, cfg_.precision, cfg_.slot_bytes, L, devs))
             return set_err(ctx_, FSM_ENOMEM, "batch does not fit the slot workspace");
         int rc = ensure(ctx_, s.ws, L.total, L.total - L.sims, (size_t)L.n);
         if (rc != FSM_OK) return rc;
@@ -255,9 +239,8 @@ public:
         for (int v : batch) plans.push_back(book_.shape[v]);
         SetLayout L;
         std::vector<DevSim> devs;
-        int64_t bucket = 0;
         status = FSM_ENOMEM;
-        return fit_layout(probe_, plans, cfg_.precision, cfg_.slot_bytes, L, devs, bucket);
+        return fit_slot(probe_, plans, cfg_.precision, cfg_.slot_bytes, L, devs);
     }
     int submit(int slot, const std::vector<int> &batch, const std::vector<fsm::SchedResult> &) override
     {
