@@ -104,9 +104,9 @@ def run_precision(ctx, sim, prec, steps, warmup, profile, graphs=False):
 
 def batch_leg(ctx, n_sims):
     """Configuration 3 (n_sims seeded simulations, sides up to 2048): every simulation once,
-    batched (one fsm_simulate_batch), plain (one fsm_simulate per simulation, each waited
-    for) and asynchronous (batches of 32 on two slots), in both precisions.  Z-maps resident
-    in HBM."""
+    batched (one fsm_simulate_batch, eager and replayed from a captured graph), plain (one
+    fsm_simulate per simulation, each waited for) and asynchronous (batches of 32 on two
+    slots), in both precisions.  Z-maps resident in HBM."""
     import torch
     from paper_2603_28160_amd import workloads
     sims = workloads.config3(n_sims)
@@ -121,6 +121,15 @@ def batch_leg(ctx, n_sims):
         ctx.fsm_simulate_batch(sims, prec, zmaps=zmaps)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
+        # the same batch replayed from a captured graph (the first call captures it)
+        ctx.set_graphs(True)
+        ctx.fsm_simulate_batch(sims, prec, zmaps=zmaps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.fsm_simulate_batch(sims, prec, zmaps=zmaps)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        ctx.set_graphs(False)
         for s, z in zip(sims, zmaps):
             ctx.fsm_simulate(s, prec, z)
         torch.cuda.synchronize()
@@ -149,35 +158,52 @@ def batch_leg(ctx, n_sims):
         del zmaps
         torch.cuda.empty_cache()
         out[prec] = {"batched": {"s": tb, "sims_per_s": n_sims / tb, "cells_per_s": cells / tb},
+                     "batched_graph": {"s": tg, "sims_per_s": n_sims / tg, "cells_per_s": cells / tg},
                      "plain": {"s": tp, "sims_per_s": n_sims / tp, "cells_per_s": cells / tp},
                      "async_32x2": {"s": ta, "sims_per_s": n_sims / ta, "cells_per_s": cells / ta}}
-        print(f"[bench] config3 x{n_sims} {prec}: batched {tb:.3f} s, plain {tp:.3f} s, async {ta:.3f} s",
+        print(f"[bench] config3 x{n_sims} {prec}: batched {tb:.3f} s, graph {tg:.3f} s, plain {tp:.3f} s, async {ta:.3f} s",
               file=sys.stderr, flush=True)
     return out
 
 
 def large_leg(ctx, steps=3):
-    """Configuration 5: one 40000 x 40000 field at 0.5 um (1.6e9 cells, FP32 map of 6.4 GB),
-    the D = 12 mm four-flute mill with variable pitch; simulations per second and cells/s."""
+    """Configuration 5: one 40000 x 40000 field at 0.5 um (1.6e9 cells; the map is 6.4 GB in
+    single and 12.8 GB in double precision), the D = 12 mm four-flute mill with variable pitch;
+    both precisions: time per simulation, cells/s, and the per-stage times of one profiled step
+    with the roofline of each Z-map stage (the binning passes against the vector peak, the tile
+    reduction against HBM)."""
     import torch
     from paper_2603_28160_amd import fsm_plan, workloads
     sim = workloads.config5()
     plan = fsm_plan(sim, "f32")
-    z = ctx.new_zmap(sim.grid, "f32")
-    ctx.fsm_simulate(sim, "f32", z)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        _, r = ctx.fsm_simulate(sim, "f32", z)
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / steps
     cells = sim.grid.nx * sim.grid.ny
-    del z
-    torch.cuda.empty_cache()
-    print(f"[bench] config5 f32: {el * 1e3:.2f} ms per simulation", file=sys.stderr, flush=True)
-    return {"workload": sim.name, "precision": "f32", "ms_per_sim": el * 1e3,
-            "cells_per_s": cells / el, "evals_per_s": plan["n_evals"] / el,
-            "coverage": r["n_hit"] / cells, "steps": steps}
+    out = {"workload": sim.name, "evals": plan["n_evals"], "steps": steps}
+    for prec in ("f32", "f64"):
+        z = ctx.new_zmap(sim.grid, prec)
+        ctx.fsm_simulate(sim, prec, z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, r = ctx.fsm_simulate(sim, prec, z)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        ctx.fsm_ctx_set_profiling(True)
+        ctx.fsm_simulate(sim, prec, z)
+        t = ctx.fsm_last_timings()
+        ctx.fsm_ctx_set_profiling(False)
+        del z
+        torch.cuda.empty_cache()
+        prof = {k: t[k] for k in ("fill_ms", "scatter_ms", "rough_ms", "count_ms", "index_ms",
+                                  "write_ms", "reduce_ms", "n_slices")}
+        prof["rough"] = r
+        out[prec] = {"ms_per_sim": el * 1e3, "cells_per_s": cells / el,
+                     "evals_per_s": plan["n_evals"] / el, "coverage": r["n_hit"] / cells,
+                     "kernel_ms": {k[:-3]: prof[k] for k in prof if k.endswith("_ms")},
+                     "n_slices": prof["n_slices"],
+                     "rooflines": stage_rooflines(sim, plan, prec, prof, run_mode=True)}
+        print(f"[bench] config5 {prec}: {el * 1e3:.2f} ms per simulation (count {t['count_ms']:.2f}, "
+              f"write {t['write_ms']:.2f}, reduce {t['reduce_ms']:.2f} ms)", file=sys.stderr, flush=True)
+    return out
 
 
 def coverage_leg(ctx, steps=3):
@@ -304,34 +330,135 @@ def paper_leg(ctx, steps=3):
     return out
 
 
-def serve_leg(ctx, n_req, rate, max_batch=16, n_slots=2):
-    """Configuration 4: n_req requests drawn like configuration 3 with sides up to 4096,
-    Poisson arrivals at `rate` per second, served with continuous batching (server-held
-    Z-maps in a device arena), in both precisions.  Latency = arrival to result on the host."""
+SERVE_RATES = (50.0, 200.0, 500.0, 1000.0, 2000.0)
+
+
+def serve_leg(ctx, rates, n_req=None, max_batch=16, n_slots=2):
+    """Configuration 4 over a sweep of Poisson arrival rates: requests drawn like configuration
+    3 with sides up to 4096, served with continuous batching (server-held Z-maps in a device
+    arena, n_slots slots, batches of up to max_batch), in both precisions: simulations/s, p50
+    and p99 latency (arrival to result on the host) per rate.  Each rate serves n_req requests
+    (default 2000, 1000 at the lowest rate so it stays near 20 s).  Beside them, the same
+    request mix as plain double-precision single-simulation launches one after another (no
+    arrivals, no batching): simulations/s and per-launch latency."""
+    import torch
     from paper_2603_28160_amd import workloads
-    reqs = workloads.config4_requests(n_req, rate)
-    out = {"workload": f"config4_poisson_{rate:g}_per_s", "requests": n_req, "rate_per_s": rate,
-           "n_slots": n_slots, "max_batch": max_batch}
-    for prec in ("f32", "f64"):
-        res = ctx.fsm_serve_run([(s, a, None) for a, s in reqs], prec, n_slots=n_slots,
-                                max_batch=max_batch, arena_bytes=8 << 30, slot_bytes=2 << 30)
-        ok = [(r, a) for r, (a, _) in zip(res, reqs) if r["status"] == 0]
-        lat = [(r["done_s"] - a) * 1e3 for r, a in ok]
-        span = max(r["done_s"] for r, _ in ok) - min(a for _, a in ok)
-        sizes = {}
-        for r, _ in ok:
-            sizes[r["batch"]] = sizes.get(r["batch"], 0) + 1
-        out[prec] = {"sims_per_s": len(ok) / span, "latency_ms": {"p50": pct(lat, 50),
-                     "p99": pct(lat, 99)}, "completed": len(ok),
-                     "mean_batch": len(ok) / max(1, len(sizes))}
-        print(f"[bench] serving {prec}: {len(ok)}/{n_req} done, {len(ok) / span:.1f} sims/s, "
-              f"p50 {pct(lat, 50):.2f} ms, p99 {pct(lat, 99):.2f} ms", file=sys.stderr, flush=True)
+    out = {"workload": "config4_poisson_sweep", "n_slots": n_slots, "max_batch": max_batch,
+           "rates": {}}
+    for rate in rates:
+        n = n_req or (1000 if rate < 100 else 2000)
+        reqs = workloads.config4_requests(n, rate)
+        row = {"requests": n}
+        for prec in ("f32", "f64"):
+            res = ctx.fsm_serve_run([(s, a, None) for a, s in reqs], prec, n_slots=n_slots,
+                                    max_batch=max_batch, arena_bytes=8 << 30, slot_bytes=2 << 30)
+            ok = [(r, a) for r, (a, _) in zip(res, reqs) if r["status"] == 0]
+            lat = [(r["done_s"] - a) * 1e3 for r, a in ok]
+            span = max(r["done_s"] for r, _ in ok) - min(a for _, a in ok)
+            sizes = {}
+            for r, _ in ok:
+                sizes[r["batch"]] = sizes.get(r["batch"], 0) + 1
+            row[prec] = {"sims_per_s": len(ok) / span, "latency_ms": {"p50": pct(lat, 50),
+                         "p99": pct(lat, 99)}, "completed": len(ok),
+                         "mean_batch": len(ok) / max(1, len(sizes))}
+            print(f"[bench] serving {rate:g}/s {prec}: {len(ok)}/{n} done, {len(ok) / span:.1f} sims/s, "
+                  f"p50 {pct(lat, 50):.2f} ms, p99 {pct(lat, 99):.2f} ms, mean batch "
+                  f"{row[prec]['mean_batch']:.2f}", file=sys.stderr, flush=True)
+        out["rates"][f"{rate:g}"] = row
+    # plain double-precision launches over the same request mix
+    reqs = workloads.config4_requests(2000, rates[0])
+    sims = [s for _, s in reqs]
+    for s in sims[:8]:
+        ctx.fsm_simulate(s, "f64")
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for s in sims:
+        a = time.perf_counter()
+        ctx.fsm_simulate(s, "f64")
+        lat.append((time.perf_counter() - a) * 1e3)
+    el = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    out["plain_f64"] = {"requests": len(sims), "sims_per_s": len(sims) / el,
+                        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)}}
+    print(f"[bench] plain f64 launches over the mix: {len(sims) / el:.1f} sims/s, p50 "
+          f"{pct(lat, 50):.2f} ms, p99 {pct(lat, 99):.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def latency_leg(ctx, steps=200):
+    """Configuration 1 (200 x 200 at 5 um, one pass, double precision): launch latency of one
+    plain fsm_simulate call, eager and replayed from a captured graph: p50/p99 over `steps`
+    calls, each from the call to the roughness on the host."""
+    import torch
+    from paper_2603_28160_amd import workloads
+    sim = workloads.config1()
+    out = {"workload": sim.name, "precision": "f64", "steps": steps}
+    z = ctx.new_zmap(sim.grid, "f64")
+    for graphs in (False, True):
+        ctx.set_graphs(graphs)
+        for _ in range(10):
+            ctx.fsm_simulate(sim, "f64", z)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(steps):
+            a = time.perf_counter()
+            ctx.fsm_simulate(sim, "f64", z)
+            lat.append((time.perf_counter() - a) * 1e3)
+        out["graphs" if graphs else "eager"] = {"p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                                                "mean_ms": statistics.mean(lat)}
+    ctx.set_graphs(False)
+    print(f"[bench] config1 f64 latency: eager p50 {out['eager']['p50_ms']:.3f} ms, graphs p50 "
+          f"{out['graphs']['p50_ms']:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
+def stage_rooflines(sim, plan, prec, prof, run_mode=False):
+    """Roofline of every stage of one step, per launch, from the library's HIP events (recorded
+    on the stream it launches on).  The binning passes are bound by the vector rate: the
+    algorithmic work is flop_per_eval(tool) times the evaluations.  The scans move the row
+    matrix and are reported by time.  The tile reduction reads every bucket entry (key + 16-bit
+    cell) and writes every cell; the roughness reads every cell once more (its first pass is
+    fused into the reduction)."""
+    r = prof["rough"]
+    n_launch = max(1, prof["n_slices"])
+    cells = sim.grid.nx * sim.grid.ny
+    kb = KEY_BYTES[prec]
+    names = ("bin_points<%s,false>" if run_mode else "hist_count<%s>",
+             "bin_points<%s,true>" if run_mode else "hist_write<%s>")
+    fpe = flop_per_eval(sim.tool)
+    out = {}
+    for stage, name in (("count", names[0]), ("write", names[1])):
+        ms = prof[f"{stage}_ms"] / n_launch
+        if ms <= 0.0:
+            continue
+        a = fpe * plan["n_evals"] / n_launch / (ms * 1e-3) / 1e12
+        out[stage] = {"kernel": name % prec, "bound": "alu", "unit": "TFLOP/s", "launch_ms": ms,
+                      "flop_per_eval": fpe, "achieved": a, "peak": VALU_PEAK_TFLOPS[prec],
+                      "frac": a / VALU_PEAK_TFLOPS[prec]}
+    if prof["index_ms"] > 0.0:
+        out["index"] = {"kernel": "row-matrix scans" if not run_mode else "tile-count scan",
+                        "bound": "hbm", "launch_ms": prof["index_ms"] / n_launch}
+    ms = prof["reduce_ms"] / n_launch
+    if ms > 0.0:
+        work = (r["n_binned"] * (kb + 2) + cells * kb) / n_launch
+        a = work / (ms * 1e-3) / 1e9
+        out["reduce"] = {"kernel": f"tile_reduce<{prec}>", "bound": "hbm", "unit": "GB/s",
+                         "launch_ms": ms, "bytes_per_launch": work, "achieved": a,
+                         "peak": HBM_PEAK_GBS, "frac": a / HBM_PEAK_GBS}
+    ms = prof["rough_ms"]
+    if ms > 0.0:
+        a = cells * kb / (ms * 1e-3) / 1e9
+        out["roughness"] = {"kernel": f"tile_stats2<{prec}> + combines", "bound": "hbm",
+                            "unit": "GB/s", "launch_ms": ms, "bytes_per_launch": cells * kb,
+                            "achieved": a, "peak": HBM_PEAK_GBS, "frac": a / HBM_PEAK_GBS}
     return out
 
 
 def roofline(sim, plan, prec, prof):
-    """Roofline of the longest stage of the Z-map, timed with HIP events on the stream the
-    library launches on (mean over the profiled steps, per launch)."""
+    """Roofline of the longest stage of the Z-map (the dominant kernel), timed with HIP events
+    on the stream the library launches on (mean over the profiled steps, per launch), with the
+    HBM traffic of the committed counter summary when it was taken on this kernel source."""
     stages = {k: prof[f"{k}_ms"] for k in ("count", "write", "reduce")}
     stage = max(stages, key=stages.get)
     n_launch = max(1, prof["n_slices"])
@@ -362,6 +489,78 @@ def roofline(sim, plan, prec, prof):
     return out
 
 
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(sim, max_threads=16):
+    """The FP64 oracle, unchanged, on the host cores: the whole workload on one thread, then
+    on all the process's cores as one task per pass (a pass run alone sits at the same y as in
+    the raster, so the passes' maps merge by cell-wise minimum into the same map bit for bit,
+    which is checked).  Returns (record, the one-thread map)."""
+    import dataclasses
+    from concurrent.futures import ThreadPoolExecutor, as_completed
+
+    import oracle
+    model, nproc = cpu_info()
+    print(f"[bench] cpu baseline: FP64 oracle on the full workload, 1 thread then "
+          f"{min(nproc, max_threads)} ({model})", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    zo, cnt = oracle.simulate(sim)
+    el1 = time.perf_counter() - t0
+    pl = oracle.plan(sim)
+    base = dataclasses.replace(sim.cut, x_start=pl["x_start"], n_steps=pl["n_steps"], n_passes=1)
+    passes = [sim.replace(cut=dataclasses.replace(base, y_first=pl["y_first"] + float(q) * sim.cut.a_e))
+              for q in range(pl["n_passes"])]
+    threads = min(nproc, max_threads)
+    t0 = time.perf_counter()
+    acc = None
+    with ThreadPoolExecutor(threads) as pool:
+        for f in as_completed([pool.submit(oracle.simulate, p) for p in passes]):
+            z, _ = f.result()
+            acc = z if acc is None else np.minimum(acc, z, out=acc)
+    eln = time.perf_counter() - t0
+    same = bool(np.array_equal(acc, zo))
+    n_cells = sim.grid.nx * sim.grid.ny
+    rec = {"value": n_cells / el1, "unit": "cells/s", "cores": 1, "kind": "oracle",
+           "sample": f"full {sim.name} FP64, one simulation, {el1:.1f} s",
+           "cpu_model": model, "nproc": nproc,
+           "all_cores": {"value": n_cells / eln, "unit": "cells/s", "threads": threads,
+                         "s": eln, "identical_to_one_thread": same,
+                         "split": f"{len(passes)} single-pass tasks merged by cell-wise minimum"}}
+    return rec, zo
+
+
+def f32_error(zg, rg, zo):
+    """Error statement of the single-precision map against the FP64 oracle's map of the same
+    workload: the library's own bound and near-boundary count, the cells whose hit state or
+    height moved beyond that bound, the cells outside +-2e-6 mm, and the relative error of
+    every roughness parameter."""
+    import oracle
+    ro = oracle.roughness(zo)
+    hg, ho = np.isfinite(zg), np.isfinite(zo)
+    both = hg & ho
+    d = np.where(both, np.abs(zg - zo), 0.0)
+    rel = {}
+    for k in ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean"):
+        rel[k] = abs(rg[k] - ro[k]) / abs(ro[k]) if ro[k] else abs(rg[k] - ro[k])
+    return {"against": "FP64 oracle, full map", "pos_err_mm": rg["pos_err"],
+            "n_near": rg["n_near"], "n_binned": rg["n_binned"],
+            "hit_state_changed": int((hg != ho).sum()),
+            "cells_moved_beyond_pos_err": int((hg != ho).sum() + (d > rg["pos_err"]).sum()),
+            "cells_outside_2e-6_mm": int((d > 2e-6).sum()),
+            "max_abs_dz_same_hit_mm": float(d.max()),
+            "rel_err": rel, "rel_err_max_areal": max(rel[k] for k in ("Sa", "Sq", "Ssk", "Sku"))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1, help="GPUs to use; only 1 is supported")
@@ -385,12 +584,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batch (configuration 3) and serving (configuration 4) legs")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated extra legs to run (default all): batch, serving, "
-                         "large_field, paper_mode, coverage_complete, dataset")
+                    help="comma-separated extra legs to run (default all): latency, batch, "
+                         "serving, large_field, paper_mode, coverage_complete, dataset")
     ap.add_argument("--batch-sims", type=int, default=256, help="simulations in the batch leg")
-    ap.add_argument("--serve-requests", type=int, default=400, help="requests in the serving leg")
-    ap.add_argument("--serve-rate", type=float, default=500.0,
-                    help="Poisson arrival rate of the serving leg, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests per arrival rate in the serving leg (0: 2000, 1000 below "
+                         "100 requests/s)")
+    ap.add_argument("--serve-rates", default=",".join(f"{r:g}" for r in SERVE_RATES),
+                    help="comma-separated Poisson arrival rates of the serving leg, requests/s")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reads 1 GiB, writes "
                          "1 GiB) five times, to scale HBM byte counters")
@@ -447,9 +648,17 @@ def main():
                   f"(count {p['count_ms']:.3f}, index {p['index_ms']:.3f}, write {p['write_ms']:.3f}, "
                   f"reduce {p['reduce_ms']:.3f}), roughness {p['rough_ms']:.3f} ms",
                   file=sys.stderr, flush=True)
+        # the single-precision map of the workload, for its error against the oracle
+        f32_map = f32_rough = None
+        if "f32" in precs and not args.no_cpu_baseline:
+            z32, f32_rough = ctx.fsm_simulate(sim, "f32")
+            f32_map = z32.cpu().numpy().astype(np.float64)
+            del z32
         extras = {}
-        legs = {"batch": lambda: batch_leg(ctx, args.batch_sims),
-                "serving": lambda: serve_leg(ctx, args.serve_requests, args.serve_rate),
+        rates = tuple(float(x) for x in args.serve_rates.split(",") if x)
+        legs = {"latency": lambda: latency_leg(ctx),
+                "batch": lambda: batch_leg(ctx, args.batch_sims),
+                "serving": lambda: serve_leg(ctx, rates, args.serve_requests),
                 "large_field": lambda: large_leg(ctx),
                 "paper_mode": lambda: paper_leg(ctx),
                 "coverage_complete": lambda: coverage_leg(ctx),
@@ -496,6 +705,7 @@ def main():
         "coverage": r["n_hit"] / n_cells,
         "kernel_ms": kernel_ms(m["prof"]),
         "roofline": roofline(sim, plan, main_prec, m["prof"]),
+        "rooflines": stage_rooflines(sim, plan, main_prec, m["prof"]),
     }
     for prec in res:
         if prec == main_prec:
@@ -506,20 +716,14 @@ def main():
                      "latency_ms": {"p50": pct(o["lat"], 50), "p99": pct(o["lat"], 99)},
                      "kernel_ms": kernel_ms(o["prof"]),
                      "roofline": roofline(sim, plan, prec, o["prof"]),
-                     "Sa": o["rough"]["Sa"], "Sa_f64": r["Sa"]}
+                     "rooflines": stage_rooflines(sim, plan, prec, o["prof"])}
     if other:
         out["other_strategy"] = other
     out.update(extras)
     if not args.no_cpu_baseline:
-        import oracle
-        print("[bench] cpu baseline: FP64 oracle on the full workload, 1 thread",
-              file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        oracle.simulate(sim)
-        el = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": n_cells / el, "unit": "cells/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"full {sim.name} FP64, one simulation, {el:.1f} s"}
+        out["cpu_baseline"], zo = cpu_baseline(sim)
+        if f32_map is not None:
+            out["f32_error"] = f32_error(f32_map, f32_rough, zo)
     print(json.dumps(out), flush=True)
 
 
