@@ -225,7 +225,7 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
                                        LDS and store it once; FSM_ZMAP_SCATTER: one global
                                        atomic min per point */
 #define FSM_OPT_BUCKET_BYTES 2    /* device bytes the binned strategy may use for its point
-                                       buckets (default 4 GiB); larger simulations run in
+                                       buckets (default 8 GiB); larger simulations run in
                                        slices of the evaluation range */
 #define FSM_OPT_GRAPHS 3           /* nonzero: capture the launch sequences of fsm_simulate and
                                        fsm_simulate_batch into HIP graphs (on a stream of the
@@ -233,7 +233,8 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
                                        later calls of the same shape */
 #define FSM_OPT_TILE_SHAPE 4      /* cell tile of the binned Z-map and of the roughness partials:
                                        16 * log2(width) + log2(height), both 16..256 cells and the
-                                       tile's keys at most 64 KiB; 0 (default): 64 x 64 cells in
+                                       tile's keys within the device's LDS per workgroup (160
+                                       KiB on gfx950); 0 (default): 64 x 64 cells in
                                        double precision, 128 x 64 in single */
 #define FSM_OPT_TARGET_ROWS 5     /* binning rows (one workgroup each) per launch of the
                                        histogram mode, 256..65536; 0 (default): 4096 */
@@ -257,7 +258,11 @@ int fsm_ctx_set_profiling(fsm_ctx *ctx, int on);
 /* Timings of the last profiled call (valid == 0 if there is none). */
 int fsm_last_timings(const fsm_ctx *ctx, fsm_timings *out);
 
-/* One simulation.  zmap_dev: caller-owned device memory of nx*ny doubles (FSM_F64) or floats
+/* One simulation: the forward solution of Sec. 2.3 -- every edge point of Eq. (6) at every time
+ * step moved into the workpiece frame by Eq. (2)-(5), binned into the sampling boundary of a
+ * grid node by Eq. (7) and kept as that node's lowest height -- then the roughness of the map
+ * (Sec. 4.1: ISO 25178-2 amplitude parameters, profile Ra).
+ * zmap_dev: caller-owned device memory of nx*ny doubles (FSM_F64) or floats
  * (FSM_F32), overwritten with the Z-map.  out: host memory for the roughness, or NULL to
  * compute the Z-map only.  The work is queued on `stream`; the call returns after it has
  * finished.  FSM_EINVAL on bad parameters, FSM_EDEVICE on a HIP error. */
@@ -298,7 +303,8 @@ typedef struct fsm_job {
     void *zmap_dev;          /* caller-owned device Z-map of this job (precision of the batch) */
 } fsm_job;
 
-/* Many simulations of different shapes in one launch sequence: all their work items and
+/* Many simulations of different shapes in one launch sequence (the dataset generation of
+ * Sec. 4.3, which calls the method for many parameter sets): all their work items and
  * tiles are numbered consecutively and every kernel of the pipeline covers the whole batch
  * at once, so small and large simulations share the device (the batched form of the method,
  * used for dataset generation).  out: n host records.  With FSM_OPT_GRAPHS on, the launch
@@ -371,7 +377,9 @@ int fsm_tune_get(const fsm_ctx *ctx, fsm_tune_entry *out, int cap, int *n);
 int fsm_tune_set(fsm_ctx *ctx, const fsm_tune_entry *entries, int n);
 
 /* Roughness of an existing Z-map in device memory (+inf = empty cell), same estimator as
- * fsm_simulate.  n_evals and n_binned of the result are zero. */
+ * fsm_simulate: the ISO 25178-2 amplitude parameters of Sec. 4.1 about the mean plane of the
+ * reached cells, and the profile Ra of Sec. 4.1 along row ny/2 and column nx/2.  n_evals and
+ * n_binned of the result are zero. */
 int fsm_roughness(fsm_ctx *ctx, const fsm_grid *grid, int precision, const void *zmap_dev,
                   fsm_rough *out, void *stream);
 

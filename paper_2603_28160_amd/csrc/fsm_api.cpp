@@ -59,9 +59,9 @@ bool valid_tile_shape(const fsm_ctx *ctx, int precision, int code)
 {
     const int sx = code >> 4, sy = code & 15;
     const size_t key = precision == FSM_F64 ? 8 : 4;
-    const size_t lds = std::min<size_t>(ctx->max_lds, 65536);
+    // the tile's keys live in LDS during the reduction; cell indices inside a tile are 16-bit
     return code >= 0 && (code >> 8) == 0 && sx >= 4 && sx <= 8 && sy >= 4 && sy <= 8 &&
-           (key << (sx + sy)) <= lds;
+           (key << (sx + sy)) <= ctx->max_lds;
 }
 
 void choose_tiles(const fsm_ctx *ctx, int precision, int code, int &sx, int &sy)
@@ -1090,7 +1090,8 @@ int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tu
         best = base;
         best_ms = base_ms;
         // 1. tile shape with the default rows
-        static const int shapes[] = {0x55, 0x65, 0x56, 0x66, 0x75, 0x76, 0x67, 0x77, 0x86};
+        static const int shapes[] = {0x55, 0x65, 0x56, 0x66, 0x75, 0x76, 0x67, 0x77, 0x86, 0x68,
+                                     0x78, 0x87};
         for (int code : shapes) {
             int dsx = 0, dsy = 0;
             choose_tiles(ctx, precision, 0, dsx, dsy);

@@ -28,6 +28,7 @@
 // (centre plus the widened float offset) and the binning stay in double.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -169,6 +170,9 @@ int stream_blocks(int64_t work, int64_t per_block, int cap)
 
 constexpr int64_t kMaxGrid = (int64_t)1 << 20;
 
+// Tiles with more keys than this run their reduction with eight waves per block.
+constexpr size_t kTileLdsSmall = 65536;
+
 // ---- fill ------------------------------------------------------------------------------------
 
 // Every Z-map of a set starts at +inf (the scatter strategy min-reduces into it).  The map
@@ -236,23 +240,35 @@ __device__ __forceinline__ Turn<PREC> spindle_turn(const DevSim &d, int K, int m
     return t;
 }
 
+// Tilt modes: which of the two tilt rotations a simulation applies (bit 0 lead, bit 1 side).
+// Kernels that walk many points pick the mode once per row and run a specialised loop; kTiltAny
+// reads the flags per call.
+constexpr int kTiltLead = 1, kTiltSide = 2, kTiltAny = -1;
+__device__ __forceinline__ int tilt_mode(const DevSim &d)
+{
+    return (d.tilt_lead ? kTiltLead : 0) | (d.tilt_side ? kTiltSide : 0);
+}
+
 // Workpiece-frame horizontal offsets (xs, ys) of an edge point from the tool centre, and its
 // height key.  Double precision: Eq. (3) [[c, s], [-s, c]] then the tilt rotations, in the
 // oracle's operation order with no contraction.  Single precision: the same with fused
 // multiply-adds.
+template <int TILT = kTiltAny>
 __device__ __forceinline__ void turn_point(const DevSim &d, const Turn<FSM_F64> &a,
                                            const Edge<FSM_F64> &e, double &xs, double &ys,
                                            int64_t &key)
 {
+    const bool lead = TILT == kTiltAny ? d.tilt_lead != 0 : (TILT & kTiltLead) != 0;
+    const bool side = TILT == kTiltAny ? d.tilt_side != 0 : (TILT & kTiltSide) != 0;
     double x = a.c * e.x + a.s * e.y;
     double y = a.c * e.y - a.s * e.x;
     double z = e.z;
-    if (d.tilt_lead) {
+    if (lead) {
         const double x1 = d.tl_c * x + d.tl_s * z;
         z = d.tl_c * z - d.tl_s * x;
         x = x1;
     }
-    if (d.tilt_side) {
+    if (side) {
         const double y1 = d.ts_c * y - d.ts_s * z;
         z = d.ts_s * y + d.ts_c * z;
         y = y1;
@@ -261,20 +277,23 @@ __device__ __forceinline__ void turn_point(const DevSim &d, const Turn<FSM_F64> 
     ys = y;
     key = enc64(__double_as_longlong(z));
 }
+template <int TILT = kTiltAny>
 __device__ __forceinline__ void turn_point(const DevSim &d, const Turn<FSM_F32> &a,
                                            const Edge<FSM_F32> &e, float &xs, float &ys,
                                            int32_t &key)
 {
+    const bool lead = TILT == kTiltAny ? d.tilt_lead != 0 : (TILT & kTiltLead) != 0;
+    const bool side = TILT == kTiltAny ? d.tilt_side != 0 : (TILT & kTiltSide) != 0;
     float x = fmaf(a.c, e.x, a.s * e.y);
     float y = fmaf(a.c, e.y, -(a.s * e.x));
     float z = e.z;
-    if (d.tilt_lead) {
+    if (lead) {
         const float c = (float)d.tl_c, s = (float)d.tl_s;
         const float x1 = fmaf(c, x, s * z);
         z = fmaf(c, z, -(s * x));
         x = x1;
     }
-    if (d.tilt_side) {
+    if (side) {
         const float c = (float)d.ts_c, s = (float)d.ts_s;
         const float y1 = fmaf(c, y, -(s * z));
         z = fmaf(s, y, c * z);
@@ -305,22 +324,24 @@ __device__ __forceinline__ bool bin_cell(const DevSim &d, double xcs, double yq,
 // double: the workpiece position x_c + (double)x_S and its cell follow in double precision,
 // exactly as for a double-precision point.  near (single precision): the position lies within
 // the error bound of a cell boundary, so double precision might bin it into a neighbour.
+template <int TILT = kTiltAny>
 __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F64> &a,
                                             const Edge<FSM_F64> &e, double xcs, double yq,
                                             int32_t &i, int32_t &j, int64_t &key, bool &near)
 {
     double xs, ys, fx, fy;
-    turn_point(d, a, e, xs, ys, key);
+    turn_point<TILT>(d, a, e, xs, ys, key);
     near = false;
     return bin_cell(d, xcs, yq, xs, ys, i, j, fx, fy);
 }
+template <int TILT = kTiltAny>
 __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F32> &a,
                                             const Edge<FSM_F32> &e, double xcs, double yq,
                                             int32_t &i, int32_t &j, int32_t &key, bool &near)
 {
     float xs, ys;
     double fx, fy;
-    turn_point(d, a, e, xs, ys, key);
+    turn_point<TILT>(d, a, e, xs, ys, key);
     const bool in = bin_cell(d, xcs, yq, (double)xs, (double)ys, i, j, fx, fy);
     const double rx = fx - (double)i, ry = fy - (double)j, w = d.near_w;
     near = in && (rx < w || rx > 1.0 - w || ry < w || ry > 1.0 - w);
@@ -373,14 +394,14 @@ __device__ __forceinline__ bool wave_near(const DevSim &d, const WaveSteps &w, d
 // places the group's reference point at its own step, the first and last lanes' offsets span
 // a box that the group's margin widens (arc sagitta, group spread, rounding slack).  Called in
 // uniform control flow with every lane up to w.last active.
-template <int PREC>
+template <int PREC, int TILT = kTiltAny>
 __device__ __forceinline__ bool group_near(const DevSim &d, const Turn<PREC> &a,
                                            const Edge<PREC> &ref, int K, int g,
                                            const WaveSteps &w, double yq)
 {
     typename KeyOf<PREC>::T k;
     decltype(ref.x) fx, fy;
-    turn_point(d, a, ref, fx, fy, k);
+    turn_point<TILT>(d, a, ref, fx, fy, k);
     const double ax = (double)fx, ay = (double)fy;
     const double ax0 = lane_value(ax, 0), ax1 = lane_value(ax, w.last);
     const double ay0 = lane_value(ay, 0), ay1 = lane_value(ay, w.last);
@@ -634,15 +655,17 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
 // recomputes the points, claiming slots with LDS atomics on the row's cursors.
 
 // Visit every in-grid point of binning items [i0, i1) of simulation d: f(tile, cell, key, near)
-// with the tile numbered inside the simulation.  Lanes hold consecutive time steps; the edge points
-// are walked one at a time (the compiler overlaps consecutive iterations).
-template <int PREC, typename F>
-__device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t i1, F &&f)
+// with the tile numbered inside the simulation.  Lanes hold consecutive time steps; the edge
+// points of a culling group are loaded kBatch at a time ahead of their arithmetic.
+constexpr int kBatch = 4;
+template <int PREC, int TILT, typename F>
+__device__ __forceinline__ void row_points_tilt(const DevSim &d, int64_t i0, int64_t i1, F &f)
 {
     using Key = typename KeyOf<PREC>::T;
     const int lane = threadIdx.x & 63;
     const int sx = d.sx, sy = d.sy;
     const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
+    const uint32_t tiles_x = (uint32_t)d.tiles_x;
     for (int64_t it = i0; it < i1; ++it) {
         int64_t local = it;
         const int K = (int)(local % d.z_n);
@@ -659,17 +682,38 @@ __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t 
         const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
         const double xcs = centre_x(d, s);
         for (int g = 0; g < d.n_groups; ++g) {
-            if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
+            if (!group_near<PREC, TILT>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
             const int pg = g * kGroup;
             const int pe = pg + kGroup < d.N ? pg + kGroup : d.N;
-            for (int p = pg; p < pe; ++p) {
-                Key key;
-                int32_t i, j;
-                bool near;
-                if (act && place_point(d, a, edge_point<PREC>(d, K, p), xcs, yq, i, j, key, near))
-                    f((j >> sy) * d.tiles_x + (i >> sx), (uint16_t)(((j & my) << sx) | (i & mx)), key, near);
+            for (int p = pg; p < pe; p += kBatch) {
+                Edge<PREC> e[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) e[u] = edge_point<PREC>(d, K, p + u < pe ? p + u : pe - 1);
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    Key key;
+                    int32_t i, j;
+                    bool near;
+                    // the tile is numbered inside the simulation; a histogram holds at most
+                    // kMaxHistTiles tiles, so both factors fit the 24-bit multiply
+                    if (p + u < pe && act && place_point<TILT>(d, a, e[u], xcs, yq, i, j, key, near))
+                        f((int32_t)(__umul24((uint32_t)(j >> sy), tiles_x) + (uint32_t)(i >> sx)),
+                          (uint16_t)(((j & my) << sx) | (i & mx)), key, near);
+                }
             }
         }
+    }
+}
+
+// The same with the simulation's tilt mode fixed once for the row.
+template <int PREC, typename F>
+__device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t i1, F &&f)
+{
+    switch (tilt_mode(d)) {
+    case 0: row_points_tilt<PREC, 0>(d, i0, i1, f); break;
+    case kTiltLead: row_points_tilt<PREC, kTiltLead>(d, i0, i1, f); break;
+    case kTiltSide: row_points_tilt<PREC, kTiltSide>(d, i0, i1, f); break;
+    default: row_points_tilt<PREC, kTiltLead | kTiltSide>(d, i0, i1, f); break;
     }
 }
 
@@ -947,21 +991,50 @@ struct Stat1Acc {
             if (on_col) { col_sum += v; ++col_n; }
         }
     }
+    // Block totals in every thread of a block of NW waves: butterflies within each wave, then
+    // the waves' partials by a pairwise tree in wave order (for four waves, the order of
+    // block_reduce), with one barrier for all eight values.
+    template <int NW = kWaves>
     __device__ TileStat1 reduce()
     {
-        __shared__ double bd[4];
-        __shared__ int64_t bl[4];
-        __shared__ int32_t bi[4];
+        static_assert(NW == 4 || NW == 8, "four or eight waves");
+        __shared__ double bd[5][8];
+        __shared__ int64_t bl[8];
+        __shared__ int32_t bi[2][8];
+        const int w = threadIdx.x >> 6;
+        const double s0 = wave_sum(sum), s1 = wave_min(mn), s2 = wave_max(mx);
+        const double s3 = wave_sum(row_sum), s4 = wave_sum(col_sum);
+        const int64_t c0 = wave_sum(n);
+        const int32_t c1 = wave_sum(row_n), c2 = wave_sum(col_n);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            bd[0][w] = s0;
+            bd[1][w] = s1;
+            bd[2][w] = s2;
+            bd[3][w] = s3;
+            bd[4][w] = s4;
+            bl[w] = c0;
+            bi[0][w] = c1;
+            bi[1][w] = c2;
+        }
+        __syncthreads();
         TileStat1 t;
-        t.sum = block_sum(sum, bd);
-        t.mn = block_reduce(wave_min(mn), bd, Min());
-        t.mx = block_reduce(wave_max(mx), bd, Max());
-        t.row_sum = block_sum(row_sum, bd);
-        t.col_sum = block_sum(col_sum, bd);
-        t.n = block_sum(n, bl);
-        t.row_n = block_sum(row_n, bi);
-        t.col_n = block_sum(col_n, bi);
+        t.sum = tree<NW>(bd[0], Add());
+        t.mn = tree<NW>(bd[1], Min());
+        t.mx = tree<NW>(bd[2], Max());
+        t.row_sum = tree<NW>(bd[3], Add());
+        t.col_sum = tree<NW>(bd[4], Add());
+        t.n = tree<NW>(bl, Add());
+        t.row_n = tree<NW>(bi[0], Add());
+        t.col_n = tree<NW>(bi[1], Add());
         return t;
+    }
+    template <int NW, typename T, typename Op>
+    __device__ static T tree(const T *v, Op op)
+    {
+        const T a = op(op(v[0], v[1]), op(v[2], v[3]));
+        if constexpr (NW == 4) return a;
+        else return op(a, op(op(v[4], v[5]), op(v[6], v[7])));
     }
 };
 
@@ -985,9 +1058,11 @@ __device__ __forceinline__ TileGeom tile_geom(const DevSim &d, int64_t t)
 
 // Tiles [bb.tile0, bb.tile0 + n_tiles).  first_slice / last_slice: whether the tiles start
 // from +inf (else from the Z-map) and whether the first roughness pass runs; -1 takes both per
-// simulation from the slice's rows [r0, r1) (histogram mode).
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__ sims, int n_sims,
+// simulation from the slice's rows [r0, r1) (histogram mode).  NT threads per block: tiles of
+// more than 64 KiB of keys leave room for one block per compute unit, which then takes eight
+// waves to keep enough bucket loads in flight.
+template <int PREC, int NT>
+__global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sims, int n_sims,
                                                       const int64_t *__restrict__ tile_base,
                                                       int64_t n_tiles, BinBuffers bb, int first_slice,
                                                       int last_slice, int64_t r0, int64_t r1,
@@ -1011,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
         const TileGeom g = tile_geom(d, t);
         const int sx = d.sx, TX = 1 << sx, TC = TX << d.sy;
         FSM_GLOBAL Key *Z = gptr(static_cast<Key *>(d.zmap)) + g.j0 * d.nx + g.i0;
-        for (int l = tid; l < TC; l += kBlock) {
+        for (int l = tid; l < TC; l += NT) {
             const int li = l & (TX - 1), lj = l >> sx;
             Key v = KT::inf;
             if (!first && li < g.w && lj < g.h) v = KT::enc(Z[(int64_t)lj * d.nx + li]);
@@ -1027,26 +1102,26 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
         // Z-map, which the roughness passes read next
         uint32_t e = e0 + tid;
         constexpr int kDepth = 8;   // bucket entries in flight per thread
-        for (; e + (kDepth - 1) * kBlock < e1; e += kDepth * kBlock) {
+        for (; e + (kDepth - 1) * NT < e1; e += kDepth * NT) {
             Key k4[kDepth];
             uint16_t c4[kDepth];
 #pragma unroll
             for (int v = 0; v < kDepth; ++v) {
-                k4[v] = __builtin_nontemporal_load(&bkey[e + v * kBlock]);
-                c4[v] = __builtin_nontemporal_load(&bix[e + v * kBlock]);
+                k4[v] = __builtin_nontemporal_load(&bkey[e + v * NT]);
+                c4[v] = __builtin_nontemporal_load(&bix[e + v * NT]);
             }
 #pragma unroll
             for (int v = 0; v < kDepth; ++v)
                 __hip_atomic_fetch_min(&lds[c4[v]], k4[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        for (; e < e1; e += kBlock)
+        for (; e < e1; e += NT)
             __hip_atomic_fetch_min(&lds[__builtin_nontemporal_load(&bix[e])], __builtin_nontemporal_load(&bkey[e]),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (tid == 0 && e1 > e0) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)(e1 - e0));
         __syncthreads();
         Stat1Acc acc;
         const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
-        for (int l = tid; l < TC; l += kBlock) {
+        for (int l = tid; l < TC; l += NT) {
             const int li = l & (TX - 1), lj = l >> sx;
             if (li < g.w && lj < g.h) {
                 const Key k = KT::enc(lds[l]);
@@ -1055,7 +1130,7 @@ __global__ __launch_bounds__(kBlock) void tile_reduce(const DevSim *__restrict__
             }
         }
         if (last) {
-            const TileStat1 s = acc.reduce();
+            const TileStat1 s = acc.reduce<NT / 64>();
             if (tid == 0) st1[t] = s;
         }
         __syncthreads();
@@ -1147,7 +1222,10 @@ struct Stat2Acc {
     }
 };
 
-// Second pass: central moments about each simulation's mean, and the profile deviations.
+// Second pass: central moments about each simulation's mean, and the profile deviations.  One
+// block per tile, its threads over consecutive cells of the tile's rows with kRows2 loads in
+// flight each; the waves' butterfly sums are combined left to right after one barrier.
+constexpr int kRows2 = 8;
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__ sims, int n_sims,
                                                       const int64_t *__restrict__ tile_base,
@@ -1156,34 +1234,66 @@ __global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__
 {
     using KT = KeyOf<PREC>;
     using Key = typename KT::T;
-    const int tid = threadIdx.x;
+    __shared__ double part[6][kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
-        const DevSim d = sims[si];
+        const DevSim &d = sims[si];
         const RoughState st = state[d.sim];
         const TileGeom g = tile_geom(d, t);
-        const int TX = 1 << d.sx, TC = TX << d.sy;
-        const FSM_GLOBAL Key *Z = gptr(static_cast<const Key *>(d.zmap)) + g.j0 * d.nx + g.i0;
+        const int sx = d.sx, TX = 1 << sx, TC = TX << d.sy;
+        const int64_t nx = d.nx;
+        const FSM_GLOBAL Key *Z = gptr(static_cast<const Key *>(d.zmap)) + g.j0 * nx + g.i0;
         const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
-        Stat2Acc a;
-        for (int l = tid; l < TC; l += kBlock) {
-            const int li = l & (TX - 1), lj = l >> d.sx;
-            if (li < g.w && lj < g.h) {
-                const double v = KT::height(Z[(int64_t)lj * d.nx + li]);
-                if (v < INFINITY) {
-                    const double dv = v - st.mean;
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, row_abs = 0.0, col_abs = 0.0;
+        for (int l0 = tid; l0 < TC; l0 += kRows2 * kBlock) {
+            double v[kRows2];
+#pragma unroll
+            for (int u = 0; u < kRows2; ++u) {
+                const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
+                v[u] = l < TC && li < g.w && lj < g.h ? KT::height(Z[(int64_t)lj * nx + li]) : INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < kRows2; ++u) {
+                if (v[u] < INFINITY) {
+                    const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
+                    const double dv = v[u] - st.mean;
                     const double d2 = dv * dv;
-                    a.s1 += fabs(dv);
-                    a.s2 += d2;
-                    a.s3 += d2 * dv;
-                    a.s4 += d2 * d2;
-                    if (lj == rj) a.row_abs += fabs(v - st.row_mean);
-                    if (li == ci) a.col_abs += fabs(v - st.col_mean);
+                    s1 += fabs(dv);
+                    s2 += d2;
+                    s3 += d2 * dv;
+                    s4 += d2 * d2;
+                    if (lj == rj) row_abs += fabs(v[u] - st.row_mean);
+                    if (li == ci) col_abs += fabs(v[u] - st.col_mean);
                 }
             }
         }
-        const TileStat2 s = a.reduce();
-        if (tid == 0) st2[t] = s;
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        s3 = wave_sum(s3);
+        s4 = wave_sum(s4);
+        row_abs = wave_sum(row_abs);
+        col_abs = wave_sum(col_abs);
+        if (lane == 0) {
+            part[0][wv] = s1;
+            part[1][wv] = s2;
+            part[2][wv] = s3;
+            part[3][wv] = s4;
+            part[4][wv] = row_abs;
+            part[5][wv] = col_abs;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            TileStat2 r;
+            r.s1 = (part[0][0] + part[0][1]) + (part[0][2] + part[0][3]);
+            r.s2 = (part[1][0] + part[1][1]) + (part[1][2] + part[1][3]);
+            r.s3 = (part[2][0] + part[2][1]) + (part[2][2] + part[2][3]);
+            r.s4 = (part[3][0] + part[3][1]) + (part[3][2] + part[3][3]);
+            r.row_abs = (part[4][0] + part[4][1]) + (part[4][2] + part[4][3]);
+            r.col_abs = (part[5][0] + part[5][1]) + (part[5][2] + part[5][3]);
+            st2[t] = r;
+        }
+        __syncthreads();
     }
 }
 
@@ -1314,7 +1424,10 @@ void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
     if (ib > 0)
         hipLaunchKernelGGL((bin_points<PREC, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
     stage(marks, 3, s);
-    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
+    if (lds > kTileLdsSmall)
+        hipLaunchKernelGGL((tile_reduce<PREC, 2 * kBlock>), dim3(tb), dim3(2 * kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
+    else
+        hipLaunchKernelGGL((tile_reduce<PREC, kBlock>), dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
     stage(marks, 4, s);
 }
 
@@ -1348,7 +1461,10 @@ void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
     if (rb > 0)
         hipLaunchKernelGGL(hist_write<PREC>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
     stage(marks, 3, s);
-    hipLaunchKernelGGL(tile_reduce<PREC>, dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, -1, -1, row_begin, row_end, st1, d_binned);
+    if (lds > kTileLdsSmall)
+        hipLaunchKernelGGL((tile_reduce<PREC, 2 * kBlock>), dim3(tb), dim3(2 * kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, -1, -1, row_begin, row_end, st1, d_binned);
+    else
+        hipLaunchKernelGGL((tile_reduce<PREC, kBlock>), dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, -1, -1, row_begin, row_end, st1, d_binned);
     stage(marks, 4, s);
 }
 

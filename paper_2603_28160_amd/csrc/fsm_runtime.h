@@ -35,7 +35,7 @@ struct LaunchParams {
     int strategy = kStrategyBinned;
     int tile_shape = 0;
     int64_t target_rows = 4096;
-    int64_t bucket_bytes = (int64_t)4 << 30;
+    int64_t bucket_bytes = (int64_t)8 << 30;
     int64_t hist_bytes = (int64_t)1 << 30;   // row matrix of the histogram mode, at most
 };
 
@@ -82,7 +82,7 @@ struct fsm_ctx {
     int stages_used = 0;                      // slices of the last profiled call
     fsm_timings timings = {};
     int strategy = fsm::kStrategyBinned;
-    int64_t bucket_bytes = (int64_t)4 << 30;
+    int64_t bucket_bytes = (int64_t)8 << 30;
     bool graphs = false;
     int tile_shape = 0;          // FSM_OPT_TILE_SHAPE (0: default)
     int64_t target_rows = 4096;  // FSM_OPT_TARGET_ROWS

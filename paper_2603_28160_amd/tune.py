@@ -38,8 +38,6 @@ def main(argv=None):
     with Context(0) as ctx:
         for name, sims in jobs:
             for prec in ("f64", "f32"):
-                if name == "config5" and prec == "f64":
-                    continue
                 zmaps = [ctx.new_zmap(s.grid, prec) for s in sims]
                 t0 = time.perf_counter()
                 r = ctx.fsm_autotune(sims, prec, zmaps=zmaps)

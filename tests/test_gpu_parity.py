@@ -154,6 +154,23 @@ def test_binned_slices_f64_exact(ctx):
         ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 2 << 30)
 
 
+@pytest.mark.parametrize("shape", [0x77, 0x87])
+def test_large_tiles_exact(ctx, shape):
+    # tiles of 128 KiB (FP64 128 x 128, FP32 256 x 128): the reduction runs with eight waves
+    # per block; the double-precision map stays bit-exact and the single one inside its bounds
+    # (a shape too large for a precision falls back to that precision's default)
+    from paper_2603_28160_amd import _abi
+    s = W.config2(nx=777, ny=613, dd=0.004)
+    ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 0)
+    try:
+        ctx.fsm_ctx_set_option(_abi.OPT_TILE_SHAPE, shape)
+        check_f64(ctx, s)
+        check_f32(ctx, s)
+    finally:
+        ctx.fsm_ctx_set_option(_abi.OPT_TILE_SHAPE, 0)
+        ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 1)
+
+
 def test_paper_case2_tool_f64_exact(ctx):
     # the paper's own face-milling tool with rake and per-insert runout (Sec. 4.2)
     t = W.paper_case2_tool(eps_r=-0.026, eps_a=0.009, n_edge=30)
