@@ -386,6 +386,32 @@ def serve_leg(ctx, rates, n_req=None, max_batch=16, n_slots=2):
     return out
 
 
+def trajectory_leg(ctx, steps=5):
+    """The trajectory module (Sec. 3.2) on the configuration 2 path: for every pass, step and
+    tooth the lowest of the tooth's edge points in the workpiece frame, in both precisions;
+    time per call and evaluations/s.  It evaluates every edge point of every step (the lowest
+    point is wanted off the grid too), which the Z-map's culling skips."""
+    import torch
+    from paper_2603_28160_amd import fsm_plan, workloads
+    sim = workloads.config2()
+    plan = fsm_plan(sim)
+    out = {"workload": sim.name, "evals": plan["n_evals"],
+           "entries": plan["n_passes"] * plan["n_steps"] * sim.tool.n_teeth}
+    for prec in ("f64", "f32"):
+        ctx.fsm_trajectory(sim, prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.fsm_trajectory(sim, prec)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        out[prec] = {"ms": el * 1e3, "evals_per_s": plan["n_evals"] / el}
+        torch.cuda.empty_cache()
+    print(f"[bench] trajectory f64 {out['f64']['ms']:.3f} ms, f32 {out['f32']['ms']:.3f} ms",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def latency_leg(ctx, steps=200):
     """Configuration 1 (200 x 200 at 5 um, one pass, double precision): launch latency of one
     plain fsm_simulate call, eager and replayed from a captured graph: p50/p99 over `steps`
@@ -584,8 +610,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batch (configuration 3) and serving (configuration 4) legs")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated extra legs to run (default all): latency, batch, "
-                         "serving, large_field, paper_mode, coverage_complete, dataset")
+                    help="comma-separated extra legs to run (default all): latency, trajectory, "
+                         "batch, serving, large_field, paper_mode, coverage_complete, dataset")
     ap.add_argument("--batch-sims", type=int, default=256, help="simulations in the batch leg")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests per arrival rate in the serving leg (0: 2000, 1000 below "
@@ -657,6 +683,7 @@ def main():
         extras = {}
         rates = tuple(float(x) for x in args.serve_rates.split(",") if x)
         legs = {"latency": lambda: latency_leg(ctx),
+                "trajectory": lambda: trajectory_leg(ctx),
                 "batch": lambda: batch_leg(ctx, args.batch_sims),
                 "serving": lambda: serve_leg(ctx, rates, args.serve_requests),
                 "large_field": lambda: large_leg(ctx),

@@ -1248,10 +1248,20 @@ __global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__
         double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, row_abs = 0.0, col_abs = 0.0;
         for (int l0 = tid; l0 < TC; l0 += kRows2 * kBlock) {
             double v[kRows2];
+            // every load is issued (cells outside the tile read its first cell) so that all
+            // kRows2 are in flight together; their values are masked afterwards
+            Key k[kRows2];
 #pragma unroll
             for (int u = 0; u < kRows2; ++u) {
                 const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
-                v[u] = l < TC && li < g.w && lj < g.h ? KT::height(Z[(int64_t)lj * nx + li]) : INFINITY;
+                const bool in = l < TC && li < g.w && lj < g.h;
+                k[u] = Z[in ? (int64_t)lj * nx + li : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < kRows2; ++u) {
+                const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
+                const bool in = l < TC && li < g.w && lj < g.h;
+                v[u] = in ? KT::height(k[u]) : INFINITY;
             }
 #pragma unroll
             for (int u = 0; u < kRows2; ++u) {
