@@ -76,6 +76,12 @@ template <> struct KeyOf<FSM_F32> {
 };
 template <int PREC> __device__ __forceinline__ typename KeyOf<PREC>::T KT_inf() { return KeyOf<PREC>::inf; }
 
+// 16-byte vectors of keys (two double keys or four float keys) for the tile fill and drain.
+template <typename Key> struct KeyVec {
+    static constexpr int n = 16 / (int)sizeof(Key);
+    typedef Key T __attribute__((ext_vector_type(16 / sizeof(Key))));
+};
+
 // Block b of a launch runs on XCD (b mod 8).  Give every XCD a contiguous range of items so
 // that the items sharing one XCD's L2 are neighbours along the tool path.
 __device__ __forceinline__ int64_t xcd_item(int64_t b, int64_t G)
@@ -391,20 +397,21 @@ __device__ __forceinline__ bool wave_near(const DevSim &d, const WaveSteps &w, d
 }
 
 // False when no point of edge-point group g can land in the grid during the wave: every lane
-// places the group's reference point at its own step, the first and last lanes' offsets span
-// a box that the group's margin widens (arc sagitta, group spread, rounding slack).  Called in
-// uniform control flow with every lane up to w.last active.
+// places the group's reference point at its own step, the offsets of the lanes holding the
+// wave's first step (lane 0) and its last step (last_lane) span a box that the group's margin
+// widens (arc sagitta, group spread, rounding slack).  Called in uniform control flow with
+// every lane active.
 template <int PREC, int TILT = kTiltAny>
 __device__ __forceinline__ bool group_near(const DevSim &d, const Turn<PREC> &a,
                                            const Edge<PREC> &ref, int K, int g,
-                                           const WaveSteps &w, double yq)
+                                           const WaveSteps &w, int last_lane, double yq)
 {
     typename KeyOf<PREC>::T k;
     decltype(ref.x) fx, fy;
     turn_point<TILT>(d, a, ref, fx, fy, k);
     const double ax = (double)fx, ay = (double)fy;
-    const double ax0 = lane_value(ax, 0), ax1 = lane_value(ax, w.last);
-    const double ay0 = lane_value(ay, 0), ay1 = lane_value(ay, w.last);
+    const double ax0 = lane_value(ax, 0), ax1 = lane_value(ax, last_lane);
+    const double ay0 = lane_value(ay, 0), ay1 = lane_value(ay, last_lane);
     const double m = gptr(d.gm)[K * d.n_groups + g];
     return w.xc1 + fmax(ax0, ax1) + m >= d.x_lo && w.xc0 + fmin(ax0, ax1) - m < d.x_hi &&
            yq + fmax(ay0, ay1) + m >= d.y_lo && yq + fmin(ay0, ay1) - m < d.y_hi;
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
         const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
         uint32_t n_near = 0;
         for (int g = 0; g < d.n_groups; ++g) {
-            if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
+            if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, w.last, yq)) continue;
             const int pg = g * kGroup;
             Edge<PREC> ep[kGroup];
 #pragma unroll
@@ -655,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
 // recomputes the points, claiming slots with LDS atomics on the row's cursors.
 
 // Visit every in-grid point of binning items [i0, i1) of simulation d: f(tile, cell, key, near)
-// with the tile numbered inside the simulation.  Lanes hold consecutive time steps; the edge
+// with the tile numbered inside the simulation.  Lanes hold the steps of a wave; the edge
 // points of a culling group are loaded kBatch at a time ahead of their arithmetic.
 constexpr int kBatch = 4;
 template <int PREC, int TILT, typename F>
@@ -676,13 +683,18 @@ __device__ __forceinline__ void row_points_tilt(const DevSim &d, int64_t i0, int
         if (!wave_steps(d, sb, w)) continue;
         const double yq = d.y_first + (double)q * d.a_e;
         if (!wave_near(d, w, yq)) continue;
-        // lanes past the last step repeat it (they take part in the culling test only)
-        const bool act = lane <= w.last;
-        const int s = w.s0 + (act ? lane : w.last);
+        // the even steps of the wave go to lanes 0..31 and the odd ones to lanes 32..63, so
+        // that neighbouring steps, which often share a tile, fall into different halves of
+        // the wave's LDS accesses; lanes past the last step repeat it (they take part in the
+        // culling test only)
+        const int o = ((lane & 31) << 1) | (lane >> 5);
+        const int last_lane = (w.last >> 1) | ((w.last & 1) << 5);
+        const bool act = o <= w.last;
+        const int s = w.s0 + (act ? o : w.last);
         const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
         const double xcs = centre_x(d, s);
         for (int g = 0; g < d.n_groups; ++g) {
-            if (!group_near<PREC, TILT>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, yq)) continue;
+            if (!group_near<PREC, TILT>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, last_lane, yq)) continue;
             const int pg = g * kGroup;
             const int pe = pg + kGroup < d.N ? pg + kGroup : d.N;
             for (int p = pg; p < pe; p += kBatch) {
@@ -1071,7 +1083,7 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
 {
     using KT = KeyOf<PREC>;
     using Key = typename KT::T;
-    extern __shared__ unsigned char smem[];
+    extern __shared__ __align__(16) unsigned char smem[];
     Key *lds = reinterpret_cast<Key *>(smem);
     const FSM_GLOBAL Key *bkey = gptr(static_cast<const Key *>(bb.bkey));
     const FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
@@ -1086,11 +1098,31 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
         const TileGeom g = tile_geom(d, t);
         const int sx = d.sx, TX = 1 << sx, TC = TX << d.sy;
         FSM_GLOBAL Key *Z = gptr(static_cast<Key *>(d.zmap)) + g.j0 * d.nx + g.i0;
-        for (int l = tid; l < TC; l += NT) {
-            const int li = l & (TX - 1), lj = l >> sx;
-            Key v = KT::inf;
-            if (!first && li < g.w && lj < g.h) v = KT::enc(Z[(int64_t)lj * d.nx + li]);
-            lds[l] = v;
+        // 16-byte vectors of cells along the tile's rows when every row of the map starts on
+        // a 16-byte boundary and the tile's width is a whole number of vectors (a vector then
+        // lies wholly inside or wholly outside the grid); single cells otherwise
+        constexpr int V = KeyVec<Key>::n;
+        using Vec = typename KeyVec<Key>::T;
+        const bool vec = (((uintptr_t)d.zmap | (uintptr_t)(d.nx * (int64_t)sizeof(Key))) & 15) == 0 &&
+                         (g.w & (V - 1)) == 0;
+        if (vec) {
+            for (int l = tid * V; l < TC; l += NT * V) {
+                const int li = l & (TX - 1), lj = l >> sx;
+                Vec v = (Vec)KT::inf;
+                if (!first && li < g.w && lj < g.h) {
+                    v = *reinterpret_cast<const FSM_GLOBAL Vec *>(Z + (int64_t)lj * d.nx + li);
+#pragma unroll
+                    for (int c = 0; c < V; ++c) v[c] = KT::enc(v[c]);
+                }
+                *reinterpret_cast<Vec *>(lds + l) = v;
+            }
+        } else {
+            for (int l = tid; l < TC; l += NT) {
+                const int li = l & (TX - 1), lj = l >> sx;
+                Key v = KT::inf;
+                if (!first && li < g.w && lj < g.h) v = KT::enc(Z[(int64_t)lj * d.nx + li]);
+                lds[l] = v;
+            }
         }
         __syncthreads();
         // entries past the capacity were never written (the planner sizes slices so that none
@@ -1121,12 +1153,28 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
         __syncthreads();
         Stat1Acc acc;
         const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
-        for (int l = tid; l < TC; l += NT) {
-            const int li = l & (TX - 1), lj = l >> sx;
-            if (li < g.w && lj < g.h) {
-                const Key k = KT::enc(lds[l]);
-                Z[(int64_t)lj * d.nx + li] = k;
-                if (last) acc.add(KT::height(k), lj == rj, li == ci);
+        if (vec) {
+            for (int l = tid * V; l < TC; l += NT * V) {
+                const int li = l & (TX - 1), lj = l >> sx;
+                if (li < g.w && lj < g.h) {
+                    Vec v = *reinterpret_cast<const Vec *>(lds + l);
+#pragma unroll
+                    for (int c = 0; c < V; ++c) v[c] = KT::enc(v[c]);
+                    *reinterpret_cast<FSM_GLOBAL Vec *>(Z + (int64_t)lj * d.nx + li) = v;
+                    if (last) {
+#pragma unroll
+                        for (int c = 0; c < V; ++c) acc.add(KT::height(v[c]), lj == rj, li + c == ci);
+                    }
+                }
+            }
+        } else {
+            for (int l = tid; l < TC; l += NT) {
+                const int li = l & (TX - 1), lj = l >> sx;
+                if (li < g.w && lj < g.h) {
+                    const Key k = KT::enc(lds[l]);
+                    Z[(int64_t)lj * d.nx + li] = k;
+                    if (last) acc.add(KT::height(k), lj == rj, li == ci);
+                }
             }
         }
         if (last) {

@@ -29,7 +29,7 @@ def main(argv=None):
     import torch
     from paper_2603_28160_amd import Context, workloads as W
 
-    jobs = [("config2", [W.config2()])]
+    jobs = [("config2", [W.config2()]), ("config1", [W.config1()])]
     if not args.quick:
         jobs += [("config3_mix_256", W.config3(256)),
                  ("config5", [W.config5()])]

@@ -171,6 +171,19 @@ def test_large_tiles_exact(ctx, shape):
         ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 1)
 
 
+def test_binned_slices_aligned_rows_exact(ctx):
+    # rows a whole number of 16-byte vectors long: the tile reduction fills and drains its
+    # tiles in vectors, and later slices fold into the map read back in vectors
+    from paper_2603_28160_amd import _abi
+    s = W.config2(nx=800, ny=613, dd=0.004)
+    ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 1 << 20)
+    try:
+        check_f64(ctx, s)
+        check_f32(ctx, s)
+    finally:
+        ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 2 << 30)
+
+
 def test_paper_case2_tool_f64_exact(ctx):
     # the paper's own face-milling tool with rake and per-insert runout (Sec. 4.2)
     t = W.paper_case2_tool(eps_r=-0.026, eps_a=0.009, n_edge=30)
