@@ -34,8 +34,8 @@ struct Plan {
     // x_start + v_f (s dt) at a fixed time step; formed on the device in that order
     bool fixed_dt = false;
     double feed = 0, dt = 0;  // fpr (per revolution) or v_f (fixed step); dt
-    // swept-box culling: per tooth and group of kGroup consecutive edge points, a margin that
-    // bounds every point of the group over one wave of steps around its reference point's arc
+    // culling: per tooth and group of kGroup consecutive edge points, a radius that bounds
+    // every point of the group around its reference point at any step
     int n_groups = 0;
     double x_hi = 0, y_hi = 0, cull_reach = 0;
     std::vector<double> gm;   // [z_n][n_groups]
@@ -153,7 +153,7 @@ struct DevSim {
     int64_t row_base;        // first global row of this simulation
     int64_t hbase;           // offset of this simulation's first row in the row matrix
     // swept-box culling
-    const double *gm;        // [z_n][n_groups] group margins
+    const double *gm;        // [z_n][n_groups] group radii
     int32_t n_groups;
     int32_t pad1;
     double x_hi, y_hi;       // upper grid boundaries

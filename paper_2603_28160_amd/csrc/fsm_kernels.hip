@@ -362,15 +362,6 @@ __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F32>
 // when a conservative box around their positions misses the grid.  The skipped points would
 // have been dropped by the in-grid test, so results do not change.
 
-// Value of v in lane l (l uniform over the wave).
-__device__ __forceinline__ double lane_value(double v, int l)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 // The steps of this thread's wave in step block sb: the first step, the last active lane and
 // the tool-centre x at both ends (x grows with the step).  False past the pass's last step.
 struct WaveSteps {
@@ -397,24 +388,23 @@ __device__ __forceinline__ bool wave_near(const DevSim &d, const WaveSteps &w, d
 }
 
 // False when no point of edge-point group g can land in the grid during the wave: every lane
-// places the group's reference point at its own step, the offsets of the lanes holding the
-// wave's first step (lane 0) and its last step (last_lane) span a box that the group's margin
-// widens (arc sagitta, group spread, rounding slack).  Called in uniform control flow with
-// every lane active.
+// places the group's reference point at its own step, and every point of the group lies
+// within the group's radius of it (the turn and tilts are rigid; the radius carries rounding
+// slack), so a group whose discs around all active lanes' reference positions miss the grid
+// has no point in the grid at any of the wave's steps.  Called in uniform control flow with
+// every lane active; act: the lane holds one of the wave's steps.
 template <int PREC, int TILT = kTiltAny>
 __device__ __forceinline__ bool group_near(const DevSim &d, const Turn<PREC> &a,
-                                           const Edge<PREC> &ref, int K, int g,
-                                           const WaveSteps &w, int last_lane, double yq)
+                                           const Edge<PREC> &ref, int K, int g, double xcs,
+                                           double yq, bool act)
 {
     typename KeyOf<PREC>::T k;
     decltype(ref.x) fx, fy;
     turn_point<TILT>(d, a, ref, fx, fy, k);
-    const double ax = (double)fx, ay = (double)fy;
-    const double ax0 = lane_value(ax, 0), ax1 = lane_value(ax, last_lane);
-    const double ay0 = lane_value(ay, 0), ay1 = lane_value(ay, last_lane);
-    const double m = gptr(d.gm)[K * d.n_groups + g];
-    return w.xc1 + fmax(ax0, ax1) + m >= d.x_lo && w.xc0 + fmin(ax0, ax1) - m < d.x_hi &&
-           yq + fmax(ay0, ay1) + m >= d.y_lo && yq + fmin(ay0, ay1) - m < d.y_hi;
+    const double X = xcs + (double)fx, Y = yq + (double)fy;
+    const double r = gptr(d.gm)[K * d.n_groups + g];
+    const bool hit = act && X + r >= d.x_lo && X - r < d.x_hi && Y + r >= d.y_lo && Y - r < d.y_hi;
+    return __ballot(hit) != 0;
 }
 
 // Add a wave's near-boundary counts to the simulation's counter (single precision).
@@ -597,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
         const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
         uint32_t n_near = 0;
         for (int g = 0; g < d.n_groups; ++g) {
-            if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, w.last, yq)) continue;
+            if (!group_near<PREC>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, xcs, yq, vs)) continue;
             const int pg = g * kGroup;
             Edge<PREC> ep[kGroup];
 #pragma unroll
@@ -688,13 +678,12 @@ __device__ __forceinline__ void row_points_tilt(const DevSim &d, int64_t i0, int
         // the wave's LDS accesses; lanes past the last step repeat it (they take part in the
         // culling test only)
         const int o = ((lane & 31) << 1) | (lane >> 5);
-        const int last_lane = (w.last >> 1) | ((w.last & 1) << 5);
         const bool act = o <= w.last;
         const int s = w.s0 + (act ? o : w.last);
         const Turn<PREC> a = spindle_turn<PREC>(d, K, s % d.S);
         const double xcs = centre_x(d, s);
         for (int g = 0; g < d.n_groups; ++g) {
-            if (!group_near<PREC, TILT>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, w, last_lane, yq)) continue;
+            if (!group_near<PREC, TILT>(d, a, edge_point<PREC>(d, K, group_ref(g, d.N)), K, g, xcs, yq, act)) continue;
             const int pg = g * kGroup;
             const int pe = pg + kGroup < d.N ? pg + kGroup : d.N;
             for (int p = pg; p < pe; p += kBatch) {

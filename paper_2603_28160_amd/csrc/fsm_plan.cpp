@@ -328,15 +328,11 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     P.feed = fixed_dt ? v_f : fpr;
     P.dt = fixed_dt ? c.dt : 0.0;
 
-    // --- culling margins.  Over the 64 consecutive steps of one wave the reference point of a
-    // group turns by at most 63 steps about the tool axis (a circular arc of radius r_m, tilted
-    // as a whole) while the centre moves along a line, so every position lies within the
-    // arc's sagitta of the box spanned by the first and last positions; every other point of
-    // the group stays within its distance rho from the reference point under any rigid motion.
-    // The slack eps covers rounding of the box and of single-precision points.
+    // --- culling radii.  Every point of a group stays within its distance rho from the
+    // group's reference point under the rigid turn and tilts, so at any step the group's
+    // points lie within rho of where the reference point lands.  The slack eps covers the
+    // rounding of the test and of single-precision points.
     const double eps = 1e-5 * (reach + 1.0);
-    // half the angle the spindle turns over 63 steps
-    const double half = fixed_dt ? 0.5 * (63.0 * (omega * c.dt)) : 63.0 * M_PI / (double)S;
     P.gm.assign((size_t)Z * P.n_groups, 0.0);
     for (int K = 0; K < Z; ++K) {
         for (int gi = 0; gi < P.n_groups; ++gi) {
@@ -347,9 +343,7 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
                 const double dx = q[0] - m[0], dy = q[1] - m[1], dz = q[2] - m[2];
                 rho = std::max(rho, std::sqrt(dx * dx + dy * dy + dz * dz));
             }
-            const double rm = std::sqrt(m[0] * m[0] + m[1] * m[1]);
-            const double sag = half <= 0.5 * M_PI ? rm * (1.0 - std::cos(half)) : 2.0 * rm;
-            P.gm[(size_t)K * P.n_groups + gi] = rho + sag + eps;
+            P.gm[(size_t)K * P.n_groups + gi] = rho + eps;
         }
     }
     P.cull_reach = reach + eps;
