@@ -980,16 +980,53 @@ __global__ __launch_bounds__(kBlock) void scan_single(const uint32_t *counts, in
 struct Stat1Acc {
     double sum = 0.0, mn = INFINITY, mx = -INFINITY, row_sum = 0.0, col_sum = 0.0;
     int64_t n = 0;
-    int32_t row_n = 0, col_n = 0;
+    int32_t cnt = 0, row_n = 0, col_n = 0;   // cnt: cells counted by add / add_vec
+    // One cell; +inf (not cut) counts nowhere.  Branch-free: an uncut cell adds 0 to the
+    // sum, and +inf cannot lower the minimum.
     __device__ void add(double v, bool on_row, bool on_col)
     {
-        if (v < INFINITY) {
-            sum += v;
-            mn = fmin(mn, v);
-            mx = fmax(mx, v);
-            ++n;
-            if (on_row) { row_sum += v; ++row_n; }
-            if (on_col) { col_sum += v; ++col_n; }
+        const bool h = v < INFINITY;
+        const double w = h ? v : 0.0;
+        sum += w;
+        mn = fmin(mn, v);
+        mx = fmax(mx, h ? v : -INFINITY);
+        cnt += h;
+        if (on_row) { row_sum += w; row_n += h; }
+        if (on_col) { col_sum += w; col_n += h; }
+    }
+    // V neighbouring cells of one map row (row_hit: the row is the feed profile; col_at: the
+    // index among them of the pick profile's column, or -1): their sum joins the running sum
+    // as one term, which shortens the dependency chain.
+    template <int V>
+    __device__ void add_vec(const double (&v)[V], bool row_hit, int col_at)
+    {
+        double w[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            const bool h = v[c] < INFINITY;
+            w[c] = h ? v[c] : 0.0;
+            mn = fmin(mn, v[c]);
+            mx = fmax(mx, h ? v[c] : -INFINITY);
+            cnt += h;
+        }
+        double t;
+        if constexpr (V == 2) t = w[0] + w[1];
+        else if constexpr (V == 4) t = (w[0] + w[1]) + (w[2] + w[3]);
+        else {
+            t = w[0];
+#pragma unroll
+            for (int c = 1; c < V; ++c) t += w[c];
+        }
+        sum += t;
+        if (row_hit) {
+            row_sum += t;
+#pragma unroll
+            for (int c = 0; c < V; ++c) row_n += v[c] < INFINITY;
+        }
+        if (col_at >= 0) {
+#pragma unroll
+            for (int c = 0; c < V; ++c)
+                if (c == col_at) { col_sum += w[c]; col_n += v[c] < INFINITY; }
         }
     }
     // Block totals in every thread of a block of NW waves: butterflies within each wave, then
@@ -1005,7 +1042,7 @@ struct Stat1Acc {
         const int w = threadIdx.x >> 6;
         const double s0 = wave_sum(sum), s1 = wave_min(mn), s2 = wave_max(mx);
         const double s3 = wave_sum(row_sum), s4 = wave_sum(col_sum);
-        const int64_t c0 = wave_sum(n);
+        const int64_t c0 = wave_sum(n + (int64_t)cnt);
         const int32_t c1 = wave_sum(row_n), c2 = wave_sum(col_n);
         __syncthreads();
         if ((threadIdx.x & 63) == 0) {
@@ -1078,6 +1115,39 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
     const FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
     const FSM_GLOBAL uint32_t *offsets = gptr(bb.offsets);
     const int tid = threadIdx.x;
+    // entries past the capacity were never written (the planner sizes slices so that none
+    // are dropped); the clamp keeps the reads inside the bucket arrays regardless
+    const int64_t cap = bb.cap;
+    auto clamp = [cap](uint32_t o) { return (int64_t)o < cap ? o : (uint32_t)cap; };
+    // The first kDepth entries per thread of a tile's bucket are loaded while the tile before
+    // it drains, and the bucket bounds one tile further ahead still: a sparse tile's entries
+    // then arrive without two dependent load latencies of their own.  Bucket entries are read
+    // once: non-temporal loads keep them from displacing the Z-map, which the roughness
+    // passes read next.  Lanes past the bucket's end load entry 0 and drop it.
+    constexpr int kDepth = 8;   // bucket entries in flight per thread
+    Key ak[kDepth];
+    uint16_t ac[kDepth];
+    uint32_t a0 = 0, a1 = 0;   // bucket of the tile whose first entries are in ak / ac
+    uint32_t n0 = 0, n1 = 0;   // bucket of the tile after it
+    auto bounds = [&](int64_t tl, uint32_t &o0, uint32_t &o1) {
+        o0 = o1 = 0;
+        if (tl < n_tiles) {
+            o0 = clamp(offsets[tl]);
+            o1 = clamp(offsets[tl + 1]);
+        }
+    };
+    auto ahead = [&]() {
+#pragma unroll
+        for (int v = 0; v < kDepth; ++v) {
+            const uint32_t e = a0 + tid + v * NT;
+            const uint32_t ee = e < a1 ? e : 0u;
+            ak[v] = __builtin_nontemporal_load(&bkey[ee]);
+            ac[v] = __builtin_nontemporal_load(&bix[ee]);
+        }
+    };
+    bounds(blockIdx.x, a0, a1);
+    bounds(blockIdx.x + gridDim.x, n0, n1);
+    ahead();
     for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
         const int64_t t = bb.tile0 + tl;
         const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
@@ -1114,15 +1184,12 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
             }
         }
         __syncthreads();
-        // entries past the capacity were never written (the planner sizes slices so that none
-        // are dropped); the clamp keeps the reads inside the bucket arrays regardless
-        const int64_t cap = bb.cap;
-        const uint32_t e0 = (int64_t)offsets[tl] < cap ? offsets[tl] : (uint32_t)cap;
-        const uint32_t e1 = (int64_t)offsets[tl + 1] < cap ? offsets[tl + 1] : (uint32_t)cap;
-        // bucket entries are read once: non-temporal loads keep them from displacing the
-        // Z-map, which the roughness passes read next
-        uint32_t e = e0 + tid;
-        constexpr int kDepth = 8;   // bucket entries in flight per thread
+        const uint32_t e0 = a0, e1 = a1;
+#pragma unroll
+        for (int v = 0; v < kDepth; ++v)
+            if (e0 + tid + v * NT < e1)
+                __hip_atomic_fetch_min(&lds[ac[v]], ak[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        uint32_t e = e0 + tid + kDepth * NT;
         for (; e + (kDepth - 1) * NT < e1; e += kDepth * NT) {
             Key k4[kDepth];
             uint16_t c4[kDepth];
@@ -1140,6 +1207,11 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (tid == 0 && e1 > e0) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)(e1 - e0));
         __syncthreads();
+        // the next tile's first entries travel while this one drains
+        a0 = n0;
+        a1 = n1;
+        bounds(tl + 2 * (int64_t)gridDim.x, n0, n1);
+        ahead();
         Stat1Acc acc;
         const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
         if (vec) {
@@ -1151,8 +1223,11 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
                     for (int c = 0; c < V; ++c) v[c] = KT::enc(v[c]);
                     *reinterpret_cast<FSM_GLOBAL Vec *>(Z + (int64_t)lj * d.nx + li) = v;
                     if (last) {
+                        double h[V];
 #pragma unroll
-                        for (int c = 0; c < V; ++c) acc.add(KT::height(v[c]), lj == rj, li + c == ci);
+                        for (int c = 0; c < V; ++c) h[c] = KT::height(v[c]);
+                        const int64_t at = ci - li;
+                        acc.add_vec<V>(h, lj == rj, at >= 0 && at < V ? (int)at : -1);
                     }
                 }
             }
@@ -1261,8 +1336,37 @@ struct Stat2Acc {
 
 // Second pass: central moments about each simulation's mean, and the profile deviations.  One
 // block per tile, its threads over consecutive cells of the tile's rows with kRows2 loads in
-// flight each; the waves' butterfly sums are combined left to right after one barrier.
+// flight each (16-byte vectors of cells when the map's rows allow it, as in tile_reduce); the
+// waves' butterfly sums are combined left to right after one barrier.
 constexpr int kRows2 = 8;
+struct Moments {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, row_abs = 0.0, col_abs = 0.0;
+    // V neighbouring cells of one map row, +inf (not cut) counting nowhere; their terms are
+    // summed among themselves first, which shortens the dependency chains
+    template <int V>
+    __device__ void add(const double (&v)[V], const RoughState &st, bool row_hit, int col_at)
+    {
+        double a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, ra = 0.0;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            const bool h = v[c] < INFINITY;
+            const double dv = h ? v[c] - st.mean : 0.0;
+            const double d2 = dv * dv;
+            a1 += fabs(dv);
+            a2 += d2;
+            a3 += d2 * dv;
+            a4 += d2 * d2;
+            if (row_hit && h) ra += fabs(v[c] - st.row_mean);
+            if (c == col_at && h) col_abs += fabs(v[c] - st.col_mean);
+        }
+        s1 += a1;
+        s2 += a2;
+        s3 += a3;
+        s4 += a4;
+        row_abs += ra;
+    }
+};
+
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__ sims, int n_sims,
                                                       const int64_t *__restrict__ tile_base,
@@ -1271,6 +1375,8 @@ __global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__
 {
     using KT = KeyOf<PREC>;
     using Key = typename KT::T;
+    constexpr int V = KeyVec<Key>::n;
+    using Vec = typename KeyVec<Key>::T;
     __shared__ double part[6][kWaves];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
@@ -1282,39 +1388,50 @@ __global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__
         const int64_t nx = d.nx;
         const FSM_GLOBAL Key *Z = gptr(static_cast<const Key *>(d.zmap)) + g.j0 * nx + g.i0;
         const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
-        double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, row_abs = 0.0, col_abs = 0.0;
-        for (int l0 = tid; l0 < TC; l0 += kRows2 * kBlock) {
-            double v[kRows2];
-            // every load is issued (cells outside the tile read its first cell) so that all
-            // kRows2 are in flight together; their values are masked afterwards
-            Key k[kRows2];
+        Moments m;
+        const bool vec = (((uintptr_t)d.zmap | (uintptr_t)(nx * (int64_t)sizeof(Key))) & 15) == 0 &&
+                         (g.w & (V - 1)) == 0;
+        if (vec) {
+            for (int l0 = tid * V; l0 < TC; l0 += kRows2 * kBlock * V) {
+                // every load is issued (vectors outside the tile read its first one) so that
+                // all kRows2 are in flight together; their values are masked afterwards
+                Vec k[kRows2];
 #pragma unroll
-            for (int u = 0; u < kRows2; ++u) {
-                const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
-                const bool in = l < TC && li < g.w && lj < g.h;
-                k[u] = Z[in ? (int64_t)lj * nx + li : 0];
+                for (int u = 0; u < kRows2; ++u) {
+                    const int l = l0 + u * kBlock * V, li = l & (TX - 1), lj = l >> sx;
+                    const bool in = l < TC && li < g.w && lj < g.h;
+                    k[u] = *reinterpret_cast<const FSM_GLOBAL Vec *>(Z + (in ? (int64_t)lj * nx + li : 0));
+                }
+#pragma unroll
+                for (int u = 0; u < kRows2; ++u) {
+                    const int l = l0 + u * kBlock * V, li = l & (TX - 1), lj = l >> sx;
+                    const bool in = l < TC && li < g.w && lj < g.h;
+                    double v[V];
+#pragma unroll
+                    for (int c = 0; c < V; ++c) v[c] = in ? KT::height(k[u][c]) : INFINITY;
+                    const int64_t at = ci - li;
+                    m.add<V>(v, st, lj == rj, at >= 0 && at < V ? (int)at : -1);
+                }
             }
+        } else {
+            for (int l0 = tid; l0 < TC; l0 += kRows2 * kBlock) {
+                Key k[kRows2];
 #pragma unroll
-            for (int u = 0; u < kRows2; ++u) {
-                const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
-                const bool in = l < TC && li < g.w && lj < g.h;
-                v[u] = in ? KT::height(k[u]) : INFINITY;
-            }
-#pragma unroll
-            for (int u = 0; u < kRows2; ++u) {
-                if (v[u] < INFINITY) {
+                for (int u = 0; u < kRows2; ++u) {
                     const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
-                    const double dv = v[u] - st.mean;
-                    const double d2 = dv * dv;
-                    s1 += fabs(dv);
-                    s2 += d2;
-                    s3 += d2 * dv;
-                    s4 += d2 * d2;
-                    if (lj == rj) row_abs += fabs(v[u] - st.row_mean);
-                    if (li == ci) col_abs += fabs(v[u] - st.col_mean);
+                    const bool in = l < TC && li < g.w && lj < g.h;
+                    k[u] = Z[in ? (int64_t)lj * nx + li : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < kRows2; ++u) {
+                    const int l = l0 + u * kBlock, li = l & (TX - 1), lj = l >> sx;
+                    const bool in = l < TC && li < g.w && lj < g.h;
+                    const double v[1] = {in ? KT::height(k[u]) : INFINITY};
+                    m.add<1>(v, st, lj == rj, li == ci ? 0 : -1);
                 }
             }
         }
+        double s1 = m.s1, s2 = m.s2, s3 = m.s3, s4 = m.s4, row_abs = m.row_abs, col_abs = m.col_abs;
         s1 = wave_sum(s1);
         s2 = wave_sum(s2);
         s3 = wave_sum(s3);
