@@ -1119,15 +1119,40 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
     // are dropped); the clamp keeps the reads inside the bucket arrays regardless
     const int64_t cap = bb.cap;
     auto clamp = [cap](uint32_t o) { return (int64_t)o < cap ? o : (uint32_t)cap; };
-    // The first kDepth entries per thread of a tile's bucket are loaded while the tile before
-    // it drains, and the bucket bounds one tile further ahead still: a sparse tile's entries
-    // then arrive without two dependent load latencies of their own.  Bucket entries are read
-    // once: non-temporal loads keep them from displacing the Z-map, which the roughness
-    // passes read next.  Lanes past the bucket's end load entry 0 and drop it.
-    constexpr int kDepth = 8;   // bucket entries in flight per thread
-    Key ak[kDepth];
-    uint16_t ac[kDepth];
-    uint32_t a0 = 0, a1 = 0;   // bucket of the tile whose first entries are in ak / ac
+    // Bucket entries travel in units of E neighbours: E keys in one 16-byte load, their cells
+    // in one 4- or 8-byte load.  A bucket [e0, e1) splits into whole units [u0, u1) and at most
+    // E - 1 single entries at each end.  The first kDepth units per thread and the single
+    // entries of a tile's bucket are loaded while the tile before it drains, and the bucket
+    // bounds one tile further ahead still: a sparse tile's entries then arrive without two
+    // dependent load latencies of their own.  Bucket entries are read once: non-temporal loads
+    // keep them from displacing the Z-map, which the roughness passes read next.  Lanes past
+    // the bucket's end load unit 0 and drop it.
+    constexpr int E = KeyVec<Key>::n;
+    using KU = typename KeyVec<Key>::T;
+    typedef uint16_t CU __attribute__((ext_vector_type(E)));
+    const FSM_GLOBAL KU *ukey = reinterpret_cast<const FSM_GLOBAL KU *>(bkey);
+    const FSM_GLOBAL CU *uix = reinterpret_cast<const FSM_GLOBAL CU *>(bix);
+    constexpr int kDepth = 8 / E;   // units in flight per thread (eight entries)
+    struct Split {
+        uint32_t e0, e1, u0, u1, hb, tb;   // single entries: [e0, hb) and [tb, e1)
+    };
+    auto split = [](uint32_t e0, uint32_t e1) {
+        Split q;
+        q.e0 = e0;
+        q.e1 = e1;
+        q.u0 = (e0 + E - 1) / E;
+        q.u1 = e1 / E > q.u0 ? e1 / E : q.u0;
+        q.hb = e1 < q.u0 * E ? e1 : q.u0 * E;
+        q.tb = q.hb > q.u1 * E ? q.hb : q.u1 * E;
+        if (q.tb > e1) q.tb = e1;   // no whole unit: the single entries end at e1
+        return q;
+    };
+    KU ak[kDepth];
+    CU ac[kDepth];
+    Key ok = KT::inf;           // this thread's single entry, if any
+    uint16_t oc = 0;
+    bool has_one = false;
+    uint32_t a0 = 0, a1 = 0;   // bucket of the tile whose first entries are in ak / ac / ok
     uint32_t n0 = 0, n1 = 0;   // bucket of the tile after it
     auto bounds = [&](int64_t tl, uint32_t &o0, uint32_t &o1) {
         o0 = o1 = 0;
@@ -1137,12 +1162,20 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
         }
     };
     auto ahead = [&]() {
+        const Split q = split(a0, a1);
 #pragma unroll
         for (int v = 0; v < kDepth; ++v) {
-            const uint32_t e = a0 + tid + v * NT;
-            const uint32_t ee = e < a1 ? e : 0u;
-            ak[v] = __builtin_nontemporal_load(&bkey[ee]);
-            ac[v] = __builtin_nontemporal_load(&bix[ee]);
+            const uint32_t u = q.u0 + tid + v * NT;
+            const uint32_t uu = u < q.u1 ? u : 0u;
+            ak[v] = __builtin_nontemporal_load(&ukey[uu]);
+            ac[v] = __builtin_nontemporal_load(&uix[uu]);
+        }
+        const uint32_t nh = q.hb - q.e0, nt = q.e1 - q.tb;
+        has_one = (uint32_t)tid < nh + nt;
+        if (has_one) {
+            const uint32_t e = (uint32_t)tid < nh ? q.e0 + tid : q.tb + (tid - nh);
+            ok = __builtin_nontemporal_load(&bkey[e]);
+            oc = __builtin_nontemporal_load(&bix[e]);
         }
     };
     bounds(blockIdx.x, a0, a1);
@@ -1185,26 +1218,37 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
         }
         __syncthreads();
         const uint32_t e0 = a0, e1 = a1;
+        const Split q = split(e0, e1);
+        if (has_one) __hip_atomic_fetch_min(&lds[oc], ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
         for (int v = 0; v < kDepth; ++v)
-            if (e0 + tid + v * NT < e1)
-                __hip_atomic_fetch_min(&lds[ac[v]], ak[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        uint32_t e = e0 + tid + kDepth * NT;
-        for (; e + (kDepth - 1) * NT < e1; e += kDepth * NT) {
-            Key k4[kDepth];
-            uint16_t c4[kDepth];
+            if (q.u0 + tid + v * NT < q.u1) {
+#pragma unroll
+                for (int c = 0; c < E; ++c)
+                    __hip_atomic_fetch_min(&lds[ac[v][c]], ak[v][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        uint32_t u = q.u0 + tid + kDepth * NT;
+        for (; u + (kDepth - 1) * NT < q.u1; u += kDepth * NT) {
+            KU k4[kDepth];
+            CU c4[kDepth];
 #pragma unroll
             for (int v = 0; v < kDepth; ++v) {
-                k4[v] = __builtin_nontemporal_load(&bkey[e + v * NT]);
-                c4[v] = __builtin_nontemporal_load(&bix[e + v * NT]);
+                k4[v] = __builtin_nontemporal_load(&ukey[u + v * NT]);
+                c4[v] = __builtin_nontemporal_load(&uix[u + v * NT]);
             }
 #pragma unroll
             for (int v = 0; v < kDepth; ++v)
-                __hip_atomic_fetch_min(&lds[c4[v]], k4[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+                for (int c = 0; c < E; ++c)
+                    __hip_atomic_fetch_min(&lds[c4[v][c]], k4[v][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        for (; e < e1; e += NT)
-            __hip_atomic_fetch_min(&lds[__builtin_nontemporal_load(&bix[e])], __builtin_nontemporal_load(&bkey[e]),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (; u < q.u1; u += NT) {
+            const KU k1 = __builtin_nontemporal_load(&ukey[u]);
+            const CU c1 = __builtin_nontemporal_load(&uix[u]);
+#pragma unroll
+            for (int c = 0; c < E; ++c)
+                __hip_atomic_fetch_min(&lds[c1[c]], k1[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         if (tid == 0 && e1 > e0) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)(e1 - e0));
         __syncthreads();
         // the next tile's first entries travel while this one drains
