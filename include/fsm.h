@@ -176,7 +176,18 @@ typedef struct fsm_timings {
     float reduce_ms;         /* per-tile minimum in LDS (+ first roughness pass) */
     int32_t n_slices;        /* slices of the binned Z-map */
     int32_t valid;           /* 1 once a profiled call has completed */
+    int32_t zmap_path;       /* FSM_PATH_* the Z-map took */
+    int32_t reserved;
 } fsm_timings;
+
+/* Z-map paths (fsm_timings.zmap_path).  The binned strategy counts the points of a row of
+ * binning items per tile in LDS when a simulation's tiles fit one histogram (histogram mode),
+ * per super-tile of several tiles with a split pass into the tiles otherwise (super mode), and
+ * with global atomics per tile when even its super-tiles do not fit (run mode). */
+#define FSM_PATH_SCATTER 0
+#define FSM_PATH_RUN 1
+#define FSM_PATH_HIST 2
+#define FSM_PATH_SUPER 3
 
 typedef struct fsm_ctx fsm_ctx;
 
@@ -225,7 +236,7 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
                                        LDS and store it once; FSM_ZMAP_SCATTER: one global
                                        atomic min per point */
 #define FSM_OPT_BUCKET_BYTES 2    /* device bytes the binned strategy may use for its point
-                                       buckets (default 8 GiB); larger simulations run in
+                                       buckets (default 16 GiB); larger simulations run in
                                        slices of the evaluation range */
 #define FSM_OPT_GRAPHS 3           /* nonzero: capture the launch sequences of fsm_simulate and
                                        fsm_simulate_batch into HIP graphs (on a stream of the
@@ -245,6 +256,10 @@ int fsm_last_error(const fsm_ctx *ctx, char *buf, size_t n);
                                        FSM_EAGAIN while any is in flight */
 #define FSM_OPT_HBM_BUDGET 8       /* device bytes the workspaces of the asynchronous slots may
                                        hold together; 0 (default): no limit */
+#define FSM_OPT_HIST_BYTES 9       /* device bytes the binned strategy's row matrix may take
+                                       (histogram and super modes; default 1 GiB); a launch
+                                       whose matrix would be larger runs in run mode, and 0
+                                       makes every binned launch do so */
 #define FSM_ZMAP_BINNED 0
 #define FSM_ZMAP_SCATTER 1
 

@@ -24,9 +24,11 @@ FLAG_SQ_ZERO, FLAG_NO_HIT, FLAG_LOW_COVERAGE = 1, 2, 4
 OPT_ZMAP_STRATEGY, OPT_BUCKET_BYTES, OPT_GRAPHS = 1, 2, 3
 OPT_TILE_SHAPE, OPT_TARGET_ROWS, OPT_AUTOTUNED = 4, 5, 6
 FILTER_SMOOTH, FILTER_ROUGH = 0, 1
-OPT_ASYNC_SLOTS, OPT_HBM_BUDGET = 7, 8
+OPT_ASYNC_SLOTS, OPT_HBM_BUDGET, OPT_HIST_BYTES = 7, 8, 9
 FSM_EAGAIN = -4
 ZMAP_BINNED, ZMAP_SCATTER = 0, 1
+# Z-map path of the last call (fsm_timings.zmap_path)
+PATH_SCATTER, PATH_RUN, PATH_HIST, PATH_SUPER = 0, 1, 2, 3
 
 
 class FsmTool(C.Structure):
@@ -78,7 +80,8 @@ class FsmTimings(C.Structure):
     _fields_ = [("upload_ms", C.c_float), ("fill_ms", C.c_float), ("scatter_ms", C.c_float),
                 ("rough_ms", C.c_float), ("total_ms", C.c_float), ("count_ms", C.c_float),
                 ("index_ms", C.c_float), ("write_ms", C.c_float), ("reduce_ms", C.c_float),
-                ("n_slices", C.c_int32), ("valid", C.c_int32)]
+                ("n_slices", C.c_int32), ("valid", C.c_int32), ("zmap_path", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class FsmJob(C.Structure):

@@ -45,12 +45,19 @@ int hip_err(fsm_ctx *ctx, hipError_t e, const char *where)
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Bucket capacity in points: the bucket budget over the bytes of one entry (key and cell
-// index), at least one binning item's worst case and at most what 32-bit offsets address.
-int64_t bucket_cap(int64_t bucket_bytes, int precision, int64_t per_item)
+// Bytes of bucket space per point: key and cell index, and with super-tiles the super-tile
+// bucket's key and 32-bit cell besides.
+int64_t entry_bytes(int precision, bool super)
 {
     const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
-    int64_t cap = bucket_bytes / (key_bytes + 2);
+    return key_bytes + 2 + (super ? key_bytes + 4 : 0);
+}
+
+// Bucket capacity in points: the bucket budget over the bytes of one entry, at least one
+// binning item's worst case and at most what 32-bit offsets address.
+int64_t bucket_cap(int64_t bucket_bytes, int64_t entry, int64_t per_item)
+{
+    int64_t cap = bucket_bytes / entry;
     cap = std::max<int64_t>(cap, per_item);
     return std::min<int64_t>(cap, (int64_t)UINT32_MAX);
 }
@@ -99,6 +106,7 @@ LaunchParams params_for(const fsm_ctx *ctx, const std::vector<Plan> &plans, int 
     lp.tile_shape = ctx->tile_shape;
     lp.target_rows = ctx->target_rows;
     lp.bucket_bytes = ctx->bucket_bytes;
+    lp.hist_bytes = ctx->hist_bytes;
     if (ctx->use_tuned && !ctx->tuned.empty()) {
         auto it = ctx->tuned.find(tune_key(plans, precision));
         if (it != ctx->tuned.end()) {
@@ -172,6 +180,10 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         d.n_tiles = (int64_t)d.tiles_x * d.tiles_y;
         d.tile_base = tiles;
         tiles += d.n_tiles;
+        d.ux = d.uy = 0;
+        d.h_tiles_x = d.tiles_x;
+        d.h_tiles = d.n_tiles;
+        d.h_base = d.tile_base;
         d.sim = k;
         if (precision == FSM_F32) {
             d.pos_err = fsm::kF32PosErr * P.pos_r;
@@ -183,37 +195,81 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         L.max_n = std::max(L.max_n, P.N);
     }
     L.total_tiles = tiles;
+    L.total_htiles = tiles;
     const bool binned = strategy == fsm::kStrategyBinned;
     L.total_items = binned ? bitems : items;
     if (binned) {
-        // histogram mode when every simulation's tile histogram fits in LDS and the row
-        // matrix fits its budget.  Rows: about target_rows per launch, but never more items
-        // than one bucket slice can take, and small enough that a slice still holds
-        // kMinSliceRows rows (blocks) when the work runs in many slices; coarser only when the
-        // row matrix would outgrow its budget.
+        // histogram mode when every simulation's row histogram fits in LDS and the row matrix
+        // fits its budget; simulations with more tiles than a histogram holds count per
+        // super-tile, grown along its shorter side (in cells) until a histogram holds at most
+        // kSuperHistTiles of them.
+        int64_t max_tiles = 0;
+        for (const DevSim &d : devs) max_tiles = std::max(max_tiles, d.n_tiles);
+        int ux = 0, uy = 0;
+        int64_t max_h = max_tiles;
+        if (max_tiles > fsm::kMaxHistTiles) {
+            for (;;) {
+                max_h = 0;
+                for (const DevSim &d : devs)
+                    max_h = std::max(max_h, ceil_div(d.tiles_x, (int64_t)1 << ux) * ceil_div(d.tiles_y, (int64_t)1 << uy));
+                if (max_h <= fsm::kSuperHistTiles || ux + uy >= fsm::kMaxSubShift) break;
+                if (L.sx + ux <= L.sy + uy) ++ux; else ++uy;
+            }
+            if (max_h > fsm::kMaxHistTiles) ux = uy = 0;
+        }
+        const bool super = ux + uy > 0;
+        if (super) {
+            int64_t htiles = 0;
+            for (DevSim &d : devs) {
+                d.ux = ux;
+                d.uy = uy;
+                d.h_tiles_x = (int32_t)ceil_div(d.tiles_x, (int64_t)1 << ux);
+                d.h_tiles = d.h_tiles_x * ceil_div(d.tiles_y, (int64_t)1 << uy);
+                d.h_base = htiles;
+                htiles += d.h_tiles;
+            }
+            L.total_htiles = htiles;
+        }
+        L.entry = entry_bytes(precision, super);
+        // Rows: about target_rows per launch, but never more items than one bucket slice can
+        // take, and small enough that a slice still holds kMinSliceRows rows (blocks) when the
+        // work runs in many slices; coarser only when the row matrix would outgrow its budget.
         const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
         const int64_t slice_items = std::max<int64_t>(
-            1, std::min(bucket_cap(bucket_bytes, precision, per_item), std::max(per_item, bitems * per_item)) / per_item);
+            1, std::min(bucket_cap(bucket_bytes, L.entry, per_item), std::max(per_item, bitems * per_item)) / per_item);
         int64_t ipr = std::max<int64_t>(1, std::min(ceil_div(bitems, std::max<int64_t>(1, lp.target_rows)), slice_items / kMinSliceRows));
         int64_t rows = 0, hsize = 0;
         for (;;) {
             rows = hsize = 0;
             for (DevSim &d : devs) {
-                L.max_tiles = std::max(L.max_tiles, d.n_tiles);
                 d.items_per_row = (int32_t)ipr;
                 d.n_rows = ceil_div(d.n_bitems, ipr);
                 d.row_base = rows;
                 d.hbase = hsize;
                 rows += d.n_rows;
-                hsize += d.n_rows * d.n_tiles;
+                hsize += d.n_rows * d.h_tiles;
             }
             if (hsize * 4 <= lp.hist_bytes || ipr >= slice_items) break;
             ipr = std::min(slice_items, ipr * 2);
         }
         L.items_per_row = ipr;
         L.total_rows = rows;
+        L.max_tiles = 0;
+        for (const DevSim &d : devs) L.max_tiles = std::max(L.max_tiles, d.h_tiles);
         L.hist = L.max_tiles <= fsm::kMaxHistTiles && hsize * 4 <= lp.hist_bytes;
-        if (!L.hist) L.max_tiles = 0;
+        L.super = L.hist && super;
+        if (!L.hist) {
+            // run mode: global atomics per tile
+            L.max_tiles = 0;
+            L.total_htiles = tiles;
+            L.entry = entry_bytes(precision, false);
+            for (DevSim &d : devs) {
+                d.ux = d.uy = 0;
+                d.h_tiles_x = d.tiles_x;
+                d.h_tiles = d.n_tiles;
+                d.h_base = d.tile_base;
+            }
+        }
     }
 
     size_t o = 0;
@@ -225,26 +281,35 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     if (binned) {
         const int64_t key_bytes = precision == FSM_F64 ? 8 : 4;
         const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
-        int64_t cap = bucket_cap(bucket_bytes, precision, per_item);
+        int64_t cap = bucket_cap(bucket_bytes, L.entry, per_item);
         cap = std::min<int64_t>(cap, std::max<int64_t>(per_item, bitems * per_item));
         L.per_slice = std::max<int64_t>(1, cap / per_item);
         L.per_slice = std::min<int64_t>(L.per_slice, std::max<int64_t>(1, bitems));
         L.cap = cap;
-        const int64_t nb = ceil_div(tiles, 4096);
-        L.counts = take(sizeof(uint32_t) * tiles);
-        L.offsets = take(sizeof(uint32_t) * (tiles + 1));
-        L.cursor = take(sizeof(uint32_t) * tiles);
+        const int64_t ht = L.total_htiles;
+        const int64_t nb = ceil_div(ht, 4096);
+        L.counts = take(sizeof(uint32_t) * ht);
+        L.offsets = take(sizeof(uint32_t) * (ht + 1));
+        L.cursor = take(sizeof(uint32_t) * ht);
         L.bsum = take(sizeof(uint32_t) * nb);
         L.bkey = take((size_t)key_bytes * cap);
         L.bidx = take(sizeof(uint16_t) * cap);
+        if (L.super) {
+            L.tile_lo = take(sizeof(uint32_t) * tiles);
+            L.tile_hi = take(sizeof(uint32_t) * tiles);
+            L.skey = take((size_t)key_bytes * cap);
+            L.spk = take(sizeof(uint32_t) * cap);
+        }
         if (L.hist) {
+            // one slice when every item fits the bucket (the last row of a simulation may be
+            // partial, so whole rows would overestimate); otherwise whole rows per slice
             const int64_t per_row = L.items_per_row * per_item;
-            L.rows_per_slice = std::max<int64_t>(1, cap / per_row);
+            L.rows_per_slice = bitems * per_item <= cap ? L.total_rows : std::max<int64_t>(1, cap / per_row);
             L.rows_per_slice = std::min<int64_t>(L.rows_per_slice, std::max<int64_t>(1, L.total_rows));
             int64_t hsize = 0;
-            for (const DevSim &d : devs) hsize += d.n_rows * d.n_tiles;
+            for (const DevSim &d : devs) hsize += d.n_rows * d.h_tiles;
             L.hist_m = take(sizeof(uint32_t) * std::max<int64_t>(1, hsize));
-            L.chunk = take(sizeof(uint32_t) * ceil_div(L.rows_per_slice, kRowChunk) * std::max<int64_t>(1, tiles));
+            L.chunk = take(sizeof(uint32_t) * ceil_div(L.rows_per_slice, kRowChunk) * std::max<int64_t>(1, ht));
         }
     }
     L.scratch_end = o;
@@ -252,6 +317,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     L.ibase = take(sizeof(int64_t) * L.n);
     L.bbase = take(sizeof(int64_t) * L.n);
     L.tbase = take(sizeof(int64_t) * L.n);
+    L.hbase = take(sizeof(int64_t) * L.n);
     L.binned = take(sizeof(uint64_t) * L.n);
     L.evals = take(sizeof(int64_t) * L.n);
     L.near = take(sizeof(uint64_t) * L.n);
@@ -273,10 +339,10 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
 bool fit_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int precision,
                 int64_t bytes, LaunchParams lp, SetLayout &L, std::vector<DevSim> &devs)
 {
-    const int64_t entry = precision == FSM_F64 ? 10 : 6;
     for (int it = 0; it < 8; ++it) {
         devs.clear();
         L = make_layout(ctx, plans, precision, lp, devs);
+        const int64_t entry = L.entry;
         if ((int64_t)L.total <= bytes) return true;
         const int64_t floor_bytes = (int64_t)fsm::kBlock * L.max_n * entry;
         const int64_t used = L.cap * entry;
@@ -336,7 +402,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
                 const std::vector<void *> &zmaps, char *dev, char *host)
 {
     auto H = [&](size_t off) { return host + (off - L.sims); };
-    std::vector<int64_t> ib(L.n), bb(L.n), tb(L.n), ev(L.n), rbase(L.n);
+    std::vector<int64_t> ib(L.n), bb(L.n), tb(L.n), hb(L.n), ev(L.n), rbase(L.n);
     std::vector<uint64_t> zero(L.n, 0);
     // every simulation writes its own descriptor and table ranges of the staging image
     parallel_for(L.n, [&](int k) {
@@ -352,6 +418,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         ib[k] = d.item_base;
         bb[k] = d.bitem_base;
         tb[k] = d.tile_base;
+        hb[k] = d.h_base;
         rbase[k] = d.row_base;
         ev[k] = P.n_evals;
         if (!P.pT.empty()) std::memcpy(H(L.pT[k]), P.pT.data(), sizeof(double) * P.pT.size());
@@ -374,6 +441,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
     std::memcpy(H(L.ibase), ib.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.bbase), (L.hist ? rbase : bb).data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.tbase), tb.data(), sizeof(int64_t) * L.n);
+    std::memcpy(H(L.hbase), hb.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.binned), zero.data(), sizeof(uint64_t) * L.n);
     std::memcpy(H(L.evals), ev.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.near), zero.data(), sizeof(uint64_t) * L.n);
@@ -426,6 +494,7 @@ void collect(fsm_ctx *ctx, bool phases)
     ctx->timings.write_ms = st[2];
     ctx->timings.reduce_ms = st[3];
     ctx->timings.n_slices = phases ? ctx->stages_used : 0;
+    ctx->timings.zmap_path = ctx->zmap_path;
     float tot = 0.0f;
     if (hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[4]) != hipSuccess) tot = 0.0f;
     ctx->timings.total_ms = tot;
@@ -440,6 +509,7 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
     const int64_t *d_ibase = reinterpret_cast<const int64_t *>(dev + L.ibase);
     const int64_t *d_bbase = reinterpret_cast<const int64_t *>(dev + L.bbase);
     const int64_t *d_tbase = reinterpret_cast<const int64_t *>(dev + L.tbase);
+    const int64_t *d_hbase = reinterpret_cast<const int64_t *>(dev + L.hbase);
     uint64_t *d_binned = reinterpret_cast<uint64_t *>(dev + L.binned);
     const int64_t *d_evals = reinterpret_cast<const int64_t *>(dev + L.evals);
     auto *st1 = reinterpret_cast<fsm::TileStat1 *>(dev + L.st1);
@@ -447,6 +517,7 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
     auto *state = reinterpret_cast<fsm::RoughState *>(dev + L.state);
     auto *d_out = reinterpret_cast<fsm_rough *>(dev + L.out);
     const bool binned = L.strategy == fsm::kStrategyBinned;
+    ctx->zmap_path = !binned ? FSM_PATH_SCATTER : !L.hist ? FSM_PATH_RUN : L.super ? FSM_PATH_SUPER : FSM_PATH_HIST;
     int he = 0;
     mark(ctx, 1, s, capturing);
     if (!binned) {
@@ -465,7 +536,13 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
         bb.bkey = dev + L.bkey;
         bb.bidx = reinterpret_cast<uint16_t *>(dev + L.bidx);
         bb.cap = L.cap;
-        bb.tile0 = 0;
+        bb.tile0 = bb.htile0 = 0;
+        // per-tile bucket bounds: the split pass writes them with super-tiles; otherwise a
+        // tile's bucket ends where the next one starts
+        bb.tile_lo = L.super ? reinterpret_cast<uint32_t *>(dev + L.tile_lo) : bb.offsets;
+        bb.tile_hi = L.super ? reinterpret_cast<uint32_t *>(dev + L.tile_hi) : bb.offsets + 1;
+        bb.skey = L.super ? static_cast<void *>(dev + L.skey) : nullptr;
+        bb.spk = L.super ? reinterpret_cast<uint32_t *>(dev + L.spk) : nullptr;
         bb.hist = L.hist ? reinterpret_cast<uint32_t *>(dev + L.hist_m) : nullptr;
         bb.chunk = L.hist ? reinterpret_cast<uint32_t *>(dev + L.chunk) : nullptr;
         bb.max_tiles = (int32_t)L.max_tiles;
@@ -488,13 +565,17 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
                 const int64_t r1 = std::min<int64_t>(L.total_rows, r0 + L.rows_per_slice);
                 const DevSim &da = devs[sim_of_row(r0)], &db = devs[sim_of_row(r1 - 1)];
                 const int64_t t0 = da.tile_base, t1 = db.tile_base + db.n_tiles;
+                const int64_t h0 = da.h_base, h1 = db.h_base + db.h_tiles;
                 fsm::BinBuffers bs = bb;
                 bs.tile0 = t0;
-                bs.counts += t0;
-                bs.offsets += t0;
-                bs.cursor += t0;
-                he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, t1 - t0, r0, r1, bs,
-                                            L.precision, L.sx, L.sy, st1, d_binned, s,
+                bs.htile0 = h0;
+                bs.counts += h0;
+                bs.offsets += h0;
+                bs.cursor += h0;
+                bs.tile_lo += L.super ? t0 : h0;
+                bs.tile_hi += L.super ? t0 : h0;
+                he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, t1 - t0, d_hbase, h1 - h0,
+                                            r0, r1, bs, L.precision, L.sx, L.sy, st1, d_binned, s,
                                             stage_marks(ctx, slice++, capturing));
                 if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
                 r0 = r1;
@@ -578,9 +659,9 @@ int run_set(fsm_ctx *ctx, const std::vector<Plan> &plans, const std::vector<void
         e = hipMemcpyAsync(dev + L.sims, host, L.total - L.sims, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_err(ctx, e, "hipMemcpyAsync(plan)");
         char key[256];
-        std::snprintf(key, sizeof key, "%d/%d/%d/%lld/%lld/%lld/%lld/%d/%d/%d/%lld/%lld/%p", L.precision,
+        std::snprintf(key, sizeof key, "%d/%d/%d/%lld/%lld/%lld/%lld/%d/%d/%d/%d/%lld/%lld/%p", L.precision,
                       L.strategy, L.n, (long long)L.total_tiles, (long long)L.total_items,
-                      (long long)L.per_slice, (long long)L.cap, L.sx, L.sy, (int)L.hist,
+                      (long long)L.per_slice, (long long)L.cap, L.sx, L.sy, (int)L.hist, (int)L.super,
                       (long long)L.total_rows, (long long)L.rows_per_slice, w.d_ws);
         // every host value a captured launch bakes in follows from these: the grids (tiles,
         // fill sizes) and each simulation's item and row counts (the tile range of every
@@ -906,6 +987,10 @@ int fsm_ctx_set_option(fsm_ctx *ctx, int option, int64_t value)
         if (value < 0) return set_err(ctx, FSM_EINVAL, "negative HBM budget");
         ctx->hbm_budget = value;
         return FSM_OK;
+    case FSM_OPT_HIST_BYTES:
+        if (value < 0) return set_err(ctx, FSM_EINVAL, "negative row matrix budget");
+        ctx->hist_bytes = value;
+        return FSM_OK;
     default:
         return set_err(ctx, FSM_EINVAL, "unknown option");
     }
@@ -1085,6 +1170,7 @@ int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tu
         base.tile_shape = 0;
         base.target_rows = 4096;
         base.bucket_bytes = ctx->bucket_bytes;
+        base.hist_bytes = ctx->hist_bytes;
         int rc = time_of(base, base_ms);
         if (rc != FSM_OK) return rc;
         best = base;
@@ -1178,6 +1264,7 @@ int fsm_tune_set(fsm_ctx *ctx, const fsm_tune_entry *entries, int n)
         lp.tile_shape = e.tile_shape;
         lp.target_rows = e.target_rows;
         lp.bucket_bytes = ctx->bucket_bytes;
+    lp.hist_bytes = ctx->hist_bytes;
         ctx->tuned[std::string(e.key, strnlen(e.key, sizeof e.key))] = lp;
     }
     return FSM_OK;

@@ -108,6 +108,13 @@ inline int tile_sx(int precision) { return precision == FSM_F64 ? 6 : 7; }
 inline int tile_sy(int precision) { (void)precision; return 6; }
 // Largest per-simulation tile count whose per-block histogram fits in LDS (64 KiB).
 constexpr int64_t kMaxHistTiles = 16384;
+// Simulations with more tiles count their points per super-tile, a block of (1 << ux) x
+// (1 << uy) tiles, so that a row histogram holds at most kSuperHistTiles counters (32 KiB,
+// several blocks per compute unit); a split pass then sorts each super-tile's bucket into its
+// tiles.  At most kMaxSubTiles tiles per super-tile.
+constexpr int64_t kSuperHistTiles = 8192;
+constexpr int kMaxSubShift = 6;
+constexpr int kMaxSubTiles = 1 << kMaxSubShift;
 
 // Z-map strategies
 constexpr int kStrategyBinned = 0;     // bucket points by tile, reduce each tile in LDS
@@ -152,6 +159,12 @@ struct DevSim {
     int64_t n_rows;          // histogram binning: rows of this simulation
     int64_t row_base;        // first global row of this simulation
     int64_t hbase;           // offset of this simulation's first row in the row matrix
+    // histogram tiles: the tiles themselves, or super-tiles of (1 << ux) x (1 << uy) tiles
+    int32_t ux, uy;
+    int32_t h_tiles_x;       // histogram tiles per grid row
+    int32_t pad2;
+    int64_t h_tiles;         // histogram tiles of this simulation (row width)
+    int64_t h_base;          // first global histogram tile of this simulation
     // swept-box culling
     const double *gm;        // [z_n][n_groups] group radii
     int32_t n_groups;
@@ -182,16 +195,24 @@ struct RoughState {
 
 // Buffers of the binned strategy (device memory).
 struct BinBuffers {
-    // counts, offsets and cursor are indexed by (global tile - tile0): a slice of the histogram
-    // mode covers only the tiles of the simulations its rows belong to
-    int64_t tile0;
-    uint32_t *counts;        // [n_tiles] points per tile
-    uint32_t *offsets;       // [n_tiles + 1] bucket starts
-    uint32_t *cursor;        // [n_tiles] write cursors (run mode)
-    uint32_t *bsum;          // [ceil(n_tiles / scan segment)] scan block sums
+    // counts, offsets and cursor are indexed by (global histogram tile - htile0), tile_lo and
+    // tile_hi by (global tile - tile0): a slice of the histogram mode covers only the tiles of
+    // the simulations its rows belong to.  Without super-tiles the histogram tiles are the
+    // tiles, htile0 = tile0, and tile_lo / tile_hi are offsets / offsets + 1.
+    int64_t tile0, htile0;
+    uint32_t *counts;        // [n_htiles] points per histogram tile
+    uint32_t *offsets;       // [n_htiles + 1] bucket starts
+    uint32_t *cursor;        // [n_htiles] write cursors (run mode)
+    uint32_t *bsum;          // [ceil(n_htiles / scan segment)] scan block sums
+    uint32_t *tile_lo;       // [n_tiles] bucket of each tile: [tile_lo, tile_hi)
+    uint32_t *tile_hi;
     void *bkey;              // [cap] int64 (FP64) or int32 (FP32) height keys
     uint16_t *bidx;          // [cap] cell index inside the tile
     int64_t cap;             // bucket capacity (points)
+    // super-tiles: the write pass fills the super-tile buckets, whose cells carry the tile
+    // inside the super-tile in their upper 16 bits; the split pass sorts them into bkey / bidx
+    void *skey;              // [cap] keys, or nullptr without super-tiles
+    uint32_t *spk;           // [cap] (tile inside the super-tile << 16) | cell inside the tile
     // histogram mode
     uint32_t *hist;          // row matrix: per row, the points of each tile of its simulation
     uint32_t *chunk;         // [n_chunks][n_tiles] column-scan partials
@@ -224,11 +245,14 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
 // touches only the n_tiles tiles from bb.tile0 on (those of the simulations its rows belong
 // to); a simulation's tiles are initialised in the slice holding its first row and their
 // first roughness pass runs in the slice holding its last row.
+// With super-tiles (bb.skey set) the histograms, scans and buckets are per super-tile
+// (n_htiles of them from bb.htile0 on, simulations found through d_hbase) and a split pass
+// sorts every super-tile's bucket into its tiles before the reduction.
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
-                      const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
-                      int64_t row_end, const BinBuffers &bb, int precision, int sx, int sy,
-                      TileStat1 *st1, uint64_t *d_binned, void *stream,
-                      const StageEvents *marks = nullptr);
+                      const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
+                      int64_t n_htiles, int64_t row_begin, int64_t row_end, const BinBuffers &bb,
+                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                      void *stream, const StageEvents *marks = nullptr);
 // Trajectory module: per (pass, step, tooth) the lowest edge point's workpiece position.
 int launch_trajectory(const DevSim *d_sim, int64_t n_items, int precision, void *traj,
                       int32_t *index, void *stream);

@@ -651,18 +651,21 @@ __global__ __launch_bounds__(kBlock) void bin_points(const DevSim *__restrict__ 
 // matrix into the offset of every (row, tile) inside the tile's bucket, and the write pass
 // recomputes the points, claiming slots with LDS atomics on the row's cursors.
 
-// Visit every in-grid point of binning items [i0, i1) of simulation d: f(tile, cell, key, near)
-// with the tile numbered inside the simulation.  Lanes hold the steps of a wave; the edge
-// points of a culling group are loaded kBatch at a time ahead of their arithmetic.
+// Visit every in-grid point of binning items [i0, i1) of simulation d: f(htile, cell, key,
+// near) with the histogram tile numbered inside the simulation and the cell inside its tile;
+// SUPER: the cell carries the tile inside the super-tile in its upper 16 bits.  Lanes hold
+// the steps of a wave; the edge points of a culling group are loaded kBatch at a time ahead
+// of their arithmetic.
 constexpr int kBatch = 4;
-template <int PREC, int TILT, typename F>
+template <int PREC, int TILT, bool SUPER, typename F>
 __device__ __forceinline__ void row_points_tilt(const DevSim &d, int64_t i0, int64_t i1, F &f)
 {
     using Key = typename KeyOf<PREC>::T;
     const int lane = threadIdx.x & 63;
-    const int sx = d.sx, sy = d.sy;
+    const int sx = d.sx, sy = d.sy, hsx = sx + d.ux, hsy = sy + d.uy;
     const int32_t mx = (1 << sx) - 1, my = (1 << sy) - 1;
-    const uint32_t tiles_x = (uint32_t)d.tiles_x;
+    const int32_t mux = (1 << d.ux) - 1, muy = (1 << d.uy) - 1;
+    const uint32_t htiles_x = (uint32_t)d.h_tiles_x;
     for (int64_t it = i0; it < i1; ++it) {
         int64_t local = it;
         const int K = (int)(local % d.z_n);
@@ -695,11 +698,15 @@ __device__ __forceinline__ void row_points_tilt(const DevSim &d, int64_t i0, int
                     Key key;
                     int32_t i, j;
                     bool near;
-                    // the tile is numbered inside the simulation; a histogram holds at most
-                    // kMaxHistTiles tiles, so both factors fit the 24-bit multiply
-                    if (p + u < pe && act && place_point<TILT>(d, a, e[u], xcs, yq, i, j, key, near))
-                        f((int32_t)(__umul24((uint32_t)(j >> sy), tiles_x) + (uint32_t)(i >> sx)),
-                          (uint16_t)(((j & my) << sx) | (i & mx)), key, near);
+                    // the histogram tile is numbered inside the simulation; a histogram holds
+                    // at most kMaxHistTiles tiles, so both factors fit the 24-bit multiply
+                    if (p + u < pe && act && place_point<TILT>(d, a, e[u], xcs, yq, i, j, key, near)) {
+                        uint32_t cell = (uint32_t)(((j & my) << sx) | (i & mx));
+                        if constexpr (SUPER)
+                            cell |= (uint32_t)((((j >> sy) & muy) << d.ux) | ((i >> sx) & mux)) << 16;
+                        f((int32_t)(__umul24((uint32_t)(j >> hsy), htiles_x) + (uint32_t)(i >> hsx)),
+                          cell, key, near);
+                    }
                 }
             }
         }
@@ -707,14 +714,14 @@ __device__ __forceinline__ void row_points_tilt(const DevSim &d, int64_t i0, int
 }
 
 // The same with the simulation's tilt mode fixed once for the row.
-template <int PREC, typename F>
+template <int PREC, bool SUPER, typename F>
 __device__ __forceinline__ void row_points(const DevSim &d, int64_t i0, int64_t i1, F &&f)
 {
     switch (tilt_mode(d)) {
-    case 0: row_points_tilt<PREC, 0>(d, i0, i1, f); break;
-    case kTiltLead: row_points_tilt<PREC, kTiltLead>(d, i0, i1, f); break;
-    case kTiltSide: row_points_tilt<PREC, kTiltSide>(d, i0, i1, f); break;
-    default: row_points_tilt<PREC, kTiltLead | kTiltSide>(d, i0, i1, f); break;
+    case 0: row_points_tilt<PREC, 0, SUPER>(d, i0, i1, f); break;
+    case kTiltLead: row_points_tilt<PREC, kTiltLead, SUPER>(d, i0, i1, f); break;
+    case kTiltSide: row_points_tilt<PREC, kTiltSide, SUPER>(d, i0, i1, f); break;
+    default: row_points_tilt<PREC, kTiltLead | kTiltSide, SUPER>(d, i0, i1, f); break;
     }
 }
 
@@ -733,11 +740,11 @@ __global__ __launch_bounds__(kBlock) void hist_count(const DevSim *__restrict__ 
         const int64_t lr = r - d.row_base;
         const int64_t i0 = lr * d.items_per_row;
         const int64_t i1 = i0 + d.items_per_row < d.n_bitems ? i0 + d.items_per_row : d.n_bitems;
-        const int T = (int)d.n_tiles;
+        const int T = (int)d.h_tiles;
         for (int t = tid; t < T; t += kBlock) hist[t] = 0u;
         __syncthreads();
         uint32_t n_near = 0;
-        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t, Key, bool near) {
+        row_points<PREC, false>(d, i0, i1, [&](int32_t lt, uint32_t, Key, bool near) {
             __hip_atomic_fetch_add(&hist[lt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             n_near += near;
         });
@@ -766,14 +773,14 @@ __global__ __launch_bounds__(kBlock) void hist_colsum(const DevSim *__restrict__
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n_chunks * n_tiles; x += stride) {
-        const int64_t c = x / n_tiles, t = bb.tile0 + (x - c * n_tiles);
+        const int64_t c = x / n_tiles, t = bb.htile0 + (x - c * n_tiles);
         const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
         const DevSim &d = sims[si];
         int64_t a, b;
         sim_rows(d, r0 + c * bb.row_chunk, r0 + (c + 1) * bb.row_chunk < r1 ? r0 + (c + 1) * bb.row_chunk : r1, a, b);
-        const int64_t lt = t - d.tile_base;
+        const int64_t lt = t - d.h_base;
         uint32_t sum = 0;
-        for (int64_t r = a; r < b; ++r) sum += bb.hist[d.hbase + (r - d.row_base) * d.n_tiles + lt];
+        for (int64_t r = a; r < b; ++r) sum += bb.hist[d.hbase + (r - d.row_base) * d.h_tiles + lt];
         bb.chunk[x] = sum;
     }
 }
@@ -813,36 +820,36 @@ __global__ __launch_bounds__(kBlock) void hist_apply(const DevSim *__restrict__ 
 {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x; x < n_chunks * n_tiles; x += stride) {
-        const int64_t c = x / n_tiles, t = bb.tile0 + (x - c * n_tiles);
+        const int64_t c = x / n_tiles, t = bb.htile0 + (x - c * n_tiles);
         const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
         const DevSim &d = sims[si];
         int64_t a, b;
         sim_rows(d, r0 + c * bb.row_chunk, r0 + (c + 1) * bb.row_chunk < r1 ? r0 + (c + 1) * bb.row_chunk : r1, a, b);
-        const int64_t lt = t - d.tile_base;
+        const int64_t lt = t - d.h_base;
         uint32_t run = bb.chunk[x];
-        uint32_t *e = bb.hist + d.hbase + (a - d.row_base) * d.n_tiles + lt;
+        uint32_t *e = bb.hist + d.hbase + (a - d.row_base) * d.h_tiles + lt;
         const int64_t nr = b - a;
         if (nr == kRowChunk) {
             // the chunk's counts in flight before their offsets are stored over them
             uint32_t v[kRowChunk];
 #pragma unroll
-            for (int u = 0; u < kRowChunk; ++u) v[u] = e[(int64_t)u * d.n_tiles];
+            for (int u = 0; u < kRowChunk; ++u) v[u] = e[(int64_t)u * d.h_tiles];
 #pragma unroll
             for (int u = 0; u < kRowChunk; ++u) {
-                e[(int64_t)u * d.n_tiles] = run;
+                e[(int64_t)u * d.h_tiles] = run;
                 run += v[u];
             }
         } else {
             for (int64_t r = 0; r < nr; ++r) {
-                const uint32_t v = e[r * d.n_tiles];
-                e[r * d.n_tiles] = run;
+                const uint32_t v = e[r * d.h_tiles];
+                e[r * d.h_tiles] = run;
                 run += v;
             }
         }
     }
 }
 
-template <int PREC>
+template <int PREC, bool SUPER>
 __global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ sims, int n_sims,
                                                      const int64_t *__restrict__ row_base,
                                                      int64_t r0, int64_t n_rows, BinBuffers bb)
@@ -850,8 +857,9 @@ __global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ 
     using Key = typename KeyOf<PREC>::T;
     extern __shared__ uint32_t cur[];
     const int tid = threadIdx.x;
-    FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bb.bkey));
+    FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(SUPER ? bb.skey : bb.bkey));
     FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
+    FSM_GLOBAL uint32_t *spk = gptr(bb.spk);
     for (int64_t b = blockIdx.x; b < n_rows; b += gridDim.x) {
         const int64_t r = r0 + loop_chunk(b, n_rows);
         const int si = n_sims == 1 ? 0 : find_sim(row_base, n_sims, r);
@@ -859,19 +867,111 @@ __global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ 
         const int64_t lr = r - d.row_base;
         const int64_t i0 = lr * d.items_per_row;
         const int64_t i1 = i0 + d.items_per_row < d.n_bitems ? i0 + d.items_per_row : d.n_bitems;
-        const int T = (int)d.n_tiles;
+        const int T = (int)d.h_tiles;
         const FSM_GLOBAL uint32_t *row = gptr(bb.hist) + d.hbase + lr * T;
-        const FSM_GLOBAL uint32_t *off = gptr(bb.offsets) + (d.tile_base - bb.tile0);
+        const FSM_GLOBAL uint32_t *off = gptr(bb.offsets) + (d.h_base - bb.htile0);
         for (int t = tid; t < T; t += kBlock) cur[t] = off[t] + row[t];
         __syncthreads();
         const int64_t cap = bb.cap;
-        row_points<PREC>(d, i0, i1, [&](int32_t lt, uint16_t cell, Key key, bool) {
+        row_points<PREC, SUPER>(d, i0, i1, [&](int32_t lt, uint32_t cell, Key key, bool) {
             const uint32_t pos = __hip_atomic_fetch_add(&cur[lt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if ((int64_t)pos < cap) {
                 bkey[pos] = key;
-                bix[pos] = cell;
+                if constexpr (SUPER) spk[pos] = cell;
+                else bix[pos] = (uint16_t)cell;
             }
         });
+        __syncthreads();
+    }
+}
+
+// Super-tiles n_htiles from bb.htile0 on: sort each super-tile's bucket into the buckets of its
+// tiles, in place of the same range of bkey / bidx, and write every tile's [tile_lo, tile_hi).
+// One block per super-tile: an LDS count per tile inside the super-tile, their running sum,
+// then a second read that claims slots with LDS atomics (the order inside a tile's bucket does
+// not matter to its minimum).
+constexpr int kSplitDepth = 8;
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void split_super(const DevSim *__restrict__ sims, int n_sims,
+                                                      const int64_t *__restrict__ hbase,
+                                                      int64_t n_htiles, BinBuffers bb)
+{
+    using Key = typename KeyOf<PREC>::T;
+    __shared__ uint32_t cnt[kMaxSubTiles], cur[kMaxSubTiles];
+    const int tid = threadIdx.x;
+    const FSM_GLOBAL Key *skey = gptr(static_cast<const Key *>(bb.skey));
+    const FSM_GLOBAL uint32_t *spk = gptr(bb.spk);
+    FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bb.bkey));
+    FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
+    const int64_t cap = bb.cap;
+    for (int64_t b = blockIdx.x; b < n_htiles; b += gridDim.x) {
+        const int64_t h = bb.htile0 + b;
+        const int si = n_sims == 1 ? 0 : find_sim(hbase, n_sims, h);
+        const DevSim &d = sims[si];
+        const int64_t lh = h - d.h_base;
+        const int stx = (int)(lh % d.h_tiles_x), sty = (int)(lh / d.h_tiles_x);
+        const int ux = d.ux, nsub = 1 << (ux + d.uy);
+        // entries past the capacity were never written; the clamp keeps the reads inside
+        const uint32_t s0 = (int64_t)bb.offsets[b] < cap ? bb.offsets[b] : (uint32_t)cap;
+        const uint32_t s1 = (int64_t)bb.offsets[b + 1] < cap ? bb.offsets[b + 1] : (uint32_t)cap;
+        const uint32_t sm = (uint32_t)(nsub - 1);
+        if (tid < nsub) cnt[tid] = 0u;
+        __syncthreads();
+        // kSplitDepth entries in flight per thread in both reads
+        uint32_t e = s0 + tid;
+        for (; e + (kSplitDepth - 1) * kBlock < s1; e += kSplitDepth * kBlock) {
+            uint32_t p[kSplitDepth];
+#pragma unroll
+            for (int v = 0; v < kSplitDepth; ++v) p[v] = __builtin_nontemporal_load(&spk[e + v * kBlock]);
+#pragma unroll
+            for (int v = 0; v < kSplitDepth; ++v)
+                __hip_atomic_fetch_add(&cnt[(p[v] >> 16) & sm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        for (; e < s1; e += kBlock)
+            __hip_atomic_fetch_add(&cnt[(spk[e] >> 16) & sm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t run = s0;
+            for (int k = 0; k < nsub; ++k) {
+                cur[k] = run;
+                run += cnt[k];
+            }
+        }
+        __syncthreads();
+        if (tid < nsub) {
+            const int tx = (stx << ux) + (tid & ((1 << ux) - 1)), ty = (sty << d.uy) + (tid >> ux);
+            if (tx < d.tiles_x && ty < d.tiles_y) {
+                const int64_t t = d.tile_base + (int64_t)ty * d.tiles_x + tx - bb.tile0;
+                bb.tile_lo[t] = cur[tid];
+                bb.tile_hi[t] = cur[tid] + cnt[tid];
+            }
+        }
+        __syncthreads();
+        e = s0 + tid;
+        for (; e + (kSplitDepth - 1) * kBlock < s1; e += kSplitDepth * kBlock) {
+            Key k[kSplitDepth];
+            uint32_t p[kSplitDepth];
+#pragma unroll
+            for (int v = 0; v < kSplitDepth; ++v) {
+                k[v] = __builtin_nontemporal_load(&skey[e + v * kBlock]);
+                p[v] = __builtin_nontemporal_load(&spk[e + v * kBlock]);
+            }
+#pragma unroll
+            for (int v = 0; v < kSplitDepth; ++v) {
+                const uint32_t pos = __hip_atomic_fetch_add(&cur[(p[v] >> 16) & sm], 1u, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+                bkey[pos] = k[v];
+                bix[pos] = (uint16_t)p[v];
+            }
+        }
+        for (; e < s1; e += kBlock) {
+            const Key k = skey[e];
+            const uint32_t pk = spk[e];
+            const uint32_t pos = __hip_atomic_fetch_add(&cur[(pk >> 16) & sm], 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+            bkey[pos] = k;
+            bix[pos] = (uint16_t)pk;
+        }
         __syncthreads();
     }
 }
@@ -1113,7 +1213,7 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
     Key *lds = reinterpret_cast<Key *>(smem);
     const FSM_GLOBAL Key *bkey = gptr(static_cast<const Key *>(bb.bkey));
     const FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
-    const FSM_GLOBAL uint32_t *offsets = gptr(bb.offsets);
+    const FSM_GLOBAL uint32_t *tile_lo = gptr(bb.tile_lo), *tile_hi = gptr(bb.tile_hi);
     const int tid = threadIdx.x;
     // entries past the capacity were never written (the planner sizes slices so that none
     // are dropped); the clamp keeps the reads inside the bucket arrays regardless
@@ -1157,8 +1257,8 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
     auto bounds = [&](int64_t tl, uint32_t &o0, uint32_t &o1) {
         o0 = o1 = 0;
         if (tl < n_tiles) {
-            o0 = clamp(offsets[tl]);
-            o1 = clamp(offsets[tl + 1]);
+            o0 = clamp(tile_lo[tl]);
+            o1 = clamp(tile_hi[tl]);
         }
     };
     auto ahead = [&]() {
@@ -1329,6 +1429,8 @@ __global__ __launch_bounds__(kBlock) void tile_stats1(const DevSim *__restrict__
     }
 }
 
+constexpr int kFinalDepth = 8;   // tile partials in flight per thread of the final combines
+
 // One block per simulation: combine its tiles' first-pass partials in a fixed order.
 __global__ __launch_bounds__(kBlock) void rough_final1(const DevSim *__restrict__ sims,
                                                        const TileStat1 *__restrict__ st1,
@@ -1336,8 +1438,7 @@ __global__ __launch_bounds__(kBlock) void rough_final1(const DevSim *__restrict_
 {
     const DevSim d = sims[blockIdx.x];
     Stat1Acc a;
-    for (int64_t k = threadIdx.x; k < d.n_tiles; k += kBlock) {
-        const TileStat1 s = st1[d.tile_base + k];
+    auto add = [&a](const TileStat1 &s) {
         a.sum += s.sum;
         a.mn = fmin(a.mn, s.mn);
         a.mx = fmax(a.mx, s.mx);
@@ -1346,7 +1447,18 @@ __global__ __launch_bounds__(kBlock) void rough_final1(const DevSim *__restrict_
         a.n += s.n;
         a.row_n += s.row_n;
         a.col_n += s.col_n;
+    };
+    // each thread's tiles in order, kFinalDepth partials in flight
+    const TileStat1 *p = st1 + d.tile_base;
+    int64_t k = threadIdx.x;
+    for (; k + (kFinalDepth - 1) * kBlock < d.n_tiles; k += kFinalDepth * kBlock) {
+        TileStat1 s[kFinalDepth];
+#pragma unroll
+        for (int v = 0; v < kFinalDepth; ++v) s[v] = p[k + v * kBlock];
+#pragma unroll
+        for (int v = 0; v < kFinalDepth; ++v) add(s[v]);
     }
+    for (; k < d.n_tiles; k += kBlock) add(p[k]);
     const TileStat1 r = a.reduce();
     if (threadIdx.x == 0) {
         RoughState st;
@@ -1515,15 +1627,24 @@ __global__ __launch_bounds__(kBlock) void rough_final2(const DevSim *__restrict_
 {
     const DevSim d = sims[blockIdx.x];
     Stat2Acc a;
-    for (int64_t k = threadIdx.x; k < d.n_tiles; k += kBlock) {
-        const TileStat2 s = st2[d.tile_base + k];
+    auto add = [&a](const TileStat2 &s) {
         a.s1 += s.s1;
         a.s2 += s.s2;
         a.s3 += s.s3;
         a.s4 += s.s4;
         a.row_abs += s.row_abs;
         a.col_abs += s.col_abs;
+    };
+    const TileStat2 *p = st2 + d.tile_base;
+    int64_t k = threadIdx.x;
+    for (; k + (kFinalDepth - 1) * kBlock < d.n_tiles; k += kFinalDepth * kBlock) {
+        TileStat2 s[kFinalDepth];
+#pragma unroll
+        for (int v = 0; v < kFinalDepth; ++v) s[v] = p[k + v * kBlock];
+#pragma unroll
+        for (int v = 0; v < kFinalDepth; ++v) add(s[v]);
     }
+    for (; k < d.n_tiles; k += kBlock) add(p[k]);
     const TileStat2 r = a.reduce();
     if (threadIdx.x == 0) {
         const RoughState st = state[d.sim];
@@ -1641,33 +1762,41 @@ void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
 
 template <int PREC>
 void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
-                const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin, int64_t row_end,
-                const BinBuffers &bb, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                hipStream_t s, const StageEvents *marks)
+                const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
+                int64_t n_htiles, int64_t row_begin, int64_t row_end, const BinBuffers &bb, int sx,
+                int sy, TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
 {
     const int64_t nr = row_end - row_begin;
     const int rb = (int)(nr < kMaxGrid ? nr : kMaxGrid);
     const size_t hist_lds = sizeof(uint32_t) * (size_t)(bb.max_tiles > 0 ? bb.max_tiles : 1);
     const int64_t n_chunks = (nr + bb.row_chunk - 1) / bb.row_chunk;
-    const int cb = stream_blocks(n_chunks * n_tiles, kBlock, 16384);
-    const int tb1 = stream_blocks(n_tiles, kBlock, 16384);
+    const int cb = stream_blocks(n_chunks * n_htiles, kBlock, 16384);
+    const int tb1 = stream_blocks(n_htiles, kBlock, 16384);
+    const int hb = (int)(n_htiles < kMaxGrid ? n_htiles : kMaxGrid);
     const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
     const size_t lds = sizeof(typename KeyOf<PREC>::T) << (sx + sy);
+    const bool super = bb.skey != nullptr;
     stage(marks, 0, s);
     if (rb > 0)
         hipLaunchKernelGGL(hist_count<PREC>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
     stage(marks, 1, s);
     if (n_chunks > 0) {
-        hipLaunchKernelGGL(hist_colsum, dim3(cb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, row_begin, row_end, n_chunks, bb);
-        hipLaunchKernelGGL(hist_chunkscan, dim3(tb1), dim3(kBlock), 0, s, n_tiles, n_chunks, bb);
-        hipLaunchKernelGGL(hist_apply, dim3(cb), dim3(kBlock), 0, s, d_sims, n_sims, d_tile_base, n_tiles, row_begin, row_end, n_chunks, bb);
+        hipLaunchKernelGGL(hist_colsum, dim3(cb), dim3(kBlock), 0, s, d_sims, n_sims, d_hbase, n_htiles, row_begin, row_end, n_chunks, bb);
+        hipLaunchKernelGGL(hist_chunkscan, dim3(tb1), dim3(kBlock), 0, s, n_htiles, n_chunks, bb);
+        hipLaunchKernelGGL(hist_apply, dim3(cb), dim3(kBlock), 0, s, d_sims, n_sims, d_hbase, n_htiles, row_begin, row_end, n_chunks, bb);
     } else {
-        hipLaunchKernelGGL(zero_u32, dim3(tb1), dim3(kBlock), 0, s, bb.counts, n_tiles);
+        hipLaunchKernelGGL(zero_u32, dim3(tb1), dim3(kBlock), 0, s, bb.counts, n_htiles);
     }
-    launch_scan(n_tiles, bb, s);
+    launch_scan(n_htiles, bb, s);
     stage(marks, 2, s);
-    if (rb > 0)
-        hipLaunchKernelGGL(hist_write<PREC>, dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+    if (rb > 0) {
+        if (super)
+            hipLaunchKernelGGL((hist_write<PREC, true>), dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+        else
+            hipLaunchKernelGGL((hist_write<PREC, false>), dim3(rb), dim3(kBlock), hist_lds, s, d_sims, n_sims, d_row_base, row_begin, nr, bb);
+    }
+    if (super && hb > 0)
+        hipLaunchKernelGGL(split_super<PREC>, dim3(hb), dim3(kBlock), 0, s, d_sims, n_sims, d_hbase, n_htiles, bb);
     stage(marks, 3, s);
     if (lds > kTileLdsSmall)
         hipLaunchKernelGGL((tile_reduce<PREC, 2 * kBlock>), dim3(tb), dim3(2 * kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, -1, -1, row_begin, row_end, st1, d_binned);
@@ -1693,15 +1822,16 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
 }
 
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
-                      const int64_t *d_tile_base, int64_t n_tiles, int64_t row_begin,
-                      int64_t row_end, const BinBuffers &bb, int precision, int sx, int sy,
-                      TileStat1 *st1, uint64_t *d_binned, void *stream, const StageEvents *marks)
+                      const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
+                      int64_t n_htiles, int64_t row_begin, int64_t row_end, const BinBuffers &bb,
+                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
+                      void *stream, const StageEvents *marks)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64)
-        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     else
-        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     return (int)hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 // and the kernels clear their counts themselves.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -100,7 +101,7 @@ extern "C" int fsm_simulate_noalloc(fsm_ctx *ctx, const fsm_tool *tool, const fs
         // the context's launch parameters, with the row matrix and the buckets cut to the
         // array (the row matrix to a quarter of it; the buckets to what is left)
         LaunchParams lp = params_for(ctx, plans, precision);
-        lp.hist_bytes = (int64_t)kScratchBytes / 4;
+        lp.hist_bytes = std::min<int64_t>(lp.hist_bytes, (int64_t)kScratchBytes / 4);
         SetLayout L;
         std::vector<fsm::DevSim> devs;
         if (!fit_layout(ctx, plans, precision, (int64_t)kScratchBytes, lp, L, devs))

@@ -35,7 +35,7 @@ struct LaunchParams {
     int strategy = kStrategyBinned;
     int tile_shape = 0;
     int64_t target_rows = 4096;
-    int64_t bucket_bytes = (int64_t)8 << 30;
+    int64_t bucket_bytes = (int64_t)16 << 30;
     int64_t hist_bytes = (int64_t)1 << 30;   // row matrix of the histogram mode, at most
 };
 
@@ -44,15 +44,18 @@ struct SetLayout {
     int n = 0, precision = 0, strategy = 0, sx = 7, sy = 6;
     int64_t total_tiles = 0, total_items = 0, per_slice = 0, cap = 0;
     int max_n = 1;
-    // histogram mode of the binned strategy (no global atomics)
-    bool hist = false;
+    // histogram mode of the binned strategy (no global atomics), with super-tiles when a
+    // simulation has more tiles than a row histogram holds
+    bool hist = false, super = false;
     int64_t total_rows = 0, rows_per_slice = 0, max_tiles = 0, items_per_row = 1;
+    int64_t total_htiles = 0;   // histogram tiles (super-tiles, else tiles)
+    int64_t entry = 0;          // bucket bytes per point
     // device-only region
     size_t st1 = 0, st2 = 0, state = 0, out = 0, counts = 0, offsets = 0, cursor = 0, bsum = 0,
-           bkey = 0, bidx = 0, hist_m = 0, chunk = 0;
+           bkey = 0, bidx = 0, hist_m = 0, chunk = 0, tile_lo = 0, tile_hi = 0, skey = 0, spk = 0;
     size_t scratch_end = 0;
     // uploaded region
-    size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, binned = 0, evals = 0, near = 0;
+    size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, hbase = 0, binned = 0, evals = 0, near = 0;
     std::vector<size_t> pT, pTf, cs, csf, gm;
     size_t total = 0;
 };
@@ -80,9 +83,11 @@ struct fsm_ctx {
     hipEvent_t ev[5] = {};       // upload, fill, z-map, roughness, end
     std::vector<fsm::StageEvents> stage_ev;   // per binned slice: the five stage events
     int stages_used = 0;                      // slices of the last profiled call
+    int zmap_path = 0;                        // FSM_PATH_* of the last launch
     fsm_timings timings = {};
     int strategy = fsm::kStrategyBinned;
-    int64_t bucket_bytes = (int64_t)8 << 30;
+    int64_t bucket_bytes = (int64_t)16 << 30;
+    int64_t hist_bytes = (int64_t)1 << 30;    // FSM_OPT_HIST_BYTES
     bool graphs = false;
     int tile_shape = 0;          // FSM_OPT_TILE_SHAPE (0: default)
     int64_t target_rows = 4096;  // FSM_OPT_TARGET_ROWS

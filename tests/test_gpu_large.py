@@ -1,7 +1,8 @@
 """The large single field at its full size: a D = 12 mm four-flute round-edge mill over
 40000 x 40000 cells at 0.5 um (1.6e9 cells, 5.7e8 edge-point evaluations), the launch the
-benchmark's large-field leg times.  Its 16384+ tiles per map run the binned strategy's
-run mode (global bucket cursors) rather than the histogram mode.
+benchmark's large-field leg times.  Its 98 125 (FP64) or 49 141 (FP32) tiles per map are
+more than one row histogram holds, so the binned strategy counts per super-tile and splits
+the super-tile buckets into the tiles (super mode).
 
 Double precision: the whole 12.8 GB Z-map equals the oracle's, bit for bit, with identical
 in-grid counts and roughness within 1e-4.  Single precision: sampled windows inside the
@@ -41,8 +42,13 @@ def test_config5_f64_full_field_exact(ctx):
     with ThreadPoolExecutor(1) as pool:
         fut = pool.submit(oracle.simulate, s)
         print("[gpu] config5 f64 40000x40000", flush=True)
+        ctx.fsm_ctx_set_profiling(True)
         z, r = ctx.fsm_simulate(s, "f64")
         torch.cuda.synchronize()
+        t = ctx.fsm_last_timings()
+        ctx.fsm_ctx_set_profiling(False)
+        from paper_2603_28160_amd import _abi
+        assert t["zmap_path"] == _abi.PATH_SUPER and t["n_slices"] == 1, t
         zg = z.cpu().numpy()
         del z
         torch.cuda.empty_cache()

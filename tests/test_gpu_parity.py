@@ -184,6 +184,58 @@ def test_binned_slices_aligned_rows_exact(ctx):
         ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 2 << 30)
 
 
+def last_path(ctx):
+    t = ctx.fsm_last_timings()
+    return t["zmap_path"], t["n_slices"]
+
+
+@pytest.mark.parametrize("budget", [0, 96 << 20])
+def test_super_tiles_exact(ctx, budget):
+    # 16 x 16-cell tiles over 2100 x 2050 cells: 132 x 129 = 17 028 tiles, more than one row
+    # histogram holds, so the rows count per super-tile of 2 x 2 tiles (the last super-tile
+    # row half outside the grid) and a split pass sorts each super-tile's bucket into its
+    # tiles; with a 96 MiB bucket budget the rows also run in many slices, each folding its
+    # tiles into the map of the one before
+    from paper_2603_28160_amd import _abi
+    s = W.config2(nx=2100, ny=2050, dd=0.002)
+    ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 0)
+    ctx.fsm_ctx_set_option(_abi.OPT_TILE_SHAPE, 0x44)
+    # 0: the default budget, which holds every evaluation of this grid in one slice
+    ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, budget or 16 << 30)
+    ctx.fsm_ctx_set_profiling(True)
+    try:
+        check_f64(ctx, s)
+        path, slices = last_path(ctx)
+        assert path == _abi.PATH_SUPER
+        assert (slices > 1) == bool(budget), slices
+        check_f32(ctx, s)
+        assert last_path(ctx)[0] == _abi.PATH_SUPER
+    finally:
+        ctx.fsm_ctx_set_profiling(False)
+        ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 2 << 30)
+        ctx.fsm_ctx_set_option(_abi.OPT_TILE_SHAPE, 0)
+        ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 1)
+
+
+def test_run_mode_exact(ctx):
+    # no room for a row matrix: the binned strategy counts and claims with global atomics
+    # per tile (run mode), over several slices
+    from paper_2603_28160_amd import _abi
+    s = W.config2(nx=777, ny=613, dd=0.004)
+    ctx.fsm_ctx_set_option(_abi.OPT_HIST_BYTES, 0)
+    ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 16 << 20)
+    ctx.fsm_ctx_set_profiling(True)
+    try:
+        check_f64(ctx, s)
+        path, slices = last_path(ctx)
+        assert path == _abi.PATH_RUN and slices > 1, (path, slices)
+        check_f32(ctx, s)
+    finally:
+        ctx.fsm_ctx_set_profiling(False)
+        ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, 2 << 30)
+        ctx.fsm_ctx_set_option(_abi.OPT_HIST_BYTES, 1 << 30)
+
+
 def test_paper_case2_tool_f64_exact(ctx):
     # the paper's own face-milling tool with rake and per-insert runout (Sec. 4.2)
     t = W.paper_case2_tool(eps_r=-0.026, eps_a=0.009, n_edge=30)
