@@ -1132,8 +1132,11 @@ struct Stat1Acc {
     // Block totals in every thread of a block of NW waves: butterflies within each wave, then
     // the waves' partials by a pairwise tree in wave order (for four waves, the order of
     // block_reduce), with one barrier for all eight values.
+    // rows / cols (uniform over the block): whether any thread may hold cells of the feed /
+    // pick profile (every thread's profile terms are zero otherwise, and their sums are
+    // skipped); tile: the accumulator holds one tile's cells, whose count fits 32 bits.
     template <int NW = kWaves>
-    __device__ TileStat1 reduce()
+    __device__ TileStat1 reduce(bool rows = true, bool cols = true, bool tile = false)
     {
         static_assert(NW == 4 || NW == 8, "four or eight waves");
         __shared__ double bd[5][8];
@@ -1141,9 +1144,9 @@ struct Stat1Acc {
         __shared__ int32_t bi[2][8];
         const int w = threadIdx.x >> 6;
         const double s0 = wave_sum(sum), s1 = wave_min(mn), s2 = wave_max(mx);
-        const double s3 = wave_sum(row_sum), s4 = wave_sum(col_sum);
-        const int64_t c0 = wave_sum(n + (int64_t)cnt);
-        const int32_t c1 = wave_sum(row_n), c2 = wave_sum(col_n);
+        const double s3 = rows ? wave_sum(row_sum) : 0.0, s4 = cols ? wave_sum(col_sum) : 0.0;
+        const int64_t c0 = tile ? (int64_t)wave_sum(cnt) : wave_sum(n + (int64_t)cnt);
+        const int32_t c1 = rows ? wave_sum(row_n) : 0, c2 = cols ? wave_sum(col_n) : 0;
         __syncthreads();
         if ((threadIdx.x & 63) == 0) {
             bd[0][w] = s0;
@@ -1386,7 +1389,7 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
             }
         }
         if (last) {
-            const TileStat1 s = acc.reduce<NT / 64>();
+            const TileStat1 s = acc.reduce<NT / 64>(rj >= 0 && rj < g.h, ci >= 0 && ci < g.w, true);
             if (tid == 0) st1[t] = s;
         }
         __syncthreads();
@@ -1424,7 +1427,7 @@ __global__ __launch_bounds__(kBlock) void tile_stats1(const DevSim *__restrict__
                 acc.add(KT::height(k), lj == rj, li == ci);
             }
         }
-        const TileStat1 s = acc.reduce();
+        const TileStat1 s = acc.reduce(rj >= 0 && rj < g.h, ci >= 0 && ci < g.w, true);
         if (tid == 0) st1[t] = s;
     }
 }
@@ -1592,8 +1595,9 @@ __global__ __launch_bounds__(kBlock) void tile_stats2(const DevSim *__restrict__
         s2 = wave_sum(s2);
         s3 = wave_sum(s3);
         s4 = wave_sum(s4);
-        row_abs = wave_sum(row_abs);
-        col_abs = wave_sum(col_abs);
+        // the profile terms are zero in every thread of a tile off the profile lines
+        if (rj >= 0 && rj < g.h) row_abs = wave_sum(row_abs);
+        if (ci >= 0 && ci < g.w) col_abs = wave_sum(col_abs);
         if (lane == 0) {
             part[0][wv] = s1;
             part[1][wv] = s2;
