@@ -129,7 +129,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     L.strategy = strategy;
     choose_tiles(ctx, precision, lp.tile_shape, L.sx, L.sy);
     devs.assign(L.n, DevSim{});
-    int64_t items = 0, bitems = 0, tiles = 0;
+    int64_t items = 0, bitems = 0, tiles = 0, groups = 0;
     for (int k = 0; k < L.n; ++k) {
         const Plan &P = plans[k];
         DevSim &d = devs[k];
@@ -184,6 +184,15 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         d.h_tiles_x = d.tiles_x;
         d.h_tiles = d.n_tiles;
         d.h_base = d.tile_base;
+        // reduction groups: the largest power of two of tiles (up to 64) that still leaves
+        // kReduceGroups groups; it follows from the simulation's own tiles only, so a
+        // simulation reduces alike alone and in a batch
+        d.tg_shift = 0;
+        while (d.tg_shift < fsm::kMaxGroupShift && (d.n_tiles >> (d.tg_shift + 1)) >= fsm::kReduceGroups)
+            ++d.tg_shift;
+        d.n_tgroups = ceil_div(d.n_tiles, (int64_t)1 << d.tg_shift);
+        d.tgroup_base = groups;
+        groups += d.n_tgroups;
         d.sim = k;
         if (precision == FSM_F32) {
             d.pos_err = fsm::kF32PosErr * P.pos_r;
@@ -196,6 +205,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     }
     L.total_tiles = tiles;
     L.total_htiles = tiles;
+    L.total_groups = groups;
     const bool binned = strategy == fsm::kStrategyBinned;
     L.total_items = binned ? bitems : items;
     if (binned) {
@@ -318,6 +328,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
     L.bbase = take(sizeof(int64_t) * L.n);
     L.tbase = take(sizeof(int64_t) * L.n);
     L.hbase = take(sizeof(int64_t) * L.n);
+    L.gbase = take(sizeof(int64_t) * L.n);
     L.binned = take(sizeof(uint64_t) * L.n);
     L.evals = take(sizeof(int64_t) * L.n);
     L.near = take(sizeof(uint64_t) * L.n);
@@ -402,7 +413,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
                 const std::vector<void *> &zmaps, char *dev, char *host)
 {
     auto H = [&](size_t off) { return host + (off - L.sims); };
-    std::vector<int64_t> ib(L.n), bb(L.n), tb(L.n), hb(L.n), ev(L.n), rbase(L.n);
+    std::vector<int64_t> ib(L.n), bb(L.n), tb(L.n), hb(L.n), gb(L.n), ev(L.n), rbase(L.n);
     std::vector<uint64_t> zero(L.n, 0);
     // every simulation writes its own descriptor and table ranges of the staging image
     parallel_for(L.n, [&](int k) {
@@ -419,6 +430,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         bb[k] = d.bitem_base;
         tb[k] = d.tile_base;
         hb[k] = d.h_base;
+        gb[k] = d.tgroup_base;
         rbase[k] = d.row_base;
         ev[k] = P.n_evals;
         if (!P.pT.empty()) std::memcpy(H(L.pT[k]), P.pT.data(), sizeof(double) * P.pT.size());
@@ -442,6 +454,7 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
     std::memcpy(H(L.bbase), (L.hist ? rbase : bb).data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.tbase), tb.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.hbase), hb.data(), sizeof(int64_t) * L.n);
+    std::memcpy(H(L.gbase), gb.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.binned), zero.data(), sizeof(uint64_t) * L.n);
     std::memcpy(H(L.evals), ev.data(), sizeof(int64_t) * L.n);
     std::memcpy(H(L.near), zero.data(), sizeof(uint64_t) * L.n);
@@ -510,6 +523,7 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
     const int64_t *d_bbase = reinterpret_cast<const int64_t *>(dev + L.bbase);
     const int64_t *d_tbase = reinterpret_cast<const int64_t *>(dev + L.tbase);
     const int64_t *d_hbase = reinterpret_cast<const int64_t *>(dev + L.hbase);
+    const int64_t *d_gbase = reinterpret_cast<const int64_t *>(dev + L.gbase);
     uint64_t *d_binned = reinterpret_cast<uint64_t *>(dev + L.binned);
     const int64_t *d_evals = reinterpret_cast<const int64_t *>(dev + L.evals);
     auto *st1 = reinterpret_cast<fsm::TileStat1 *>(dev + L.st1);
@@ -566,6 +580,7 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
                 const DevSim &da = devs[sim_of_row(r0)], &db = devs[sim_of_row(r1 - 1)];
                 const int64_t t0 = da.tile_base, t1 = db.tile_base + db.n_tiles;
                 const int64_t h0 = da.h_base, h1 = db.h_base + db.h_tiles;
+                const int64_t g0 = da.tgroup_base, g1 = db.tgroup_base + db.n_tgroups;
                 fsm::BinBuffers bs = bb;
                 bs.tile0 = t0;
                 bs.htile0 = h0;
@@ -575,23 +590,24 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
                 bs.tile_lo += L.super ? t0 : h0;
                 bs.tile_hi += L.super ? t0 : h0;
                 he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, t1 - t0, d_hbase, h1 - h0,
-                                            r0, r1, bs, L.precision, L.sx, L.sy, st1, d_binned, s,
-                                            stage_marks(ctx, slice++, capturing));
+                                            d_gbase, g0, g1 - g0, r0, r1, bs, L.precision, L.sx,
+                                            L.sy, st1, d_binned, s, stage_marks(ctx, slice++, capturing));
                 if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
                 r0 = r1;
             } while (r0 < L.total_rows);
         } else if (L.total_items == 0) {
             // nothing to bin: the maps are still initialised and the first pass still runs
-            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, 0, 0, bb,
-                                          true, true, L.precision, L.sx, L.sy, st1, d_binned, s,
-                                          stage_marks(ctx, slice++, capturing));
+            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, d_gbase, 0,
+                                          L.total_groups, 0, 0, bb, true, true, L.precision, L.sx,
+                                          L.sy, st1, d_binned, s, stage_marks(ctx, slice++, capturing));
             if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
         }
         for (int64_t b0 = 0; !L.hist && b0 < L.total_items; b0 += L.per_slice) {
             const int64_t nit = std::min<int64_t>(L.per_slice, L.total_items - b0);
-            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, b0, nit, bb,
-                                          b0 == 0, b0 + nit >= L.total_items, L.precision, L.sx,
-                                          L.sy, st1, d_binned, s, stage_marks(ctx, slice++, capturing));
+            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, d_gbase, 0,
+                                          L.total_groups, b0, nit, bb, b0 == 0, b0 + nit >= L.total_items,
+                                          L.precision, L.sx, L.sy, st1, d_binned, s,
+                                          stage_marks(ctx, slice++, capturing));
             if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
         }
     } else {

@@ -115,6 +115,10 @@ constexpr int64_t kMaxHistTiles = 16384;
 constexpr int64_t kSuperHistTiles = 8192;
 constexpr int kMaxSubShift = 6;
 constexpr int kMaxSubTiles = 1 << kMaxSubShift;
+// Tile groups of the reduction: as many tiles per group (a power of two, at most 64) as keep
+// at least kReduceGroups groups per simulation; small maps reduce one tile per workgroup.
+constexpr int64_t kReduceGroups = 2048;
+constexpr int kMaxGroupShift = 6;
 
 // Z-map strategies
 constexpr int kStrategyBinned = 0;     // bucket points by tile, reduce each tile in LDS
@@ -165,6 +169,12 @@ struct DevSim {
     int32_t pad2;
     int64_t h_tiles;         // histogram tiles of this simulation (row width)
     int64_t h_base;          // first global histogram tile of this simulation
+    // tile reduction: groups of (1 << tg_shift) consecutive tiles, one workgroup each, whose
+    // first-pass partials are summed before a single block reduction
+    int32_t tg_shift;
+    int32_t pad3;
+    int64_t n_tgroups;
+    int64_t tgroup_base;     // first global tile group of this simulation
     // swept-box culling
     const double *gm;        // [z_n][n_groups] group radii
     int32_t n_groups;
@@ -234,11 +244,14 @@ int launch_scatter(const DevSim *d_sims, int n_sims, const int64_t *d_item_base,
                    int64_t n_items, int precision, uint64_t *d_binned, void *stream);
 // One slice [item_begin, item_begin + n_items) of binning items: count -> scan -> write ->
 // per-tile LDS reduction into the Z-maps (with the first roughness pass on the last slice).
+// Tiles are reduced in groups: d_gbase holds each simulation's first tile group, and the
+// slice's tiles are the tile groups [g0, g0 + n_groups).
 int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
-                        const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
-                        int64_t n_items, const BinBuffers &bb, bool first_slice,
-                        bool last_slice, int precision, int sx, int sy, TileStat1 *st1,
-                        uint64_t *d_binned, void *stream, const StageEvents *marks = nullptr);
+                        const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_gbase,
+                        int64_t g0, int64_t n_groups, int64_t item_begin, int64_t n_items,
+                        const BinBuffers &bb, bool first_slice, bool last_slice, int precision,
+                        int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
+                        const StageEvents *marks = nullptr);
 // Histogram mode of the binned strategy, one slice of rows [row_begin, row_end): per-block
 // LDS histograms written as rows, a chunked column scan into per-(row, tile) offsets, a write
 // pass that claims slots with LDS atomics only, then the per-tile LDS reduction.  The slice
@@ -250,9 +263,10 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
 // sorts every super-tile's bucket into its tiles before the reduction.
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
                       const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
-                      int64_t n_htiles, int64_t row_begin, int64_t row_end, const BinBuffers &bb,
-                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                      void *stream, const StageEvents *marks = nullptr);
+                      int64_t n_htiles, const int64_t *d_gbase, int64_t g0, int64_t n_groups,
+                      int64_t row_begin, int64_t row_end, const BinBuffers &bb, int precision,
+                      int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
+                      const StageEvents *marks = nullptr);
 // Trajectory module: per (pass, step, tooth) the lowest edge point's workpiece position.
 int launch_trajectory(const DevSim *d_sim, int64_t n_items, int precision, void *traj,
                       int32_t *index, void *stream);

@@ -1132,6 +1132,20 @@ struct Stat1Acc {
     // Block totals in every thread of a block of NW waves: butterflies within each wave, then
     // the waves' partials by a pairwise tree in wave order (for four waves, the order of
     // block_reduce), with one barrier for all eight values.
+    // This thread's values as a partial (an empty one for a fresh accumulator).
+    __device__ TileStat1 partial() const
+    {
+        TileStat1 t;
+        t.sum = sum;
+        t.mn = mn;
+        t.mx = mx;
+        t.row_sum = row_sum;
+        t.col_sum = col_sum;
+        t.n = n + cnt;
+        t.row_n = row_n;
+        t.col_n = col_n;
+        return t;
+    }
     // rows / cols (uniform over the block): whether any thread may hold cells of the feed /
     // pick profile (every thread's profile terms are zero otherwise, and their sums are
     // skipped); tile: the accumulator holds one tile's cells, whose count fits 32 bits.
@@ -1197,17 +1211,18 @@ __device__ __forceinline__ TileGeom tile_geom(const DevSim &d, int64_t t)
     return g;
 }
 
-// Tiles [bb.tile0, bb.tile0 + n_tiles).  first_slice / last_slice: whether the tiles start
-// from +inf (else from the Z-map) and whether the first roughness pass runs; -1 takes both per
-// simulation from the slice's rows [r0, r1) (histogram mode).  NT threads per block: tiles of
-// more than 64 KiB of keys leave room for one block per compute unit, which then takes eight
-// waves to keep enough bucket loads in flight.
+// The tiles of the tile groups [g0, g0 + n_groups) (those of the simulations whose tiles run
+// from bb.tile0 on).  first_slice / last_slice: whether the tiles start from +inf (else from
+// the Z-map) and whether the first roughness pass runs; -1 takes both per simulation from the
+// slice's rows [r0, r1) (histogram mode).  NT threads per block: tiles of more than 64 KiB of
+// keys leave room for one block per compute unit, which then takes eight waves to keep enough
+// bucket loads in flight.
 template <int PREC, int NT>
 __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sims, int n_sims,
-                                                      const int64_t *__restrict__ tile_base,
-                                                      int64_t n_tiles, BinBuffers bb, int first_slice,
-                                                      int last_slice, int64_t r0, int64_t r1,
-                                                      TileStat1 *__restrict__ st1,
+                                                      const int64_t *__restrict__ group_base,
+                                                      int64_t g0, int64_t n_groups, BinBuffers bb,
+                                                      int first_slice, int last_slice, int64_t r0,
+                                                      int64_t r1, TileStat1 *__restrict__ st1,
                                                       uint64_t *__restrict__ binned)
 {
     using KT = KeyOf<PREC>;
@@ -1257,9 +1272,41 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
     bool has_one = false;
     uint32_t a0 = 0, a1 = 0;   // bucket of the tile whose first entries are in ak / ac / ok
     uint32_t n0 = 0, n1 = 0;   // bucket of the tile after it
-    auto bounds = [&](int64_t tl, uint32_t &o0, uint32_t &o1) {
+    // This block's tiles: the tile groups g0 + blockIdx.x, + gridDim.x, ..., each group's
+    // tiles in order.  A position is the group (inside the slice) and the tile inside its
+    // simulation; ok: the position exists.
+    struct Pos {
+        int64_t gl, lt, lt_end;
+        int si;
+        bool ok;
+    };
+    auto group_pos = [&](int64_t gl) {
+        Pos p;
+        p.gl = gl;
+        p.ok = gl < n_groups;
+        p.si = 0;
+        p.lt = p.lt_end = 0;
+        if (p.ok) {
+            const int64_t gg = g0 + gl;
+            p.si = n_sims == 1 ? 0 : find_sim(group_base, n_sims, gg);
+            const DevSim &d = sims[p.si];
+            p.lt = (gg - d.tgroup_base) << d.tg_shift;
+            const int64_t e = p.lt + ((int64_t)1 << d.tg_shift);
+            p.lt_end = e < d.n_tiles ? e : d.n_tiles;
+        }
+        return p;
+    };
+    auto succ = [&](Pos p) {
+        if (!p.ok) return p;
+        if (++p.lt < p.lt_end) return p;
+        return group_pos(p.gl + gridDim.x);
+    };
+    // slice-local tile index of a position
+    auto local_tile = [&](const Pos &p) { return sims[p.si].tile_base + p.lt - bb.tile0; };
+    auto bounds = [&](const Pos &p, uint32_t &o0, uint32_t &o1) {
         o0 = o1 = 0;
-        if (tl < n_tiles) {
+        if (p.ok) {
+            const int64_t tl = local_tile(p);
             o0 = clamp(tile_lo[tl]);
             o1 = clamp(tile_hi[tl]);
         }
@@ -1281,13 +1328,17 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
             oc = __builtin_nontemporal_load(&bix[e]);
         }
     };
-    bounds(blockIdx.x, a0, a1);
-    bounds(blockIdx.x + gridDim.x, n0, n1);
+    Pos pc = group_pos(blockIdx.x), pn = succ(pc);
+    bounds(pc, a0, a1);
+    bounds(pn, n0, n1);
     ahead();
-    for (int64_t tl = blockIdx.x; tl < n_tiles; tl += gridDim.x) {
-        const int64_t t = bb.tile0 + tl;
-        const int si = n_sims == 1 ? 0 : find_sim(tile_base, n_sims, t);
-        const DevSim d = sims[si];
+    // first-pass partials of the current group; whether any of its tiles holds the feed /
+    // pick profile's row / column
+    Stat1Acc acc;
+    bool grp_rows = false, grp_cols = false;
+    while (pc.ok) {
+        const DevSim d = sims[pc.si];
+        const int64_t t = d.tile_base + pc.lt;
         const bool first = first_slice >= 0 ? first_slice != 0 : d.row_base >= r0;
         const bool last = last_slice >= 0 ? last_slice != 0 : d.row_base + d.n_rows <= r1;
         const TileGeom g = tile_geom(d, t);
@@ -1355,12 +1406,14 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
         if (tid == 0 && e1 > e0) atomicAdd((unsigned long long *)(binned + d.sim), (unsigned long long)(e1 - e0));
         __syncthreads();
         // the next tile's first entries travel while this one drains
+        const Pos pn2 = succ(pn);
         a0 = n0;
         a1 = n1;
-        bounds(tl + 2 * (int64_t)gridDim.x, n0, n1);
+        bounds(pn2, n0, n1);
         ahead();
-        Stat1Acc acc;
         const int64_t rj = d.ny / 2 - g.j0, ci = d.nx / 2 - g.i0;
+        grp_rows |= rj >= 0 && rj < g.h;
+        grp_cols |= ci >= 0 && ci < g.w;
         if (vec) {
             for (int l = tid * V; l < TC; l += NT * V) {
                 const int li = l & (TX - 1), lj = l >> sx;
@@ -1389,10 +1442,20 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
             }
         }
         if (last) {
-            const TileStat1 s = acc.reduce<NT / 64>(rj >= 0 && rj < g.h, ci >= 0 && ci < g.w, true);
-            if (tid == 0) st1[t] = s;
+            // one block reduction per group: its partials go to the group's last tile, the
+            // other tiles of the group get empty ones
+            if (pc.lt + 1 == pc.lt_end) {
+                const TileStat1 s = acc.reduce<NT / 64>(grp_rows, grp_cols, true);
+                if (tid == 0) st1[t] = s;
+                acc = Stat1Acc();
+                grp_rows = grp_cols = false;
+            } else if (tid == 0) {
+                st1[t] = Stat1Acc().partial();
+            }
         }
         __syncthreads();
+        pc = pn;
+        pn = pn2;
     }
 }
 
@@ -1740,12 +1803,14 @@ void launch_scan(int64_t n_tiles, const BinBuffers &bb, hipStream_t s)
 
 template <int PREC>
 void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
-                  const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin, int64_t n_items,
-                  const BinBuffers &bb, bool first_slice, bool last_slice, int sx, int sy,
-                  TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
+                  const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_gbase, int64_t g0,
+                  int64_t n_groups, int64_t item_begin, int64_t n_items, const BinBuffers &bb,
+                  bool first_slice, bool last_slice, int sx, int sy, TileStat1 *st1,
+                  uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
 {
+    (void)d_tile_base;
     const int ib = (int)(n_items < kMaxGrid ? n_items : kMaxGrid);
-    const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
+    const int tb = (int)(n_groups < kMaxGrid ? n_groups : kMaxGrid);
     const size_t lds = sizeof(typename KeyOf<PREC>::T) << (sx + sy);
     stage(marks, 0, s);
     hipLaunchKernelGGL(zero_u32, dim3(stream_blocks(n_tiles, kBlock, 4096)), dim3(kBlock), 0, s, bb.counts, n_tiles);
@@ -1757,19 +1822,22 @@ void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
     if (ib > 0)
         hipLaunchKernelGGL((bin_points<PREC, true>), dim3(ib), dim3(kBlock), 0, s, d_sims, n_sims, d_bitem_base, item_begin, n_items, bb);
     stage(marks, 3, s);
-    if (lds > kTileLdsSmall)
-        hipLaunchKernelGGL((tile_reduce<PREC, 2 * kBlock>), dim3(tb), dim3(2 * kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
-    else
-        hipLaunchKernelGGL((tile_reduce<PREC, kBlock>), dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
+    if (tb > 0 && lds > kTileLdsSmall)
+        hipLaunchKernelGGL((tile_reduce<PREC, 2 * kBlock>), dim3(tb), dim3(2 * kBlock), lds, s, d_sims, n_sims, d_gbase, g0, n_groups, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
+    else if (tb > 0)
+        hipLaunchKernelGGL((tile_reduce<PREC, kBlock>), dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_gbase, g0, n_groups, bb, first_slice ? 1 : 0, last_slice ? 1 : 0, (int64_t)0, (int64_t)0, st1, d_binned);
     stage(marks, 4, s);
 }
 
 template <int PREC>
 void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
                 const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
-                int64_t n_htiles, int64_t row_begin, int64_t row_end, const BinBuffers &bb, int sx,
-                int sy, TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
+                int64_t n_htiles, const int64_t *d_gbase, int64_t g0, int64_t n_groups,
+                int64_t row_begin, int64_t row_end, const BinBuffers &bb, int sx, int sy,
+                TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
 {
+    (void)d_tile_base;
+    (void)n_tiles;
     const int64_t nr = row_end - row_begin;
     const int rb = (int)(nr < kMaxGrid ? nr : kMaxGrid);
     const size_t hist_lds = sizeof(uint32_t) * (size_t)(bb.max_tiles > 0 ? bb.max_tiles : 1);
@@ -1777,7 +1845,7 @@ void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
     const int cb = stream_blocks(n_chunks * n_htiles, kBlock, 16384);
     const int tb1 = stream_blocks(n_htiles, kBlock, 16384);
     const int hb = (int)(n_htiles < kMaxGrid ? n_htiles : kMaxGrid);
-    const int tb = (int)(n_tiles < kMaxGrid ? n_tiles : kMaxGrid);
+    const int tb = (int)(n_groups < kMaxGrid ? n_groups : kMaxGrid);
     const size_t lds = sizeof(typename KeyOf<PREC>::T) << (sx + sy);
     const bool super = bb.skey != nullptr;
     stage(marks, 0, s);
@@ -1802,40 +1870,42 @@ void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
     if (super && hb > 0)
         hipLaunchKernelGGL(split_super<PREC>, dim3(hb), dim3(kBlock), 0, s, d_sims, n_sims, d_hbase, n_htiles, bb);
     stage(marks, 3, s);
-    if (lds > kTileLdsSmall)
-        hipLaunchKernelGGL((tile_reduce<PREC, 2 * kBlock>), dim3(tb), dim3(2 * kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, -1, -1, row_begin, row_end, st1, d_binned);
-    else
-        hipLaunchKernelGGL((tile_reduce<PREC, kBlock>), dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_tile_base, n_tiles, bb, -1, -1, row_begin, row_end, st1, d_binned);
+    if (tb > 0 && lds > kTileLdsSmall)
+        hipLaunchKernelGGL((tile_reduce<PREC, 2 * kBlock>), dim3(tb), dim3(2 * kBlock), lds, s, d_sims, n_sims, d_gbase, g0, n_groups, bb, -1, -1, row_begin, row_end, st1, d_binned);
+    else if (tb > 0)
+        hipLaunchKernelGGL((tile_reduce<PREC, kBlock>), dim3(tb), dim3(kBlock), lds, s, d_sims, n_sims, d_gbase, g0, n_groups, bb, -1, -1, row_begin, row_end, st1, d_binned);
     stage(marks, 4, s);
 }
 
 }  // namespace
 
 int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
-                        const int64_t *d_tile_base, int64_t n_tiles, int64_t item_begin,
-                        int64_t n_items, const BinBuffers &bb, bool first_slice, bool last_slice,
-                        int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                        void *stream, const StageEvents *marks)
+                        const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_gbase,
+                        int64_t g0, int64_t n_groups, int64_t item_begin, int64_t n_items,
+                        const BinBuffers &bb, bool first_slice, bool last_slice, int precision,
+                        int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
+                        const StageEvents *marks)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64)
-        binned_slice<FSM_F64>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+        binned_slice<FSM_F64>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, d_gbase, g0, n_groups, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
     else
-        binned_slice<FSM_F32>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+        binned_slice<FSM_F32>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, d_gbase, g0, n_groups, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
     return (int)hipGetLastError();
 }
 
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
                       const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
-                      int64_t n_htiles, int64_t row_begin, int64_t row_end, const BinBuffers &bb,
-                      int precision, int sx, int sy, TileStat1 *st1, uint64_t *d_binned,
-                      void *stream, const StageEvents *marks)
+                      int64_t n_htiles, const int64_t *d_gbase, int64_t g0, int64_t n_groups,
+                      int64_t row_begin, int64_t row_end, const BinBuffers &bb, int precision,
+                      int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
+                      const StageEvents *marks)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64)
-        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, d_gbase, g0, n_groups, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     else
-        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, d_gbase, g0, n_groups, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     return (int)hipGetLastError();
 }
 
