@@ -184,11 +184,13 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
         d.h_tiles_x = d.tiles_x;
         d.h_tiles = d.n_tiles;
         d.h_base = d.tile_base;
-        // reduction groups: the largest power of two of tiles (up to 64) that still leaves
-        // kReduceGroups groups; it follows from the simulation's own tiles only, so a
-        // simulation reduces alike alone and in a batch
+        // reduction groups of the binned strategy: the largest power of two of tiles (up to
+        // 64) that still leaves kReduceGroups groups; it follows from the simulation's own
+        // tiles only, so a simulation reduces alike alone and in a batch.  The scatter
+        // strategy's first pass (and the roughness of given maps) leaves a partial per tile.
         d.tg_shift = 0;
-        while (d.tg_shift < fsm::kMaxGroupShift && (d.n_tiles >> (d.tg_shift + 1)) >= fsm::kReduceGroups)
+        while (strategy == fsm::kStrategyBinned && d.tg_shift < fsm::kMaxGroupShift &&
+               (d.n_tiles >> (d.tg_shift + 1)) >= fsm::kReduceGroups)
             ++d.tg_shift;
         d.n_tgroups = ceil_div(d.n_tiles, (int64_t)1 << d.tg_shift);
         d.tgroup_base = groups;

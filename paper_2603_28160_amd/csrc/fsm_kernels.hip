@@ -1514,17 +1514,24 @@ __global__ __launch_bounds__(kBlock) void rough_final1(const DevSim *__restrict_
         a.row_n += s.row_n;
         a.col_n += s.col_n;
     };
-    // each thread's tiles in order, kFinalDepth partials in flight
+    // the partials of the tile groups (each at its group's last tile; the other tiles' are
+    // empty, and so are all of a scatter-strategy pass's but the ones read here when the
+    // groups are single tiles), each thread's in order with kFinalDepth in flight
     const TileStat1 *p = st1 + d.tile_base;
+    const int sh = d.tg_shift;
+    auto at = [&](int64_t g) {
+        const int64_t e = (g + 1) << sh;
+        return p[(e < d.n_tiles ? e : d.n_tiles) - 1];
+    };
     int64_t k = threadIdx.x;
-    for (; k + (kFinalDepth - 1) * kBlock < d.n_tiles; k += kFinalDepth * kBlock) {
+    for (; k + (kFinalDepth - 1) * kBlock < d.n_tgroups; k += kFinalDepth * kBlock) {
         TileStat1 s[kFinalDepth];
 #pragma unroll
-        for (int v = 0; v < kFinalDepth; ++v) s[v] = p[k + v * kBlock];
+        for (int v = 0; v < kFinalDepth; ++v) s[v] = at(k + v * kBlock);
 #pragma unroll
         for (int v = 0; v < kFinalDepth; ++v) add(s[v]);
     }
-    for (; k < d.n_tiles; k += kBlock) add(p[k]);
+    for (; k < d.n_tgroups; k += kBlock) add(at(k));
     const TileStat1 r = a.reduce();
     if (threadIdx.x == 0) {
         RoughState st;
@@ -1703,13 +1710,14 @@ __global__ __launch_bounds__(kBlock) void rough_final2(const DevSim *__restrict_
         a.col_abs += s.col_abs;
     };
     const TileStat2 *p = st2 + d.tile_base;
+    constexpr int D = 2 * kFinalDepth;
     int64_t k = threadIdx.x;
-    for (; k + (kFinalDepth - 1) * kBlock < d.n_tiles; k += kFinalDepth * kBlock) {
-        TileStat2 s[kFinalDepth];
+    for (; k + (D - 1) * kBlock < d.n_tiles; k += D * kBlock) {
+        TileStat2 s[D];
 #pragma unroll
-        for (int v = 0; v < kFinalDepth; ++v) s[v] = p[k + v * kBlock];
+        for (int v = 0; v < D; ++v) s[v] = p[k + v * kBlock];
 #pragma unroll
-        for (int v = 0; v < kFinalDepth; ++v) add(s[v]);
+        for (int v = 0; v < D; ++v) add(s[v]);
     }
     for (; k < d.n_tiles; k += kBlock) add(p[k]);
     const TileStat2 r = a.reduce();

@@ -325,6 +325,27 @@ def test_roughness_entry(ctx, prec, shape):
     assert np.array_equal(zt.cpu().numpy().astype(np.float64), Z)
 
 
+@pytest.mark.parametrize("strategy", ["binned", "scatter"])
+def test_many_tiles_roughness(ctx, strategy):
+    # 16 x 16-cell tiles over 3001 x 2000 cells (23 500 tiles): the binned strategy reduces
+    # them in groups of eight with one partial per group, the scatter strategy's first pass
+    # and the roughness entry point keep one per tile; every path sums to the oracle's values
+    import torch
+    from paper_2603_28160_amd import _abi
+    ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 0)
+    ctx.fsm_ctx_set_option(_abi.OPT_TILE_SHAPE, 0x44)
+    ctx.set_strategy(strategy)
+    try:
+        s = W.config2(nx=3001, ny=2000, dd=0.002)
+        zo = check_f64(ctx, s)
+        rg = ctx.fsm_roughness(s.grid, torch.tensor(zo, device="cuda:0"), "f64")
+        check_rough(rg, oracle.roughness(zo), rtol=1e-10)
+    finally:
+        ctx.set_strategy("binned")
+        ctx.fsm_ctx_set_option(_abi.OPT_TILE_SHAPE, 0)
+        ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 1)
+
+
 def test_roughness_sinusoid_closed_form(ctx):
     import torch
     A = 0.3
