@@ -362,8 +362,9 @@ typedef struct fsm_tune_result {
 
 /* The project's autotuner for the batched launch.  Times candidate launch parameters (Z-map
  * strategy, cell tile shape, histogram rows per launch) on the n jobs run as one batch, by
- * coordinate search from the defaults, each candidate the best of two timed runs after one
- * untimed one, and keeps the fastest for the jobs' workload class (precision, number of
+ * coordinate search from the defaults, each candidate the fastest of at least three timed
+ * runs (and of as many as fill 20 ms, at most 64) after one untimed one, and keeps the
+ * fastest for the jobs' workload class (precision, number of
  * simulations, and the binary orders of magnitude of their total cells and edge-point
  * evaluations).  Later fsm_simulate / fsm_simulate_batch / fsm_serve_run calls of the same
  * class use them while FSM_OPT_AUTOTUNED is on.  Parameters change only the launch, not the

@@ -27,7 +27,6 @@ namespace fsm {
 namespace rt {
 
 constexpr int kItersPerItem = 16;   // steps each thread walks per scatter item and edge point
-constexpr int64_t kMinSliceRows = 2048;    // rows (blocks) a slice of the histogram mode keeps
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -243,13 +242,13 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
             L.total_htiles = htiles;
         }
         L.entry = entry_bytes(precision, super);
-        // Rows: about target_rows per launch, but never more items than one bucket slice can
-        // take, and small enough that a slice still holds kMinSliceRows rows (blocks) when the
-        // work runs in many slices; coarser only when the row matrix would outgrow its budget.
+        // Rows: about target_rows per launch, that is per slice when the work runs in several
+        // (a row never holds more items than one bucket slice can take); coarser only when the
+        // row matrix would outgrow its budget.
         const int64_t per_item = (int64_t)fsm::kBlock * L.max_n;
         const int64_t slice_items = std::max<int64_t>(
             1, std::min(bucket_cap(bucket_bytes, L.entry, per_item), std::max(per_item, bitems * per_item)) / per_item);
-        int64_t ipr = std::max<int64_t>(1, std::min(ceil_div(bitems, std::max<int64_t>(1, lp.target_rows)), slice_items / kMinSliceRows));
+        int64_t ipr = std::max<int64_t>(1, ceil_div(std::min(bitems, slice_items), std::max<int64_t>(1, lp.target_rows)));
         int64_t rows = 0, hsize = 0;
         for (;;) {
             rows = hsize = 0;
@@ -1169,15 +1168,20 @@ int fsm_autotune(fsm_ctx *ctx, int n, const fsm_job *jobs, int precision, fsm_tu
         Guard guard{ctx, ctx->tuned, ctx->use_tuned, ctx->graphs};
         ctx->use_tuned = true;
         ctx->graphs = false;
+        // one warm-up call, then the fastest of at least three timed calls and of as many as
+        // fill 20 ms (at most 64): short workloads need many to rise above the noise
         auto time_of = [&](const LaunchParams &lp, float &ms) -> int {
             ctx->tuned[key] = lp;
-            double best = 1e300;
-            for (int rep = 0; rep < 3; ++rep) {
+            double best = 1e300, total = 0.0;
+            for (int rep = 0; rep < 65 && (rep < 4 || total < 20.0); ++rep) {
                 const auto t0 = std::chrono::steady_clock::now();
                 const int rc = run_set(ctx, plans, zmaps, precision, nullptr, s);
                 if (rc != FSM_OK) return rc;
                 const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-                if (rep > 0) best = std::min(best, el);
+                if (rep > 0) {
+                    best = std::min(best, el);
+                    total += el;
+                }
             }
             ms = (float)best;
             ++tried;

@@ -327,9 +327,11 @@ __device__ __forceinline__ bool bin_cell(const DevSim &d, double xcs, double yq,
 
 // One point of either precision: its cell (i, j) and key; false outside the grid.  Single
 // precision turns the point in float on tool-local coordinates and widens the offsets to
-// double: the workpiece position x_c + (double)x_S and its cell follow in double precision,
-// exactly as for a double-precision point.  near (single precision): the position lies within
-// the error bound of a cell boundary, so double precision might bin it into a neighbour.
+// double; the position in cell units is then one double fused multiply-add per coordinate,
+// (double)x_S / dd + (x_c - x_lo) / dd, whose second term is the same for every point of the
+// step (a rounding of the order of 1e-11 cells away from the double-precision point's own
+// formula).  near (single precision): the position lies within the error bound of a cell
+// boundary, so double precision might bin it into a neighbour.
 template <int TILT = kTiltAny>
 __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F64> &a,
                                             const Edge<FSM_F64> &e, double xcs, double yq,
@@ -346,9 +348,13 @@ __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F32>
                                             int32_t &i, int32_t &j, int32_t &key, bool &near)
 {
     float xs, ys;
-    double fx, fy;
     turn_point<TILT>(d, a, e, xs, ys, key);
-    const bool in = bin_cell(d, xcs, yq, (double)xs, (double)ys, i, j, fx, fy);
+    // the step's centre in cell units: invariant over the step's edge points
+    const double cx = (xcs - d.x_lo) * d.inv_dd, cy = (yq - d.y_lo) * d.inv_dd;
+    const double fx = fma((double)xs, d.inv_dd, cx), fy = fma((double)ys, d.inv_dd, cy);
+    const bool in = fx >= 0.0 && fx < d.nx_d && fy >= 0.0 && fy < d.ny_d;
+    i = in ? (int32_t)fx : 0;
+    j = in ? (int32_t)fy : 0;
     const double rx = fx - (double)i, ry = fy - (double)j, w = d.near_w;
     near = in && (rx < w || rx > 1.0 - w || ry < w || ry > 1.0 - w);
     return in;
