@@ -320,6 +320,7 @@ SetLayout make_layout(const fsm_ctx *ctx, const std::vector<Plan> &plans, int pr
             int64_t hsize = 0;
             for (const DevSim &d : devs) hsize += d.n_rows * d.h_tiles;
             L.hist_m = take(sizeof(uint32_t) * std::max<int64_t>(1, hsize));
+            if (precision == FSM_F32) L.near_rows = take(sizeof(uint32_t) * std::max<int64_t>(1, L.total_rows));
             L.chunk = take(sizeof(uint32_t) * ceil_div(L.rows_per_slice, kRowChunk) * std::max<int64_t>(1, ht));
         }
     }
@@ -427,6 +428,8 @@ void fill_image(const SetLayout &L, const std::vector<Plan> &plans, std::vector<
         d.gm = reinterpret_cast<const double *>(dev + L.gm[k]);
         d.zmap = zmaps[k];
         d.near = reinterpret_cast<uint64_t *>(dev + L.near) + k;
+        // every row of the histogram mode writes its own count (indexed by global row)
+        d.near_rows = L.near_rows ? reinterpret_cast<uint32_t *>(dev + L.near_rows) : nullptr;
         ib[k] = d.item_base;
         bb[k] = d.bitem_base;
         tb[k] = d.tile_base;

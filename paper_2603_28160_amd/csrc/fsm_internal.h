@@ -186,6 +186,9 @@ struct DevSim {
     // of in-grid evaluations that lay that close to a cell boundary
     double pos_err, near_w;
     uint64_t *near;
+    // histogram mode: each row's count of those evaluations, indexed by global row (summed
+    // with `near` into the result; nullptr in the other modes)
+    uint32_t *near_rows;
 };
 
 // Per-tile partial sums of the roughness passes (device memory).  Row ny/2 and column nx/2

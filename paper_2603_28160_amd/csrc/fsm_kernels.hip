@@ -754,7 +754,14 @@ __global__ __launch_bounds__(kBlock) void hist_count(const DevSim *__restrict__ 
             __hip_atomic_fetch_add(&hist[lt], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             n_near += near;
         });
-        if (PREC == FSM_F32) add_near(d, n_near);
+        if (PREC == FSM_F32) {
+            // the row's count in its own slot: no atomics on a shared counter
+            __shared__ uint32_t wn[kWaves];
+            const uint32_t w = wave_sum(n_near);
+            if ((tid & 63) == 0) wn[tid >> 6] = w;
+            __syncthreads();
+            if (tid == 0) d.near_rows[r] = (wn[0] + wn[1]) + (wn[2] + wn[3]);
+        }
         __syncthreads();
         FSM_GLOBAL uint32_t *row = gptr(bb.hist) + d.hbase + lr * T;
         for (int t = tid; t < T; t += kBlock) row[t] = hist[t];
@@ -1727,6 +1734,13 @@ __global__ __launch_bounds__(kBlock) void rough_final2(const DevSim *__restrict_
     }
     for (; k < d.n_tiles; k += kBlock) add(p[k]);
     const TileStat2 r = a.reduce();
+    // the per-row near-boundary counts of the histogram mode
+    uint64_t near_rows = 0;
+    if (d.near_rows) {
+        __shared__ uint64_t nb[kWaves];
+        for (int64_t k = threadIdx.x; k < d.n_rows; k += kBlock) near_rows += d.near_rows[d.row_base + k];
+        near_rows = block_sum(near_rows, nb);
+    }
     if (threadIdx.x == 0) {
         const RoughState st = state[d.sim];
         fsm_rough o;
@@ -1741,7 +1755,7 @@ __global__ __launch_bounds__(kBlock) void rough_final2(const DevSim *__restrict_
         o.reserved = 0;
         o.mean = st.mean;
         o.pos_err = d.pos_err;
-        o.n_near = d.near ? (int64_t)*d.near : 0;
+        o.n_near = (d.near ? (int64_t)*d.near : 0) + (int64_t)near_rows;
         if (n == 0) {
             o.Sa = o.Sq = o.Sp = o.Sv = o.Sz = o.Ssk = o.Sku = NAN;
             o.flags |= FSM_FLAG_NO_HIT;

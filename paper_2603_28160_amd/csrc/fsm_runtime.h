@@ -53,7 +53,8 @@ struct SetLayout {
     int64_t entry = 0;          // bucket bytes per point
     // device-only region
     size_t st1 = 0, st2 = 0, state = 0, out = 0, counts = 0, offsets = 0, cursor = 0, bsum = 0,
-           bkey = 0, bidx = 0, hist_m = 0, chunk = 0, tile_lo = 0, tile_hi = 0, skey = 0, spk = 0;
+           bkey = 0, bidx = 0, hist_m = 0, chunk = 0, tile_lo = 0, tile_hi = 0, skey = 0, spk = 0,
+           near_rows = 0;
     size_t scratch_end = 0;
     // uploaded region
     size_t sims = 0, ibase = 0, bbase = 0, tbase = 0, hbase = 0, gbase = 0, binned = 0, evals = 0,
