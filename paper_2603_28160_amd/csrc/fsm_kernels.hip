@@ -898,12 +898,31 @@ __global__ __launch_bounds__(kBlock) void hist_write(const DevSim *__restrict__ 
     }
 }
 
+// A bucket [e0, e1) read in units of E neighbouring entries: the whole units [u0, u1) and at
+// most E - 1 single entries at each end, [e0, hb) and [tb, e1).
+struct UnitSplit {
+    uint32_t e0, e1, u0, u1, hb, tb;
+};
+template <int E>
+__device__ __forceinline__ UnitSplit unit_split(uint32_t e0, uint32_t e1)
+{
+    UnitSplit q;
+    q.e0 = e0;
+    q.e1 = e1;
+    q.u0 = (e0 + E - 1) / E;
+    q.u1 = e1 / E > q.u0 ? e1 / E : q.u0;
+    q.hb = e1 < q.u0 * E ? e1 : q.u0 * E;
+    q.tb = q.hb > q.u1 * E ? q.hb : q.u1 * E;
+    if (q.tb > e1) q.tb = e1;   // no whole unit: the single entries end at e1
+    return q;
+}
+
 // Super-tiles n_htiles from bb.htile0 on: sort each super-tile's bucket into the buckets of its
 // tiles, in place of the same range of bkey / bidx, and write every tile's [tile_lo, tile_hi).
 // One block per super-tile: an LDS count per tile inside the super-tile, their running sum,
 // then a second read that claims slots with LDS atomics (the order inside a tile's bucket does
 // not matter to its minimum).
-constexpr int kSplitDepth = 8;
+constexpr int kSplitDepth = 2;   // units of four entries in flight per thread
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void split_super(const DevSim *__restrict__ sims, int n_sims,
                                                       const int64_t *__restrict__ hbase,
@@ -916,6 +935,10 @@ __global__ __launch_bounds__(kBlock) void split_super(const DevSim *__restrict__
     const FSM_GLOBAL uint32_t *spk = gptr(bb.spk);
     FSM_GLOBAL Key *bkey = gptr(static_cast<Key *>(bb.bkey));
     FSM_GLOBAL uint16_t *bix = gptr(bb.bidx);
+    typedef uint32_t P4 __attribute__((ext_vector_type(4)));
+    typedef Key K4 __attribute__((ext_vector_type(4)));
+    const FSM_GLOBAL P4 *upk = reinterpret_cast<const FSM_GLOBAL P4 *>(spk);
+    const FSM_GLOBAL K4 *ukey = reinterpret_cast<const FSM_GLOBAL K4 *>(skey);
     const int64_t cap = bb.cap;
     for (int64_t b = blockIdx.x; b < n_htiles; b += gridDim.x) {
         const int64_t h = bb.htile0 + b;
@@ -930,18 +953,30 @@ __global__ __launch_bounds__(kBlock) void split_super(const DevSim *__restrict__
         const uint32_t sm = (uint32_t)(nsub - 1);
         if (tid < nsub) cnt[tid] = 0u;
         __syncthreads();
-        // kSplitDepth entries in flight per thread in both reads
-        uint32_t e = s0 + tid;
-        for (; e + (kSplitDepth - 1) * kBlock < s1; e += kSplitDepth * kBlock) {
-            uint32_t p[kSplitDepth];
+        // both reads in units of four entries (the cells in one 16-byte load, the keys in one or
+        // two), kSplitDepth units in flight per thread; single entries at the ends
+        const UnitSplit q = unit_split<4>(s0, s1);
+        const uint32_t nh = q.hb - q.e0, n1 = nh + (q.e1 - q.tb);
+        const uint32_t eo = (uint32_t)tid < nh ? q.e0 + tid : q.tb + (tid - nh);   // thread's single entry
+        uint32_t u = q.u0 + tid;
+        for (; u + (kSplitDepth - 1) * kBlock < q.u1; u += kSplitDepth * kBlock) {
+            P4 p[kSplitDepth];
 #pragma unroll
-            for (int v = 0; v < kSplitDepth; ++v) p[v] = __builtin_nontemporal_load(&spk[e + v * kBlock]);
+            for (int v = 0; v < kSplitDepth; ++v) p[v] = __builtin_nontemporal_load(&upk[u + v * kBlock]);
 #pragma unroll
             for (int v = 0; v < kSplitDepth; ++v)
-                __hip_atomic_fetch_add(&cnt[(p[v] >> 16) & sm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    __hip_atomic_fetch_add(&cnt[(p[v][c] >> 16) & sm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        for (; e < s1; e += kBlock)
-            __hip_atomic_fetch_add(&cnt[(spk[e] >> 16) & sm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (; u < q.u1; u += kBlock) {
+            const P4 p = __builtin_nontemporal_load(&upk[u]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                __hip_atomic_fetch_add(&cnt[(p[c] >> 16) & sm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if ((uint32_t)tid < n1)
+            __hip_atomic_fetch_add(&cnt[(spk[eo] >> 16) & sm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __syncthreads();
         if (tid == 0) {
             uint32_t run = s0;
@@ -960,31 +995,33 @@ __global__ __launch_bounds__(kBlock) void split_super(const DevSim *__restrict__
             }
         }
         __syncthreads();
-        e = s0 + tid;
-        for (; e + (kSplitDepth - 1) * kBlock < s1; e += kSplitDepth * kBlock) {
-            Key k[kSplitDepth];
-            uint32_t p[kSplitDepth];
-#pragma unroll
-            for (int v = 0; v < kSplitDepth; ++v) {
-                k[v] = __builtin_nontemporal_load(&skey[e + v * kBlock]);
-                p[v] = __builtin_nontemporal_load(&spk[e + v * kBlock]);
-            }
-#pragma unroll
-            for (int v = 0; v < kSplitDepth; ++v) {
-                const uint32_t pos = __hip_atomic_fetch_add(&cur[(p[v] >> 16) & sm], 1u, __ATOMIC_RELAXED,
-                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                bkey[pos] = k[v];
-                bix[pos] = (uint16_t)p[v];
-            }
-        }
-        for (; e < s1; e += kBlock) {
-            const Key k = skey[e];
-            const uint32_t pk = spk[e];
+        auto place = [&](Key k, uint32_t pk) {
             const uint32_t pos = __hip_atomic_fetch_add(&cur[(pk >> 16) & sm], 1u, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
             bkey[pos] = k;
             bix[pos] = (uint16_t)pk;
+        };
+        u = q.u0 + tid;
+        for (; u + (kSplitDepth - 1) * kBlock < q.u1; u += kSplitDepth * kBlock) {
+            K4 k[kSplitDepth];
+            P4 p[kSplitDepth];
+#pragma unroll
+            for (int v = 0; v < kSplitDepth; ++v) {
+                k[v] = __builtin_nontemporal_load(&ukey[u + v * kBlock]);
+                p[v] = __builtin_nontemporal_load(&upk[u + v * kBlock]);
+            }
+#pragma unroll
+            for (int v = 0; v < kSplitDepth; ++v)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) place(k[v][c], p[v][c]);
         }
+        for (; u < q.u1; u += kBlock) {
+            const K4 k = __builtin_nontemporal_load(&ukey[u]);
+            const P4 p = __builtin_nontemporal_load(&upk[u]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) place(k[c], p[c]);
+        }
+        if ((uint32_t)tid < n1) place(skey[eo], spk[eo]);
         __syncthreads();
     }
 }
@@ -1264,20 +1301,6 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
     const FSM_GLOBAL KU *ukey = reinterpret_cast<const FSM_GLOBAL KU *>(bkey);
     const FSM_GLOBAL CU *uix = reinterpret_cast<const FSM_GLOBAL CU *>(bix);
     constexpr int kDepth = 8 / E;   // units in flight per thread (eight entries)
-    struct Split {
-        uint32_t e0, e1, u0, u1, hb, tb;   // single entries: [e0, hb) and [tb, e1)
-    };
-    auto split = [](uint32_t e0, uint32_t e1) {
-        Split q;
-        q.e0 = e0;
-        q.e1 = e1;
-        q.u0 = (e0 + E - 1) / E;
-        q.u1 = e1 / E > q.u0 ? e1 / E : q.u0;
-        q.hb = e1 < q.u0 * E ? e1 : q.u0 * E;
-        q.tb = q.hb > q.u1 * E ? q.hb : q.u1 * E;
-        if (q.tb > e1) q.tb = e1;   // no whole unit: the single entries end at e1
-        return q;
-    };
     KU ak[kDepth];
     CU ac[kDepth];
     Key ok = KT::inf;           // this thread's single entry, if any
@@ -1325,7 +1348,7 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
         }
     };
     auto ahead = [&]() {
-        const Split q = split(a0, a1);
+        const UnitSplit q = unit_split<E>(a0, a1);
 #pragma unroll
         for (int v = 0; v < kDepth; ++v) {
             const uint32_t u = q.u0 + tid + v * NT;
@@ -1385,7 +1408,7 @@ __global__ __launch_bounds__(NT) void tile_reduce(const DevSim *__restrict__ sim
         }
         __syncthreads();
         const uint32_t e0 = a0, e1 = a1;
-        const Split q = split(e0, e1);
+        const UnitSplit q = unit_split<E>(e0, e1);
         if (has_one) __hip_atomic_fetch_min(&lds[oc], ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
         for (int v = 0; v < kDepth; ++v)
