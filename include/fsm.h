@@ -134,6 +134,8 @@ typedef struct fsm_plan_info {
     int64_t n_cells;         /* nx * ny */
     int64_t zmap_bytes;      /* bytes of the caller's Z-map at this precision */
     int64_t workspace_bytes; /* device bytes the library needs for this simulation */
+    int32_t zmap_path;       /* FSM_PATH_* a fresh context's launch parameters take */
+    int32_t n_slices;        /* slices of its binned Z-map with those parameters */
 } fsm_plan_info;
 
 typedef struct fsm_rough {

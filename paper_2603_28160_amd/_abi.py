@@ -58,7 +58,7 @@ class FsmPlanInfo(C.Structure):
     _fields_ = [("r_reach", C.c_double), ("x_start", C.c_double), ("y_first", C.c_double),
                 ("n_passes", C.c_int64), ("n_steps", C.c_int64), ("n_evals", C.c_int64),
                 ("n_cells", C.c_int64), ("zmap_bytes", C.c_int64),
-                ("workspace_bytes", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("zmap_path", C.c_int32), ("n_slices", C.c_int32)]
 
 
 ROUGH_DOUBLES = ("Sa", "Sq", "Sp", "Sv", "Sz", "Ssk", "Sku", "Ra_feed", "Ra_pick", "mean",

@@ -836,7 +836,11 @@ int fsm_plan(const fsm_tool *tool, const fsm_cut *cut, const fsm_grid *grid, int
         fsm_ctx probe;
         std::vector<Plan> one{P};
         std::vector<DevSim> devs;
-        out->workspace_bytes = (int64_t)make_layout(&probe, one, precision, LaunchParams(), devs).total;
+        const SetLayout L = make_layout(&probe, one, precision, LaunchParams(), devs);
+        out->workspace_bytes = (int64_t)L.total;
+        out->zmap_path = !L.hist ? FSM_PATH_RUN : L.super ? FSM_PATH_SUPER : FSM_PATH_HIST;
+        out->n_slices = (int32_t)std::max<int64_t>(
+            1, L.hist ? ceil_div(L.total_rows, L.rows_per_slice) : ceil_div(L.total_items, L.per_slice));
         return FSM_OK;
     } catch (const std::bad_alloc &) {
         return FSM_ENOMEM;
