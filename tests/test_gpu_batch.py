@@ -193,3 +193,33 @@ def test_overlapping_maps_rejected(Ctx):
         zs, rs = ctx.fsm_simulate_batch(sims, "f64", zmaps=[a, c])
         assert np.array_equal(zs[0].cpu().numpy(), zs[1].cpu().numpy())
         same_rough(rs[0], rs[1])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_super_mode_batch_equals_alone(Ctx, prec):
+    # one member with more 16 x 16-cell tiles than a row histogram holds (132 x 129): the whole
+    # batch counts per super-tile, each member's found through the super-tile bases, and
+    # splits them into tiles; every member must equal its run alone (the small ones alone take
+    # the histogram mode), with the default bucket budget and with a small one (more slices)
+    big = W.config2(nx=2100, ny=2050, dd=0.002)
+    mix = small_mix(3)
+    sims = [mix[0], big, mix[1], mix[2]]
+    slices = []
+    with Ctx(0) as ctx:
+        ctx.fsm_ctx_set_option(_abi.OPT_AUTOTUNED, 0)
+        ctx.fsm_ctx_set_option(_abi.OPT_TILE_SHAPE, 0x44)
+        for budget in (16 << 30, 256 << 20):
+            ctx.fsm_ctx_set_option(_abi.OPT_BUCKET_BYTES, budget)
+            print(f"[gpu] super-mode batch {prec}, bucket budget {budget >> 20} MiB", flush=True)
+            ctx.fsm_ctx_set_profiling(True)
+            zb, rb = ctx.fsm_simulate_batch(sims, prec)
+            t = ctx.fsm_last_timings()
+            ctx.fsm_ctx_set_profiling(False)
+            assert t["zmap_path"] == _abi.PATH_SUPER, t
+            slices.append(t["n_slices"])
+            mb = np_maps(zb)
+            for k, s in enumerate(sims):
+                z1, r1 = ctx.fsm_simulate(s, prec)
+                assert np.array_equal(mb[k], z1.cpu().numpy().astype(np.float64)), (budget, k)
+                same_rough(rb[k], r1)
+    assert slices[1] > slices[0], slices
