@@ -582,7 +582,7 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
             do {
                 const int64_t r1 = std::min<int64_t>(L.total_rows, r0 + L.rows_per_slice);
                 const DevSim &da = devs[sim_of_row(r0)], &db = devs[sim_of_row(r1 - 1)];
-                const int64_t t0 = da.tile_base, t1 = db.tile_base + db.n_tiles;
+                const int64_t t0 = da.tile_base;
                 const int64_t h0 = da.h_base, h1 = db.h_base + db.h_tiles;
                 const int64_t g0 = da.tgroup_base, g1 = db.tgroup_base + db.n_tgroups;
                 fsm::BinBuffers bs = bb;
@@ -593,7 +593,7 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
                 bs.cursor += h0;
                 bs.tile_lo += L.super ? t0 : h0;
                 bs.tile_hi += L.super ? t0 : h0;
-                he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_tbase, t1 - t0, d_hbase, h1 - h0,
+                he = fsm::launch_hist_slice(d_sims, L.n, d_bbase, d_hbase, h1 - h0,
                                             d_gbase, g0, g1 - g0, r0, r1, bs, L.precision, L.sx,
                                             L.sy, st1, d_binned, s, stage_marks(ctx, slice++, capturing));
                 if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
@@ -601,14 +601,14 @@ int launch_set(fsm_ctx *ctx, const SetLayout &L, const std::vector<DevSim> &devs
             } while (r0 < L.total_rows);
         } else if (L.total_items == 0) {
             // nothing to bin: the maps are still initialised and the first pass still runs
-            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, d_gbase, 0,
+            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, L.total_tiles, d_gbase, 0,
                                           L.total_groups, 0, 0, bb, true, true, L.precision, L.sx,
                                           L.sy, st1, d_binned, s, stage_marks(ctx, slice++, capturing));
             if (he) return hip_err(ctx, (hipError_t)he, "binned Z-map kernels");
         }
         for (int64_t b0 = 0; !L.hist && b0 < L.total_items; b0 += L.per_slice) {
             const int64_t nit = std::min<int64_t>(L.per_slice, L.total_items - b0);
-            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, d_tbase, L.total_tiles, d_gbase, 0,
+            he = fsm::launch_binned_slice(d_sims, L.n, d_bbase, L.total_tiles, d_gbase, 0,
                                           L.total_groups, b0, nit, bb, b0 == 0, b0 + nit >= L.total_items,
                                           L.precision, L.sx, L.sy, st1, d_binned, s,
                                           stage_marks(ctx, slice++, capturing));

@@ -250,8 +250,8 @@ int launch_scatter(const DevSim *d_sims, int n_sims, const int64_t *d_item_base,
 // Tiles are reduced in groups: d_gbase holds each simulation's first tile group, and the
 // slice's tiles are the tile groups [g0, g0 + n_groups).
 int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
-                        const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_gbase,
-                        int64_t g0, int64_t n_groups, int64_t item_begin, int64_t n_items,
+                        int64_t n_tiles, const int64_t *d_gbase, int64_t g0, int64_t n_groups,
+                        int64_t item_begin, int64_t n_items,
                         const BinBuffers &bb, bool first_slice, bool last_slice, int precision,
                         int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
                         const StageEvents *marks = nullptr);
@@ -265,8 +265,8 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
 // (n_htiles of them from bb.htile0 on, simulations found through d_hbase) and a split pass
 // sorts every super-tile's bucket into its tiles before the reduction.
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
-                      const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
-                      int64_t n_htiles, const int64_t *d_gbase, int64_t g0, int64_t n_groups,
+                      const int64_t *d_hbase, int64_t n_htiles, const int64_t *d_gbase,
+                      int64_t g0, int64_t n_groups,
                       int64_t row_begin, int64_t row_end, const BinBuffers &bb, int precision,
                       int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
                       const StageEvents *marks = nullptr);

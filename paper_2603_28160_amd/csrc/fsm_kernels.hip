@@ -1854,12 +1854,11 @@ void launch_scan(int64_t n_tiles, const BinBuffers &bb, hipStream_t s)
 
 template <int PREC>
 void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
-                  const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_gbase, int64_t g0,
+                  int64_t n_tiles, const int64_t *d_gbase, int64_t g0,
                   int64_t n_groups, int64_t item_begin, int64_t n_items, const BinBuffers &bb,
                   bool first_slice, bool last_slice, int sx, int sy, TileStat1 *st1,
                   uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
 {
-    (void)d_tile_base;
     const int ib = (int)(n_items < kMaxGrid ? n_items : kMaxGrid);
     const int tb = (int)(n_groups < kMaxGrid ? n_groups : kMaxGrid);
     const size_t lds = sizeof(typename KeyOf<PREC>::T) << (sx + sy);
@@ -1882,13 +1881,11 @@ void binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
 
 template <int PREC>
 void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
-                const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
-                int64_t n_htiles, const int64_t *d_gbase, int64_t g0, int64_t n_groups,
+                const int64_t *d_hbase, int64_t n_htiles, const int64_t *d_gbase, int64_t g0,
+                int64_t n_groups,
                 int64_t row_begin, int64_t row_end, const BinBuffers &bb, int sx, int sy,
                 TileStat1 *st1, uint64_t *d_binned, hipStream_t s, const StageEvents *marks)
 {
-    (void)d_tile_base;
-    (void)n_tiles;
     const int64_t nr = row_end - row_begin;
     const int rb = (int)(nr < kMaxGrid ? nr : kMaxGrid);
     const size_t hist_lds = sizeof(uint32_t) * (size_t)(bb.max_tiles > 0 ? bb.max_tiles : 1);
@@ -1931,7 +1928,7 @@ void hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
 }  // namespace
 
 int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem_base,
-                        const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_gbase,
+                        int64_t n_tiles, const int64_t *d_gbase,
                         int64_t g0, int64_t n_groups, int64_t item_begin, int64_t n_items,
                         const BinBuffers &bb, bool first_slice, bool last_slice, int precision,
                         int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
@@ -1939,24 +1936,24 @@ int launch_binned_slice(const DevSim *d_sims, int n_sims, const int64_t *d_bitem
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64)
-        binned_slice<FSM_F64>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, d_gbase, g0, n_groups, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+        binned_slice<FSM_F64>(d_sims, n_sims, d_bitem_base, n_tiles, d_gbase, g0, n_groups, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
     else
-        binned_slice<FSM_F32>(d_sims, n_sims, d_bitem_base, d_tile_base, n_tiles, d_gbase, g0, n_groups, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
+        binned_slice<FSM_F32>(d_sims, n_sims, d_bitem_base, n_tiles, d_gbase, g0, n_groups, item_begin, n_items, bb, first_slice, last_slice, sx, sy, st1, d_binned, s, marks);
     return (int)hipGetLastError();
 }
 
 int launch_hist_slice(const DevSim *d_sims, int n_sims, const int64_t *d_row_base,
-                      const int64_t *d_tile_base, int64_t n_tiles, const int64_t *d_hbase,
-                      int64_t n_htiles, const int64_t *d_gbase, int64_t g0, int64_t n_groups,
+                      const int64_t *d_hbase, int64_t n_htiles, const int64_t *d_gbase,
+                      int64_t g0, int64_t n_groups,
                       int64_t row_begin, int64_t row_end, const BinBuffers &bb, int precision,
                       int sx, int sy, TileStat1 *st1, uint64_t *d_binned, void *stream,
                       const StageEvents *marks)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == FSM_F64)
-        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, d_gbase, g0, n_groups, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F64>(d_sims, n_sims, d_row_base, d_hbase, n_htiles, d_gbase, g0, n_groups, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     else
-        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_tile_base, n_tiles, d_hbase, n_htiles, d_gbase, g0, n_groups, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
+        hist_slice<FSM_F32>(d_sims, n_sims, d_row_base, d_hbase, n_htiles, d_gbase, g0, n_groups, row_begin, row_end, bb, sx, sy, st1, d_binned, s, marks);
     return (int)hipGetLastError();
 }
 
