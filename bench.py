@@ -32,6 +32,8 @@ KEY_BYTES = {"f64": 8, "f32": 4}
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_28160_amd", "csrc", "fsm_kernels.hip")
 STAGE_KERNEL = {"count": "hist_count", "write": "hist_write", "reduce": "tile_reduce"}
+# the Z-map path a call took (fsm_timings.zmap_path)
+PATH_NAMES = {0: "scatter", 1: "run", 2: "histogram", 3: "super"}
 
 
 def pct(xs, q):
@@ -99,6 +101,7 @@ def run_precision(ctx, sim, prec, steps, warmup, profile, graphs=False):
                   "reduce_ms"):
             out[k] = statistics.mean(t[k] for t in tim)
         out["n_slices"] = tim[-1]["n_slices"]
+        out["zmap_path"] = tim[-1]["zmap_path"]
     return out
 
 
@@ -194,13 +197,13 @@ def large_leg(ctx, steps=3):
         del z
         torch.cuda.empty_cache()
         prof = {k: t[k] for k in ("fill_ms", "scatter_ms", "rough_ms", "count_ms", "index_ms",
-                                  "write_ms", "reduce_ms", "n_slices")}
+                                  "write_ms", "reduce_ms", "n_slices", "zmap_path")}
         prof["rough"] = r
         out[prec] = {"ms_per_sim": el * 1e3, "cells_per_s": cells / el,
                      "evals_per_s": plan["n_evals"] / el, "coverage": r["n_hit"] / cells,
                      "kernel_ms": {k[:-3]: prof[k] for k in prof if k.endswith("_ms")},
-                     "n_slices": prof["n_slices"],
-                     "rooflines": stage_rooflines(sim, plan, prec, prof, run_mode=True)}
+                     "n_slices": prof["n_slices"], "zmap_path": PATH_NAMES[prof["zmap_path"]],
+                     "rooflines": stage_rooflines(sim, plan, prec, prof)}
         print(f"[bench] config5 {prec}: {el * 1e3:.2f} ms per simulation (count {t['count_ms']:.2f}, "
               f"write {t['write_ms']:.2f}, reduce {t['reduce_ms']:.2f} ms)", file=sys.stderr, flush=True)
     return out
@@ -439,19 +442,23 @@ def latency_leg(ctx, steps=200):
     return out
 
 
-def stage_rooflines(sim, plan, prec, prof, run_mode=False):
+def stage_rooflines(sim, plan, prec, prof):
     """Roofline of every stage of one step, per launch, from the library's HIP events (recorded
     on the stream it launches on).  The binning passes are bound by the vector rate: the
-    algorithmic work is flop_per_eval(tool) times the evaluations.  The scans move the row
-    matrix and are reported by time.  The tile reduction reads every bucket entry (key + 16-bit
-    cell) and writes every cell; the roughness reads every cell once more (its first pass is
-    fused into the reduction)."""
+    algorithmic work is flop_per_eval(tool) times the evaluations (in super mode the write
+    stage also holds the split of the super-tile buckets).  The scans move the row matrix and
+    are reported by time.  The tile reduction reads every bucket entry (key + 16-bit cell) and
+    writes every cell; the roughness reads every cell once more (its first pass is fused into
+    the reduction)."""
     r = prof["rough"]
     n_launch = max(1, prof["n_slices"])
     cells = sim.grid.nx * sim.grid.ny
     kb = KEY_BYTES[prec]
+    path = PATH_NAMES.get(prof.get("zmap_path"), "histogram")
+    run_mode = path == "run"
     names = ("bin_points<%s,false>" if run_mode else "hist_count<%s>",
-             "bin_points<%s,true>" if run_mode else "hist_write<%s>")
+             "bin_points<%s,true>" if run_mode else
+             ("hist_write<%s> + split_super" if path == "super" else "hist_write<%s>"))
     fpe = flop_per_eval(sim.tool)
     out = {}
     for stage, name in (("count", names[0]), ("write", names[1])):
@@ -723,7 +730,9 @@ def main():
                    "passes": plan["n_passes"], "steps_per_pass": plan["n_steps"],
                    "edge_points": sim.tool.n_edge, "evals": plan["n_evals"],
                    "precision": main_prec, "mode": "plain single-simulation launches",
-                   "zmap_strategy": args.strategy, "graphs": args.graphs,
+                   "zmap_strategy": args.strategy,
+                   "zmap_path": PATH_NAMES.get(m["prof"].get("zmap_path"), "scatter"),
+                   "graphs": args.graphs,
                    "tuning_entries": n_tuned, "autotuned": tuned.get(main_prec)},
         "sims_per_s": args.steps / m["elapsed_s"],
         "latency_ms": {"p50": pct(m["lat"], 50), "p99": pct(m["lat"], 99)},
