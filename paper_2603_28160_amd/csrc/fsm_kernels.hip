@@ -8,24 +8,32 @@
 //   scatter : one global integer atomic min per point on an order-preserving encoding of the
 //             height.  Each point touches its own cache line of the map.
 //   binned  : points are sorted by cell tile first and every tile is min-reduced in LDS.
-//             count  - per point its tile; lanes are consecutive time steps, so equal tiles
-//                      come in runs and one atomic add per run counts them;
-//             scan   - exclusive prefix sum of the tile counts (three launches);
-//             write  - the same points again; one atomic add per run on the tile's cursor
-//                      claims the run's slots and each lane stores (height key, cell inside
-//                      the tile);
-//             reduce - one block per tile: keys in LDS, integer ds_min of every bucket entry,
-//                      one coalesced store of the decoded tile, and the first roughness pass
-//                      on the fly.
+//     histogram mode (default): a block owns a row of binning items.
+//             count  - the row's points per tile in an LDS histogram, stored as the row's line
+//                      of a row matrix;
+//             index  - a chunked scan down the matrix's columns gives every (row, tile) its
+//                      offset inside the tile's bucket;
+//             write  - the row's points again; slots claimed with LDS atomics on the row's
+//                      cursors, (height key, cell inside the tile) stored;
+//             reduce - one block per group of consecutive tiles: keys in LDS, integer ds_min
+//                      of every bucket entry, one coalesced store of each decoded tile, and the
+//                      first roughness pass on the fly.
+//     super mode: a map with more tiles than one histogram holds counts and writes per
+//             super-tile (a block of tiles); a split pass then sorts every super-tile's bucket
+//             into its tiles.
+//     run mode: without room for a row matrix, counts and cursors are global atomics, one per
+//             run of equal tiles in a wave (lanes are consecutive time steps).
 //
-// Roughness is tiled as well: per-tile partial sums (count, sum, min, max and the two profile
-// lines; then the central moments), combined per simulation in a fixed order by one block.
+// Roughness is tiled as well: per-tile (or per-group) partial sums (count, sum, min, max and
+// the two profile lines; then the central moments), combined per simulation in a fixed order.
 //
-// Double precision: only +, -, * run on the device (no contraction: -ffp-contract=off), in
-// the order the host planner documents, so binning decisions equal those of the plain
-// definition bit for bit.  Single precision: rotation and tilt in float with explicit fused
-// multiply-adds on tool-local coordinates; the tool-centre position, the workpiece position
-// (centre plus the widened float offset) and the binning stay in double.
+// Double precision: only +, -, * and the correctly rounded division of the tool-centre
+// position run on the device (no contraction: -ffp-contract=off), in the order the host
+// planner documents, so binning decisions equal those of the plain definition bit for bit.
+// Single precision: rotation and tilt in float with explicit fused multiply-adds on
+// tool-local coordinates; the tool-centre position, the binning (one double fused
+// multiply-add per coordinate on the widened float offset) and the roughness moments stay in
+// double.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -360,13 +368,14 @@ __device__ __forceinline__ bool place_point(const DevSim &d, const Turn<FSM_F32>
     return in;
 }
 
-// ---- swept-box culling -------------------------------------------------------------------------
+// ---- culling -------------------------------------------------------------------------------------
 //
 // A wave of a binning item covers 64 consecutive steps of one pass and tooth.  Most of the
 // auto path's evaluations land outside the grid (the path overshoots the grid by the tool
-// reach on every side), so whole waves, and then groups of kGroup edge points, are skipped
-// when a conservative box around their positions misses the grid.  The skipped points would
-// have been dropped by the in-grid test, so results do not change.
+// reach on every side), so whole waves are skipped when the tool centre's path, widened by
+// the reach, misses the grid, and then groups of kGroup edge points when no lane's disc around
+// the group's reference point touches it.  The skipped points would have been dropped by the
+// in-grid test, so results do not change.
 
 // The steps of this thread's wave in step block sb: the first step, the last active lane and
 // the tool-centre x at both ends (x grows with the step).  False past the pass's last step.
@@ -413,7 +422,8 @@ __device__ __forceinline__ bool group_near(const DevSim &d, const Turn<PREC> &a,
     return __ballot(hit) != 0;
 }
 
-// Add a wave's near-boundary counts to the simulation's counter (single precision).
+// Add a wave's near-boundary counts to the simulation's counter (single precision; the
+// scatter strategy and run mode: the histogram mode keeps one count per row instead).
 __device__ __forceinline__ void add_near(const DevSim &d, uint32_t n)
 {
     const uint32_t w = wave_sum(n);
@@ -529,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void trajectory(const DevSim *__restrict__ 
     }
 }
 
-// ---- binned strategy ---------------------------------------------------------------------------
+// ---- binned strategy, run mode -------------------------------------------------------------------
 
 constexpr int kUnroll = 4;   // edge points in flight per lane
 
@@ -1126,7 +1136,7 @@ __global__ __launch_bounds__(kBlock) void scan_single(const uint32_t *counts, in
     if (threadIdx.x == 0) offsets[n] = tot;
 }
 
-// Accumulator of the first roughness pass over one tile.
+// Accumulator of the first roughness pass over one tile or group of tiles.
 struct Stat1Acc {
     double sum = 0.0, mn = INFINITY, mx = -INFINITY, row_sum = 0.0, col_sum = 0.0;
     int64_t n = 0;
@@ -1533,7 +1543,7 @@ __global__ __launch_bounds__(kBlock) void tile_stats1(const DevSim *__restrict__
 
 constexpr int kFinalDepth = 8;   // tile partials in flight per thread of the final combines
 
-// One block per simulation: combine its tiles' first-pass partials in a fixed order.
+// One block per simulation: combine its tile groups' first-pass partials in a fixed order.
 __global__ __launch_bounds__(kBlock) void rough_final1(const DevSim *__restrict__ sims,
                                                        const TileStat1 *__restrict__ st1,
                                                        RoughState *state)
