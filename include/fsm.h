@@ -182,10 +182,12 @@ typedef struct fsm_timings {
     int32_t reserved;
 } fsm_timings;
 
-/* Z-map paths (fsm_timings.zmap_path).  The binned strategy counts the points of a row of
- * binning items per tile in LDS when a simulation's tiles fit one histogram (histogram mode),
- * per super-tile of several tiles with a split pass into the tiles otherwise (super mode), and
- * with global atomics per tile when even its super-tiles do not fit (run mode). */
+/* Z-map paths (fsm_timings.zmap_path, fsm_plan_info.zmap_path).  The binned strategy counts
+ * the points of a row of binning items per tile in LDS when a simulation's tiles fit one
+ * histogram (histogram mode), per super-tile of up to 64 tiles with a split pass into the
+ * tiles otherwise (super mode), and with global atomics per tile when even its super-tiles do
+ * not fit or the row matrix would exceed FSM_OPT_HIST_BYTES (run mode).  Every path gives the
+ * same Z-map; FSM_PATH_SCATTER is the scatter strategy. */
 #define FSM_PATH_SCATTER 0
 #define FSM_PATH_RUN 1
 #define FSM_PATH_HIST 2
