@@ -198,18 +198,24 @@ int build_plan(const fsm_tool &t, const fsm_cut &c, const fsm_grid &g, Plan &P,
     const double off = t.kind == FSM_TOOL_ROUND ? t.D / 2.0 : 0.0;
     const double tanb = std::tan(t.helix);
     const double rref = t.D / 2.0;
+    // the edge profile and the helix lag depend on the point only, not on the tooth
+    std::vector<double> el((size_t)N), ez((size_t)N), lc((size_t)N), ls((size_t)N);
+    for (int p = 0; p < N; ++p) {
+        edge_point(t, c, p, el[p], ez[p]);
+        const double psi = (ez[p] * tanb) / rref;           // helix lag angle
+        lc[p] = std::cos(psi);
+        ls[p] = std::sin(psi);
+    }
     for (int K = 0; K < Z; ++K) {
         const double tx = off + t.eps_r[K];
         const double ph = t.runout_phase + tooth_angle(t, K);
         const double ex = t.runout_ecc * std::cos(ph), ey = t.runout_ecc * std::sin(ph);
         for (int p = 0; p < N; ++p) {
-            double l, zc;
-            edge_point(t, c, p, l, zc);
+            const double l = el[p], zc = ez[p];
             const double a0 = (cf * l + m02 * zc) + tx;     // Eq. (2), row 1
             const double a1 = (-sf) * l + m12 * zc;         // Eq. (2), row 2
             const double a2 = cp * zc + t.eps_a[K];         // Eq. (2), row 3
-            const double psi = (zc * tanb) / rref;          // helix lag angle
-            const double cq = std::cos(psi), sq = std::sin(psi);
+            const double cq = lc[p], sq = ls[p];
             const double b0 = cq * a0 + sq * a1;
             const double b1 = (-sq) * a0 + cq * a1;
             double *o = &P.pT[((size_t)K * N + p) * 3];
