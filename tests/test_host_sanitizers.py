@@ -1,7 +1,8 @@
 """The host-only C++ checks rebuilt with the compiler's sanitizers: the planner's thread pool
-under ThreadSanitizer (no data race, no lock-order problem), and the pool, map-overlap sweep
-and serving arena under AddressSanitizer with UndefinedBehaviorSanitizer (no out-of-bounds
-access, leak or undefined operation).  g++ on the CPU only; no device code is built here."""
+and the planner itself under ThreadSanitizer (no data race, no lock-order problem), and the
+pool, the planner, map-overlap sweep and serving arena under AddressSanitizer with
+UndefinedBehaviorSanitizer (no out-of-bounds access, leak or undefined operation).  g++ on the
+CPU only; no device code is built here."""
 import os
 import subprocess
 
@@ -15,13 +16,15 @@ CHECKS = {
     "pool": ["pool_check.cpp", os.path.join(CSRC, "fsm_plan.cpp")],
     "spans": ["spans_check.cpp"],
     "arena": ["arena_check.cpp", os.path.join(CSRC, "fsm_sched.cpp")],
+    "plan": ["plan_check.cpp", os.path.join(CSRC, "fsm_plan.cpp")],
 }
 SANITIZERS = {
     "thread": (["-fsanitize=thread"], {"TSAN_OPTIONS": "halt_on_error=1"}),
     "address": (["-fsanitize=address,undefined", "-fno-sanitize-recover=all"],
                 {"ASAN_OPTIONS": "detect_leaks=1", "UBSAN_OPTIONS": "halt_on_error=1"}),
 }
-CASES = [("pool", "thread"), ("pool", "address"), ("spans", "address"), ("arena", "address")]
+CASES = [("pool", "thread"), ("pool", "address"), ("spans", "address"), ("arena", "address"),
+         ("plan", "address"), ("plan", "thread")]
 
 
 @pytest.mark.parametrize("check,san", CASES, ids=[f"{c}-{s}" for c, s in CASES])
