@@ -56,3 +56,6 @@ def test_benchmark_workloads_have_entries(table, prec):
     keys = {e["key"] for e in table["entries"]}
     assert class_key([W.config2()], prec) in keys
     assert class_key(W.config3(256), prec) in keys
+    # the large field and the latency workload are timed with the table as well
+    assert class_key([W.config5()], prec) in keys
+    assert class_key([W.config1()], prec) in keys
